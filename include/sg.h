@@ -1,0 +1,245 @@
+/*
+ * sg.h -- C ABI of libsg: single-bit-upset injection into stored 3D Gaussian
+ * splatting parameters, batched forward rendering of the corrupted variants,
+ * per-variant image metrics, and the per-primitive support guard.
+ *
+ * Paper: "Single-Event Upsets in 3D Gaussian Splatting Rendering: Bit-Level
+ * Criticality, Spatial Extent, and a Parallel Support Guard".  Each entry
+ * point cites the passage that defines the operation it performs.
+ *
+ * Conventions shared by every call
+ *   - Pointers are DEVICE pointers unless the comment says "host".
+ *   - The caller owns every array it passes (scenes, sites, boxes, images,
+ *     metrics).  A context owns its workspaces; a prepared scene (sg_prep)
+ *     owns its resident clean state; a server owns its resident copies.
+ *   - Every call is asynchronous on the given HIP stream (hipStream_t passed
+ *     as void*; NULL is the null stream).  Outputs are valid once the stream
+ *     has been synchronised.  Calls that must size data-dependent buffers
+ *     (sg_render, sg_prepare, and the multi-upset fallback of
+ *     sg_render_batch) synchronise the stream once internally.
+ *   - Errors are status codes; nothing throws across the boundary.  Argument
+ *     validation runs before any device work, so a call that returns
+ *     SG_E_INVAL has modified nothing.  A failing HIP call returns
+ *     SG_E_DEVICE; sg_last_error() gives the text (thread-local).
+ *   - A context and the objects made from it are single-threaded: one host
+ *     thread at a time.  The server API is thread-safe.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sg_status;
+enum {
+  SG_OK = 0,
+  SG_E_INVAL = -1,        /* bad argument; nothing was modified */
+  SG_E_NOMEM = -2,        /* device allocation failed or budget exceeded */
+  SG_E_DEVICE = -3,       /* a HIP call failed (see sg_last_error) */
+  SG_E_BUSY = -4,         /* server queue full */
+  SG_E_PENDING = -5,      /* server request not finished yet */
+  SG_E_UNSUPPORTED = -6
+};
+
+/* Storage formats (Sec. 3, "Single-bit upset model"): fp32 1|8|23, fp16 1|5|10, bf16 1|8|7. */
+enum { SG_F32 = 0, SG_F16 = 1, SG_BF16 = 2 };
+/* Rounding of sg_cast: nearest-even, toward -Inf, toward +Inf. */
+enum { SG_RNE = 0, SG_RD = 1, SG_RU = 2 };
+
+/* The six stored fields of a primitive (Sec. 3, "Parameter layout"):
+ * mean (3), log-scale (3), quaternion w,x,y,z (4), opacity logit (1),
+ * degree-0 SH colour (3), higher-order SH (3*((L+1)^2-1), component
+ * c = 3*k + channel for coefficient k = 1..(L+1)^2-1). */
+enum { SG_MEANS = 0, SG_LOG_SCALES = 1, SG_QUATS = 2, SG_OPACITY = 3, SG_SH_DC = 4, SG_SH_REST = 5 };
+#define SG_FIELD_MASK_GUARD 0x1Fu   /* fields 0..4: the 14 components the guard covers (Sec. 5.12) */
+
+/* A scene in storage format: field f, primitive i, component c lives at
+ * ptr[f] + (i * prim_stride[f] + c * comp_stride[f]) elements of the
+ * format's width (4 bytes for fp32, 2 for fp16/bf16).  Component-major
+ * (prim_stride = 1, comp_stride = n) is the fast layout.  16-bit fields must
+ * start on a 4-byte boundary and their allocation must extend to a 4-byte
+ * boundary (true of hipMalloc and torch allocations): sg_inject flips a 16-bit
+ * word through its aligned 32-bit container.  Caller-owned device memory. */
+typedef struct {
+  void* ptr[6];
+  int64_t prim_stride[6];
+  int64_t comp_stride[6];
+  int32_t n;           /* primitives, >= 1 */
+  int32_t sh_degree;   /* 0..3 */
+  int32_t dtype;       /* SG_F32 / SG_F16 / SG_BF16 */
+  int32_t _pad;
+} sg_scene;
+
+/* A fault site (field, primitive, component, bit) (Sec. 3). bit < format width. */
+typedef struct {
+  uint8_t field;
+  uint8_t bit;
+  uint16_t comp;
+  uint32_t prim;
+} sg_site;
+
+/* Pinhole camera, OpenCV axes: a world point X maps to camera point R X + t,
+ * pixel (u, v) = (fx x/z + cx, fy y/z + cy); pixel (i, j) has its centre at
+ * (i + 0.5, j + 0.5).  Primitives with z <= near_z or z > far_z are culled. */
+typedef struct {
+  double R[9];         /* row-major */
+  double t[3];
+  double fx, fy, cx, cy, near_z, far_z;
+  int32_t width, height;
+} sg_camera;
+
+/* Compositing constants (3DGS rasterizer; 0.99 and 1e-4 as configured for
+ * the paper's workloads).  Pass NULL for the defaults shown. */
+typedef struct {
+  int32_t tile;        /* 8, 16 or 32 pixels; 0 = tuned default (16) */
+  float alpha_max;     /* 0.99 */
+  float alpha_min;     /* 1/255 */
+  float t_min;         /* 1e-4 */
+  float cut_q;         /* 9 (3-sigma ellipse) */
+  float dilation;      /* 0.3 */
+  float bg[3];         /* 1, 1, 1 (white, Sec. 3 "Metrics") */
+} sg_raster;
+
+/* Support box (Alg. 1; Thm. 1).  mode SG_BOX_GLOBAL: lo[f], hi[f] hold C_f
+ * words each (per field and component).  mode SG_BOX_PER_PRIM: lo[f], hi[f]
+ * hold C_f * n words, component-major (component c of primitive i at
+ * c * n + i).  Words are in the scene's storage format. */
+enum { SG_BOX_GLOBAL = 0, SG_BOX_PER_PRIM = 1 };
+typedef struct {
+  int32_t mode;
+  int32_t dtype;
+  void* lo[6];
+  void* hi[6];
+} sg_box;
+
+/* One corrupted variant of a prepared scene: sites[site_off .. site_off+n_sites)
+ * of the batch's site array are applied together; guard != 0 clamps the
+ * variant into the batch's box before it is rendered. */
+typedef struct {
+  uint32_t site_off;
+  uint32_t n_sites;
+  uint32_t guard;
+  uint32_t _pad;
+} sg_variant;
+
+/* Per-variant result (Sec. 3 "Metrics"; Def. 1; Def. 2).  footprint is the
+ * fraction of pixels with max over RGB |delta| > 1/255; catastrophic is
+ * nonfinite || footprint > 0.01; psnr is +Inf when mse == 0. */
+typedef struct {
+  double sse;
+  double mse;
+  double psnr;
+  float footprint;
+  float max_abs;
+  uint32_t nonfinite;
+  uint32_t catastrophic;
+  uint32_t changed_px;
+  uint32_t dirty_tiles;   /* tiles re-composited for this variant */
+  uint64_t clamps;        /* guard clamps applied to this variant */
+  uint32_t n_pixels;      /* K * H * W compared */
+  uint32_t path;          /* 0 incremental, 1 full render */
+} sg_metrics_t;
+
+typedef struct sg_ctx sg_ctx;
+typedef struct sg_prep sg_prep;
+
+/* Context on HIP device `device`.  hbm_budget_bytes caps the context's own
+ * workspaces (0 = no cap).  Returns SG_E_DEVICE if the device is absent. */
+sg_status sg_ctx_create(int32_t device, size_t hbm_budget_bytes, sg_ctx** out);
+void sg_ctx_destroy(sg_ctx* ctx);
+const char* sg_last_error(void);
+/* Bytes of device memory the context and its prepared scenes hold. */
+size_t sg_ctx_bytes(const sg_ctx* ctx);
+
+/* Cast n fp32 values into `dtype` words with rounding mode `rounding`
+ * (Sec. 3: reduced precisions hold the clean fp32 parameter cast to the
+ * format).  Subnormals are kept; RNE overflows to Inf.  dst holds n words. */
+sg_status sg_cast(sg_ctx* ctx, const float* src, void* dst, int64_t n, int32_t dtype, int32_t rounding,
+                  void* stream);
+
+/* Flip sites[k].bit of each addressed stored word in place (Sec. 3: the word
+ * is XORed with 1 << bit).  sites is a HOST array of n entries; it is
+ * validated (field present, comp < C_f, prim < n, bit < width) before any
+ * device work.  saved (nullable, n words) receives each word's value before
+ * its own flip.  Flipping the same sites again restores the scene (sg_restore). */
+sg_status sg_inject(sg_ctx* ctx, const sg_scene* scene, const sg_site* sites, int32_t n, uint32_t* saved,
+                    void* stream);
+/* Undo sg_inject by flipping the same sites again (the paper restores the
+ * working copy after each injection, Sec. 3 "Parallel injection engine").
+ * saved is accepted for symmetry and may be NULL. */
+sg_status sg_restore(sg_ctx* ctx, const sg_scene* scene, const sg_site* sites, int32_t n,
+                     const uint32_t* saved, void* stream);
+
+/* Precompute the support box of a clean scene (Alg. 1, first loop): for each
+ * field in field_mask and each component, lo = minimum and hi = maximum of
+ * the stored values over all primitives (IEEE order; a -0/+0 tie gives -0 for
+ * lo and +0 for hi).  out->mode must be SG_BOX_GLOBAL and out->lo[f],
+ * out->hi[f] must point to C_f words each for every field in the mask.  The
+ * clean scene must be finite. */
+sg_status sg_guard_box(sg_ctx* ctx, const sg_scene* clean, uint32_t field_mask, sg_box* out, void* stream);
+
+/* Clamp every component of every primitive of the fields in field_mask into
+ * the box, in place (Alg. 1, per-frame loop; Thm. 1): NaN -> lo, x < lo ->
+ * lo, x > hi -> hi, otherwise the word is untouched.  clamp_count (device,
+ * one uint64) receives the number of clamped components; health_alert
+ * (device uint32, nullable) receives clamp_count > health_threshold. */
+sg_status sg_guard(sg_ctx* ctx, const sg_scene* scene, const sg_box* box, uint32_t field_mask,
+                   uint64_t health_threshold, uint64_t* clamp_count, uint32_t* health_alert, void* stream);
+
+/* Full render of `scene` as it is in memory: projection, tile binning,
+ * depth sort and front-to-back compositing over raster->bg (Sec. 2 "Gaussian
+ * splatting"; Sec. 3 "Metrics").  box (nullable) clamps every guarded
+ * component while it is loaded (the guard applied without writing the
+ * scene).  image_out (nullable) receives height*width*3 floats, row-major
+ * RGB.  If clean_frame (nullable) is given, metrics_out (device, one entry)
+ * receives the metrics of this render against it.  This is the plain
+ * one-render-per-injection path.  Synchronises the stream once. */
+sg_status sg_render(sg_ctx* ctx, const sg_scene* scene, const sg_camera* cam, const sg_raster* raster,
+                    const sg_box* box, uint32_t box_field_mask, float* image_out, const float* clean_frame,
+                    sg_metrics_t* metrics_out, void* stream);
+
+/* Make a scene resident for batched injection: project it, bin and sort its
+ * tiles and render its clean frame once, and keep all of it on the device
+ * (Sec. 3: the clean parameters stay resident).  The scene's memory must stay
+ * valid and unmodified while the sg_prep is alive.  Synchronises once. */
+sg_status sg_prepare(sg_ctx* ctx, const sg_scene* clean, const sg_camera* cam, const sg_raster* raster,
+                     sg_prep** out, void* stream);
+void sg_prep_destroy(sg_prep* prep);
+/* Device pointer to the prepared clean frame (height*width*3 floats). */
+const float* sg_prep_frame(const sg_prep* prep);
+/* Instances (primitive-tile pairs) in the prepared tile lists. */
+int64_t sg_prep_instances(const sg_prep* prep);
+/* Copy the prepared clean frame into dst (device, height*width*3 floats). */
+sg_status sg_prep_copy_frame(const sg_prep* prep, float* dst, void* stream);
+
+/* Render B corrupted variants of a prepared scene and score each against the
+ * clean frame (Sec. 5.12: many independently corrupted variants per launch;
+ * Sec. 3 "Metrics"; Def. 1; Def. 2).  sites: HOST array of n_sites;
+ * variants: HOST array of B.  box (nullable) is used by variants with
+ * guard != 0 and must contain the clean scene (Thm. 1 (i)); box_field_mask
+ * selects the guarded fields.  mode SG_INCREMENTAL re-composites only the
+ * tiles covered by the old or new footprint of each corrupted primitive
+ * (bit-identical to a full render); variants touching more than 8 primitives
+ * take the full-render path.  mode SG_FULL renders every variant in full.
+ * images_out (nullable) receives B*height*width*3 floats; metrics_out
+ * (device) receives B entries.  The scene is never modified. */
+enum { SG_INCREMENTAL = 0, SG_FULL = 1 };
+sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites,
+                          const sg_variant* variants, int32_t B, const sg_box* box, uint32_t box_field_mask,
+                          float* images_out, sg_metrics_t* metrics_out, int32_t mode, void* stream);
+
+/* Metrics of B*K frames against K clean frames (Sec. 3; Def. 1; Def. 2):
+ * images is [B][K][H][W][3], clean is [K][H][W][3]; MSE and the footprint are
+ * pooled over the K views of a variant.  nonfinite is set for a variant with
+ * any non-finite value in its frames.  out: B entries (device). */
+sg_status sg_metrics(sg_ctx* ctx, const float* images, const float* clean, int32_t B, int32_t K, int32_t H,
+                     int32_t W, sg_metrics_t* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SG_H */

@@ -1,0 +1,212 @@
+// Element-wise and reduction kernels of libsg: format casts, bit-flip
+// injection, the support-box reduction and the guard clamp (Alg. 1), and
+// the fixed-order reduction of metric partials.
+#include "sg_device.h"
+#include "sg_kernels.h"
+
+namespace sg {
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_cast(const float* __restrict__ src, void* __restrict__ dst, int64_t n, int dtype, int mode) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t w = cast_word(src[i], dtype, mode);
+    if (dtype == SG_F32) reinterpret_cast<uint32_t*>(dst)[i] = w;
+    else reinterpret_cast<uint16_t*>(dst)[i] = (uint16_t)w;
+  }
+}
+
+// XOR one bit of each addressed word.  16-bit words are flipped with a 32-bit
+// atomic on their aligned container so that sites sharing a word compose.
+__global__ void k_inject(DevScene s, const sg_site* __restrict__ sites, int n, uint32_t* saved) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const sg_site st = sites[k];
+  const int64_t idx = (int64_t)st.prim * s.ps[st.field] + (int64_t)st.comp * s.cs[st.field];
+  uint32_t old;
+  if (s.dtype == SG_F32) {
+    uint32_t* p = const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(s.ptr[st.field])) + idx;
+    old = atomicXor(p, 1u << st.bit);
+  } else {
+    uintptr_t a = reinterpret_cast<uintptr_t>(reinterpret_cast<const uint16_t*>(s.ptr[st.field]) + idx);
+    const uint32_t shift = (a & 2u) ? 16u : 0u;
+    uint32_t* p = reinterpret_cast<uint32_t*>(a & ~(uintptr_t)3);
+    old = (atomicXor(p, 1u << (st.bit + shift)) >> shift) & 0xffffu;
+  }
+  if (saved) saved[k] = old;
+}
+
+// Box reduction (Alg. 1 precompute): order keys of every component, min and
+// max by atomics on the keys (the result does not depend on the order).
+__global__ void k_box_reduce(DevScene s, int f, uint32_t* __restrict__ kmin, uint32_t* __restrict__ kmax) {
+  const int c = blockIdx.y;
+  uint32_t mn = 0xffffffffu, mx = 0u;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t key = order_key(load_word(s, f, i, c), s.dtype);
+    mn = min(mn, key);
+    mx = max(mx, key);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, o));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(kmin + c, mn);
+    atomicMax(kmax + c, mx);
+  }
+}
+
+__global__ void k_box_finalize(const uint32_t* kmin, const uint32_t* kmax, int C, int dtype, void* lo, void* hi) {
+  const int c = threadIdx.x;
+  if (c >= C) return;
+  const uint32_t l = key_to_word(kmin[c], dtype), h = key_to_word(kmax[c], dtype);
+  if (dtype == SG_F32) {
+    reinterpret_cast<uint32_t*>(lo)[c] = l;
+    reinterpret_cast<uint32_t*>(hi)[c] = h;
+  } else {
+    reinterpret_cast<uint16_t*>(lo)[c] = (uint16_t)l;
+    reinterpret_cast<uint16_t*>(hi)[c] = (uint16_t)h;
+  }
+}
+
+// Guard clamp of one field in place (Alg. 1 per frame).  Only clamped words
+// are written.  Clamps are counted per wave with a ballot.
+__global__ void k_guard(DevScene s, DevBox b, int f, unsigned long long* __restrict__ count) {
+  const int c = blockIdx.y;
+  uint32_t local = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t w = load_word(s, f, i, c);
+    uint32_t lo, hi;
+    box_words(b, f, i, c, s.n, &lo, &hi);
+    bool clamped;
+    const uint32_t g = clamp_word(w, lo, hi, s.dtype, &clamped);
+    if (clamped) {
+      const int64_t idx = i * s.ps[f] + (int64_t)c * s.cs[f];
+      if (s.dtype == SG_F32) const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(s.ptr[f]))[idx] = g;
+      else const_cast<uint16_t*>(reinterpret_cast<const uint16_t*>(s.ptr[f]))[idx] = (uint16_t)g;
+      ++local;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) local += (uint32_t)__shfl_xor((int)local, o);
+  if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, (unsigned long long)local);
+}
+
+__global__ void k_health(const unsigned long long* count, unsigned long long threshold, uint32_t* alert) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *alert = (*count > threshold) ? 1u : 0u;
+}
+
+// Frame metrics of standalone images: one block per (chunk, variant).
+__global__ void k_metrics_partials(const float* __restrict__ img, const float* __restrict__ clean, int64_t px_per_var,
+                                   int64_t chunk, Partial* __restrict__ out) {
+  const int v = blockIdx.y;
+  const int64_t beg = blockIdx.x * chunk, end = min(px_per_var, beg + chunk);
+  const float* I = img + (int64_t)v * px_per_var * 3;
+  double sse = 0.0;
+  uint32_t changed = 0, nonfin = 0;
+  float mx = 0.f;
+  for (int64_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
+    const float* a = I + p * 3;
+    const float* c = clean + p * 3;
+    double dm = 0.0;
+    for (int ch = 0; ch < 3; ++ch) {
+      const double d = (double)a[ch] - (double)c[ch];
+      if (!isfinite(a[ch])) nonfin = 1;
+      sse += d * d;
+      dm = fmax(dm, fabs(d));
+    }
+    changed += dm > (1.0 / 255.0) ? 1u : 0u;
+    mx = fmaxf(mx, (float)dm);
+  }
+  block_reduce_partial(sse, changed, mx, nonfin, out + (int64_t)v * gridDim.x + blockIdx.x);
+}
+
+// Per variant: partials[item_off[v] .. + n_items[v]) in a fixed order -> metrics.
+__global__ void k_reduce_metrics(const Partial* __restrict__ parts, const uint32_t* __restrict__ item_off,
+                                 const uint32_t* __restrict__ n_items, uint32_t uniform_items, const VariantState* vs,
+                                 const uint32_t* flags, const unsigned long long* clamps, uint32_t n_pixels,
+                                 sg_metrics_t* __restrict__ out, uint32_t path) {
+  const int v = blockIdx.x;
+  const uint32_t off = item_off ? item_off[v] : v * uniform_items;
+  const uint32_t n = n_items ? n_items[v] : uniform_items;
+  double sse = 0.0;
+  uint32_t changed = 0, nonfin = 0;
+  float mx = 0.f;
+  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const Partial p = parts[off + k];
+    sse += p.sse;
+    changed += p.changed;
+    mx = fmaxf(mx, p.max_abs);
+    nonfin |= p.nonfinite;
+  }
+  __shared__ Partial red;
+  block_reduce_partial(sse, changed, mx, nonfin, &red);
+  if (threadIdx.x == 0) {
+    sg_metrics_t m;
+    m.sse = red.sse;
+    m.mse = red.sse / (3.0 * (double)n_pixels);
+    m.psnr = m.mse == 0.0 ? __longlong_as_double(0x7ff0000000000000ll) : 10.0 * log10(1.0 / m.mse);
+    m.changed_px = red.changed;
+    m.footprint = (float)((double)red.changed / (double)n_pixels);
+    m.max_abs = red.max_abs;
+    m.nonfinite = red.nonfinite | (vs ? vs[v].nonfinite : 0u) | (flags ? (flags[0] & 1u) : 0u);
+    m.catastrophic = (m.nonfinite || (double)red.changed > 0.01 * (double)n_pixels) ? 1u : 0u;
+    m.dirty_tiles = vs ? vs[v].n_dirty : n;
+    m.clamps = vs ? vs[v].clamps : (clamps ? *clamps : 0ull);
+    m.n_pixels = n_pixels;
+    m.path = path;
+    out[v] = m;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// host launchers
+
+static inline int blocks_for(int64_t n, int bs, int cap = 65535) {
+  int64_t b = (n + bs - 1) / bs;
+  return (int)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill_u32<<<blocks_for(n, 256, 4096), 256, 0, st>>>(p, v, n);
+}
+void launch_cast(const float* src, void* dst, int64_t n, int dtype, int mode, hipStream_t st) {
+  k_cast<<<blocks_for(n, 256, 16384), 256, 0, st>>>(src, dst, n, dtype, mode);
+}
+void launch_inject(const DevScene& s, const sg_site* sites, int n, uint32_t* saved, hipStream_t st) {
+  if (n <= 0) return;
+  k_inject<<<(n + 255) / 256, 256, 0, st>>>(s, sites, n, saved);
+}
+void launch_box_reduce(const DevScene& s, int f, uint32_t* kmin, uint32_t* kmax, hipStream_t st) {
+  dim3 g(blocks_for(s.n, 256, 1024), s.ncomp[f]);
+  k_box_reduce<<<g, 256, 0, st>>>(s, f, kmin, kmax);
+}
+void launch_box_finalize(const uint32_t* kmin, const uint32_t* kmax, int C, int dtype, void* lo, void* hi,
+                         hipStream_t st) {
+  k_box_finalize<<<1, 64, 0, st>>>(kmin, kmax, C, dtype, lo, hi);
+}
+void launch_guard(const DevScene& s, const DevBox& b, int f, unsigned long long* count, hipStream_t st) {
+  dim3 g(blocks_for(s.n, 256, 2048), s.ncomp[f]);
+  k_guard<<<g, 256, 0, st>>>(s, b, f, count);
+}
+void launch_health(const unsigned long long* count, unsigned long long thr, uint32_t* alert, hipStream_t st) {
+  k_health<<<1, 64, 0, st>>>(count, thr, alert);
+}
+void launch_metrics_partials(const float* img, const float* clean, int64_t px_per_var, int nchunks, int B,
+                             Partial* out, hipStream_t st) {
+  const int64_t chunk = (px_per_var + nchunks - 1) / nchunks;
+  dim3 g(nchunks, B);
+  k_metrics_partials<<<g, 256, 0, st>>>(img, clean, px_per_var, chunk, out);
+}
+void launch_reduce_metrics(const Partial* parts, const uint32_t* item_off, const uint32_t* n_items,
+                           uint32_t uniform_items, const VariantState* vs, const uint32_t* flags,
+                           const unsigned long long* clamps, uint32_t n_pixels, sg_metrics_t* out, int B,
+                           uint32_t path, hipStream_t st) {
+  if (B <= 0) return;
+  k_reduce_metrics<<<B, 256, 0, st>>>(parts, item_off, n_items, uniform_items, vs, flags, clamps, n_pixels, out,
+                                      path);
+}
+
+}  // namespace sg

@@ -1,0 +1,230 @@
+// Front-to-back compositing of one tile, fused with the metric partials
+// against the clean frame.
+//
+// One workgroup per tile (TILE x TILE threads, one pixel each).  The tile's
+// list is streamed through LDS in batches of TILE*TILE records; every thread
+// walks the batch for its own pixel.  A pixel stops at the first contributor
+// whose transmittance would fall below t_min (that contributor is not
+// blended); the workgroup leaves as soon as all its pixels have stopped.
+//
+// The incremental path composites the *merged* list of a (variant, tile)
+// work item: the clean list with the variant's corrupted primitives removed
+// and their new records inserted at their (depth, id) position.  Both paths
+// run this same code per pixel, so an incrementally re-composited tile is
+// bit-identical to a full render of the variant.
+#include "sg_device.h"
+#include "sg_kernels.h"
+
+namespace sg {
+
+struct MergeSpec {
+  uint32_t raw_start, raw_len, mlen;
+  int n_rm, n_ins;
+  uint32_t rm_pos[kMaxTouch];
+  uint32_t ins_mpos[kMaxTouch];
+  uint32_t ins_src[kMaxTouch];   // index into the override records
+};
+
+template <int TILE>
+__device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, const MergeSpec* ms, const Rec* ovr,
+                                               float* img, Partial* part, float4* s_r0, float4* s_r1,
+                                               float4* s_r2) {
+  constexpr int BS = TILE * TILE;
+  const int tid = threadIdx.x;
+  const int tx = tile % A.ras.tiles_x, ty = tile / A.ras.tiles_x;
+  const int x = tx * TILE + (tid % TILE), y = ty * TILE + (tid / TILE);
+  const bool inside = x < A.W && y < A.H;
+  const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+  const float amax = A.ras.amax, amin = A.ras.amin, tmin = A.ras.tmin, qc = A.ras.qcut2;
+
+  uint32_t raw_start, mlen;
+  if (ms) { raw_start = ms->raw_start; mlen = ms->mlen; }
+  else { raw_start = A.tile_start[tile]; mlen = A.tile_cnt[tile]; }
+
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  bool done = !inside;
+  for (uint32_t base = 0; base < mlen; base += BS) {
+    if (__syncthreads_and(done)) break;
+    const uint32_t m = base + tid;
+    if (m < mlen) {
+      float4 a, b, c;
+      if (!ms) {
+        const uint32_t id = (uint32_t)A.keys[raw_start + m];
+        a = A.r0[id]; b = A.r1[id]; c = A.r2[id];
+      } else {
+        int before = 0, hit = -1;
+        for (int j = 0; j < ms->n_ins; ++j) {
+          if (ms->ins_mpos[j] == m) hit = j;
+          before += ms->ins_mpos[j] < m ? 1 : 0;
+        }
+        if (hit >= 0) {
+          const Rec r = ovr[ms->ins_src[hit]];
+          a = r.r0; b = r.r1; c = r.r2;
+        } else {
+          uint32_t raw = m - before;
+          for (int k = 0; k < ms->n_rm; ++k) raw += ms->rm_pos[k] <= raw ? 1u : 0u;
+          const uint32_t id = (uint32_t)A.keys[raw_start + raw];
+          a = A.r0[id]; b = A.r1[id]; c = A.r2[id];
+        }
+      }
+      s_r0[tid] = a; s_r1[tid] = b; s_r2[tid] = c;
+    }
+    __syncthreads();
+    if (!done) {
+      const int cnt = (int)min((uint32_t)BS, mlen - base);
+      for (int j = 0; j < cnt; ++j) {
+        const float4 a = s_r0[j];
+        const float4 b = s_r1[j];
+        const float ex = px - a.x, ey = py - a.y;
+        const float uu = fmaf(ex, a.z, fmaf(ey, a.w, -b.x));
+        const float vv = fmaf(ey, a.z, fmaf(-ex, a.w, -b.y));
+        const float q = fmaf(vv, vv * b.w, uu * (uu * b.z));
+        if (q > qc) continue;
+        const float4 c = s_r2[j];
+        const float alpha = fminf(amax, c.x * __builtin_amdgcn_exp2f(-q));
+        if (alpha < amin) continue;
+        const float Tn = T * (1.f - alpha);
+        if (Tn < tmin) { done = true; break; }
+        const float w = alpha * T;
+        C0 = fmaf(c.y, w, C0);
+        C1 = fmaf(c.z, w, C1);
+        C2 = fmaf(c.w, w, C2);
+        T = Tn;
+      }
+    }
+  }
+
+  double sse = 0.0;
+  uint32_t changed = 0, nonfin = 0;
+  float mx = 0.f;
+  if (inside) {
+    const float p0 = fmaf(T, A.ras.bg[0], C0), p1 = fmaf(T, A.ras.bg[1], C1), p2 = fmaf(T, A.ras.bg[2], C2);
+    nonfin = (isfinite(p0) && isfinite(p1) && isfinite(p2)) ? 0u : 1u;
+    const float i0 = fminf(p0, 1.f), i1 = fminf(p1, 1.f), i2 = fminf(p2, 1.f);
+    const int64_t off = ((int64_t)y * A.W + x) * 3;
+    if (img) { img[off] = i0; img[off + 1] = i1; img[off + 2] = i2; }
+    if (A.clean) {
+      const double d0 = (double)i0 - (double)A.clean[off], d1 = (double)i1 - (double)A.clean[off + 1],
+                   d2 = (double)i2 - (double)A.clean[off + 2];
+      sse = d0 * d0 + d1 * d1 + d2 * d2;
+      const double dm = fmax(fabs(d0), fmax(fabs(d1), fabs(d2)));
+      changed = dm > (1.0 / 255.0) ? 1u : 0u;
+      mx = (float)dm;
+    }
+  }
+  if (part) block_reduce_partial(sse, changed, mx, nonfin, part);
+}
+
+// Full render: one workgroup per tile.  Block b of the grid serves tile
+// (b % 8) * chunk + b / 8 so the tiles that one XCD (which receives every
+// 8th workgroup) composites form a contiguous band of the frame whose
+// primitive records share that XCD's L2.
+template <int TILE>
+__global__ void __launch_bounds__(TILE * TILE) k_composite_full(CompArgs A) {
+  __shared__ float4 s_r0[TILE * TILE], s_r1[TILE * TILE], s_r2[TILE * TILE];
+  const int nt = A.ras.n_tiles;
+  const int chunk = (nt + 7) / 8;
+  const int b = blockIdx.x;
+  const int tile = (b % 8) * chunk + b / 8;
+  if (tile >= nt) return;
+  composite_tile<TILE>(A, tile, nullptr, nullptr, A.image, A.parts ? A.parts + tile : nullptr, s_r0, s_r1, s_r2);
+}
+
+__device__ __forceinline__ bool rect_has(uint32_t r0, uint32_t r1, int tx, int ty) {
+  return tx >= (int)(r0 & 0xffff) && tx <= (int)(r1 & 0xffff) && ty >= (int)(r0 >> 16) && ty <= (int)(r1 >> 16);
+}
+
+__device__ __forceinline__ uint32_t lower_bound_keys(const uint64_t* k, uint32_t n, uint64_t key) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (k[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Persistent incremental compositing: a fixed grid of workgroups pops
+// (variant, tile) work items from a device counter until the batch's item
+// count (known only on the device) is exhausted.
+template <int TILE>
+__global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, ItemArgs I) {
+  __shared__ float4 s_r0[TILE * TILE], s_r1[TILE * TILE], s_r2[TILE * TILE];
+  __shared__ MergeSpec ms;
+  __shared__ uint32_t s_item;
+  __shared__ uint64_t s_ins_key[kMaxTouch];
+  const uint32_t total = *I.n_items_total;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(I.counter, 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    if (item >= total) break;
+    const uint2 it = I.items[item];
+    const uint32_t v = it.x;
+    const int tile = (int)it.y;
+    if (threadIdx.x == 0) {
+      const VariantState& vs = I.vs[v];
+      const int tx = tile % A.ras.tiles_x, ty = tile / A.ras.tiles_x;
+      ms.raw_start = A.tile_start[tile];
+      ms.raw_len = A.tile_cnt[tile];
+      const uint64_t* keys = A.keys + ms.raw_start;
+      int nr = 0, ni = 0;
+      for (uint32_t j = 0; j < vs.n_touch; ++j) {
+        const Touch t = vs.touch[j];
+        if (t.flags & 4u) continue;   // unchanged primitive
+        if ((t.flags & 1u) && rect_has(t.old_rect0, t.old_rect1, tx, ty)) {
+          const uint64_t k = ((uint64_t)t.old_depth << 32) | t.prim;
+          const uint32_t pos = lower_bound_keys(keys, ms.raw_len, k);
+          if (pos < ms.raw_len && keys[pos] == k) ms.rm_pos[nr++] = pos;
+        }
+        if ((t.flags & 2u) && rect_has(t.new_rect0, t.new_rect1, tx, ty)) {
+          s_ins_key[ni] = ((uint64_t)t.new_depth << 32) | t.prim;
+          ms.ins_src[ni] = v * kMaxTouch + j;
+          ++ni;
+        }
+      }
+      // sort removals by position and insertions by key
+      for (int a = 1; a < nr; ++a)
+        for (int b = a; b > 0 && ms.rm_pos[b - 1] > ms.rm_pos[b]; --b) {
+          const uint32_t x = ms.rm_pos[b]; ms.rm_pos[b] = ms.rm_pos[b - 1]; ms.rm_pos[b - 1] = x;
+        }
+      for (int a = 1; a < ni; ++a)
+        for (int b = a; b > 0 && s_ins_key[b - 1] > s_ins_key[b]; --b) {
+          const uint64_t k = s_ins_key[b]; s_ins_key[b] = s_ins_key[b - 1]; s_ins_key[b - 1] = k;
+          const uint32_t x = ms.ins_src[b]; ms.ins_src[b] = ms.ins_src[b - 1]; ms.ins_src[b - 1] = x;
+        }
+      for (int j = 0; j < ni; ++j) {
+        const uint32_t praw = lower_bound_keys(keys, ms.raw_len, s_ins_key[j]);
+        uint32_t rm_before = 0;
+        for (int k = 0; k < nr; ++k) rm_before += ms.rm_pos[k] < praw ? 1u : 0u;
+        ms.ins_mpos[j] = praw - rm_before + (uint32_t)j;
+      }
+      ms.n_rm = nr;
+      ms.n_ins = ni;
+      ms.mlen = ms.raw_len - (uint32_t)nr + (uint32_t)ni;
+    }
+    __syncthreads();
+    float* img = A.image ? A.image + (int64_t)v * I.image_stride : nullptr;
+    composite_tile<TILE>(A, tile, &ms, I.ovr, img, A.parts + item, s_r0, s_r1, s_r2);
+    __syncthreads();
+  }
+}
+
+void launch_composite_full(const CompArgs& a, hipStream_t st) {
+  const int nt = a.ras.n_tiles;
+  const int grid = ((nt + 7) / 8) * 8;
+  switch (a.ras.tile) {
+    case 8: k_composite_full<8><<<grid, 64, 0, st>>>(a); break;
+    case 32: k_composite_full<32><<<grid, 1024, 0, st>>>(a); break;
+    default: k_composite_full<16><<<grid, 256, 0, st>>>(a); break;
+  }
+}
+
+void launch_composite_items(const CompArgs& a, const ItemArgs& it, hipStream_t st) {
+  switch (a.ras.tile) {
+    case 8: k_composite_items<8><<<it.grid, 64, 0, st>>>(a, it); break;
+    case 32: k_composite_items<32><<<it.grid, 1024, 0, st>>>(a, it); break;
+    default: k_composite_items<16><<<it.grid, 256, 0, st>>>(a, it); break;
+  }
+}
+
+}  // namespace sg

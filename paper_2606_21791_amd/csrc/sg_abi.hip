@@ -1,0 +1,597 @@
+// C ABI of libsg (include/sg.h): argument validation, contexts and their
+// workspaces, prepared scenes, and the orchestration of the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sg_kernels.h"
+
+using namespace sg;
+
+namespace {
+
+thread_local std::string g_err;
+
+sg_status fail(sg_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                                   \
+  do {                                                                                                  \
+    hipError_t _e = (expr);                                                                             \
+    if (_e != hipSuccess) return fail(SG_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+#define SG_TRY(expr)                 \
+  do {                               \
+    sg_status _s = (expr);           \
+    if (_s != SG_OK) return _s;      \
+  } while (0)
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int n_components(int f, int sh_degree) {
+  static const int base[5] = {3, 3, 4, 1, 3};
+  if (f < 5) return base[f];
+  return 3 * ((sh_degree + 1) * (sh_degree + 1) - 1);
+}
+
+}  // namespace
+
+// A device buffer that grows on demand.  Bytes are charged to the owning
+// context's budget.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct sg_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t in_use = 0;
+  int n_cu = 256;
+  // workspaces of full renders
+  DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
+      big_prims, big_tiles, parts, work_scene, sites_dev, saved_tmp, box_keys, metrics_tmp;
+  unsigned long long* h_total = nullptr;   // pinned
+  sg_site* h_sites = nullptr;              // pinned staging
+  size_t h_sites_cap = 0;
+  sg_variant* h_vars = nullptr;
+  size_t h_vars_cap = 0;
+};
+
+struct sg_prep {
+  sg_ctx* ctx;
+  DevScene scene;
+  sg_scene host_scene;
+  DevCam cam;
+  DevRaster ras;
+  int64_t n_inst = 0;
+  DevBuf r0, r1, r2, depth, rect, tile_cnt, tile_start, keys, frame;
+  // batch workspaces
+  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, parts, counter, sites, vars, metrics;
+  int batch_cap = 0;
+  int bm_words = 0, row_words = 0;
+};
+
+namespace {
+
+sg_status dev_alloc(sg_ctx* ctx, DevBuf& b, size_t bytes) {
+  if (bytes <= b.bytes) return SG_OK;
+  bytes = std::max<size_t>(bytes, 256);
+  if (ctx->budget && ctx->in_use - b.bytes + bytes > ctx->budget)
+    return fail(SG_E_NOMEM, "device budget exceeded");
+  if (b.p) {
+    (void)hipFree(b.p);
+    ctx->in_use -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(SG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  b.p = p;
+  b.bytes = bytes;
+  ctx->in_use += bytes;
+  return SG_OK;
+}
+
+void dev_free(sg_ctx* ctx, DevBuf& b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    ctx->in_use -= b.bytes;
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+template <class T>
+T* P(DevBuf& b) {
+  return reinterpret_cast<T*>(b.p);
+}
+
+sg_status check_last(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return SG_OK;
+}
+
+sg_status to_dev_scene(const sg_scene* s, DevScene* d) {
+  if (!s) return fail(SG_E_INVAL, "scene is NULL");
+  if (s->n < 1) return fail(SG_E_INVAL, "scene.n must be >= 1");
+  if (s->sh_degree < 0 || s->sh_degree > 3) return fail(SG_E_INVAL, "scene.sh_degree must be 0..3");
+  if (s->dtype < SG_F32 || s->dtype > SG_BF16) return fail(SG_E_INVAL, "scene.dtype invalid");
+  for (int f = 0; f < 6; ++f) {
+    const int C = n_components(f, s->sh_degree);
+    d->ncomp[f] = C;
+    d->ptr[f] = s->ptr[f];
+    d->ps[f] = s->prim_stride[f];
+    d->cs[f] = s->comp_stride[f];
+    if (C == 0) continue;
+    if (!s->ptr[f]) return fail(SG_E_INVAL, "scene.ptr[" + std::to_string(f) + "] is NULL");
+    if (s->prim_stride[f] < 0 || s->comp_stride[f] < 0) return fail(SG_E_INVAL, "negative stride");
+    if (s->dtype != SG_F32 && (reinterpret_cast<uintptr_t>(s->ptr[f]) & 3u))
+      return fail(SG_E_INVAL, "16-bit fields must start on a 4-byte boundary");
+  }
+  d->n = s->n;
+  d->sh_degree = s->sh_degree;
+  d->dtype = s->dtype;
+  return SG_OK;
+}
+
+int64_t field_extent(const DevScene& s, int f) {
+  if (s.ncomp[f] == 0) return 0;
+  return (int64_t)(s.n - 1) * s.ps[f] + (int64_t)(s.ncomp[f] - 1) * s.cs[f] + 1;
+}
+
+sg_status to_dev_cam(const sg_camera* c, DevCam* d) {
+  if (!c) return fail(SG_E_INVAL, "camera is NULL");
+  if (c->width < 1 || c->height < 1 || c->width > 16384 || c->height > 16384)
+    return fail(SG_E_INVAL, "camera size out of range");
+  if (!(c->fx > 0) || !(c->fy > 0)) return fail(SG_E_INVAL, "focal lengths must be positive");
+  if (!(c->near_z > 0) || !(c->far_z > c->near_z)) return fail(SG_E_INVAL, "need 0 < near < far");
+  for (int i = 0; i < 9; ++i) d->R[i] = c->R[i];
+  for (int i = 0; i < 3; ++i) d->t[i] = c->t[i];
+  d->fx = c->fx; d->fy = c->fy; d->cx = c->cx; d->cy = c->cy;
+  d->nearz = c->near_z; d->farz = c->far_z;
+  for (int i = 0; i < 3; ++i) d->campos[i] = -(c->R[0 * 3 + i] * c->t[0] + c->R[1 * 3 + i] * c->t[1] + c->R[2 * 3 + i] * c->t[2]);
+  d->limx = 1.3 * (0.5 * c->width) / c->fx;
+  d->limy = 1.3 * (0.5 * c->height) / c->fy;
+  d->W = c->width;
+  d->H = c->height;
+  return SG_OK;
+}
+
+sg_status to_dev_raster(const sg_raster* r, int W, int H, DevRaster* d) {
+  sg_raster def = {16, 0.99f, 1.0f / 255.0f, 1e-4f, 9.0f, 0.3f, {1.f, 1.f, 1.f}};
+  if (!r) r = &def;
+  int tile = r->tile == 0 ? 16 : r->tile;
+  if (tile != 8 && tile != 16 && tile != 32) return fail(SG_E_INVAL, "raster.tile must be 8, 16 or 32");
+  if (!(r->alpha_max > 0 && r->alpha_max < 1) || !(r->alpha_min > 0 && r->alpha_min < r->alpha_max) ||
+      !(r->t_min > 0 && r->t_min < 1) || !(r->cut_q > 0) || !(r->dilation >= 0))
+    return fail(SG_E_INVAL, "raster constants out of range");
+  d->tile = tile;
+  d->tiles_x = (W + tile - 1) / tile;
+  d->tiles_y = (H + tile - 1) / tile;
+  d->n_tiles = d->tiles_x * d->tiles_y;
+  d->amax = r->alpha_max; d->amin = r->alpha_min; d->tmin = r->t_min; d->cutq = r->cut_q; d->dil = r->dilation;
+  for (int i = 0; i < 3; ++i) d->bg[i] = r->bg[i];
+  d->qcut2 = (float)((double)r->cut_q * 0.72134752044448170);
+  return SG_OK;
+}
+
+sg_status to_dev_box(const sg_box* b, uint32_t mask, const DevScene& s, DevBox* d) {
+  std::memset(d, 0, sizeof(*d));
+  if (!b || !mask) return SG_OK;
+  if (mask & ~0x3Fu) return fail(SG_E_INVAL, "box field mask has bits above 5");
+  if (b->mode != SG_BOX_GLOBAL && b->mode != SG_BOX_PER_PRIM) return fail(SG_E_INVAL, "box.mode invalid");
+  if (b->dtype != s.dtype) return fail(SG_E_INVAL, "box dtype differs from the scene's");
+  for (int f = 0; f < 6; ++f) {
+    if (!((mask >> f) & 1u) || s.ncomp[f] == 0) continue;
+    if (!b->lo[f] || !b->hi[f]) return fail(SG_E_INVAL, "box bounds of a masked field are NULL");
+    d->lo[f] = b->lo[f];
+    d->hi[f] = b->hi[f];
+  }
+  d->mode = b->mode;
+  d->dtype = b->dtype;
+  for (int f = 0; f < 6; ++f)
+    if (((mask >> f) & 1u) && s.ncomp[f] > 0) d->mask |= 1u << f;
+  return SG_OK;
+}
+
+sg_status validate_sites(const DevScene& s, const sg_site* sites, int n) {
+  if (n < 0) return fail(SG_E_INVAL, "negative site count");
+  if (n > 0 && !sites) return fail(SG_E_INVAL, "sites is NULL");
+  const int width = s.dtype == SG_F32 ? 32 : 16;
+  for (int k = 0; k < n; ++k) {
+    const sg_site& x = sites[k];
+    if (x.field > 5 || s.ncomp[x.field] == 0) return fail(SG_E_INVAL, "site " + std::to_string(k) + ": field absent");
+    if (x.comp >= s.ncomp[x.field]) return fail(SG_E_INVAL, "site " + std::to_string(k) + ": component out of range");
+    if (x.prim >= (uint32_t)s.n) return fail(SG_E_INVAL, "site " + std::to_string(k) + ": primitive out of range");
+    if (x.bit >= width) return fail(SG_E_INVAL, "site " + std::to_string(k) + ": bit out of range");
+  }
+  return SG_OK;
+}
+
+sg_status stage_sites(sg_ctx* ctx, const sg_site* sites, int n, DevBuf& dst, hipStream_t st) {
+  if (n <= 0) return SG_OK;
+  SG_TRY(dev_alloc(ctx, dst, (size_t)n * sizeof(sg_site)));
+  HIP_TRY(hipMemcpyAsync(dst.p, sites, (size_t)n * sizeof(sg_site), hipMemcpyHostToDevice, st));
+  return SG_OK;
+}
+
+// Buffers of one full render, sized for n primitives and the raster's tiles.
+struct RenderBufs {
+  float4 *r0, *r1, *r2;
+  uint32_t* depth;
+  uint2* rect;
+  uint32_t *tile_cnt, *tile_start;
+  uint64_t* keys;
+  int64_t n_inst;
+};
+
+// Full render of a scene: project (with optional clamp-on-load), bin, sort,
+// composite (with metric partials against `clean` when given).  The record and
+// list buffers are either the context's workspaces or a prepared scene's.
+sg_status full_render(sg_ctx* ctx, const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
+                      DevBuf& r0, DevBuf& r1, DevBuf& r2, DevBuf& depth, DevBuf& rect, DevBuf& tile_cnt,
+                      DevBuf& tile_start, DevBuf& keys, float* image, const float* clean, Partial* parts,
+                      hipStream_t st, int64_t* n_inst_out) {
+  const int64_t n = s.n;
+  SG_TRY(dev_alloc(ctx, r0, n * sizeof(float4)));
+  SG_TRY(dev_alloc(ctx, r1, n * sizeof(float4)));
+  SG_TRY(dev_alloc(ctx, r2, n * sizeof(float4)));
+  SG_TRY(dev_alloc(ctx, depth, n * sizeof(uint32_t)));
+  SG_TRY(dev_alloc(ctx, rect, n * sizeof(uint2)));
+  const int64_t diff_n = (int64_t)(ras.tiles_x + 1) * (ras.tiles_y + 1);
+  SG_TRY(dev_alloc(ctx, ctx->diff, diff_n * sizeof(int32_t)));
+  SG_TRY(dev_alloc(ctx, ctx->flags, 16));
+  SG_TRY(dev_alloc(ctx, ctx->clamps, 16));
+  SG_TRY(dev_alloc(ctx, tile_cnt, ras.n_tiles * sizeof(uint32_t)));
+  SG_TRY(dev_alloc(ctx, tile_start, ras.n_tiles * sizeof(uint32_t)));
+  SG_TRY(dev_alloc(ctx, ctx->cursor, ras.n_tiles * sizeof(uint32_t)));
+  SG_TRY(dev_alloc(ctx, ctx->total, 4 * sizeof(unsigned long long)));
+  SG_TRY(dev_alloc(ctx, ctx->big_prims, n * sizeof(uint32_t)));
+  SG_TRY(dev_alloc(ctx, ctx->big_tiles, ras.n_tiles * sizeof(uint32_t)));
+  launch_fill_u32(P<uint32_t>(ctx->diff), 0u, diff_n, st);
+  launch_fill_u32(P<uint32_t>(ctx->flags), 0u, 4, st);
+  launch_fill_u32(P<uint32_t>(ctx->clamps), 0u, 4, st);
+  ProjBuffers pb{P<float4>(r0), P<float4>(r1), P<float4>(r2), P<uint32_t>(depth), P<uint2>(rect),
+                 P<int32_t>(ctx->diff), P<uint32_t>(ctx->flags), P<unsigned long long>(ctx->clamps)};
+  launch_project(s, box, cam, ras, pb, st);
+  BinBuffers bb{P<int32_t>(ctx->diff), P<uint32_t>(tile_cnt), P<uint32_t>(tile_start), P<uint32_t>(ctx->cursor),
+                P<unsigned long long>(ctx->total), nullptr, nullptr, P<uint32_t>(ctx->big_prims),
+                P<uint32_t>(ctx->big_tiles), 0};
+  launch_tile_prefix(ras, bb, st);
+  SG_TRY(check_last("project/binning launch"));
+  HIP_TRY(hipMemcpyAsync(ctx->h_total, ctx->total.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const int64_t n_inst = (int64_t)ctx->h_total[0];
+  if (n_inst >= (int64_t)0xffffffffu) return fail(SG_E_UNSUPPORTED, "more than 2^32 primitive-tile instances");
+  SG_TRY(dev_alloc(ctx, keys, std::max<int64_t>(n_inst, 1) * sizeof(uint64_t)));
+  SG_TRY(dev_alloc(ctx, ctx->keys_tmp, std::max<int64_t>(n_inst, 1) * sizeof(uint64_t)));
+  bb.keys = P<uint64_t>(keys);
+  bb.keys_tmp = P<uint64_t>(ctx->keys_tmp);
+  bb.capacity = n_inst;
+  launch_emit(s.n, P<uint32_t>(depth), P<uint2>(rect), ras, bb, st);
+  launch_tile_sort(ras, bb, st);
+  CompArgs ca{P<float4>(r0), P<float4>(r1), P<float4>(r2), P<uint32_t>(tile_start), P<uint32_t>(tile_cnt),
+              P<uint64_t>(keys), clean, image, parts, ras, cam.W, cam.H};
+  launch_composite_full(ca, st);
+  SG_TRY(check_last("render launch"));
+  if (n_inst_out) *n_inst_out = n_inst;
+  return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sg_last_error(void) { return g_err.c_str(); }
+
+sg_status sg_ctx_create(int32_t device, size_t hbm_budget_bytes, sg_ctx** out) {
+  if (!out) return fail(SG_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return fail(SG_E_DEVICE, "no HIP device");
+  if (device < 0 || device >= count) return fail(SG_E_INVAL, "device index out of range");
+  HIP_TRY(hipSetDevice(device));
+  sg_ctx* c = new sg_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0) c->n_cu = ncu;
+  if (hipHostMalloc((void**)&c->h_total, 8 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(SG_E_DEVICE, "pinned allocation failed");
+  }
+  *out = c;
+  return SG_OK;
+}
+
+void sg_ctx_destroy(sg_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  DevBuf* bufs[] = {&c->r0, &c->r1, &c->r2, &c->depth, &c->rect, &c->diff, &c->flags, &c->clamps, &c->tile_cnt,
+                    &c->tile_start, &c->cursor, &c->total, &c->keys, &c->keys_tmp, &c->big_prims, &c->big_tiles,
+                    &c->parts, &c->work_scene, &c->sites_dev, &c->saved_tmp, &c->box_keys, &c->metrics_tmp};
+  for (DevBuf* b : bufs) dev_free(c, *b);
+  if (c->h_total) (void)hipHostFree(c->h_total);
+  delete c;
+}
+
+size_t sg_ctx_bytes(const sg_ctx* c) { return c ? c->in_use : 0; }
+
+sg_status sg_cast(sg_ctx* ctx, const float* src, void* dst, int64_t n, int32_t dtype, int32_t rounding, void* stream) {
+  if (!ctx) return fail(SG_E_INVAL, "ctx is NULL");
+  if (n < 0 || (n > 0 && (!src || !dst))) return fail(SG_E_INVAL, "bad cast buffers");
+  if (dtype < SG_F32 || dtype > SG_BF16 || rounding < SG_RNE || rounding > SG_RU) return fail(SG_E_INVAL, "bad dtype/rounding");
+  if (n == 0) return SG_OK;
+  launch_cast(src, dst, n, dtype, rounding, S(stream));
+  return check_last("sg_cast");
+}
+
+sg_status sg_inject(sg_ctx* ctx, const sg_scene* scene, const sg_site* sites, int32_t n, uint32_t* saved, void* stream) {
+  if (!ctx) return fail(SG_E_INVAL, "ctx is NULL");
+  DevScene s;
+  SG_TRY(to_dev_scene(scene, &s));
+  SG_TRY(validate_sites(s, sites, n));
+  if (n == 0) return SG_OK;
+  SG_TRY(stage_sites(ctx, sites, n, ctx->sites_dev, S(stream)));
+  launch_inject(s, P<sg_site>(ctx->sites_dev), n, saved, S(stream));
+  return check_last("sg_inject");
+}
+
+sg_status sg_restore(sg_ctx* ctx, const sg_scene* scene, const sg_site* sites, int32_t n, const uint32_t* saved,
+                     void* stream) {
+  (void)saved;
+  return sg_inject(ctx, scene, sites, n, nullptr, stream);
+}
+
+sg_status sg_guard_box(sg_ctx* ctx, const sg_scene* clean, uint32_t field_mask, sg_box* out, void* stream) {
+  if (!ctx || !out) return fail(SG_E_INVAL, "ctx/out is NULL");
+  DevScene s;
+  SG_TRY(to_dev_scene(clean, &s));
+  if (field_mask & ~0x3Fu) return fail(SG_E_INVAL, "field mask has bits above 5");
+  if (out->mode != SG_BOX_GLOBAL) return fail(SG_E_INVAL, "sg_guard_box fills a SG_BOX_GLOBAL box");
+  if (out->dtype != s.dtype) return fail(SG_E_INVAL, "box dtype differs from the scene's");
+  for (int f = 0; f < 6; ++f)
+    if (((field_mask >> f) & 1u) && s.ncomp[f] > 0 && (!out->lo[f] || !out->hi[f]))
+      return fail(SG_E_INVAL, "box bounds of a masked field are NULL");
+  SG_TRY(dev_alloc(ctx, ctx->box_keys, 2 * 64 * sizeof(uint32_t)));
+  hipStream_t st = S(stream);
+  for (int f = 0; f < 6; ++f) {
+    if (!((field_mask >> f) & 1u) || s.ncomp[f] == 0) continue;
+    uint32_t* kmin = P<uint32_t>(ctx->box_keys);
+    uint32_t* kmax = kmin + 64;
+    launch_fill_u32(kmin, 0xffffffffu, 64, st);
+    launch_fill_u32(kmax, 0u, 64, st);
+    launch_box_reduce(s, f, kmin, kmax, st);
+    launch_box_finalize(kmin, kmax, s.ncomp[f], s.dtype, out->lo[f], out->hi[f], st);
+  }
+  return check_last("sg_guard_box");
+}
+
+sg_status sg_guard(sg_ctx* ctx, const sg_scene* scene, const sg_box* box, uint32_t field_mask,
+                   uint64_t health_threshold, uint64_t* clamp_count, uint32_t* health_alert, void* stream) {
+  if (!ctx || !box || !clamp_count) return fail(SG_E_INVAL, "ctx/box/clamp_count is NULL");
+  DevScene s;
+  SG_TRY(to_dev_scene(scene, &s));
+  DevBox b;
+  SG_TRY(to_dev_box(box, field_mask, s, &b));
+  hipStream_t st = S(stream);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(clamp_count), 0u, 2, st);
+  for (int f = 0; f < 6; ++f)
+    if ((b.mask >> f) & 1u) launch_guard(s, b, f, reinterpret_cast<unsigned long long*>(clamp_count), st);
+  if (health_alert) launch_health(reinterpret_cast<unsigned long long*>(clamp_count), health_threshold, health_alert, st);
+  return check_last("sg_guard");
+}
+
+sg_status sg_render(sg_ctx* ctx, const sg_scene* scene, const sg_camera* cam, const sg_raster* raster, const sg_box* box,
+                    uint32_t box_field_mask, float* image_out, const float* clean_frame, sg_metrics_t* metrics_out,
+                    void* stream) {
+  if (!ctx) return fail(SG_E_INVAL, "ctx is NULL");
+  DevScene s;
+  DevCam c;
+  DevRaster r;
+  DevBox b;
+  SG_TRY(to_dev_scene(scene, &s));
+  SG_TRY(to_dev_cam(cam, &c));
+  SG_TRY(to_dev_raster(raster, c.W, c.H, &r));
+  SG_TRY(to_dev_box(box, box_field_mask, s, &b));
+  if (metrics_out && !clean_frame) return fail(SG_E_INVAL, "metrics need a clean frame");
+  hipStream_t st = S(stream);
+  Partial* parts = nullptr;
+  if (clean_frame) {
+    SG_TRY(dev_alloc(ctx, ctx->parts, (size_t)r.n_tiles * sizeof(Partial)));
+    parts = P<Partial>(ctx->parts);
+  }
+  SG_TRY(full_render(ctx, s, b, c, r, ctx->r0, ctx->r1, ctx->r2, ctx->depth, ctx->rect, ctx->tile_cnt, ctx->tile_start,
+                     ctx->keys, image_out, clean_frame, parts, st, nullptr));
+  if (metrics_out)
+    launch_reduce_metrics(parts, nullptr, nullptr, (uint32_t)r.n_tiles, nullptr, P<uint32_t>(ctx->flags),
+                          P<unsigned long long>(ctx->clamps), (uint32_t)(c.W * c.H), metrics_out, 1, 1u, st);
+  return check_last("sg_render");
+}
+
+sg_status sg_prepare(sg_ctx* ctx, const sg_scene* clean, const sg_camera* cam, const sg_raster* raster, sg_prep** out,
+                     void* stream) {
+  if (!ctx || !out) return fail(SG_E_INVAL, "ctx/out is NULL");
+  *out = nullptr;
+  sg_prep* p = new sg_prep();
+  p->ctx = ctx;
+  sg_status rc = to_dev_scene(clean, &p->scene);
+  if (rc == SG_OK) rc = to_dev_cam(cam, &p->cam);
+  if (rc == SG_OK) rc = to_dev_raster(raster, p->cam.W, p->cam.H, &p->ras);
+  if (rc != SG_OK) {
+    delete p;
+    return rc;
+  }
+  p->host_scene = *clean;
+  DevBox nobox;
+  std::memset(&nobox, 0, sizeof(nobox));
+  hipStream_t st = S(stream);
+  rc = dev_alloc(ctx, p->frame, (size_t)p->cam.W * p->cam.H * 3 * sizeof(float));
+  if (rc == SG_OK)
+    rc = full_render(ctx, p->scene, nobox, p->cam, p->ras, p->r0, p->r1, p->r2, p->depth, p->rect, p->tile_cnt,
+                     p->tile_start, p->keys, P<float>(p->frame), nullptr, nullptr, st, &p->n_inst);
+  if (rc != SG_OK) {
+    sg_prep_destroy(p);
+    return rc;
+  }
+  p->row_words = (p->ras.tiles_x + 63) / 64;
+  p->bm_words = p->row_words * p->ras.tiles_y;
+  *out = p;
+  return SG_OK;
+}
+
+void sg_prep_destroy(sg_prep* p) {
+  if (!p) return;
+  sg_ctx* c = p->ctx;
+  (void)hipDeviceSynchronize();
+  DevBuf* bufs[] = {&p->r0, &p->r1, &p->r2, &p->depth, &p->rect, &p->tile_cnt, &p->tile_start, &p->keys, &p->frame,
+                    &p->vs, &p->ovr, &p->bitmap, &p->item_off, &p->n_items_v, &p->n_items_total, &p->items,
+                    &p->parts, &p->counter, &p->sites, &p->vars, &p->metrics};
+  for (DevBuf* b : bufs) dev_free(c, *b);
+  delete p;
+}
+
+const float* sg_prep_frame(const sg_prep* p) { return p ? reinterpret_cast<const float*>(p->frame.p) : nullptr; }
+int64_t sg_prep_instances(const sg_prep* p) { return p ? p->n_inst : -1; }
+
+sg_status sg_prep_copy_frame(const sg_prep* p, float* dst, void* stream) {
+  if (!p || !dst) return fail(SG_E_INVAL, "prep/dst is NULL");
+  HIP_TRY(hipMemcpyAsync(dst, p->frame.p, (size_t)p->cam.W * p->cam.H * 3 * sizeof(float), hipMemcpyDeviceToDevice,
+                         S(stream)));
+  return SG_OK;
+}
+
+sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites, const sg_variant* variants,
+                          int32_t B, const sg_box* box, uint32_t box_field_mask, float* images_out,
+                          sg_metrics_t* metrics_out, int32_t mode, void* stream) {
+  if (!ctx || !prep || !metrics_out) return fail(SG_E_INVAL, "ctx/prep/metrics_out is NULL");
+  if (prep->ctx != ctx) return fail(SG_E_INVAL, "prep belongs to another context");
+  if (B < 0 || (B > 0 && !variants)) return fail(SG_E_INVAL, "bad variants");
+  if (mode != SG_INCREMENTAL && mode != SG_FULL) return fail(SG_E_INVAL, "bad mode");
+  const DevScene& s = prep->scene;
+  SG_TRY(validate_sites(s, sites, n_sites));
+  DevBox b;
+  SG_TRY(to_dev_box(box, box_field_mask, s, &b));
+  std::vector<int> full_idx;
+  for (int v = 0; v < B; ++v) {
+    const sg_variant& x = variants[v];
+    if ((uint64_t)x.site_off + x.n_sites > (uint64_t)n_sites) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": sites out of range");
+    if (x.guard && !b.mask) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": guard requested without a box");
+    std::vector<uint32_t> prims;
+    bool full = mode == SG_FULL;
+    for (uint32_t k = 0; k < x.n_sites && !full; ++k) {
+      const uint32_t pr = sites[x.site_off + k].prim;
+      if (std::find(prims.begin(), prims.end(), pr) == prims.end()) {
+        prims.push_back(pr);
+        if ((int)prims.size() > kMaxTouch) full = true;
+      }
+    }
+    if (full) full_idx.push_back(v);
+  }
+  if (B == 0) return SG_OK;
+  hipStream_t st = S(stream);
+  const DevRaster& ras = prep->ras;
+  const int64_t frame_floats = (int64_t)prep->cam.W * prep->cam.H * 3;
+
+  // incremental pipeline over all B (variants needing the full path get no items)
+  if ((int)full_idx.size() < B) {
+    if (B > prep->batch_cap) {
+      SG_TRY(dev_alloc(ctx, prep->vs, (size_t)B * sizeof(VariantState)));
+      SG_TRY(dev_alloc(ctx, prep->ovr, (size_t)B * kMaxTouch * sizeof(Rec)));
+      SG_TRY(dev_alloc(ctx, prep->bitmap, (size_t)B * prep->bm_words * sizeof(uint64_t)));
+      SG_TRY(dev_alloc(ctx, prep->item_off, (size_t)B * sizeof(uint32_t)));
+      SG_TRY(dev_alloc(ctx, prep->n_items_v, (size_t)B * sizeof(uint32_t)));
+      SG_TRY(dev_alloc(ctx, prep->n_items_total, 16));
+      SG_TRY(dev_alloc(ctx, prep->counter, 16));
+      SG_TRY(dev_alloc(ctx, prep->items, (size_t)B * ras.n_tiles * sizeof(uint2)));
+      SG_TRY(dev_alloc(ctx, prep->parts, (size_t)B * ras.n_tiles * sizeof(Partial)));
+      SG_TRY(dev_alloc(ctx, prep->vars, (size_t)B * sizeof(sg_variant)));
+      prep->batch_cap = B;
+    }
+    SG_TRY(stage_sites(ctx, sites, n_sites, prep->sites, st));
+    HIP_TRY(hipMemcpyAsync(prep->vars.p, variants, (size_t)B * sizeof(sg_variant), hipMemcpyHostToDevice, st));
+    if (images_out)
+      for (int v = 0; v < B; ++v)
+        HIP_TRY(hipMemcpyAsync(images_out + v * frame_floats, prep->frame.p, frame_floats * sizeof(float),
+                               hipMemcpyDeviceToDevice, st));
+    BatchBuffers bb{P<sg_site>(prep->sites), P<sg_variant>(prep->vars), B, P<VariantState>(prep->vs), P<Rec>(prep->ovr),
+                    P<uint64_t>(prep->bitmap), prep->bm_words, prep->row_words, P<uint32_t>(prep->item_off),
+                    P<uint32_t>(prep->n_items_v), P<uint32_t>(prep->n_items_total), P<uint2>(prep->items)};
+    launch_variant_prep(s, b, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
+                        P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
+    launch_plan_expand(bb, ras.tiles_x, st);
+    launch_fill_u32(P<uint32_t>(prep->counter), 0u, 1, st);
+    CompArgs ca{P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2), P<uint32_t>(prep->tile_start),
+                P<uint32_t>(prep->tile_cnt), P<uint64_t>(prep->keys), P<float>(prep->frame), images_out,
+                P<Partial>(prep->parts), ras, prep->cam.W, prep->cam.H};
+    const int per_cu = ras.tile == 32 ? 2 : (ras.tile == 16 ? 8 : 16);
+    ItemArgs it{P<VariantState>(prep->vs), P<Rec>(prep->ovr), P<uint2>(prep->items), P<uint32_t>(prep->n_items_total),
+                P<uint32_t>(prep->counter), frame_floats, ctx->n_cu * per_cu};
+    launch_composite_items(ca, it, st);
+    launch_reduce_metrics(P<Partial>(prep->parts), P<uint32_t>(prep->item_off), P<uint32_t>(prep->n_items_v), 0,
+                          P<VariantState>(prep->vs), nullptr, nullptr, (uint32_t)(prep->cam.W * prep->cam.H),
+                          metrics_out, B, 0u, st);
+    SG_TRY(check_last("sg_render_batch incremental"));
+  }
+
+  // full-render path: a private working copy of the scene per variant
+  if (!full_idx.empty()) {
+    DevScene w = s;
+    size_t total_bytes = 0;
+    int64_t off[6];
+    const int wb = s.dtype == SG_F32 ? 4 : 2;
+    for (int f = 0; f < 6; ++f) {
+      off[f] = (int64_t)total_bytes;
+      total_bytes += (size_t)((field_extent(s, f) * wb + 255) / 256 * 256);
+    }
+    SG_TRY(dev_alloc(ctx, ctx->work_scene, total_bytes));
+    SG_TRY(dev_alloc(ctx, ctx->parts, (size_t)ras.n_tiles * sizeof(Partial)));
+    for (int f = 0; f < 6; ++f) w.ptr[f] = P<char>(ctx->work_scene) + off[f];
+    for (int v : full_idx) {
+      for (int f = 0; f < 6; ++f)
+        if (s.ncomp[f])
+          HIP_TRY(hipMemcpyAsync(const_cast<void*>(w.ptr[f]), s.ptr[f], field_extent(s, f) * wb, hipMemcpyDeviceToDevice, st));
+      const sg_variant& x = variants[v];
+      SG_TRY(stage_sites(ctx, sites + x.site_off, (int)x.n_sites, ctx->sites_dev, st));
+      launch_inject(w, P<sg_site>(ctx->sites_dev), (int)x.n_sites, nullptr, st);
+      DevBox bx = b;
+      if (!x.guard) bx.mask = 0;
+      SG_TRY(full_render(ctx, w, bx, prep->cam, ras, ctx->r0, ctx->r1, ctx->r2, ctx->depth, ctx->rect, ctx->tile_cnt,
+                         ctx->tile_start, ctx->keys, images_out ? images_out + v * frame_floats : nullptr,
+                         P<float>(prep->frame), P<Partial>(ctx->parts), st, nullptr));
+      launch_reduce_metrics(P<Partial>(ctx->parts), nullptr, nullptr, (uint32_t)ras.n_tiles, nullptr,
+                            P<uint32_t>(ctx->flags), P<unsigned long long>(ctx->clamps),
+                            (uint32_t)(prep->cam.W * prep->cam.H), metrics_out + v, 1, 1u, st);
+      SG_TRY(check_last("sg_render_batch full"));
+    }
+  }
+  return SG_OK;
+}
+
+sg_status sg_metrics(sg_ctx* ctx, const float* images, const float* clean, int32_t B, int32_t K, int32_t H, int32_t W,
+                     sg_metrics_t* out, void* stream) {
+  if (!ctx || !images || !clean || !out) return fail(SG_E_INVAL, "NULL argument");
+  if (B < 1 || K < 1 || H < 1 || W < 1) return fail(SG_E_INVAL, "sizes must be >= 1");
+  const int64_t px = (int64_t)K * H * W;
+  const int nchunks = (int)std::min<int64_t>(256, (px + 1023) / 1024);
+  SG_TRY(dev_alloc(ctx, ctx->metrics_tmp, (size_t)B * nchunks * sizeof(Partial)));
+  hipStream_t st = S(stream);
+  launch_metrics_partials(images, clean, px, nchunks, B, P<Partial>(ctx->metrics_tmp), st);
+  launch_reduce_metrics(P<Partial>(ctx->metrics_tmp), nullptr, nullptr, (uint32_t)nchunks, nullptr, nullptr, nullptr,
+                        (uint32_t)px, out, B, 1u, st);
+  return check_last("sg_metrics");
+}
+
+}  // extern "C"

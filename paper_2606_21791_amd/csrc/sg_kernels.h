@@ -1,0 +1,132 @@
+// Host-side launchers of the libsg kernels (defined in the k_*.hip files) and
+// small device helpers shared by several kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sg_types.h"
+
+namespace sg {
+
+// Block-wide reduction of a metric partial in a fixed order (wave butterflies,
+// then waves in index order), so the result does not depend on scheduling.
+// Every thread of the block must call it; thread 0 writes *out.
+__device__ __forceinline__ void block_reduce_partial(double sse, uint32_t changed, float mx, uint32_t nonfin,
+                                                     Partial* out) {
+  for (int o = 32; o > 0; o >>= 1) {
+    sse += __shfl_xor(sse, o);
+    changed += (uint32_t)__shfl_xor((int)changed, o);
+    mx = fmaxf(mx, __shfl_xor(mx, o));
+    nonfin |= (uint32_t)__shfl_xor((int)nonfin, o);
+  }
+  __shared__ double s_sse[16];
+  __shared__ uint32_t s_ch[16], s_nf[16];
+  __shared__ float s_mx[16];
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { s_sse[w] = sse; s_ch[w] = changed; s_mx[w] = mx; s_nf[w] = nonfin; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    Partial p;
+    p.sse = 0.0; p.changed = 0; p.max_abs = 0.f; p.nonfinite = 0; p._pad = 0;
+    for (int i = 0; i < nw; ++i) { p.sse += s_sse[i]; p.changed += s_ch[i]; p.max_abs = fmaxf(p.max_abs, s_mx[i]); p.nonfinite |= s_nf[i]; }
+    *out = p;
+  }
+  __syncthreads();
+}
+
+// k_basic.hip
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+void launch_cast(const float* src, void* dst, int64_t n, int dtype, int mode, hipStream_t st);
+void launch_inject(const DevScene& s, const sg_site* sites, int n, uint32_t* saved, hipStream_t st);
+void launch_box_reduce(const DevScene& s, int f, uint32_t* kmin, uint32_t* kmax, hipStream_t st);
+void launch_box_finalize(const uint32_t* kmin, const uint32_t* kmax, int C, int dtype, void* lo, void* hi,
+                         hipStream_t st);
+void launch_guard(const DevScene& s, const DevBox& b, int f, unsigned long long* count, hipStream_t st);
+void launch_health(const unsigned long long* count, unsigned long long thr, uint32_t* alert, hipStream_t st);
+void launch_metrics_partials(const float* img, const float* clean, int64_t px_per_var, int nchunks, int B,
+                             Partial* out, hipStream_t st);
+void launch_reduce_metrics(const Partial* parts, const uint32_t* item_off, const uint32_t* n_items,
+                           uint32_t uniform_items, const VariantState* vs, const uint32_t* flags,
+                           const unsigned long long* clamps, uint32_t n_pixels, sg_metrics_t* out, int B,
+                           uint32_t path, hipStream_t st);
+
+// k_project.hip
+struct ProjBuffers {
+  float4* r0;
+  float4* r1;
+  float4* r2;
+  uint32_t* depth;
+  uint2* rect;            // (tx0 | ty0 << 16, tx1 | ty1 << 16); x = 0xffffffff when culled
+  int32_t* diff;          // (tiles_y + 1) x (tiles_x + 1) 2-D difference grid of tile counts
+  uint32_t* flags;        // [0] any stored non-finite, [1] (unused)
+  unsigned long long* clamps;
+};
+void launch_project(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
+                    const ProjBuffers& pb, hipStream_t st);
+
+struct BatchBuffers {
+  const sg_site* sites;
+  const sg_variant* variants;
+  int B;
+  VariantState* vs;
+  Rec* ovr;                 // B * kMaxTouch override records
+  uint64_t* bitmap;         // B * bm_words dirty-tile bitmaps
+  int bm_words;             // words per variant bitmap
+  int row_words;            // words per tile row
+  uint32_t* item_off;       // B
+  uint32_t* n_items_v;      // B (dirty tiles per variant)
+  uint32_t* n_items_total;  // 1
+  uint2* items;             // capacity B * n_tiles
+};
+void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
+                         const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
+                         const uint2* rect, const BatchBuffers& bb, hipStream_t st);
+void launch_plan_expand(const BatchBuffers& bb, int tiles_x, hipStream_t st);
+
+// k_bin.hip
+struct BinBuffers {
+  int32_t* diff;
+  uint32_t* tile_cnt;
+  uint32_t* tile_start;
+  uint32_t* cursor;
+  unsigned long long* total;   // [0] instances, [1] big prims, [2] big tiles
+  uint64_t* keys;
+  uint64_t* keys_tmp;
+  uint32_t* big_prims;
+  uint32_t* big_tiles;
+  int64_t capacity;
+};
+void launch_tile_prefix(const DevRaster& ras, const BinBuffers& bb, hipStream_t st);
+void launch_emit(int n, const uint32_t* depth, const uint2* rect, const DevRaster& ras, const BinBuffers& bb,
+                 hipStream_t st);
+void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, hipStream_t st);
+
+// k_composite.hip
+struct CompArgs {
+  const float4* r0;
+  const float4* r1;
+  const float4* r2;
+  const uint32_t* tile_start;
+  const uint32_t* tile_cnt;
+  const uint64_t* keys;
+  const float* clean;     // nullable
+  float* image;           // nullable
+  Partial* parts;         // per tile / per item; nullable when clean is null
+  DevRaster ras;
+  int32_t W, H;
+};
+void launch_composite_full(const CompArgs& a, hipStream_t st);
+struct ItemArgs {
+  const VariantState* vs;
+  const Rec* ovr;
+  const uint2* items;
+  const uint32_t* n_items_total;
+  uint32_t* counter;
+  int64_t image_stride;   // floats per variant image (when a.image != null)
+  int grid;
+};
+void launch_composite_items(const CompArgs& a, const ItemArgs& it, hipStream_t st);
+
+}  // namespace sg

@@ -1,0 +1,218 @@
+"""GPU parity of the render path through the C ABI against the FP64 oracle:
+clean frames, corrupted variants (incremental and full paths), guarded and
+multi-upset variants, metrics; plus the internal invariants (incremental ==
+full render bit for bit, tile-size invariance)."""
+import numpy as np
+import pytest
+
+from oracle import formats, guard as oguard, metrics as om, render as orender
+from paper_2606_21791_amd import synth
+
+from ._helpers import PIXEL_TOL, PSNR_TOL_DB, LEVEL, LEVEL_BAND, apply_sites, compare_image, oracle_render, stored
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2606_21791_amd import binding
+    return binding.Context(0)
+
+
+def _batch(ctx, prep, sites, idx_groups, guard=0, box=None, mode=0, want_images=True):
+    import torch
+    from paper_2606_21791_amd import binding as b
+    flat = np.concatenate([np.atleast_1d(g) for g in idx_groups]) if idx_groups else np.zeros(0, int)
+    sa = b.sites_array(sites.field[flat], sites.comp[flat], sites.prim[flat], sites.bit[flat])
+    counts = np.array([len(np.atleast_1d(g)) for g in idx_groups])
+    offs = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    va = b.variants_array(offs, counts, guard)
+    B = len(idx_groups)
+    H, W = prep.cam.height, prep.cam.width
+    imgs = torch.zeros((B, H, W, 3), dtype=torch.float32, device="cuda") if want_images else None
+    mt = b.metrics_tensor(B)
+    ctx.render_batch(prep, sa, va, box=box, images=imgs, metrics=mt, mode=mode)
+    torch.cuda.synchronize()
+    return (imgs.cpu().numpy() if want_images else None), b.read_metrics(mt)
+
+
+def _check_variant(img, m, ref, clean_ref, clean_gpu):
+    """Pixel, PSNR and footprint parity of one variant."""
+    amb = ref["amb"] | clean_ref["amb"]
+    worst, amb_frac = compare_image(img, ref, clean_ref["amb"])
+    assert worst <= PIXEL_TOL, worst
+    assert amb_frac <= 5e-3, amb_frac
+    assert bool(m["nonfinite"]) == ref["nonfinite"]
+    ok = ~amb
+    d_gpu = np.abs(img.astype(np.float64) - clean_gpu.astype(np.float64))
+    d_ref = np.abs(ref["image"] - clean_ref["image"])
+    # the record is what the image says (exact recount on the GPU image)
+    dmax_gpu = d_gpu.max(axis=2)
+    assert int(m["changed_px"]) == int(np.count_nonzero(dmax_gpu > LEVEL))
+    assert abs(float(m["sse"]) - float(np.sum(d_gpu ** 2))) <= 1e-9 * max(1.0, float(np.sum(d_gpu ** 2)))
+    # footprint: exact on pixels not within LEVEL_BAND of the level and not ambiguous
+    dmax_ref = d_ref.max(axis=2)
+    cmp = ok & (np.abs(dmax_ref - LEVEL) > LEVEL_BAND)
+    assert np.array_equal((dmax_gpu > LEVEL)[cmp], (dmax_ref > LEVEL)[cmp])
+    # PSNR over the non-ambiguous pixels of both frames
+    mse_g = float(np.mean(d_gpu[ok] ** 2))
+    mse_r = float(np.mean(d_ref[ok] ** 2))
+    if mse_r == 0.0:
+        assert mse_g == 0.0 or 10 * np.log10(1 / mse_g) > 69.95
+    else:
+        pr = 10 * np.log10(1 / mse_r)
+        pg = 10 * np.log10(1 / mse_g) if mse_g > 0 else np.inf
+        if pr <= 70.0:
+            assert abs(pg - pr) <= PSNR_TOL_DB, (pg, pr)
+        else:
+            assert pg > 69.95
+
+
+def test_clean_frame_parity_w1_and_full_render_equal(ctx):
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(5000, seed=1)
+    cam = synth.make_camera(256, 256)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam)
+    frame = prep.frame().cpu().numpy()
+    ref = oracle_render(stored(sc, "f32"), "f32", 0, cam)
+    worst, amb = compare_image(frame, ref)
+    print(f"W1 clean: max err {worst:.3g}, ambiguous {amb:.2e}, instances {prep.instances()}")
+    assert worst <= PIXEL_TOL and amb <= 2e-3
+    img = torch.zeros((256, 256, 3), dtype=torch.float32, device="cuda")
+    ctx.render(ds, cam, image=img)
+    torch.cuda.synchronize()
+    assert np.array_equal(img.cpu().numpy(), frame)
+
+
+def test_w1_variants_parity(ctx):
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(5000, seed=1)
+    cam = synth.make_camera(256, 256)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam)
+    clean_gpu = prep.frame().cpu().numpy()
+    words = stored(sc, "f32")
+    clean_ref = oracle_render(words, "f32", 0, cam)
+    sites = synth.make_sites_uniform(sc.n, 0, 256, seed=11)
+    # every sign and top exponent bit among the W1 sites plus a spread of others
+    pick = sorted(set(np.nonzero(sites.bit >= 29)[0][:24].tolist()) | set(range(0, 256, 8)))
+    imgs, ms = _batch(ctx, prep, sites, [np.array([k]) for k in pick])
+    for j, k in enumerate(pick):
+        ref = oracle_render(apply_sites(words, sites, k), "f32", 0, cam)
+        _check_variant(imgs[j], ms[j], ref, clean_ref, clean_gpu)
+
+
+@pytest.mark.parametrize("fmt", ["f32", "f16", "bf16"])
+def test_incremental_equals_full_render(ctx, fmt):
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(6741, seed=3, sh_degree=3)
+    cam = synth.make_camera(200, 160)
+    ds = b.DeviceScene.upload(ctx, sc, fmt)
+    prep = ctx.prepare(ds, cam)
+    W = formats.width(fmt)
+    sites = synth.make_sites_stratified(sc.n, 3, 2 * W, seed=12, width_bits=W)
+    groups = [np.array([k]) for k in range(0, len(sites), 3)]
+    groups += [np.array([0, 1, 2]), np.array([5, 6])]          # multi-site variants
+    inc, mi = _batch(ctx, prep, sites, groups, mode=0)
+    full, mf = _batch(ctx, prep, sites, groups, mode=1)
+    assert np.array_equal(inc, full)
+    for key in ("changed_px", "max_abs", "nonfinite"):
+        assert np.array_equal(mi[key], mf[key]), key
+    # the same per-pixel terms summed over different tile sets: equal up to the order of the double sum
+    assert np.allclose(mi["sse"], mf["sse"], rtol=1e-12, atol=0.0)
+    assert np.all(mi["path"] == 0) and np.all(mf["path"] == 1)
+
+
+def test_tile_size_invariance(ctx):
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(6000, seed=13, sh_degree=1)
+    cam = synth.make_camera(160, 120)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    frames = [ctx.prepare(ds, cam, b.raster_struct(tile=t)).frame().cpu().numpy() for t in (8, 16, 32)]
+    assert np.array_equal(frames[0], frames[1]) and np.array_equal(frames[1], frames[2])
+
+
+def test_guarded_and_multi_upset_variants(ctx):
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(4000, seed=14)
+    cam = synth.make_camera(128, 128)
+    lo32, hi32 = synth.make_box_jitter(sc, seed=4)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    box = b.Box.per_prim(ctx, lo32, hi32, "f32")
+    prep = ctx.prepare(ds, cam)
+    clean_gpu = prep.frame().cpu().numpy()
+    words = stored(sc, "f32")
+    lo = [None if a is None else formats.f32_words(a) for a in lo32]
+    hi = [None if a is None else formats.f32_words(a) for a in hi32]
+    clean_ref = oracle_render(words, "f32", 0, cam)
+    single = synth.make_sites_stratified(sc.n, 0, 32, seed=15, width_bits=32, fields=(1,))   # log-scale bits
+    dose = synth.make_sites_dose(sc.n, 0, 300, seed=16, width_bits=32)
+    allsites = synth.Sites(*(np.concatenate([a, c]) for a, c in zip(
+        (single.field, single.comp, single.prim, single.bit), (dose.field, dose.comp, dose.prim, dose.bit))))
+    groups = [np.array([k]) for k in range(32)] + [np.arange(32, 32 + 300)]
+    for guard in (0, 1):
+        imgs, ms = _batch(ctx, prep, allsites, groups, guard=guard, box=box)
+        for j, g in enumerate(groups):
+            w = apply_sites(words, allsites, g)
+            n_cl = 0
+            if guard:
+                w, n_cl = oguard.guard_scene(w, lo, hi, "f32")
+            ref = oracle_render(w, "f32", 0, cam)
+            _check_variant(imgs[j], ms[j], ref, clean_ref, clean_gpu)
+            assert int(ms[j]["clamps"]) == (n_cl if guard else 0)
+        assert ms[-1]["path"] == 1 and np.all(ms["path"][:-1] == 0)
+        if guard:   # Thm. 2: no guarded single flip explodes a primitive across the frame
+            assert np.max(ms["footprint"][:32]) < 0.2
+
+
+def test_sg_metrics_matches_definition(ctx):
+    import torch
+    from paper_2606_21791_amd import binding as b
+    rng = np.random.default_rng(17)
+    B, K, H, W = 3, 2, 40, 30
+    clean = rng.uniform(0, 1, (K, H, W, 3)).astype(np.float32)
+    imgs = np.repeat(clean[None], B, 0).copy()
+    imgs[0, 0, :5, :5] += 0.1
+    imgs[1, 1, 10, 10, 2] += 1.5 / 255
+    imgs[2, 0, 3, 4, 1] = np.inf
+    out = b.metrics_tensor(B)
+    ctx.metrics(torch.from_numpy(imgs).cuda(), torch.from_numpy(clean).cuda(), B, K, H, W, out)
+    torch.cuda.synchronize()
+    m = b.read_metrics(out)
+    for v in range(2):
+        ref = om.frame_metrics(imgs[v].astype(np.float64), clean.astype(np.float64))
+        assert m["changed_px"][v] == ref["changed_px"]
+        assert abs(m["psnr"][v] - ref["psnr"]) < 1e-9
+        assert m["catastrophic"][v] == ref["catastrophic"]
+    assert m["nonfinite"][2] == 1 and m["catastrophic"][2] == 1
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_w2_hi_sampled_pixels(ctx, fmt):
+    """Full W2 size (N = 134,826, SH degree 3, 800 x 800): the clean frame and
+    a few variants, checked on sampled pixels the oracle evaluates one by one."""
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(134_826, seed=3, sh_degree=3)
+    cam = synth.make_camera(800, 800)
+    ds = b.DeviceScene.upload(ctx, sc, fmt)
+    prep = ctx.prepare(ds, cam)
+    words = stored(sc, fmt)
+    rng = np.random.default_rng(5)
+    xs, ys = rng.integers(0, 800, 150), rng.integers(0, 800, 150)
+    W = formats.width(fmt)
+    sites = synth.make_sites_stratified(sc.n, 3, W, seed=12, width_bits=W, fields=(1, 0, 4))
+    pick = [W - 1, W - 2, 3, W + W - 1, 2 * W + W - 2]
+    imgs, ms = _batch(ctx, prep, sites, [np.array([k]) for k in pick])
+    frame = prep.frame().cpu().numpy()
+    pr = orender.project(orender.decode_scene(words, fmt), 3, cam)
+    ref = orender.render_pixels(pr, cam, xs, ys)
+    assert np.max(np.abs(frame[ys, xs] - ref)) <= PIXEL_TOL
+    for j, k in enumerate(pick):
+        prv = orender.project(orender.decode_scene(apply_sites(words, sites, k), fmt), 3, cam)
+        refv = orender.render_pixels(prv, cam, xs, ys)
+        err = np.abs(imgs[j][ys, xs] - refv).max(axis=1)
+        assert np.mean(err <= PIXEL_TOL) >= 0.98, (k, np.sort(err)[-5:])
