@@ -142,6 +142,9 @@ typedef struct {
   uint64_t clamps;        /* guard clamps applied to this variant */
   uint32_t n_pixels;      /* K * H * W compared */
   uint32_t path;          /* 0 incremental, 1 full render */
+  uint64_t evals;         /* pixel-primitive evaluations of the front-to-back loop
+                             (per pixel: list entries up to and including the one
+                             that stops it) over the re-composited tiles */
 } sg_metrics_t;
 
 typedef struct sg_ctx sg_ctx;
@@ -231,6 +234,25 @@ enum { SG_INCREMENTAL = 0, SG_FULL = 1 };
 sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites,
                           const sg_variant* variants, int32_t B, const sg_box* box, uint32_t box_field_mask,
                           float* images_out, sg_metrics_t* metrics_out, int32_t mode, void* stream);
+
+/* Per-pass device timing, for profiling.  While enabled, calls record HIP
+ * events on their stream around each pass; sg_ctx_pass_times waits for the
+ * recorded events, adds the elapsed milliseconds per pass into ms[SG_N_PASSES]
+ * and the number of timed launches into launches[SG_N_PASSES] (both host),
+ * and clears the record. */
+enum {
+  SG_PASS_VARIANT_PREP = 0,     /* corrupted-primitive projection and dirty-tile planning */
+  SG_PASS_COMPOSITE_ITEMS = 1,  /* persistent incremental compositing */
+  SG_PASS_REDUCE = 2,           /* per-variant metric reduction */
+  SG_PASS_PROJECT = 3,          /* full projection */
+  SG_PASS_BIN = 4,              /* tile counts, offsets and instance scatter */
+  SG_PASS_SORT = 5,             /* per-tile depth sort */
+  SG_PASS_COMPOSITE_FULL = 6,   /* full-frame compositing */
+  SG_PASS_GUARD = 7,            /* guard clamp pass (sg_guard) */
+  SG_N_PASSES = 8
+};
+sg_status sg_ctx_timing(sg_ctx* ctx, int32_t enable);
+sg_status sg_ctx_pass_times(sg_ctx* ctx, double* ms, int64_t* launches);
 
 /* Metrics of B*K frames against K clean frames (Sec. 3; Def. 1; Def. 2):
  * images is [B][K][H][W][3], clean is [K][H][W][3]; MSE and the footprint are

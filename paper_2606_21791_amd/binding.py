@@ -29,8 +29,9 @@ VARIANT_DTYPE = np.dtype([("site_off", "<u4"), ("n_sites", "<u4"), ("guard", "<u
 METRICS_DTYPE = np.dtype([("sse", "<f8"), ("mse", "<f8"), ("psnr", "<f8"), ("footprint", "<f4"),
                           ("max_abs", "<f4"), ("nonfinite", "<u4"), ("catastrophic", "<u4"),
                           ("changed_px", "<u4"), ("dirty_tiles", "<u4"), ("clamps", "<u8"),
-                          ("n_pixels", "<u4"), ("path", "<u4")])
-assert SITE_DTYPE.itemsize == 8 and VARIANT_DTYPE.itemsize == 16 and METRICS_DTYPE.itemsize == 64
+                          ("n_pixels", "<u4"), ("path", "<u4"), ("evals", "<u8")])
+assert SITE_DTYPE.itemsize == 8 and VARIANT_DTYPE.itemsize == 16 and METRICS_DTYPE.itemsize == 72
+PASSES = ("variant_prep", "composite_items", "reduce", "project", "bin", "sort", "composite_full", "guard")
 
 
 class SgScene(C.Structure):
@@ -83,6 +84,8 @@ def _load():
         "sg_prep_copy_frame": (i32, [vp, vp, vp]),
         "sg_render_batch": (i32, [vp, vp, vp, i32, vp, i32, P(SgBox), u32, vp, vp, i32, vp]),
         "sg_metrics": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
+        "sg_ctx_timing": (i32, [vp, i32]),
+        "sg_ctx_pass_times": (i32, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -94,7 +97,8 @@ def _load():
 LIB = _load()
 EXPORTED = ("sg_ctx_create", "sg_ctx_destroy", "sg_last_error", "sg_ctx_bytes", "sg_cast", "sg_inject",
             "sg_restore", "sg_guard_box", "sg_guard", "sg_render", "sg_prepare", "sg_prep_destroy",
-            "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_metrics")
+            "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_metrics",
+            "sg_ctx_timing", "sg_ctx_pass_times")
 
 
 def check(code):
@@ -163,6 +167,15 @@ class Context:
 
     def bytes(self) -> int:
         return int(LIB.sg_ctx_bytes(self.h))
+
+    def timing(self, enable: bool):
+        check(LIB.sg_ctx_timing(self.h, 1 if enable else 0))
+
+    def pass_times(self) -> dict:
+        ms = np.zeros(len(PASSES), np.float64)
+        n = np.zeros(len(PASSES), np.int64)
+        check(LIB.sg_ctx_pass_times(self.h, ms.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(PASSES)}
 
     # -- storage --------------------------------------------------------------
     def cast(self, src_f32, dtype: int, rounding: int = SG_RNE):

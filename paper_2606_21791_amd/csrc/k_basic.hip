@@ -119,7 +119,7 @@ __global__ void k_metrics_partials(const float* __restrict__ img, const float* _
     changed += dm > (1.0 / 255.0) ? 1u : 0u;
     mx = fmaxf(mx, (float)dm);
   }
-  block_reduce_partial(sse, changed, mx, nonfin, out + (int64_t)v * gridDim.x + blockIdx.x);
+  block_reduce_partial(sse, changed, mx, nonfin, 0ull, out + (int64_t)v * gridDim.x + blockIdx.x);
 }
 
 // Per variant: partials[item_off[v] .. + n_items[v]) in a fixed order -> metrics.
@@ -133,15 +133,17 @@ __global__ void k_reduce_metrics(const Partial* __restrict__ parts, const uint32
   double sse = 0.0;
   uint32_t changed = 0, nonfin = 0;
   float mx = 0.f;
+  unsigned long long ev = 0;
   for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
     const Partial p = parts[off + k];
     sse += p.sse;
     changed += p.changed;
     mx = fmaxf(mx, p.max_abs);
     nonfin |= p.nonfinite;
+    ev += p.evals;
   }
   __shared__ Partial red;
-  block_reduce_partial(sse, changed, mx, nonfin, &red);
+  block_reduce_partial(sse, changed, mx, nonfin, ev, &red);
   if (threadIdx.x == 0) {
     sg_metrics_t m;
     m.sse = red.sse;
@@ -156,6 +158,7 @@ __global__ void k_reduce_metrics(const Partial* __restrict__ parts, const uint32
     m.clamps = vs ? vs[v].clamps : (clamps ? *clamps : 0ull);
     m.n_pixels = n_pixels;
     m.path = path;
+    m.evals = red.evals;
     out[v] = m;
   }
 }

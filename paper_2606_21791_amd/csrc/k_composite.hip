@@ -43,6 +43,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
 
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   bool done = !inside;
+  uint32_t evals = inside ? mlen : 0u;   // list entries this pixel evaluates
   for (uint32_t base = 0; base < mlen; base += BS) {
     if (__syncthreads_and(done)) break;
     const uint32_t m = base + tid;
@@ -84,7 +85,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
         const float alpha = fminf(amax, c.x * __builtin_amdgcn_exp2f(-q));
         if (alpha < amin) continue;
         const float Tn = T * (1.f - alpha);
-        if (Tn < tmin) { done = true; break; }
+        if (Tn < tmin) { done = true; evals = base + (uint32_t)j + 1u; break; }
         const float w = alpha * T;
         C0 = fmaf(c.y, w, C0);
         C1 = fmaf(c.z, w, C1);
@@ -112,7 +113,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
       mx = (float)dm;
     }
   }
-  if (part) block_reduce_partial(sse, changed, mx, nonfin, part);
+  if (part) block_reduce_partial(sse, changed, mx, nonfin, (unsigned long long)evals, part);
 }
 
 // Full render: one workgroup per tile.  Block b of the grid serves tile
@@ -134,24 +135,22 @@ __device__ __forceinline__ bool rect_has(uint32_t r0, uint32_t r1, int tx, int t
   return tx >= (int)(r0 & 0xffff) && tx <= (int)(r1 & 0xffff) && ty >= (int)(r0 >> 16) && ty <= (int)(r1 >> 16);
 }
 
-__device__ __forceinline__ uint32_t lower_bound_keys(const uint64_t* k, uint32_t n, uint64_t key) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (k[mid] < key) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
 // Persistent incremental compositing: a fixed grid of workgroups pops
 // (variant, tile) work items from a device counter until the batch's item
-// count (known only on the device) is exhausted.
+// count (known only on the device) is exhausted.  Per item, the positions of
+// the corrupted primitives' old keys and new keys in the tile's clean list are
+// found by one parallel counting pass over the list (the number of keys below
+// a target is its lower bound).
 template <int TILE>
 __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, ItemArgs I) {
-  __shared__ float4 s_r0[TILE * TILE], s_r1[TILE * TILE], s_r2[TILE * TILE];
+  constexpr int BS = TILE * TILE;
+  constexpr int NT = 2 * kMaxTouch;
+  __shared__ float4 s_r0[BS], s_r1[BS], s_r2[BS];
   __shared__ MergeSpec ms;
   __shared__ uint32_t s_item;
-  __shared__ uint64_t s_ins_key[kMaxTouch];
+  __shared__ uint64_t s_tgt[NT];        // removal keys, then insertion keys (sorted)
+  __shared__ uint32_t s_cnt[NT], s_fnd[NT];
+  __shared__ int s_nr, s_ni;
   const uint32_t total = *I.n_items_total;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(I.counter, 1u);
@@ -161,46 +160,69 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
     const uint2 it = I.items[item];
     const uint32_t v = it.x;
     const int tile = (int)it.y;
+    if (threadIdx.x < NT) { s_cnt[threadIdx.x] = 0; s_fnd[threadIdx.x] = 0; }
     if (threadIdx.x == 0) {
       const VariantState& vs = I.vs[v];
       const int tx = tile % A.ras.tiles_x, ty = tile / A.ras.tiles_x;
       ms.raw_start = A.tile_start[tile];
       ms.raw_len = A.tile_cnt[tile];
-      const uint64_t* keys = A.keys + ms.raw_start;
       int nr = 0, ni = 0;
+      // removal keys fill s_tgt from the front, insertion keys from the back
       for (uint32_t j = 0; j < vs.n_touch; ++j) {
         const Touch t = vs.touch[j];
         if (t.flags & 4u) continue;   // unchanged primitive
-        if ((t.flags & 1u) && rect_has(t.old_rect0, t.old_rect1, tx, ty)) {
-          const uint64_t k = ((uint64_t)t.old_depth << 32) | t.prim;
-          const uint32_t pos = lower_bound_keys(keys, ms.raw_len, k);
-          if (pos < ms.raw_len && keys[pos] == k) ms.rm_pos[nr++] = pos;
-        }
+        if ((t.flags & 1u) && rect_has(t.old_rect0, t.old_rect1, tx, ty)) s_tgt[nr++] = ((uint64_t)t.old_depth << 32) | t.prim;
         if ((t.flags & 2u) && rect_has(t.new_rect0, t.new_rect1, tx, ty)) {
-          s_ins_key[ni] = ((uint64_t)t.new_depth << 32) | t.prim;
+          s_tgt[NT - 1 - ni] = ((uint64_t)t.new_depth << 32) | t.prim;
           ms.ins_src[ni] = v * kMaxTouch + j;
           ++ni;
         }
       }
-      // sort removals by position and insertions by key
-      for (int a = 1; a < nr; ++a)
+      // move the insertion keys behind the removals, sorted by key
+      for (int j = 0; j < ni; ++j) s_tgt[nr + j] = s_tgt[NT - 1 - j];
+      for (int a = 1; a < ni; ++a)
+        for (int b = a; b > 0 && s_tgt[nr + b - 1] > s_tgt[nr + b]; --b) {
+          const uint64_t k = s_tgt[nr + b]; s_tgt[nr + b] = s_tgt[nr + b - 1]; s_tgt[nr + b - 1] = k;
+          const uint32_t x = ms.ins_src[b]; ms.ins_src[b] = ms.ins_src[b - 1]; ms.ins_src[b - 1] = x;
+        }
+      s_nr = nr;
+      s_ni = ni;
+    }
+    __syncthreads();
+    const int nr = s_nr, nt = s_nr + s_ni;
+    // one pass over the list per target keeps the register footprint of the
+    // compositing loop unchanged (targets are few: usually one old, one new key)
+    for (int j = 0; j < nt; ++j) {
+      const uint64_t tgt = s_tgt[j];
+      const uint64_t* keys = A.keys + ms.raw_start;
+      uint32_t c = 0, f = 0;
+      for (uint32_t m = threadIdx.x; m < ms.raw_len; m += BS) {
+        const uint64_t key = keys[m];
+        c += key < tgt ? 1u : 0u;
+        f |= key == tgt ? 1u : 0u;
+      }
+      for (int o = 32; o > 0; o >>= 1) { c += (uint32_t)__shfl_xor((int)c, o); f |= (uint32_t)__shfl_xor((int)f, o); }
+      if ((threadIdx.x & 63) == 0 && (c | f)) { atomicAdd(&s_cnt[j], c); atomicOr(&s_fnd[j], f); }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int n_rm = 0;
+      for (int j = 0; j < nr; ++j)
+        if (s_fnd[j]) ms.rm_pos[n_rm++] = s_cnt[j];
+      for (int a = 1; a < n_rm; ++a)
         for (int b = a; b > 0 && ms.rm_pos[b - 1] > ms.rm_pos[b]; --b) {
           const uint32_t x = ms.rm_pos[b]; ms.rm_pos[b] = ms.rm_pos[b - 1]; ms.rm_pos[b - 1] = x;
         }
-      for (int a = 1; a < ni; ++a)
-        for (int b = a; b > 0 && s_ins_key[b - 1] > s_ins_key[b]; --b) {
-          const uint64_t k = s_ins_key[b]; s_ins_key[b] = s_ins_key[b - 1]; s_ins_key[b - 1] = k;
-          const uint32_t x = ms.ins_src[b]; ms.ins_src[b] = ms.ins_src[b - 1]; ms.ins_src[b - 1] = x;
-        }
+      const int ni = nt - nr;
       for (int j = 0; j < ni; ++j) {
-        const uint32_t praw = lower_bound_keys(keys, ms.raw_len, s_ins_key[j]);
+        const uint32_t praw = s_cnt[nr + j];
         uint32_t rm_before = 0;
-        for (int k = 0; k < nr; ++k) rm_before += ms.rm_pos[k] < praw ? 1u : 0u;
+        for (int k = 0; k < n_rm; ++k) rm_before += ms.rm_pos[k] < praw ? 1u : 0u;
         ms.ins_mpos[j] = praw - rm_before + (uint32_t)j;
       }
-      ms.n_rm = nr;
+      ms.n_rm = n_rm;
       ms.n_ins = ni;
-      ms.mlen = ms.raw_len - (uint32_t)nr + (uint32_t)ni;
+      ms.mlen = ms.raw_len - (uint32_t)n_rm + (uint32_t)ni;
     }
     __syncthreads();
     float* img = A.image ? A.image + (int64_t)v * I.image_stride : nullptr;

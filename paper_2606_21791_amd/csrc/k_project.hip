@@ -6,36 +6,41 @@
 
 namespace sg {
 
-// One thread per primitive.  Coalesced: field f, component c of primitives
-// i .. i+63 are consecutive words in the component-major layout.
+// One thread per primitive.  All stored words of the primitive are loaded
+// first (independent, coalesced loads: field f, component c of primitives
+// i .. i+63 are consecutive in the component-major layout), then clamped in
+// registers if a box is given, then projected.
+template <int DEG>
 __global__ void __launch_bounds__(256) k_project(DevScene s, DevBox box, DevCam cam, DevRaster ras, ProjBuffers pb) {
+  using L = Layout<DEG>;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   uint32_t clamps = 0;
   bool nonfin = false;
   if (i < s.n) {
-    auto get = [&](int f, int c) -> uint32_t {
-      uint32_t w = load_word(s, f, i, c);
-      if ((box.mask >> f) & 1u) {
-        uint32_t lo, hi;
-        bool cl;
-        box_words(box, f, i, c, s.n, &lo, &hi);
-        w = clamp_word(w, lo, hi, s.dtype, &cl);
-      }
-      return w;
-    };
+    uint32_t w[L::kWords];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int C = f < 5 ? (f == 2 ? 4 : (f == 3 ? 1 : 3)) : L::kRest;
+#pragma unroll
+      for (int c = 0; c < C; ++c) w[L::off(f) + c] = load_word(s, f, i, c);
+    }
     if (box.mask) {
+#pragma unroll
       for (int f = 0; f < 6; ++f) {
+        const int C = f < 5 ? (f == 2 ? 4 : (f == 3 ? 1 : 3)) : L::kRest;
         if (!((box.mask >> f) & 1u)) continue;
-        for (int c = 0; c < s.ncomp[f]; ++c) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
           uint32_t lo, hi;
           bool cl;
           box_words(box, f, i, c, s.n, &lo, &hi);
-          clamp_word(load_word(s, f, i, c), lo, hi, s.dtype, &cl);
+          w[L::off(f) + c] = clamp_word(w[L::off(f) + c], lo, hi, s.dtype, &cl);
           clamps += cl ? 1u : 0u;
         }
       }
     }
-    const ProjOut o = project_prim(get, s.dtype, s.sh_degree, cam, ras);
+    auto get = [&](int f, int c) -> uint32_t { return w[L::off(f) + c]; };
+    const ProjOut o = project_prim<DEG>(get, s.dtype, cam, ras);
     nonfin = o.nonfinite;
     pb.r0[i] = o.rec.r0;
     pb.r1[i] = o.rec.r1;
@@ -59,9 +64,10 @@ __global__ void __launch_bounds__(256) k_project(DevScene s, DevBox box, DevCam 
   }
 }
 
-__device__ __forceinline__ void set_rect_bits(uint64_t* bm, int row_words, uint32_t r0, uint32_t r1) {
+__device__ __forceinline__ void set_rect_bits(uint64_t* bm, int row_words, uint32_t r0, uint32_t r1, int lane,
+                                              int nlanes) {
   const int tx0 = r0 & 0xffff, ty0 = r0 >> 16, tx1 = r1 & 0xffff, ty1 = r1 >> 16;
-  for (int ty = ty0; ty <= ty1; ++ty) {
+  for (int ty = ty0 + lane; ty <= ty1; ty += nlanes) {
     for (int w = tx0 >> 6; w <= (tx1 >> 6); ++w) {
       const int a = max(tx0, w * 64) - w * 64, b = min(tx1, w * 64 + 63) - w * 64;
       const uint64_t m = (b == 63 ? ~0ull : ((1ull << (b + 1)) - 1ull)) & ~((1ull << a) - 1ull);
@@ -70,64 +76,67 @@ __device__ __forceinline__ void set_rect_bits(uint64_t* bm, int row_words, uint3
   }
 }
 
-// One thread per variant: XOR the variant's sites into the words of each
-// corrupted primitive, clamp (if guarded), project, and mark the tiles of the
-// old and new footprints dirty.
-__global__ void k_variant_prep(DevScene s, DevBox box, DevCam cam, DevRaster ras, const float4* __restrict__ r0,
-                               const float4* __restrict__ r1, const float4* __restrict__ r2,
-                               const uint32_t* __restrict__ depth, const uint2* __restrict__ rect, BatchBuffers bb) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= bb.B) return;
+// One 64-thread workgroup per variant.  Lane c loads stored word c of each
+// corrupted primitive, XORs the variant's sites into it and clamps it (if
+// guarded); lane 0 projects the primitive from the staged words; the lanes
+// then mark the tiles of the old and new footprints dirty.
+template <int DEG>
+__global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, DevCam cam, DevRaster ras,
+                                                     const float4* __restrict__ r0, const float4* __restrict__ r1,
+                                                     const float4* __restrict__ r2,
+                                                     const uint32_t* __restrict__ depth,
+                                                     const uint2* __restrict__ rect, BatchBuffers bb) {
+  using L = Layout<DEG>;
+  const int v = blockIdx.x;
+  const int lane = threadIdx.x;
   const sg_variant var = bb.variants[v];
   const sg_site* sites = bb.sites + var.site_off;
   const bool guard = var.guard != 0 && box.mask != 0;
-  VariantState st;
-  st.n_touch = 0; st.full = 0; st.nonfinite = 0; st.n_dirty = 0; st.clamps = 0; st.item_off = 0; st._pad = 0;
-  for (uint32_t k = 0; k < var.n_sites; ++k) {
-    const uint32_t p = sites[k].prim;
-    bool seen = false;
-    for (uint32_t j = 0; j < st.n_touch; ++j) seen |= st.touch[j].prim == p;
-    if (!seen) {
-      if (st.n_touch == kMaxTouch) { st.full = 1; break; }
-      st.touch[st.n_touch++].prim = p;
+  __shared__ VariantState st;
+  __shared__ uint32_t s_w[L::kWords];
+  __shared__ uint32_t s_same;
+  uint64_t* bm = bb.bitmap + (int64_t)v * bb.bm_words;
+  for (int w = lane; w < bb.bm_words; w += 64) bm[w] = 0ull;
+  if (lane == 0) {
+    st.n_touch = 0; st.full = 0; st.nonfinite = 0; st.n_dirty = 0; st.clamps = 0; st.item_off = 0; st._pad = 0;
+    for (uint32_t k = 0; k < var.n_sites; ++k) {
+      const uint32_t p = sites[k].prim;
+      bool seen = false;
+      for (uint32_t j = 0; j < st.n_touch; ++j) seen |= st.touch[j].prim == p;
+      if (!seen) {
+        if (st.n_touch == kMaxTouch) { st.full = 1; break; }
+        st.touch[st.n_touch++].prim = p;
+      }
     }
   }
-  uint64_t* bm = bb.bitmap + (int64_t)v * bb.bm_words;
-  for (int w = 0; w < bb.bm_words; ++w) bm[w] = 0ull;
-  if (!st.full) {
-    for (uint32_t j = 0; j < st.n_touch; ++j) {
-      const uint32_t p = st.touch[j].prim;
-      auto raw = [&](int f, int c) -> uint32_t {
-        uint32_t w = load_word(s, f, p, c);
-        for (uint32_t k = 0; k < var.n_sites; ++k) {
-          const sg_site x = sites[k];
-          if (x.prim == p && x.field == f && x.comp == c) w ^= 1u << x.bit;
-        }
-        return w;
-      };
-      auto get = [&](int f, int c) -> uint32_t {
-        uint32_t w = raw(f, c);
-        if (guard && ((box.mask >> f) & 1u)) {
-          uint32_t lo, hi;
-          bool cl;
-          box_words(box, f, p, c, s.n, &lo, &hi);
-          w = clamp_word(w, lo, hi, s.dtype, &cl);
-        }
-        return w;
-      };
-      if (guard) {
-        for (int f = 0; f < 6; ++f) {
-          if (!((box.mask >> f) & 1u)) continue;
-          for (int c = 0; c < s.ncomp[f]; ++c) {
-            uint32_t lo, hi;
-            bool cl;
-            box_words(box, f, p, c, s.n, &lo, &hi);
-            clamp_word(raw(f, c), lo, hi, s.dtype, &cl);
-            st.clamps += cl ? 1u : 0u;
-          }
-        }
+  __syncthreads();
+  const uint32_t n_touch = st.full ? 0u : st.n_touch;
+  for (uint32_t j = 0; j < n_touch; ++j) {
+    const uint32_t p = st.touch[j].prim;
+    uint32_t cl_count = 0;
+    if (lane < L::kWords) {
+      const int f = lane < 3 ? 0 : lane < 6 ? 1 : lane < 10 ? 2 : lane < 11 ? 3 : lane < 14 ? 4 : 5;
+      const int c = lane - L::off(f);
+      uint32_t w = load_word(s, f, p, c);
+      for (uint32_t k = 0; k < var.n_sites; ++k) {
+        const sg_site x = sites[k];
+        if (x.prim == p && x.field == f && x.comp == c) w ^= 1u << x.bit;
       }
-      const ProjOut o = project_prim(get, s.dtype, s.sh_degree, cam, ras);
+      if (guard && ((box.mask >> f) & 1u)) {
+        uint32_t lo, hi;
+        bool cl;
+        box_words(box, f, p, c, s.n, &lo, &hi);
+        w = clamp_word(w, lo, hi, s.dtype, &cl);
+        cl_count = cl ? 1u : 0u;
+      }
+      s_w[lane] = w;
+    }
+    for (int o = 32; o > 0; o >>= 1) cl_count += (uint32_t)__shfl_xor((int)cl_count, o);
+    __syncthreads();
+    if (lane == 0) {
+      st.clamps += cl_count;
+      auto get = [&](int f, int c) -> uint32_t { return s_w[L::off(f) + c]; };
+      const ProjOut o = project_prim<DEG>(get, s.dtype, cam, ras);
       st.nonfinite |= o.nonfinite ? 1u : 0u;
       const uint2 orc = rect[p];
       const bool old_vis = orc.x != 0xffffffffu;
@@ -151,27 +160,41 @@ __global__ void k_variant_prep(DevScene s, DevBox box, DevCam cam, DevRaster ras
       }
       t.flags = (old_vis ? 1u : 0u) | (o.visible ? 2u : 0u) | (same ? 4u : 0u);
       bb.ovr[(int64_t)v * kMaxTouch + j] = o.rec;
-      if (!same) {
-        if (old_vis) set_rect_bits(bm, bb.row_words, orc.x, orc.y);
-        if (o.visible) set_rect_bits(bm, bb.row_words, o.rect0, o.rect1);
-      }
+      s_same = same ? 1u : 0u;
     }
+    __syncthreads();
+    if (!s_same) {
+      const Touch& t = st.touch[j];
+      if (t.flags & 1u) set_rect_bits(bm, bb.row_words, t.old_rect0, t.old_rect1, lane, 64);
+      __syncthreads();
+      if (t.flags & 2u) set_rect_bits(bm, bb.row_words, t.new_rect0, t.new_rect1, lane, 64);
+    }
+    __syncthreads();
   }
   uint32_t nd = 0;
-  for (int w = 0; w < bb.bm_words; ++w) nd += (uint32_t)__popcll(bm[w]);
-  st.n_dirty = nd;
-  bb.vs[v] = st;
-  bb.n_items_v[v] = nd;
+  for (int w = lane; w < bb.bm_words; w += 64) nd += (uint32_t)__popcll(bm[w]);
+  for (int o = 32; o > 0; o >>= 1) nd += (uint32_t)__shfl_xor((int)nd, o);
+  __syncthreads();
+  if (lane == 0) {
+    st.n_dirty = nd;
+    bb.vs[v] = st;
+    bb.n_items_v[v] = nd;
+  }
 }
 
-// Exclusive scan of dirty-tile counts over the batch (one block).
-__global__ void k_plan_scan(BatchBuffers bb) {
+// One block: scan the popcounts of all dirty-tile bitmap words of the batch
+// (variant-major, rows in order), so each set bit's item index is its rank;
+// write the (variant, tile) items, each variant's first item, the total, and
+// zero the compositing work counter.
+__global__ void __launch_bounds__(1024) k_plan(BatchBuffers bb, int tiles_x, uint32_t* counter) {
   __shared__ uint32_t s[1024];
+  const int64_t n_words = (int64_t)bb.B * bb.bm_words;
   uint32_t carry = 0;
-  for (int base = 0; base < bb.B; base += 1024) {
-    const int v = base + threadIdx.x;
-    const uint32_t x = v < bb.B ? bb.n_items_v[v] : 0u;
-    s[threadIdx.x] = x;
+  for (int64_t base = 0; base < n_words; base += 1024) {
+    const int64_t w = base + threadIdx.x;
+    const uint64_t word = w < n_words ? bb.bitmap[w] : 0ull;
+    const uint32_t c = (uint32_t)__popcll(word);
+    s[threadIdx.x] = c;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
       const uint32_t y = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
@@ -179,63 +202,55 @@ __global__ void k_plan_scan(BatchBuffers bb) {
       s[threadIdx.x] += y;
       __syncthreads();
     }
-    if (v < bb.B) {
-      bb.item_off[v] = carry + s[threadIdx.x] - x;
-      bb.vs[v].item_off = carry + s[threadIdx.x] - x;
+    if (w < n_words) {
+      uint32_t pos = carry + s[threadIdx.x] - c;
+      const int v = (int)(w / bb.bm_words);
+      const int wl = (int)(w % bb.bm_words);
+      if (wl == 0) {
+        bb.item_off[v] = pos;
+        bb.vs[v].item_off = pos;
+      }
+      uint64_t m = word;
+      const int row = wl / bb.row_words, col0 = (wl % bb.row_words) * 64;
+      while (m) {
+        const int b = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        bb.items[pos++] = make_uint2((uint32_t)v, (uint32_t)(row * tiles_x + col0 + b));
+      }
     }
     carry += s[1023];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *bb.n_items_total = carry;
-}
-
-// One block per variant: dirty-tile bitmap -> work items (variant, tile) in
-// increasing tile order.
-__global__ void k_expand(BatchBuffers bb, int tiles_x) {
-  const int v = blockIdx.x;
-  const uint64_t* bm = bb.bitmap + (int64_t)v * bb.bm_words;
-  __shared__ uint32_t pre[1024];
-  uint32_t off = bb.item_off[v];
-  for (int base = 0; base < bb.bm_words; base += 1024) {
-    const int w = base + threadIdx.x;
-    const uint64_t word = w < bb.bm_words ? bm[w] : 0ull;
-    const uint32_t c = (uint32_t)__popcll(word);
-    pre[threadIdx.x] = c;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const uint32_t y = threadIdx.x >= (unsigned)o ? pre[threadIdx.x - o] : 0u;
-      __syncthreads();
-      pre[threadIdx.x] += y;
-      __syncthreads();
-    }
-    uint32_t pos = off + pre[threadIdx.x] - c;
-    uint64_t m = word;
-    const int row = w / bb.row_words, col0 = (w % bb.row_words) * 64;
-    while (m) {
-      const int b = __ffsll((long long)m) - 1;
-      m &= m - 1ull;
-      bb.items[pos++] = make_uint2((uint32_t)v, (uint32_t)(row * tiles_x + col0 + b));
-    }
-    off += pre[1023];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    *bb.n_items_total = carry;
+    *counter = 0u;
   }
 }
 
 void launch_project(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                     const ProjBuffers& pb, hipStream_t st) {
-  const int64_t blocks = ((int64_t)s.n + 255) / 256;
-  k_project<<<(unsigned)blocks, 256, 0, st>>>(s, box, cam, ras, pb);
+  const unsigned blocks = (unsigned)(((int64_t)s.n + 255) / 256);
+  switch (s.sh_degree) {
+    case 0: k_project<0><<<blocks, 256, 0, st>>>(s, box, cam, ras, pb); break;
+    case 1: k_project<1><<<blocks, 256, 0, st>>>(s, box, cam, ras, pb); break;
+    case 2: k_project<2><<<blocks, 256, 0, st>>>(s, box, cam, ras, pb); break;
+    default: k_project<3><<<blocks, 256, 0, st>>>(s, box, cam, ras, pb); break;
+  }
 }
 
 void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                          const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
                          const uint2* rect, const BatchBuffers& bb, hipStream_t st) {
-  k_variant_prep<<<(bb.B + 63) / 64, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, bb);
+  switch (s.sh_degree) {
+    case 0: k_variant_prep<0><<<bb.B, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, bb); break;
+    case 1: k_variant_prep<1><<<bb.B, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, bb); break;
+    case 2: k_variant_prep<2><<<bb.B, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, bb); break;
+    default: k_variant_prep<3><<<bb.B, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, bb); break;
+  }
 }
 
-void launch_plan_expand(const BatchBuffers& bb, int tiles_x, hipStream_t st) {
-  k_plan_scan<<<1, 1024, 0, st>>>(bb);
-  k_expand<<<bb.B, 1024, 0, st>>>(bb, tiles_x);
+void launch_plan(const BatchBuffers& bb, int tiles_x, uint32_t* counter, hipStream_t st) {
+  k_plan<<<1, 1024, 0, st>>>(bb, tiles_x, counter);
 }
 
 }  // namespace sg

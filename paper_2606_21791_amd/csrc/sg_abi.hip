@@ -60,10 +60,10 @@ struct sg_ctx {
   DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
       big_prims, big_tiles, parts, work_scene, sites_dev, saved_tmp, box_keys, metrics_tmp;
   unsigned long long* h_total = nullptr;   // pinned
-  sg_site* h_sites = nullptr;              // pinned staging
-  size_t h_sites_cap = 0;
-  sg_variant* h_vars = nullptr;
-  size_t h_vars_cap = 0;
+  // per-pass event timing (sg_ctx_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[SG_N_PASSES];
 };
 
 struct sg_prep {
@@ -110,6 +110,36 @@ void dev_free(sg_ctx* ctx, DevBuf& b) {
   b.p = nullptr;
   b.bytes = 0;
 }
+
+// Records HIP events around the launches of one pass while timing is on.
+struct PassScope {
+  sg_ctx* c;
+  int pass;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  static hipEvent_t get(sg_ctx* c) {
+    if (!c->ev_pool.empty()) {
+      hipEvent_t e = c->ev_pool.back();
+      c->ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  PassScope(sg_ctx* c_, int pass_, hipStream_t st_) : c(c_), pass(pass_), st(st_) {
+    if (!c->timing) return;
+    a = get(c);
+    b = get(c);
+    if (a && b) (void)hipEventRecord(a, st);
+  }
+  ~PassScope() {
+    if (a && b) {
+      (void)hipEventRecord(b, st);
+      c->pending[pass].push_back({a, b});
+    }
+  }
+};
 
 template <class T>
 T* P(DevBuf& b) {
@@ -264,11 +294,17 @@ sg_status full_render(sg_ctx* ctx, const DevScene& s, const DevBox& box, const D
   launch_fill_u32(P<uint32_t>(ctx->clamps), 0u, 4, st);
   ProjBuffers pb{P<float4>(r0), P<float4>(r1), P<float4>(r2), P<uint32_t>(depth), P<uint2>(rect),
                  P<int32_t>(ctx->diff), P<uint32_t>(ctx->flags), P<unsigned long long>(ctx->clamps)};
-  launch_project(s, box, cam, ras, pb, st);
+  {
+    PassScope ps(ctx, SG_PASS_PROJECT, st);
+    launch_project(s, box, cam, ras, pb, st);
+  }
   BinBuffers bb{P<int32_t>(ctx->diff), P<uint32_t>(tile_cnt), P<uint32_t>(tile_start), P<uint32_t>(ctx->cursor),
                 P<unsigned long long>(ctx->total), nullptr, nullptr, P<uint32_t>(ctx->big_prims),
                 P<uint32_t>(ctx->big_tiles), 0};
-  launch_tile_prefix(ras, bb, st);
+  {
+    PassScope ps(ctx, SG_PASS_BIN, st);
+    launch_tile_prefix(ras, bb, st);
+  }
   SG_TRY(check_last("project/binning launch"));
   HIP_TRY(hipMemcpyAsync(ctx->h_total, ctx->total.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -279,11 +315,20 @@ sg_status full_render(sg_ctx* ctx, const DevScene& s, const DevBox& box, const D
   bb.keys = P<uint64_t>(keys);
   bb.keys_tmp = P<uint64_t>(ctx->keys_tmp);
   bb.capacity = n_inst;
-  launch_emit(s.n, P<uint32_t>(depth), P<uint2>(rect), ras, bb, st);
-  launch_tile_sort(ras, bb, st);
+  {
+    PassScope ps(ctx, SG_PASS_BIN, st);
+    launch_emit(s.n, P<uint32_t>(depth), P<uint2>(rect), ras, bb, st);
+  }
+  {
+    PassScope ps(ctx, SG_PASS_SORT, st);
+    launch_tile_sort(ras, bb, st);
+  }
   CompArgs ca{P<float4>(r0), P<float4>(r1), P<float4>(r2), P<uint32_t>(tile_start), P<uint32_t>(tile_cnt),
               P<uint64_t>(keys), clean, image, parts, ras, cam.W, cam.H};
-  launch_composite_full(ca, st);
+  {
+    PassScope ps(ctx, SG_PASS_COMPOSITE_FULL, st);
+    launch_composite_full(ca, st);
+  }
   SG_TRY(check_last("render launch"));
   if (n_inst_out) *n_inst_out = n_inst;
   return SG_OK;
@@ -324,10 +369,38 @@ void sg_ctx_destroy(sg_ctx* c) {
                     &c->parts, &c->work_scene, &c->sites_dev, &c->saved_tmp, &c->box_keys, &c->metrics_tmp};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->h_total) (void)hipHostFree(c->h_total);
+  for (int p = 0; p < SG_N_PASSES; ++p)
+    for (auto& pr : c->pending[p]) c->ev_pool.insert(c->ev_pool.end(), {pr.first, pr.second});
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
 
 size_t sg_ctx_bytes(const sg_ctx* c) { return c ? c->in_use : 0; }
+
+sg_status sg_ctx_timing(sg_ctx* c, int32_t enable) {
+  if (!c) return fail(SG_E_INVAL, "ctx is NULL");
+  c->timing = enable != 0;
+  return SG_OK;
+}
+
+sg_status sg_ctx_pass_times(sg_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return fail(SG_E_INVAL, "NULL argument");
+  for (int p = 0; p < SG_N_PASSES; ++p) {
+    ms[p] = 0.0;
+    launches[p] = 0;
+    for (auto& pr : c->pending[p]) {
+      HIP_TRY(hipEventSynchronize(pr.second));
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second));
+      ms[p] += t;
+      launches[p] += 1;
+      c->ev_pool.push_back(pr.first);
+      c->ev_pool.push_back(pr.second);
+    }
+    c->pending[p].clear();
+  }
+  return SG_OK;
+}
 
 sg_status sg_cast(sg_ctx* ctx, const float* src, void* dst, int64_t n, int32_t dtype, int32_t rounding, void* stream) {
   if (!ctx) return fail(SG_E_INVAL, "ctx is NULL");
@@ -388,8 +461,11 @@ sg_status sg_guard(sg_ctx* ctx, const sg_scene* scene, const sg_box* box, uint32
   SG_TRY(to_dev_box(box, field_mask, s, &b));
   hipStream_t st = S(stream);
   launch_fill_u32(reinterpret_cast<uint32_t*>(clamp_count), 0u, 2, st);
-  for (int f = 0; f < 6; ++f)
-    if ((b.mask >> f) & 1u) launch_guard(s, b, f, reinterpret_cast<unsigned long long*>(clamp_count), st);
+  {
+    PassScope ps(ctx, SG_PASS_GUARD, st);
+    for (int f = 0; f < 6; ++f)
+      if ((b.mask >> f) & 1u) launch_guard(s, b, f, reinterpret_cast<unsigned long long*>(clamp_count), st);
+  }
   if (health_alert) launch_health(reinterpret_cast<unsigned long long*>(clamp_count), health_threshold, health_alert, st);
   return check_last("sg_guard");
 }
@@ -529,20 +605,28 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
     BatchBuffers bb{P<sg_site>(prep->sites), P<sg_variant>(prep->vars), B, P<VariantState>(prep->vs), P<Rec>(prep->ovr),
                     P<uint64_t>(prep->bitmap), prep->bm_words, prep->row_words, P<uint32_t>(prep->item_off),
                     P<uint32_t>(prep->n_items_v), P<uint32_t>(prep->n_items_total), P<uint2>(prep->items)};
-    launch_variant_prep(s, b, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
-                        P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
-    launch_plan_expand(bb, ras.tiles_x, st);
-    launch_fill_u32(P<uint32_t>(prep->counter), 0u, 1, st);
+    {
+      PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
+      launch_variant_prep(s, b, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
+                          P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
+      launch_plan(bb, ras.tiles_x, P<uint32_t>(prep->counter), st);
+    }
     CompArgs ca{P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2), P<uint32_t>(prep->tile_start),
                 P<uint32_t>(prep->tile_cnt), P<uint64_t>(prep->keys), P<float>(prep->frame), images_out,
                 P<Partial>(prep->parts), ras, prep->cam.W, prep->cam.H};
     const int per_cu = ras.tile == 32 ? 2 : (ras.tile == 16 ? 8 : 16);
     ItemArgs it{P<VariantState>(prep->vs), P<Rec>(prep->ovr), P<uint2>(prep->items), P<uint32_t>(prep->n_items_total),
                 P<uint32_t>(prep->counter), frame_floats, ctx->n_cu * per_cu};
-    launch_composite_items(ca, it, st);
-    launch_reduce_metrics(P<Partial>(prep->parts), P<uint32_t>(prep->item_off), P<uint32_t>(prep->n_items_v), 0,
-                          P<VariantState>(prep->vs), nullptr, nullptr, (uint32_t)(prep->cam.W * prep->cam.H),
-                          metrics_out, B, 0u, st);
+    {
+      PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st);
+      launch_composite_items(ca, it, st);
+    }
+    {
+      PassScope ps(ctx, SG_PASS_REDUCE, st);
+      launch_reduce_metrics(P<Partial>(prep->parts), P<uint32_t>(prep->item_off), P<uint32_t>(prep->n_items_v), 0,
+                            P<VariantState>(prep->vs), nullptr, nullptr, (uint32_t)(prep->cam.W * prep->cam.H),
+                            metrics_out, B, 0u, st);
+    }
     SG_TRY(check_last("sg_render_batch incremental"));
   }
 

@@ -172,8 +172,18 @@ __device__ __forceinline__ bool in_range(double v) { return fabs(v) <= kFltMax; 
 // Project one primitive.  `get(f, c)` returns the (already flipped and
 // guarded) stored word of field f, component c.  Everything is evaluated in
 // fp64 and rounded once into the fp32 record.
-template <class Get>
-__device__ ProjOut project_prim(Get get, int dtype, int sh_degree, const DevCam& cam, const DevRaster& ras) {
+// Stored components per primitive at SH degree DEG and the offset of each
+// field in a flat per-primitive word array.
+template <int DEG>
+struct Layout {
+  static constexpr int kRest = 3 * ((DEG + 1) * (DEG + 1) - 1);
+  static constexpr int kWords = 14 + kRest;
+  static constexpr int off(int f) { return f == 0 ? 0 : f == 1 ? 3 : f == 2 ? 6 : f == 3 ? 10 : f == 4 ? 11 : 14; }
+};
+
+template <int DEG, class Get>
+__device__ __forceinline__ ProjOut project_prim(Get get, int dtype, const DevCam& cam, const DevRaster& ras) {
+  constexpr int sh_degree = DEG;
   ProjOut o;
   o.visible = false;
   o.nonfinite = false;
@@ -181,7 +191,7 @@ __device__ ProjOut project_prim(Get get, int dtype, int sh_degree, const DevCam&
   o.rect0 = 0xffffffffu;
   o.rect1 = 0;
   o.rec.r0 = o.rec.r1 = o.rec.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
-  const int n_rest = 3 * ((sh_degree + 1) * (sh_degree + 1) - 1);
+  constexpr int n_rest = Layout<DEG>::kRest;
 
   double mu[3], ls[3], qv[4], dc[3], logit;
   bool fin = true;
@@ -195,6 +205,7 @@ __device__ ProjOut project_prim(Get get, int dtype, int sh_degree, const DevCam&
   fin &= isfinite(logit);
 #pragma unroll
   for (int c = 0; c < 3; ++c) { dc[c] = decode_word(get(4, c), dtype); fin &= isfinite(dc[c]); }
+#pragma unroll
   for (int c = 0; c < n_rest; ++c) fin &= isfinite(decode_word(get(5, c), dtype));
   if (!fin) { o.nonfinite = true; return o; }
 
@@ -276,7 +287,8 @@ __device__ ProjOut project_prim(Get get, int dtype, int sh_degree, const DevCam&
   double Y[16];
   sh_basis(dx, dy, dz, sh_degree, Y);
   double col[3] = {Y[0] * dc[0], Y[0] * dc[1], Y[0] * dc[2]};
-  const int K = (sh_degree + 1) * (sh_degree + 1);
+  constexpr int K = (sh_degree + 1) * (sh_degree + 1);
+#pragma unroll
   for (int k = 1; k < K; ++k) {
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * decode_word(get(5, 3 * (k - 1) + ch), dtype);

@@ -12,25 +12,30 @@ namespace sg {
 // then waves in index order), so the result does not depend on scheduling.
 // Every thread of the block must call it; thread 0 writes *out.
 __device__ __forceinline__ void block_reduce_partial(double sse, uint32_t changed, float mx, uint32_t nonfin,
-                                                     Partial* out) {
+                                                     unsigned long long evals, Partial* out) {
   for (int o = 32; o > 0; o >>= 1) {
     sse += __shfl_xor(sse, o);
     changed += (uint32_t)__shfl_xor((int)changed, o);
     mx = fmaxf(mx, __shfl_xor(mx, o));
     nonfin |= (uint32_t)__shfl_xor((int)nonfin, o);
+    evals += __shfl_xor(evals, o);
   }
   __shared__ double s_sse[16];
+  __shared__ unsigned long long s_ev[16];
   __shared__ uint32_t s_ch[16], s_nf[16];
   __shared__ float s_mx[16];
   const int w = threadIdx.x >> 6;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) { s_sse[w] = sse; s_ch[w] = changed; s_mx[w] = mx; s_nf[w] = nonfin; }
+  if ((threadIdx.x & 63) == 0) { s_sse[w] = sse; s_ch[w] = changed; s_mx[w] = mx; s_nf[w] = nonfin; s_ev[w] = evals; }
   __syncthreads();
   if (threadIdx.x == 0) {
     const int nw = (blockDim.x + 63) >> 6;
     Partial p;
-    p.sse = 0.0; p.changed = 0; p.max_abs = 0.f; p.nonfinite = 0; p._pad = 0;
-    for (int i = 0; i < nw; ++i) { p.sse += s_sse[i]; p.changed += s_ch[i]; p.max_abs = fmaxf(p.max_abs, s_mx[i]); p.nonfinite |= s_nf[i]; }
+    p.sse = 0.0; p.evals = 0; p.changed = 0; p.max_abs = 0.f; p.nonfinite = 0; p._pad = 0;
+    for (int i = 0; i < nw; ++i) {
+      p.sse += s_sse[i]; p.changed += s_ch[i]; p.max_abs = fmaxf(p.max_abs, s_mx[i]); p.nonfinite |= s_nf[i];
+      p.evals += s_ev[i];
+    }
     *out = p;
   }
   __syncthreads();
@@ -83,7 +88,7 @@ struct BatchBuffers {
 void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                          const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
                          const uint2* rect, const BatchBuffers& bb, hipStream_t st);
-void launch_plan_expand(const BatchBuffers& bb, int tiles_x, hipStream_t st);
+void launch_plan(const BatchBuffers& bb, int tiles_x, uint32_t* counter, hipStream_t st);
 
 // k_bin.hip
 struct BinBuffers {

@@ -50,6 +50,7 @@ struct Rec {
 // Per-item (tile or (variant, tile)) metric partials, reduced in a fixed order.
 struct Partial {
   double sse;
+  unsigned long long evals;
   uint32_t changed;
   float max_abs;
   uint32_t nonfinite;

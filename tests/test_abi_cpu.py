@@ -31,7 +31,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(b.SgCamera) == 8 * 18 + 8
     assert ctypes.sizeof(b.SgRaster) == 4 * 9
     assert ctypes.sizeof(b.SgBox) == 8 + 12 * 8
-    assert b.SITE_DTYPE.itemsize == 8 and b.METRICS_DTYPE.itemsize == 64
+    assert b.SITE_DTYPE.itemsize == 8 and b.METRICS_DTYPE.itemsize == 72
 
 
 def test_invalid_arguments_are_rejected_without_a_gpu():
