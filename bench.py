@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--streams", type=int, default=1, help="HIP streams the batches rotate over")
+    ap.add_argument("--wgs-per-cu", type=int, default=0, help="persistent compositing workgroups per CU (0: default)")
     ap.add_argument("--plain", type=int, default=100, help="injections timed on the plain path")
     ap.add_argument("--cpu-inj", type=int, default=1, help="oracle injections timed on the host (0: skip)")
     args = ap.parse_args()
@@ -100,6 +102,8 @@ def main():
 
     sc, cam, sites = _workload(args.fmt)
     ctx = sgb.Context(0)
+    ctx.set_persistent(args.wgs_per_cu)
+    streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
     ds = sgb.DeviceScene.upload(ctx, sc, args.fmt)
     prep = ctx.prepare(ds, cam, sgb.raster_struct(tile=args.tile))
     torch.cuda.synchronize()
@@ -114,15 +118,19 @@ def main():
     va = sgb.variants_array(np.arange(B), np.ones(B, np.uint32))
     mts = [sgb.metrics_tensor(B) for _ in range(steps_total)]
 
+    def run(i):
+        with torch.cuda.stream(streams[i % len(streams)]):
+            ctx.render_batch(prep, batches[i], va, metrics=mts[i])
+
     for i in range(args.warmup):
-        ctx.render_batch(prep, batches[i], va, metrics=mts[i])
+        run(i)
     torch.cuda.synchronize()
     ctx.timing(True)
     ctx.pass_times()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.warmup, steps_total):
-        ctx.render_batch(prep, batches[i], va, metrics=mts[i])
+        run(i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     passes = ctx.pass_times()
@@ -185,7 +193,8 @@ def main():
         "config": {"workload": f"scaling-sweep large scene: N=134,826 Gaussians, SH degree 3, {args.fmt} storage, "
                                f"800x800, {args.tile}x{args.tile} tiles, B={B} single-bit variants per launch, "
                                "incremental dirty-tile re-composite",
-                   "global_batch": B, "n_sites": n_sites, "instances_clean": prep.instances()},
+                   "global_batch": B, "n_sites": n_sites, "instances_clean": prep.instances(),
+                   "streams": len(streams), "wgs_per_cu": args.wgs_per_cu},
         "plain": {"value": round(P / plain_dt, 1), "unit": "injections/s", "injections": P,
                   "ms_per_injection": round(plain_dt / P * 1e3, 4),
                   "pass_ms_per_injection": {k: round(v[0] / max(P, 1), 4) for k, v in plain_passes.items() if v[1]},

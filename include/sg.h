@@ -235,6 +235,15 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
                           const sg_variant* variants, int32_t B, const sg_box* box, uint32_t box_field_mask,
                           float* images_out, sg_metrics_t* metrics_out, int32_t mode, void* stream);
 
+/* Workgroups per compute unit of the persistent incremental compositing
+ * launch (0 = default for the tile size).  Fewer leave room for batches on
+ * other streams to run concurrently; this is one of the tuned parameters. */
+sg_status sg_ctx_set_persistent(sg_ctx* ctx, int32_t wgs_per_cu);
+
+/* Work issued on different HIP streams uses different workspaces of the
+ * context, so batches on different streams may overlap on the device (the
+ * host calls themselves stay single-threaded). */
+
 /* Per-pass device timing, for profiling.  While enabled, calls record HIP
  * events on their stream around each pass; sg_ctx_pass_times waits for the
  * recorded events, adds the elapsed milliseconds per pass into ms[SG_N_PASSES]

@@ -30,9 +30,15 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
                                                float* img, Partial* part, float4* s_r0, float4* s_r1,
                                                float4* s_r2) {
   constexpr int BS = TILE * TILE;
+  constexpr int NW = BS / 64;            // waves per tile; wave w covers an 8 x 8 pixel block
+  constexpr int BPR = TILE / 8;          // blocks per tile row
+  __shared__ uint16_t s_idx[NW][BS];     // per wave: batch entries whose box touches its block, in order
+  __shared__ uint32_t s_cnt[NW][NW];     // [target wave][loading wave] entry counts
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
   const int tx = tile % A.ras.tiles_x, ty = tile / A.ras.tiles_x;
-  const int x = tx * TILE + (tid % TILE), y = ty * TILE + (tid / TILE);
+  const int bx = tx * TILE + (wave % BPR) * 8, by = ty * TILE + (wave / BPR) * 8;
+  const int x = bx + (lane & 7), y = by + (lane >> 3);
   const bool inside = x < A.W && y < A.H;
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
   const float amax = A.ras.amax, amin = A.ras.amin, tmin = A.ras.tmin, qc = A.ras.qcut2;
@@ -47,6 +53,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
   for (uint32_t base = 0; base < mlen; base += BS) {
     if (__syncthreads_and(done)) break;
     const uint32_t m = base + tid;
+    uint32_t mask = 0;                   // target waves whose block this entry may reach
     if (m < mlen) {
       float4 a, b, c;
       if (!ms) {
@@ -69,28 +76,82 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
         }
       }
       s_r0[tid] = a; s_r1[tid] = b; s_r2[tid] = c;
+      // Conservative extent of the pixels this entry can reach: the ellipse
+      // q <= min(cut, 2 ln(o / alpha_min)), from its eigen-decomposition,
+      // widened by 0.1% and one pixel against fp32 rounding.
+      const float qe = fminf(qc, __log2f(c.x / amin));        // in the scaled units of the loop
+      if (qe >= 0.f) {
+        const float hl = 0.72134752f;                          // log2(e) / 2
+        const float l1 = hl / b.z, l2 = hl / b.w;              // lambda_1, lambda_2
+        const float qq = qe / hl;
+        const float sxx = a.z * a.z * l1 + a.w * a.w * l2, syy = a.w * a.w * l1 + a.z * a.z * l2;
+        const float hx = sqrtf(qq * sxx) * 1.001f + 1.f, hy = sqrtf(qq * syy) * 1.001f + 1.f;
+        const float cu = a.x + (b.x * a.z - b.y * a.w), cv = a.y + (b.x * a.w + b.y * a.z);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const float x0 = (float)(tx * TILE + (w % BPR) * 8) + 0.5f, y0 = (float)(ty * TILE + (w / BPR) * 8) + 0.5f;
+          const bool hit = (cu + hx >= x0) && (cu - hx <= x0 + 7.f) && (cv + hy >= y0) && (cv - hy <= y0 + 7.f);
+          mask |= hit ? (1u << w) : 0u;
+        }
+      }
+    }
+    // order-preserving compaction of the batch into one entry list per wave
+    unsigned long long bal[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      bal[w] = __ballot((mask >> w) & 1u);
+      if (lane == 0) s_cnt[w][wave] = (uint32_t)__popcll(bal[w]);
     }
     __syncthreads();
-    if (!done) {
-      const int cnt = (int)min((uint32_t)BS, mlen - base);
-      for (int j = 0; j < cnt; ++j) {
-        const float4 a = s_r0[j];
-        const float4 b = s_r1[j];
+    const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      if ((mask >> w) & 1u) {
+        uint32_t pos = (uint32_t)__popcll(bal[w] & lt);
+        for (int v = 0; v < wave; ++v) pos += s_cnt[w][v];
+        s_idx[w][pos] = (uint16_t)tid;
+      }
+    }
+    uint32_t len = 0;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) len += s_cnt[wave][v];
+    __syncthreads();
+    if (!__all(done) && len) {
+      // No divergent exits inside the batch: a stopped pixel is masked by
+      // `done`; the wave leaves the batch once all of its lanes have stopped.
+      const uint16_t* idx = s_idx[wave];
+      int e = idx[0];
+      int en = idx[min(1u, len - 1)];
+      float4 a = s_r0[e], b = s_r1[e], c = s_r2[e];
+      for (uint32_t j = 0; j < len; ++j) {
+        // while this entry is evaluated, the next entry's record and the
+        // index of the one after it are read from LDS
+        const int enn = idx[min(j + 2, len - 1)];
+        const float4 an = s_r0[en], bn = s_r1[en], cn = s_r2[en];
         const float ex = px - a.x, ey = py - a.y;
         const float uu = fmaf(ex, a.z, fmaf(ey, a.w, -b.x));
         const float vv = fmaf(ey, a.z, fmaf(-ex, a.w, -b.y));
         const float q = fmaf(vv, vv * b.w, uu * (uu * b.z));
-        if (q > qc) continue;
-        const float4 c = s_r2[j];
         const float alpha = fminf(amax, c.x * __builtin_amdgcn_exp2f(-q));
-        if (alpha < amin) continue;
-        const float Tn = T * (1.f - alpha);
-        if (Tn < tmin) { done = true; evals = base + (uint32_t)j + 1u; break; }
-        const float w = alpha * T;
-        C0 = fmaf(c.y, w, C0);
-        C1 = fmaf(c.z, w, C1);
-        C2 = fmaf(c.w, w, C2);
-        T = Tn;
+        if (q <= qc && alpha >= amin && !done) {
+          const float Tn = T * (1.f - alpha);
+          if (Tn < tmin) {
+            done = true;
+            evals = base + (uint32_t)e + 1u;
+          } else {
+            const float w = alpha * T;
+            C0 = fmaf(c.y, w, C0);
+            C1 = fmaf(c.z, w, C1);
+            C2 = fmaf(c.w, w, C2);
+            T = Tn;
+          }
+        }
+        e = en;
+        en = enn;
+        a = an;
+        b = bn;
+        c = cn;
+        if ((j & 7) == 7 && __all(done)) break;
       }
     }
   }

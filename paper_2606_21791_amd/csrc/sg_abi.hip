@@ -51,15 +51,25 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Buffers of the calls issued on one HIP stream.  Calls on different
+// streams use different workspaces, so their device work may overlap.
+struct Workspace {
+  hipStream_t stream = nullptr;
+  // full renders
+  DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
+      big_prims, big_tiles, parts, work_scene, sites_dev, box_keys, metrics_tmp;
+  // batches of variants
+  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, bsites, vars;
+  unsigned long long* h_total = nullptr;   // pinned
+};
+
 struct sg_ctx {
   int device = 0;
   size_t budget = 0;
   size_t in_use = 0;
   int n_cu = 256;
-  // workspaces of full renders
-  DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
-      big_prims, big_tiles, parts, work_scene, sites_dev, saved_tmp, box_keys, metrics_tmp;
-  unsigned long long* h_total = nullptr;   // pinned
+  int persistent_wgs_per_cu = 0;           // 0: default of the tile size
+  std::vector<Workspace*> ws;
   // per-pass event timing (sg_ctx_timing)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -74,9 +84,6 @@ struct sg_prep {
   DevRaster ras;
   int64_t n_inst = 0;
   DevBuf r0, r1, r2, depth, rect, tile_cnt, tile_start, keys, frame;
-  // batch workspaces
-  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, parts, counter, sites, vars, metrics;
-  int batch_cap = 0;
   int bm_words = 0, row_words = 0;
 };
 
@@ -110,6 +117,34 @@ void dev_free(sg_ctx* ctx, DevBuf& b) {
   b.p = nullptr;
   b.bytes = 0;
 }
+
+Workspace* workspace(sg_ctx* ctx, hipStream_t st) {
+  for (Workspace* w : ctx->ws)
+    if (w->stream == st) return w;
+  Workspace* w = new Workspace();
+  w->stream = st;
+  if (hipHostMalloc((void**)&w->h_total, 8 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+    delete w;
+    return nullptr;
+  }
+  ctx->ws.push_back(w);
+  return w;
+}
+
+void free_workspace(sg_ctx* ctx, Workspace* w) {
+  DevBuf* bufs[] = {&w->r0, &w->r1, &w->r2, &w->depth, &w->rect, &w->diff, &w->flags, &w->clamps, &w->tile_cnt,
+                    &w->tile_start, &w->cursor, &w->total, &w->keys, &w->keys_tmp, &w->big_prims, &w->big_tiles,
+                    &w->parts, &w->work_scene, &w->sites_dev, &w->box_keys, &w->metrics_tmp, &w->vs, &w->ovr,
+                    &w->bitmap, &w->item_off, &w->n_items_v, &w->n_items_total, &w->items, &w->bparts,
+                    &w->counter, &w->bsites, &w->vars};
+  for (DevBuf* b : bufs) dev_free(ctx, *b);
+  if (w->h_total) (void)hipHostFree(w->h_total);
+  delete w;
+}
+
+#define WS_OR_FAIL(W, ctx, st)                                            \
+  Workspace* W = workspace(ctx, st);                                      \
+  if (!W) return fail(SG_E_NOMEM, "pinned allocation for a workspace failed")
 
 // Records HIP events around the launches of one pass while timing is on.
 struct PassScope {
@@ -269,7 +304,7 @@ struct RenderBufs {
 // Full render of a scene: project (with optional clamp-on-load), bin, sort,
 // composite (with metric partials against `clean` when given).  The record and
 // list buffers are either the context's workspaces or a prepared scene's.
-sg_status full_render(sg_ctx* ctx, const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
+sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                       DevBuf& r0, DevBuf& r1, DevBuf& r2, DevBuf& depth, DevBuf& rect, DevBuf& tile_cnt,
                       DevBuf& tile_start, DevBuf& keys, float* image, const float* clean, Partial* parts,
                       hipStream_t st, int64_t* n_inst_out) {
@@ -280,40 +315,40 @@ sg_status full_render(sg_ctx* ctx, const DevScene& s, const DevBox& box, const D
   SG_TRY(dev_alloc(ctx, depth, n * sizeof(uint32_t)));
   SG_TRY(dev_alloc(ctx, rect, n * sizeof(uint2)));
   const int64_t diff_n = (int64_t)(ras.tiles_x + 1) * (ras.tiles_y + 1);
-  SG_TRY(dev_alloc(ctx, ctx->diff, diff_n * sizeof(int32_t)));
-  SG_TRY(dev_alloc(ctx, ctx->flags, 16));
-  SG_TRY(dev_alloc(ctx, ctx->clamps, 16));
+  SG_TRY(dev_alloc(ctx, W->diff, diff_n * sizeof(int32_t)));
+  SG_TRY(dev_alloc(ctx, W->flags, 16));
+  SG_TRY(dev_alloc(ctx, W->clamps, 16));
   SG_TRY(dev_alloc(ctx, tile_cnt, ras.n_tiles * sizeof(uint32_t)));
   SG_TRY(dev_alloc(ctx, tile_start, ras.n_tiles * sizeof(uint32_t)));
-  SG_TRY(dev_alloc(ctx, ctx->cursor, ras.n_tiles * sizeof(uint32_t)));
-  SG_TRY(dev_alloc(ctx, ctx->total, 4 * sizeof(unsigned long long)));
-  SG_TRY(dev_alloc(ctx, ctx->big_prims, n * sizeof(uint32_t)));
-  SG_TRY(dev_alloc(ctx, ctx->big_tiles, ras.n_tiles * sizeof(uint32_t)));
-  launch_fill_u32(P<uint32_t>(ctx->diff), 0u, diff_n, st);
-  launch_fill_u32(P<uint32_t>(ctx->flags), 0u, 4, st);
-  launch_fill_u32(P<uint32_t>(ctx->clamps), 0u, 4, st);
+  SG_TRY(dev_alloc(ctx, W->cursor, ras.n_tiles * sizeof(uint32_t)));
+  SG_TRY(dev_alloc(ctx, W->total, 4 * sizeof(unsigned long long)));
+  SG_TRY(dev_alloc(ctx, W->big_prims, n * sizeof(uint32_t)));
+  SG_TRY(dev_alloc(ctx, W->big_tiles, ras.n_tiles * sizeof(uint32_t)));
+  launch_fill_u32(P<uint32_t>(W->diff), 0u, diff_n, st);
+  launch_fill_u32(P<uint32_t>(W->flags), 0u, 4, st);
+  launch_fill_u32(P<uint32_t>(W->clamps), 0u, 4, st);
   ProjBuffers pb{P<float4>(r0), P<float4>(r1), P<float4>(r2), P<uint32_t>(depth), P<uint2>(rect),
-                 P<int32_t>(ctx->diff), P<uint32_t>(ctx->flags), P<unsigned long long>(ctx->clamps)};
+                 P<int32_t>(W->diff), P<uint32_t>(W->flags), P<unsigned long long>(W->clamps)};
   {
     PassScope ps(ctx, SG_PASS_PROJECT, st);
     launch_project(s, box, cam, ras, pb, st);
   }
-  BinBuffers bb{P<int32_t>(ctx->diff), P<uint32_t>(tile_cnt), P<uint32_t>(tile_start), P<uint32_t>(ctx->cursor),
-                P<unsigned long long>(ctx->total), nullptr, nullptr, P<uint32_t>(ctx->big_prims),
-                P<uint32_t>(ctx->big_tiles), 0};
+  BinBuffers bb{P<int32_t>(W->diff), P<uint32_t>(tile_cnt), P<uint32_t>(tile_start), P<uint32_t>(W->cursor),
+                P<unsigned long long>(W->total), nullptr, nullptr, P<uint32_t>(W->big_prims),
+                P<uint32_t>(W->big_tiles), 0};
   {
     PassScope ps(ctx, SG_PASS_BIN, st);
     launch_tile_prefix(ras, bb, st);
   }
   SG_TRY(check_last("project/binning launch"));
-  HIP_TRY(hipMemcpyAsync(ctx->h_total, ctx->total.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(W->h_total, W->total.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  const int64_t n_inst = (int64_t)ctx->h_total[0];
+  const int64_t n_inst = (int64_t)W->h_total[0];
   if (n_inst >= (int64_t)0xffffffffu) return fail(SG_E_UNSUPPORTED, "more than 2^32 primitive-tile instances");
   SG_TRY(dev_alloc(ctx, keys, std::max<int64_t>(n_inst, 1) * sizeof(uint64_t)));
-  SG_TRY(dev_alloc(ctx, ctx->keys_tmp, std::max<int64_t>(n_inst, 1) * sizeof(uint64_t)));
+  SG_TRY(dev_alloc(ctx, W->keys_tmp, std::max<int64_t>(n_inst, 1) * sizeof(uint64_t)));
   bb.keys = P<uint64_t>(keys);
-  bb.keys_tmp = P<uint64_t>(ctx->keys_tmp);
+  bb.keys_tmp = P<uint64_t>(W->keys_tmp);
   bb.capacity = n_inst;
   {
     PassScope ps(ctx, SG_PASS_BIN, st);
@@ -352,10 +387,6 @@ sg_status sg_ctx_create(int32_t device, size_t hbm_budget_bytes, sg_ctx** out) {
   c->budget = hbm_budget_bytes;
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0) c->n_cu = ncu;
-  if (hipHostMalloc((void**)&c->h_total, 8 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
-    delete c;
-    return fail(SG_E_DEVICE, "pinned allocation failed");
-  }
   *out = c;
   return SG_OK;
 }
@@ -364,11 +395,8 @@ void sg_ctx_destroy(sg_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->r0, &c->r1, &c->r2, &c->depth, &c->rect, &c->diff, &c->flags, &c->clamps, &c->tile_cnt,
-                    &c->tile_start, &c->cursor, &c->total, &c->keys, &c->keys_tmp, &c->big_prims, &c->big_tiles,
-                    &c->parts, &c->work_scene, &c->sites_dev, &c->saved_tmp, &c->box_keys, &c->metrics_tmp};
-  for (DevBuf* b : bufs) dev_free(c, *b);
-  if (c->h_total) (void)hipHostFree(c->h_total);
+  for (Workspace* w : c->ws) free_workspace(c, w);
+  c->ws.clear();
   for (int p = 0; p < SG_N_PASSES; ++p)
     for (auto& pr : c->pending[p]) c->ev_pool.insert(c->ev_pool.end(), {pr.first, pr.second});
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -376,6 +404,12 @@ void sg_ctx_destroy(sg_ctx* c) {
 }
 
 size_t sg_ctx_bytes(const sg_ctx* c) { return c ? c->in_use : 0; }
+
+sg_status sg_ctx_set_persistent(sg_ctx* c, int32_t wgs_per_cu) {
+  if (!c || wgs_per_cu < 0 || wgs_per_cu > 64) return fail(SG_E_INVAL, "wgs_per_cu must be 0..64");
+  c->persistent_wgs_per_cu = wgs_per_cu;
+  return SG_OK;
+}
 
 sg_status sg_ctx_timing(sg_ctx* c, int32_t enable) {
   if (!c) return fail(SG_E_INVAL, "ctx is NULL");
@@ -417,8 +451,9 @@ sg_status sg_inject(sg_ctx* ctx, const sg_scene* scene, const sg_site* sites, in
   SG_TRY(to_dev_scene(scene, &s));
   SG_TRY(validate_sites(s, sites, n));
   if (n == 0) return SG_OK;
-  SG_TRY(stage_sites(ctx, sites, n, ctx->sites_dev, S(stream)));
-  launch_inject(s, P<sg_site>(ctx->sites_dev), n, saved, S(stream));
+  WS_OR_FAIL(W, ctx, S(stream));
+  SG_TRY(stage_sites(ctx, sites, n, W->sites_dev, S(stream)));
+  launch_inject(s, P<sg_site>(W->sites_dev), n, saved, S(stream));
   return check_last("sg_inject");
 }
 
@@ -438,11 +473,12 @@ sg_status sg_guard_box(sg_ctx* ctx, const sg_scene* clean, uint32_t field_mask, 
   for (int f = 0; f < 6; ++f)
     if (((field_mask >> f) & 1u) && s.ncomp[f] > 0 && (!out->lo[f] || !out->hi[f]))
       return fail(SG_E_INVAL, "box bounds of a masked field are NULL");
-  SG_TRY(dev_alloc(ctx, ctx->box_keys, 2 * 64 * sizeof(uint32_t)));
   hipStream_t st = S(stream);
+  WS_OR_FAIL(W, ctx, st);
+  SG_TRY(dev_alloc(ctx, W->box_keys, 2 * 64 * sizeof(uint32_t)));
   for (int f = 0; f < 6; ++f) {
     if (!((field_mask >> f) & 1u) || s.ncomp[f] == 0) continue;
-    uint32_t* kmin = P<uint32_t>(ctx->box_keys);
+    uint32_t* kmin = P<uint32_t>(W->box_keys);
     uint32_t* kmax = kmin + 64;
     launch_fill_u32(kmin, 0xffffffffu, 64, st);
     launch_fill_u32(kmax, 0u, 64, st);
@@ -484,16 +520,17 @@ sg_status sg_render(sg_ctx* ctx, const sg_scene* scene, const sg_camera* cam, co
   SG_TRY(to_dev_box(box, box_field_mask, s, &b));
   if (metrics_out && !clean_frame) return fail(SG_E_INVAL, "metrics need a clean frame");
   hipStream_t st = S(stream);
+  WS_OR_FAIL(W, ctx, st);
   Partial* parts = nullptr;
   if (clean_frame) {
-    SG_TRY(dev_alloc(ctx, ctx->parts, (size_t)r.n_tiles * sizeof(Partial)));
-    parts = P<Partial>(ctx->parts);
+    SG_TRY(dev_alloc(ctx, W->parts, (size_t)r.n_tiles * sizeof(Partial)));
+    parts = P<Partial>(W->parts);
   }
-  SG_TRY(full_render(ctx, s, b, c, r, ctx->r0, ctx->r1, ctx->r2, ctx->depth, ctx->rect, ctx->tile_cnt, ctx->tile_start,
-                     ctx->keys, image_out, clean_frame, parts, st, nullptr));
+  SG_TRY(full_render(ctx, W, s, b, c, r, W->r0, W->r1, W->r2, W->depth, W->rect, W->tile_cnt, W->tile_start,
+                     W->keys, image_out, clean_frame, parts, st, nullptr));
   if (metrics_out)
-    launch_reduce_metrics(parts, nullptr, nullptr, (uint32_t)r.n_tiles, nullptr, P<uint32_t>(ctx->flags),
-                          P<unsigned long long>(ctx->clamps), (uint32_t)(c.W * c.H), metrics_out, 1, 1u, st);
+    launch_reduce_metrics(parts, nullptr, nullptr, (uint32_t)r.n_tiles, nullptr, P<uint32_t>(W->flags),
+                          P<unsigned long long>(W->clamps), (uint32_t)(c.W * c.H), metrics_out, 1, 1u, st);
   return check_last("sg_render");
 }
 
@@ -514,9 +551,10 @@ sg_status sg_prepare(sg_ctx* ctx, const sg_scene* clean, const sg_camera* cam, c
   DevBox nobox;
   std::memset(&nobox, 0, sizeof(nobox));
   hipStream_t st = S(stream);
-  rc = dev_alloc(ctx, p->frame, (size_t)p->cam.W * p->cam.H * 3 * sizeof(float));
+  Workspace* W = workspace(ctx, st);
+  rc = W ? dev_alloc(ctx, p->frame, (size_t)p->cam.W * p->cam.H * 3 * sizeof(float)) : SG_E_NOMEM;
   if (rc == SG_OK)
-    rc = full_render(ctx, p->scene, nobox, p->cam, p->ras, p->r0, p->r1, p->r2, p->depth, p->rect, p->tile_cnt,
+    rc = full_render(ctx, W, p->scene, nobox, p->cam, p->ras, p->r0, p->r1, p->r2, p->depth, p->rect, p->tile_cnt,
                      p->tile_start, p->keys, P<float>(p->frame), nullptr, nullptr, st, &p->n_inst);
   if (rc != SG_OK) {
     sg_prep_destroy(p);
@@ -532,9 +570,7 @@ void sg_prep_destroy(sg_prep* p) {
   if (!p) return;
   sg_ctx* c = p->ctx;
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&p->r0, &p->r1, &p->r2, &p->depth, &p->rect, &p->tile_cnt, &p->tile_start, &p->keys, &p->frame,
-                    &p->vs, &p->ovr, &p->bitmap, &p->item_off, &p->n_items_v, &p->n_items_total, &p->items,
-                    &p->parts, &p->counter, &p->sites, &p->vars, &p->metrics};
+  DevBuf* bufs[] = {&p->r0, &p->r1, &p->r2, &p->depth, &p->rect, &p->tile_cnt, &p->tile_start, &p->keys, &p->frame};
   for (DevBuf* b : bufs) dev_free(c, *b);
   delete p;
 }
@@ -578,53 +614,52 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
   }
   if (B == 0) return SG_OK;
   hipStream_t st = S(stream);
+  WS_OR_FAIL(W, ctx, st);
   const DevRaster& ras = prep->ras;
   const int64_t frame_floats = (int64_t)prep->cam.W * prep->cam.H * 3;
 
   // incremental pipeline over all B (variants needing the full path get no items)
   if ((int)full_idx.size() < B) {
-    if (B > prep->batch_cap) {
-      SG_TRY(dev_alloc(ctx, prep->vs, (size_t)B * sizeof(VariantState)));
-      SG_TRY(dev_alloc(ctx, prep->ovr, (size_t)B * kMaxTouch * sizeof(Rec)));
-      SG_TRY(dev_alloc(ctx, prep->bitmap, (size_t)B * prep->bm_words * sizeof(uint64_t)));
-      SG_TRY(dev_alloc(ctx, prep->item_off, (size_t)B * sizeof(uint32_t)));
-      SG_TRY(dev_alloc(ctx, prep->n_items_v, (size_t)B * sizeof(uint32_t)));
-      SG_TRY(dev_alloc(ctx, prep->n_items_total, 16));
-      SG_TRY(dev_alloc(ctx, prep->counter, 16));
-      SG_TRY(dev_alloc(ctx, prep->items, (size_t)B * ras.n_tiles * sizeof(uint2)));
-      SG_TRY(dev_alloc(ctx, prep->parts, (size_t)B * ras.n_tiles * sizeof(Partial)));
-      SG_TRY(dev_alloc(ctx, prep->vars, (size_t)B * sizeof(sg_variant)));
-      prep->batch_cap = B;
-    }
-    SG_TRY(stage_sites(ctx, sites, n_sites, prep->sites, st));
-    HIP_TRY(hipMemcpyAsync(prep->vars.p, variants, (size_t)B * sizeof(sg_variant), hipMemcpyHostToDevice, st));
+    SG_TRY(dev_alloc(ctx, W->vs, (size_t)B * sizeof(VariantState)));
+    SG_TRY(dev_alloc(ctx, W->ovr, (size_t)B * kMaxTouch * sizeof(Rec)));
+    SG_TRY(dev_alloc(ctx, W->bitmap, (size_t)B * prep->bm_words * sizeof(uint64_t)));
+    SG_TRY(dev_alloc(ctx, W->item_off, (size_t)B * sizeof(uint32_t)));
+    SG_TRY(dev_alloc(ctx, W->n_items_v, (size_t)B * sizeof(uint32_t)));
+    SG_TRY(dev_alloc(ctx, W->n_items_total, 16));
+    SG_TRY(dev_alloc(ctx, W->counter, 16));
+    SG_TRY(dev_alloc(ctx, W->items, (size_t)B * ras.n_tiles * sizeof(uint2)));
+    SG_TRY(dev_alloc(ctx, W->bparts, (size_t)B * ras.n_tiles * sizeof(Partial)));
+    SG_TRY(dev_alloc(ctx, W->vars, (size_t)B * sizeof(sg_variant)));
+    SG_TRY(stage_sites(ctx, sites, n_sites, W->bsites, st));
+    HIP_TRY(hipMemcpyAsync(W->vars.p, variants, (size_t)B * sizeof(sg_variant), hipMemcpyHostToDevice, st));
     if (images_out)
       for (int v = 0; v < B; ++v)
         HIP_TRY(hipMemcpyAsync(images_out + v * frame_floats, prep->frame.p, frame_floats * sizeof(float),
                                hipMemcpyDeviceToDevice, st));
-    BatchBuffers bb{P<sg_site>(prep->sites), P<sg_variant>(prep->vars), B, P<VariantState>(prep->vs), P<Rec>(prep->ovr),
-                    P<uint64_t>(prep->bitmap), prep->bm_words, prep->row_words, P<uint32_t>(prep->item_off),
-                    P<uint32_t>(prep->n_items_v), P<uint32_t>(prep->n_items_total), P<uint2>(prep->items)};
+    BatchBuffers bb{P<sg_site>(W->bsites), P<sg_variant>(W->vars), B, P<VariantState>(W->vs), P<Rec>(W->ovr),
+                    P<uint64_t>(W->bitmap), prep->bm_words, prep->row_words, P<uint32_t>(W->item_off),
+                    P<uint32_t>(W->n_items_v), P<uint32_t>(W->n_items_total), P<uint2>(W->items)};
     {
       PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
       launch_variant_prep(s, b, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
                           P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
-      launch_plan(bb, ras.tiles_x, P<uint32_t>(prep->counter), st);
+      launch_plan(bb, ras.tiles_x, P<uint32_t>(W->counter), st);
     }
     CompArgs ca{P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2), P<uint32_t>(prep->tile_start),
                 P<uint32_t>(prep->tile_cnt), P<uint64_t>(prep->keys), P<float>(prep->frame), images_out,
-                P<Partial>(prep->parts), ras, prep->cam.W, prep->cam.H};
-    const int per_cu = ras.tile == 32 ? 2 : (ras.tile == 16 ? 8 : 16);
-    ItemArgs it{P<VariantState>(prep->vs), P<Rec>(prep->ovr), P<uint2>(prep->items), P<uint32_t>(prep->n_items_total),
-                P<uint32_t>(prep->counter), frame_floats, ctx->n_cu * per_cu};
+                P<Partial>(W->bparts), ras, prep->cam.W, prep->cam.H};
+    const int per_cu = ctx->persistent_wgs_per_cu > 0 ? ctx->persistent_wgs_per_cu
+                                                      : (ras.tile == 32 ? 2 : (ras.tile == 16 ? 8 : 16));
+    ItemArgs it{P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint2>(W->items), P<uint32_t>(W->n_items_total),
+                P<uint32_t>(W->counter), frame_floats, ctx->n_cu * per_cu};
     {
       PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st);
       launch_composite_items(ca, it, st);
     }
     {
       PassScope ps(ctx, SG_PASS_REDUCE, st);
-      launch_reduce_metrics(P<Partial>(prep->parts), P<uint32_t>(prep->item_off), P<uint32_t>(prep->n_items_v), 0,
-                            P<VariantState>(prep->vs), nullptr, nullptr, (uint32_t)(prep->cam.W * prep->cam.H),
+      launch_reduce_metrics(P<Partial>(W->bparts), P<uint32_t>(W->item_off), P<uint32_t>(W->n_items_v), 0,
+                            P<VariantState>(W->vs), nullptr, nullptr, (uint32_t)(prep->cam.W * prep->cam.H),
                             metrics_out, B, 0u, st);
     }
     SG_TRY(check_last("sg_render_batch incremental"));
@@ -640,23 +675,23 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
       off[f] = (int64_t)total_bytes;
       total_bytes += (size_t)((field_extent(s, f) * wb + 255) / 256 * 256);
     }
-    SG_TRY(dev_alloc(ctx, ctx->work_scene, total_bytes));
-    SG_TRY(dev_alloc(ctx, ctx->parts, (size_t)ras.n_tiles * sizeof(Partial)));
-    for (int f = 0; f < 6; ++f) w.ptr[f] = P<char>(ctx->work_scene) + off[f];
+    SG_TRY(dev_alloc(ctx, W->work_scene, total_bytes));
+    SG_TRY(dev_alloc(ctx, W->parts, (size_t)ras.n_tiles * sizeof(Partial)));
+    for (int f = 0; f < 6; ++f) w.ptr[f] = P<char>(W->work_scene) + off[f];
     for (int v : full_idx) {
       for (int f = 0; f < 6; ++f)
         if (s.ncomp[f])
           HIP_TRY(hipMemcpyAsync(const_cast<void*>(w.ptr[f]), s.ptr[f], field_extent(s, f) * wb, hipMemcpyDeviceToDevice, st));
       const sg_variant& x = variants[v];
-      SG_TRY(stage_sites(ctx, sites + x.site_off, (int)x.n_sites, ctx->sites_dev, st));
-      launch_inject(w, P<sg_site>(ctx->sites_dev), (int)x.n_sites, nullptr, st);
+      SG_TRY(stage_sites(ctx, sites + x.site_off, (int)x.n_sites, W->sites_dev, st));
+      launch_inject(w, P<sg_site>(W->sites_dev), (int)x.n_sites, nullptr, st);
       DevBox bx = b;
       if (!x.guard) bx.mask = 0;
-      SG_TRY(full_render(ctx, w, bx, prep->cam, ras, ctx->r0, ctx->r1, ctx->r2, ctx->depth, ctx->rect, ctx->tile_cnt,
-                         ctx->tile_start, ctx->keys, images_out ? images_out + v * frame_floats : nullptr,
-                         P<float>(prep->frame), P<Partial>(ctx->parts), st, nullptr));
-      launch_reduce_metrics(P<Partial>(ctx->parts), nullptr, nullptr, (uint32_t)ras.n_tiles, nullptr,
-                            P<uint32_t>(ctx->flags), P<unsigned long long>(ctx->clamps),
+      SG_TRY(full_render(ctx, W, w, bx, prep->cam, ras, W->r0, W->r1, W->r2, W->depth, W->rect, W->tile_cnt,
+                         W->tile_start, W->keys, images_out ? images_out + v * frame_floats : nullptr,
+                         P<float>(prep->frame), P<Partial>(W->parts), st, nullptr));
+      launch_reduce_metrics(P<Partial>(W->parts), nullptr, nullptr, (uint32_t)ras.n_tiles, nullptr,
+                            P<uint32_t>(W->flags), P<unsigned long long>(W->clamps),
                             (uint32_t)(prep->cam.W * prep->cam.H), metrics_out + v, 1, 1u, st);
       SG_TRY(check_last("sg_render_batch full"));
     }
@@ -670,10 +705,11 @@ sg_status sg_metrics(sg_ctx* ctx, const float* images, const float* clean, int32
   if (B < 1 || K < 1 || H < 1 || W < 1) return fail(SG_E_INVAL, "sizes must be >= 1");
   const int64_t px = (int64_t)K * H * W;
   const int nchunks = (int)std::min<int64_t>(256, (px + 1023) / 1024);
-  SG_TRY(dev_alloc(ctx, ctx->metrics_tmp, (size_t)B * nchunks * sizeof(Partial)));
   hipStream_t st = S(stream);
-  launch_metrics_partials(images, clean, px, nchunks, B, P<Partial>(ctx->metrics_tmp), st);
-  launch_reduce_metrics(P<Partial>(ctx->metrics_tmp), nullptr, nullptr, (uint32_t)nchunks, nullptr, nullptr, nullptr,
+  WS_OR_FAIL(WS, ctx, st);
+  SG_TRY(dev_alloc(ctx, WS->metrics_tmp, (size_t)B * nchunks * sizeof(Partial)));
+  launch_metrics_partials(images, clean, px, nchunks, B, P<Partial>(WS->metrics_tmp), st);
+  launch_reduce_metrics(P<Partial>(WS->metrics_tmp), nullptr, nullptr, (uint32_t)nchunks, nullptr, nullptr, nullptr,
                         (uint32_t)px, out, B, 1u, st);
   return check_last("sg_metrics");
 }
