@@ -240,6 +240,12 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
  * other streams to run concurrently; this is one of the tuned parameters. */
 sg_status sg_ctx_set_persistent(sg_ctx* ctx, int32_t wgs_per_cu);
 
+/* Replay the incremental part of sg_render_batch as a captured HIP graph
+ * (default on).  A graph is used when every variant is incremental, no
+ * images are requested, timing is off and the stream is not the null stream;
+ * one graph is kept per batch shape and buffer set. */
+sg_status sg_ctx_set_graphs(sg_ctx* ctx, int32_t enable);
+
 /* Work issued on different HIP streams uses different workspaces of the
  * context, so batches on different streams may overlap on the device (the
  * host calls themselves stay single-threaded). */

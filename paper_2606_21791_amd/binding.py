@@ -86,6 +86,7 @@ def _load():
         "sg_metrics": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
         "sg_ctx_timing": (i32, [vp, i32]),
         "sg_ctx_set_persistent": (i32, [vp, i32]),
+        "sg_ctx_set_graphs": (i32, [vp, i32]),
         "sg_ctx_pass_times": (i32, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -99,7 +100,7 @@ LIB = _load()
 EXPORTED = ("sg_ctx_create", "sg_ctx_destroy", "sg_last_error", "sg_ctx_bytes", "sg_cast", "sg_inject",
             "sg_restore", "sg_guard_box", "sg_guard", "sg_render", "sg_prepare", "sg_prep_destroy",
             "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_metrics",
-            "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent")
+            "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_graphs")
 
 
 def check(code):
@@ -171,6 +172,9 @@ class Context:
 
     def set_persistent(self, wgs_per_cu: int):
         check(LIB.sg_ctx_set_persistent(self.h, int(wgs_per_cu)))
+
+    def set_graphs(self, enable: bool):
+        check(LIB.sg_ctx_set_graphs(self.h, 1 if enable else 0))
 
     def timing(self, enable: bool):
         check(LIB.sg_ctx_timing(self.h, 1 if enable else 0))

@@ -59,8 +59,22 @@ struct Workspace {
   DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
       big_prims, big_tiles, parts, work_scene, sites_dev, box_keys, metrics_tmp;
   // batches of variants
-  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, bsites, vars;
+  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, bsites, vars, gmetrics;
   unsigned long long* h_total = nullptr;   // pinned
+  // pinned staging ring for a batch's sites and variants; slot k may be
+  // rewritten once the copies of its previous use (event) have completed
+  static constexpr int kRing = 2;
+  sg_site* h_sites[kRing] = {nullptr, nullptr};
+  sg_variant* h_vars[kRing] = {nullptr, nullptr};
+  size_t h_sites_cap = 0, h_vars_cap = 0;
+  hipEvent_t staged[kRing] = {nullptr, nullptr};
+  int ring = 0;
+  // captured incremental batches: one executable graph per shape and buffer set
+  struct Graph {
+    std::vector<uintptr_t> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
 };
 
 struct sg_ctx {
@@ -69,6 +83,7 @@ struct sg_ctx {
   size_t in_use = 0;
   int n_cu = 256;
   int persistent_wgs_per_cu = 0;           // 0: default of the tile size
+  bool use_graphs = true;
   std::vector<Workspace*> ws;
   // per-pass event timing (sg_ctx_timing)
   bool timing = false;
@@ -136,15 +151,54 @@ void free_workspace(sg_ctx* ctx, Workspace* w) {
                     &w->tile_start, &w->cursor, &w->total, &w->keys, &w->keys_tmp, &w->big_prims, &w->big_tiles,
                     &w->parts, &w->work_scene, &w->sites_dev, &w->box_keys, &w->metrics_tmp, &w->vs, &w->ovr,
                     &w->bitmap, &w->item_off, &w->n_items_v, &w->n_items_total, &w->items, &w->bparts,
-                    &w->counter, &w->bsites, &w->vars};
+                    &w->counter, &w->bsites, &w->vars, &w->gmetrics};
+  for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);
+  w->graphs.clear();
   for (DevBuf* b : bufs) dev_free(ctx, *b);
   if (w->h_total) (void)hipHostFree(w->h_total);
+  for (int k = 0; k < Workspace::kRing; ++k) {
+    if (w->h_sites[k]) (void)hipHostFree(w->h_sites[k]);
+    if (w->h_vars[k]) (void)hipHostFree(w->h_vars[k]);
+    if (w->staged[k]) (void)hipEventDestroy(w->staged[k]);
+  }
   delete w;
 }
 
 #define WS_OR_FAIL(W, ctx, st)                                            \
   Workspace* W = workspace(ctx, st);                                      \
   if (!W) return fail(SG_E_NOMEM, "pinned allocation for a workspace failed")
+
+// Copy a batch's sites and variants into the next slot of the workspace's
+// pinned ring (waiting for that slot's previous copies), returning the slot.
+sg_status stage_batch(Workspace* w, const sg_site* sites, int n_sites, size_t site_cap, const sg_variant* vars, int B,
+                      int* slot) {
+  const int k = w->ring;
+  w->ring = (w->ring + 1) % Workspace::kRing;
+  if (site_cap > w->h_sites_cap || (size_t)B > w->h_vars_cap) {
+    for (int j = 0; j < Workspace::kRing; ++j) {
+      if (w->staged[j]) HIP_TRY(hipEventSynchronize(w->staged[j]));
+      if (w->h_sites[j]) (void)hipHostFree(w->h_sites[j]);
+      if (w->h_vars[j]) (void)hipHostFree(w->h_vars[j]);
+      w->h_sites[j] = nullptr;
+      w->h_vars[j] = nullptr;
+    }
+    const size_t sc = std::max(site_cap, w->h_sites_cap), vc = std::max((size_t)B, w->h_vars_cap);
+    for (int j = 0; j < Workspace::kRing; ++j) {
+      HIP_TRY(hipHostMalloc((void**)&w->h_sites[j], sc * sizeof(sg_site), hipHostMallocDefault));
+      HIP_TRY(hipHostMalloc((void**)&w->h_vars[j], vc * sizeof(sg_variant), hipHostMallocDefault));
+    }
+    w->h_sites_cap = sc;
+    w->h_vars_cap = vc;
+    for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);   // their sources moved
+    w->graphs.clear();
+  }
+  if (!w->staged[k]) HIP_TRY(hipEventCreateWithFlags(&w->staged[k], hipEventDisableTiming));
+  else HIP_TRY(hipEventSynchronize(w->staged[k]));
+  if (n_sites) std::memcpy(w->h_sites[k], sites, (size_t)n_sites * sizeof(sg_site));
+  std::memcpy(w->h_vars[k], vars, (size_t)B * sizeof(sg_variant));
+  *slot = k;
+  return SG_OK;
+}
 
 // Records HIP events around the launches of one pass while timing is on.
 struct PassScope {
@@ -411,6 +465,12 @@ sg_status sg_ctx_set_persistent(sg_ctx* c, int32_t wgs_per_cu) {
   return SG_OK;
 }
 
+sg_status sg_ctx_set_graphs(sg_ctx* c, int32_t enable) {
+  if (!c) return fail(SG_E_INVAL, "ctx is NULL");
+  c->use_graphs = enable != 0;
+  return SG_OK;
+}
+
 sg_status sg_ctx_timing(sg_ctx* c, int32_t enable) {
   if (!c) return fail(SG_E_INVAL, "ctx is NULL");
   c->timing = enable != 0;
@@ -620,6 +680,7 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
 
   // incremental pipeline over all B (variants needing the full path get no items)
   if ((int)full_idx.size() < B) {
+    const size_t site_cap = std::max<size_t>((size_t)n_sites, std::max<size_t>(64, (size_t)4 * B));
     SG_TRY(dev_alloc(ctx, W->vs, (size_t)B * sizeof(VariantState)));
     SG_TRY(dev_alloc(ctx, W->ovr, (size_t)B * kMaxTouch * sizeof(Rec)));
     SG_TRY(dev_alloc(ctx, W->bitmap, (size_t)B * prep->bm_words * sizeof(uint64_t)));
@@ -630,37 +691,82 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
     SG_TRY(dev_alloc(ctx, W->items, (size_t)B * ras.n_tiles * sizeof(uint2)));
     SG_TRY(dev_alloc(ctx, W->bparts, (size_t)B * ras.n_tiles * sizeof(Partial)));
     SG_TRY(dev_alloc(ctx, W->vars, (size_t)B * sizeof(sg_variant)));
-    SG_TRY(stage_sites(ctx, sites, n_sites, W->bsites, st));
-    HIP_TRY(hipMemcpyAsync(W->vars.p, variants, (size_t)B * sizeof(sg_variant), hipMemcpyHostToDevice, st));
-    if (images_out)
-      for (int v = 0; v < B; ++v)
-        HIP_TRY(hipMemcpyAsync(images_out + v * frame_floats, prep->frame.p, frame_floats * sizeof(float),
-                               hipMemcpyDeviceToDevice, st));
-    BatchBuffers bb{P<sg_site>(W->bsites), P<sg_variant>(W->vars), B, P<VariantState>(W->vs), P<Rec>(W->ovr),
-                    P<uint64_t>(W->bitmap), prep->bm_words, prep->row_words, P<uint32_t>(W->item_off),
-                    P<uint32_t>(W->n_items_v), P<uint32_t>(W->n_items_total), P<uint2>(W->items)};
-    {
-      PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
-      launch_variant_prep(s, b, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
-                          P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
-      launch_plan(bb, ras.tiles_x, P<uint32_t>(W->counter), st);
-    }
-    CompArgs ca{P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2), P<uint32_t>(prep->tile_start),
-                P<uint32_t>(prep->tile_cnt), P<uint64_t>(prep->keys), P<float>(prep->frame), images_out,
-                P<Partial>(W->bparts), ras, prep->cam.W, prep->cam.H};
+    SG_TRY(dev_alloc(ctx, W->bsites, site_cap * sizeof(sg_site)));
+    SG_TRY(dev_alloc(ctx, W->gmetrics, (size_t)B * sizeof(sg_metrics_t)));
+    int slot = 0;
+    SG_TRY(stage_batch(W, sites, n_sites, site_cap, variants, B, &slot));
     const int per_cu = ctx->persistent_wgs_per_cu > 0 ? ctx->persistent_wgs_per_cu
                                                       : (ras.tile == 32 ? 2 : (ras.tile == 16 ? 8 : 16));
-    ItemArgs it{P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint2>(W->items), P<uint32_t>(W->n_items_total),
-                P<uint32_t>(W->counter), frame_floats, ctx->n_cu * per_cu};
-    {
-      PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st);
-      launch_composite_items(ca, it, st);
-    }
-    {
-      PassScope ps(ctx, SG_PASS_REDUCE, st);
-      launch_reduce_metrics(P<Partial>(W->bparts), P<uint32_t>(W->item_off), P<uint32_t>(W->n_items_v), 0,
-                            P<VariantState>(W->vs), nullptr, nullptr, (uint32_t)(prep->cam.W * prep->cam.H),
-                            metrics_out, B, 0u, st);
+    // a graph is replayed when every variant is incremental, no images are
+    // requested and timing is off; it writes its metrics to the workspace
+    const bool graph = ctx->use_graphs && !ctx->timing && full_idx.empty() && !images_out && st != nullptr;
+    sg_metrics_t* mout = graph ? P<sg_metrics_t>(W->gmetrics) : metrics_out;
+    auto enqueue = [&]() -> sg_status {
+      HIP_TRY(hipMemcpyAsync(W->bsites.p, W->h_sites[slot], site_cap * sizeof(sg_site), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(W->vars.p, W->h_vars[slot], (size_t)B * sizeof(sg_variant), hipMemcpyHostToDevice, st));
+      if (images_out)
+        for (int v = 0; v < B; ++v)
+          HIP_TRY(hipMemcpyAsync(images_out + v * frame_floats, prep->frame.p, frame_floats * sizeof(float),
+                                 hipMemcpyDeviceToDevice, st));
+      BatchBuffers bb{P<sg_site>(W->bsites), P<sg_variant>(W->vars), B, P<VariantState>(W->vs), P<Rec>(W->ovr),
+                      P<uint64_t>(W->bitmap), prep->bm_words, prep->row_words, P<uint32_t>(W->item_off),
+                      P<uint32_t>(W->n_items_v), P<uint32_t>(W->n_items_total), P<uint2>(W->items)};
+      {
+        PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
+        launch_variant_prep(s, b, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
+                            P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
+        launch_plan(bb, ras.tiles_x, P<uint32_t>(W->counter), st);
+      }
+      CompArgs ca{P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2), P<uint32_t>(prep->tile_start),
+                  P<uint32_t>(prep->tile_cnt), P<uint64_t>(prep->keys), P<float>(prep->frame), images_out,
+                  P<Partial>(W->bparts), ras, prep->cam.W, prep->cam.H};
+      ItemArgs it{P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint2>(W->items), P<uint32_t>(W->n_items_total),
+                  P<uint32_t>(W->counter), frame_floats, ctx->n_cu * per_cu};
+      {
+        PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st);
+        launch_composite_items(ca, it, st);
+      }
+      {
+        PassScope ps(ctx, SG_PASS_REDUCE, st);
+        launch_reduce_metrics(P<Partial>(W->bparts), P<uint32_t>(W->item_off), P<uint32_t>(W->n_items_v), 0,
+                              P<VariantState>(W->vs), nullptr, nullptr, (uint32_t)(prep->cam.W * prep->cam.H), mout,
+                              B, 0u, st);
+      }
+      return SG_OK;
+    };
+    if (graph) {
+      std::vector<uintptr_t> key = {(uintptr_t)prep, (uintptr_t)B, site_cap, (uintptr_t)slot, (uintptr_t)per_cu,
+                                    (uintptr_t)b.mask, (uintptr_t)b.mode, (uintptr_t)W->vs.p, (uintptr_t)W->ovr.p,
+                                    (uintptr_t)W->bitmap.p, (uintptr_t)W->items.p, (uintptr_t)W->bparts.p,
+                                    (uintptr_t)W->bsites.p, (uintptr_t)W->vars.p, (uintptr_t)W->gmetrics.p,
+                                    (uintptr_t)W->counter.p, (uintptr_t)W->item_off.p, (uintptr_t)W->n_items_v.p,
+                                    (uintptr_t)W->n_items_total.p};
+      for (int f = 0; f < 6; ++f) { key.push_back((uintptr_t)b.lo[f]); key.push_back((uintptr_t)b.hi[f]); }
+      hipGraphExec_t exec = nullptr;
+      for (auto& g : W->graphs)
+        if (g.key == key) exec = g.exec;
+      if (!exec) {
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        sg_status rc = enqueue();
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &gr);
+        if (rc != SG_OK) { if (gr) (void)hipGraphDestroy(gr); return rc; }
+        if (e != hipSuccess) return fail(SG_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) return fail(SG_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        if (W->graphs.size() >= 16) {
+          (void)hipGraphExecDestroy(W->graphs.front().exec);
+          W->graphs.erase(W->graphs.begin());
+        }
+        W->graphs.push_back({key, exec});
+      }
+      HIP_TRY(hipGraphLaunch(exec, st));
+      HIP_TRY(hipEventRecord(W->staged[slot], st));
+      HIP_TRY(hipMemcpyAsync(metrics_out, W->gmetrics.p, (size_t)B * sizeof(sg_metrics_t), hipMemcpyDeviceToDevice, st));
+    } else {
+      SG_TRY(enqueue());
+      HIP_TRY(hipEventRecord(W->staged[slot], st));
     }
     SG_TRY(check_last("sg_render_batch incremental"));
   }

@@ -216,3 +216,36 @@ def test_w2_hi_sampled_pixels(ctx, fmt):
         refv = orender.render_pixels(prv, cam, xs, ys)
         err = np.abs(imgs[j][ys, xs] - refv).max(axis=1)
         assert np.mean(err <= PIXEL_TOL) >= 0.98, (k, np.sort(err)[-5:])
+
+
+def test_graph_replay_matches_eager(ctx):
+    """The captured incremental batch, replayed several times with eager work
+    and synchronisations in between, gives exactly the eager records."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(6741, seed=3, sh_degree=3)
+    cam = synth.make_camera(200, 160)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam)
+    sites = synth.make_sites_stratified(sc.n, 3, 64, seed=21, width_bits=32)
+    B = 32
+    st = torch.cuda.Stream()
+    va = b.variants_array(np.arange(B), np.ones(B, np.uint32))
+    eager, graphed = [], []
+    for rep in range(4):
+        idx = (np.arange(B) + rep * B) % len(sites)
+        sa = b.sites_array(sites.field[idx], sites.comp[idx], sites.prim[idx], sites.bit[idx])
+        for use_graph, out in ((False, eager), (True, graphed)):
+            ctx.set_graphs(use_graph)
+            mt = b.metrics_tensor(B)
+            with torch.cuda.stream(st):
+                ctx.render_batch(prep, sa, va, metrics=mt)
+            st.synchronize()
+            out.append(b.read_metrics(mt))
+            # eager work of the program between replays
+            _ = (torch.ones(1000, device="cuda") * 2).sum().item()
+    ctx.set_graphs(True)
+    for e, g in zip(eager, graphed):
+        for key in ("sse", "changed_px", "max_abs", "nonfinite", "dirty_tiles", "evals"):
+            assert np.array_equal(e[key], g[key]), key
+    assert not all(np.array_equal(eager[0]["sse"], e["sse"]) for e in eager[1:])   # the batches differ
