@@ -93,10 +93,19 @@ def main():
     ap.add_argument("--plain", type=int, default=100, help="injections timed on the plain path")
     ap.add_argument("--cpu-inj", type=int, default=1, help="oracle injections timed on the host (0: skip)")
     ap.add_argument("--no-graphs", action="store_true", help="launch each batch eagerly instead of replaying a graph")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="seconds of Poisson arrivals for the serving measurement (0: skip)")
+    ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve"],
+                    help="w2: the headline; guard: support guard and accumulated dose on the N=134,826 scene; "
+                         "large: the 2,056,645-primitive bf16 scene at 1600x900; stress: one guarded render at "
+                         "65,812,640 primitives")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every run here uses a single MI355X (--gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "w2":
+        {"guard": run_guard, "large": run_large, "stress": run_stress, "serve": run_serve}[args.workload](args)
+        return
 
     import torch
     from paper_2606_21791_amd import binding as sgb
@@ -216,8 +225,327 @@ def main():
                      "evals_per_launch": round(evals_per_launch), "flops_per_eval": FLOPS_PER_EVAL},
         "paper_context": PAPER_CONTEXT,
     }
+    if args.serve_seconds > 0:
+        del prep, ds
+        torch.cuda.synchronize()
+        out["serving"] = serve_workload(args.serve_seconds)
     if args.cpu_inj > 0:
         out["cpu_baseline"] = cpu_baseline(sc, cam, sites, args.fmt, args.cpu_inj)
+    print(json.dumps(out), flush=True)
+
+
+def _batched_rate(ctx, prep, sites, B, streams, steps, warmup, guard=0, box=None):
+    """Batched incremental injections/s over `steps` batches (after `warmup`)
+    and the concatenated per-variant records."""
+    import torch
+    from paper_2606_21791_amd import binding as sgb
+    n = len(sites)
+    total = warmup + steps
+    batches = []
+    for i in range(total):
+        idx = (np.arange(B) + i * B) % n
+        batches.append(sgb.sites_array(sites.field[idx], sites.comp[idx], sites.prim[idx], sites.bit[idx]))
+    va = sgb.variants_array(np.arange(B), np.ones(B, np.uint32), guard)
+    mts = [sgb.metrics_tensor(B) for _ in range(total)]
+
+    def run(i):
+        with torch.cuda.stream(streams[i % len(streams)]):
+            ctx.render_batch(prep, batches[i], va, box=box, metrics=mts[i])
+
+    for i in range(warmup):
+        run(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(warmup, total):
+        run(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    recs = np.concatenate([sgb.read_metrics(m) for m in mts[warmup:]])
+    return steps * B / dt, recs
+
+
+def _summ(recs):
+    ps = recs["psnr"][np.isfinite(recs["psnr"])]
+    return {"mean_psnr_db": round(float(ps.mean()), 3) if ps.size else None,
+            "worst_footprint": round(float(recs["footprint"].max()), 5),
+            "mean_footprint": round(float(recs["footprint"].mean()), 6),
+            "catastrophic_fraction": round(float(recs["catastrophic"].mean()), 5),
+            "nonfinite": int(recs["nonfinite"].sum()), "clamps": int(recs["clamps"].sum())}
+
+
+def run_guard(args):
+    """Support guard on the N=134,826 scene (fp32, 800x800) with a
+    per-primitive box: guard cost per frame (scrub pass and clamp-on-load),
+    guarded vs unguarded single flips, and accumulated-dose frames."""
+    import torch
+    from paper_2606_21791_amd import binding as sgb, synth
+    sc, cam, sites = _workload("f32")
+    ctx = sgb.Context(0)
+    ctx.set_persistent(args.wgs_per_cu)
+    streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
+    lo32, hi32 = synth.make_box_jitter(sc, seed=4)
+    ds = sgb.DeviceScene.upload(ctx, sc, "f32")
+    box = sgb.Box.per_prim(ctx, lo32, hi32, "f32")
+    prep = ctx.prepare(ds, cam)
+    torch.cuda.synchronize()
+    out = {"metric": "support guard: cost per frame, guarded vs unguarded injections, accumulated dose",
+           "config": {"workload": "N=134,826 Gaussians, SH degree 3, fp32, 800x800, per-primitive box "
+                                  "(value -/+ |N(0,0.2)|, rounded outward)", "B": args.batch}}
+    # guard cost: the scrub pass over the resident scene (identity on the clean scene)
+    work = ds.clone()
+    for _ in range(3):
+        ctx.guard(work, box)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.pass_times()
+    reps = 50
+    for _ in range(reps):
+        ctx.guard(work, box)
+    torch.cuda.synchronize()
+    g_ms = ctx.pass_times()["guard"][0] / reps
+    # clamp-on-load: the projection pass with and without the box
+    frame = prep.frame()
+    proj = {}
+    for name, bx in (("without", None), ("with", box)):
+        ctx.pass_times()
+        for _ in range(20):
+            ctx.render(ds, cam, box=bx)
+        torch.cuda.synchronize()
+        proj[name] = ctx.pass_times()["project"][0] / 20
+    ctx.timing(False)
+    n = sc.n
+    guarded_bytes = n * 14 * 4 * 3            # value + lo + hi words read per frame
+    out["guard_cost"] = {"scrub_us_per_frame": round(g_ms * 1e3, 2),
+                         "scrub_read_GB_s": round(guarded_bytes / (g_ms * 1e-3) / 1e9, 1),
+                         "clamp_on_load_extra_us": round((proj["with"] - proj["without"]) * 1e3, 2),
+                         "projection_us_without_guard": round(proj["without"] * 1e3, 2)}
+    # single flips, unguarded and guarded
+    for guard in (0, 1):
+        rate, recs = _batched_rate(ctx, prep, sites, args.batch, streams, args.steps, args.warmup, guard, box)
+        out["guarded" if guard else "unguarded"] = {"inj_per_s": round(rate, 1), **_summ(recs)}
+    # accumulated dose: k simultaneous flips over all stored bits, 16 frames each
+    dose = {}
+    mt = sgb.metrics_tensor(1)
+    for k, seed0 in ((1000, 31), (20000, 47)):
+        for guard in (0, 1):
+            recs, t = [], 0.0
+            for f in range(16):
+                s = synth.make_sites_dose(n, 3, k, seed=seed0 + f, width_bits=32)
+                sa = sgb.sites_array(s.field, s.comp, s.prim, s.bit)
+                va = sgb.variants_array([0], [k], guard)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.render_batch(prep, sa, va, box=box, metrics=mt)
+                recs.append(sgb.read_metrics(mt)[0])
+                t += time.perf_counter() - t0
+            recs = np.array(recs)
+            dose[f"k{k}_{'guarded' if guard else 'unguarded'}"] = {"ms_per_frame": round(t / 16 * 1e3, 3), **_summ(recs)}
+    out["dose"] = dose
+    print(json.dumps(out), flush=True)
+
+
+def _large_scene():
+    from paper_2606_21791_amd import synth
+    sc = synth.make_scene(2_056_645, seed=5, sh_degree=3, means="clusters")
+    cam = synth.make_camera(1600, 900, distance=25.0)
+    sites = synth.make_sites_stratified(sc.n, 3, 1024, seed=15, width_bits=16)
+    order = np.random.default_rng(98).permutation(len(sites))
+    return sc, cam, sites.take(order)
+
+
+def run_large(args):
+    """The 2,056,645-primitive clustered scene (bf16, SH degree 3, 1600x900):
+    batched incremental injections vs the plain path."""
+    import torch
+    from paper_2606_21791_amd import binding as sgb
+    sc, cam, sites = _large_scene()
+    ctx = sgb.Context(0)
+    ctx.set_persistent(args.wgs_per_cu)
+    streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
+    ds = sgb.DeviceScene.upload(ctx, sc, "bf16")
+    del sc
+    t0 = time.perf_counter()
+    prep = ctx.prepare(ds, cam)
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    rate, recs = _batched_rate(ctx, prep, sites, args.batch, streams, args.steps, args.warmup)
+    frame = prep.frame()
+    mt1 = sgb.metrics_tensor(1)
+    P = max(5, args.plain // 4)
+    ctx.timing(True)
+    ctx.pass_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(P):
+        sa = sgb.sites_array(sites.field[k:k + 1], sites.comp[k:k + 1], sites.prim[k:k + 1], sites.bit[k:k + 1])
+        ctx.inject(ds, sa)
+        ctx.render(ds, cam, clean=frame, metrics=mt1)
+        ctx.restore(ds, sa)
+        sgb.read_metrics(mt1)
+    plain_dt = time.perf_counter() - t0
+    pp = ctx.pass_times()
+    ctx.timing(False)
+    out = {"metric": "injections/s, 2,056,645-primitive scene, 1600x900, batched vs plain",
+           "value": round(rate, 1), "unit": "injections/s",
+           "config": {"workload": "N=2,056,645 Gaussians in 64 anisotropic clusters, SH degree 3, bf16 storage, "
+                                  f"1600x900, B={args.batch}, 6 fields x 1,024 stratified sites",
+                      "streams": len(streams), "instances_clean": prep.instances(),
+                      "prepare_s": round(prep_s, 3)},
+           "plain": {"value": round(P / plain_dt, 1), "unit": "injections/s",
+                     "pass_ms_per_injection": {k: round(v[0] / P, 4) for k, v in pp.items() if v[1]}},
+           "speedup_vs_plain": round(rate / (P / plain_dt), 2),
+           "dirty_tiles_per_injection": round(float(recs["dirty_tiles"].mean()), 2), **_summ(recs)}
+    print(json.dumps(out), flush=True)
+
+
+def run_stress(args):
+    """One guarded render of 65,812,640 primitives (SH degree 0, fp32,
+    1600x900): the box is reduced once, then the guard scrub and the render
+    are timed separately, with the render's per-pass breakdown."""
+    import torch
+    from paper_2606_21791_amd import binding as sgb, synth
+    n = 32 * 2_056_645
+    t0 = time.perf_counter()
+    sc = synth.make_scene(n, seed=6, sh_degree=0, means="clusters")
+    gen_s = time.perf_counter() - t0
+    cam = synth.make_camera(1600, 900, distance=25.0)
+    ctx = sgb.Context(0)
+    ds = sgb.DeviceScene.upload(ctx, sc, "f32")
+    del sc
+    box = ctx.guard_box(ds)
+    img = torch.empty((900, 1600, 3), dtype=torch.float32, device="cuda")
+    ctx.render(ds, cam, image=img)            # warm-up and workspace sizing
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.pass_times()
+    reps = 3
+    for _ in range(reps):
+        cnt, _ = ctx.guard(ds, box)
+    torch.cuda.synchronize()
+    g = ctx.pass_times()["guard"][0] / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.render(ds, cam, image=img)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    pp = ctx.pass_times()
+    ctx.timing(False)
+    render_ms = sum(v[0] for v in pp.values()) / reps
+    out = {"metric": "guarded render at 65,812,640 primitives: guard and render time per frame",
+           "config": {"workload": "N=65,812,640 Gaussians (64 clusters), SH degree 0, fp32, 1600x900, "
+                                  "global box from the clean model", "generate_s": round(gen_s, 1)},
+           "guard_ms_per_frame": round(g, 3),
+           "guard_read_GB_s": round(n * 14 * 4 / (g * 1e-3) / 1e9, 1),
+           "guard_hbm_frac": round(n * 14 * 4 / (g * 1e-3) / 8e12, 4),
+           "render_ms_per_frame": round(render_ms, 3), "render_wall_ms": round(wall * 1e3, 3),
+           "guard_fraction_of_render": round(g / render_ms, 4),
+           "render_mpix_per_s": round(1600 * 900 / wall / 1e6, 2),
+           "pass_ms": {k: round(v[0] / reps, 3) for k, v in pp.items() if v[1]},
+           "clamps_clean": int(cnt[0]), "device_bytes": ctx.bytes(),
+           "paper_context": {"guard_ms": 9.66, "guard_fraction": 0.183, "hardware": "Blackwell-generation GPU"}}
+    print(json.dumps(out), flush=True)
+
+
+def serve_workload(seconds, rate=2000.0, plain_seconds=1.0, slots=8, include_large=True, seed=21):
+    """Poisson stream (mean `rate` requests/s) over resident scenes of
+    6,741 / 134,826 / 500,000 / 2,056,645 primitives in fp32, fp16 and bf16,
+    viewed at 256x256, 512x512, 800x800 and 1600x900; half the requests are
+    injection campaigns (32 sites in one random (field, bit) cell), half are
+    guarded renders with k in {0, 1, 1000} simultaneous flips.  The same
+    stream (its first `plain_seconds`) also runs through the plain FIFO path."""
+    import torch
+    from paper_2606_21791_amd import binding as sgb, synth
+    sizes = [(6741, 3, "uniform", 3.0), (134_826, 3, "uniform", 3.0), (500_000, 3, "uniform", 3.0)]
+    if include_large:
+        sizes.append((2_056_645, 3, "clusters", 25.0))
+    fmts = ["f32", "f16", "bf16"]
+    res = [(256, 256), (512, 512), (800, 800), (1600, 900)]
+    ctx = sgb.Context(0)
+    scenes = []          # (n, sh, fmt, dist, DeviceScene, Box)
+    for n, deg, dist, dist_z in sizes:
+        sc = synth.make_scene(n, seed=7 + n % 97, sh_degree=deg, means=dist)
+        for fmt in fmts:
+            ds = sgb.DeviceScene.upload(ctx, sc, fmt)
+            box = ctx.guard_box(ds)
+            scenes.append((n, deg, fmt, dist_z, ds, box))
+        del sc
+    torch.cuda.synchronize()
+
+    def build(server):
+        views = []
+        for n, deg, fmt, dz, ds, box in scenes:
+            sid = server.add_scene(ds, box)
+            for w, h in res:
+                views.append((server.add_view(sid, synth.make_camera(w, h, distance=dz)), n, deg, fmt))
+        return views
+
+    rng = np.random.default_rng(seed)
+    arrivals = synth.make_arrivals(rate, seconds, seed)
+    n_views = len(scenes) * len(res)
+    plan = []
+    for t in arrivals:
+        vi = int(rng.integers(0, n_views))
+        n, deg, fmt = scenes[vi // len(res)][:3]
+        W = 32 if fmt == "f32" else 16
+        if rng.random() < 0.5:
+            comps = synth.field_components(deg)
+            f = int(rng.integers(0, 6))
+            bit = int(rng.integers(0, W))
+            sites = sgb.sites_array(np.full(32, f), rng.integers(0, comps[f], 32), rng.integers(0, n, 32),
+                                    np.full(32, bit))
+            plan.append((t, sgb.SG_REQ_CAMPAIGN, vi, sites))
+        else:
+            k = int(rng.choice([0, 1, 1000]))
+            s = synth.make_sites_dose(n, deg, k, int(rng.integers(1 << 30)), width_bits=W)
+            plan.append((t, sgb.SG_REQ_GUARDED_RENDER, vi, sgb.sites_array(s.field, s.comp, s.prim, s.bit)))
+
+    def drive(server, views, horizon):
+        tickets = []
+        t0 = time.monotonic_ns()
+        for t, kind, vi, sites in plan:
+            if t > horizon:
+                break
+            due = t0 + int(t * 1e9)
+            while time.monotonic_ns() < due:
+                pass
+            tickets.append(server.submit(kind, views[vi][0], sites, arrival_ns=due))
+        for tk in tickets:
+            r, _ = server.wait(tk, 600)
+            assert r["status"] == 0, r
+        return server.stats()
+
+    srv = sgb.Server(0, budget=0, max_slots=slots, max_batch=64)
+    t0 = time.perf_counter()
+    views = build(srv)
+    setup_s = time.perf_counter() - t0
+    st = drive(srv, views, seconds)
+    srv.close()
+    out = {"requests": len(arrivals), "arrival_rate_per_s": rate, "seconds": seconds, "slots": slots,
+           "views": len(views), "setup_s": round(setup_s, 1),
+           "throughput_inj_per_s": round(st["inj_per_s"], 1), "req_per_s": round(st["req_per_s"], 1),
+           "p50_ms": {"campaign": round(st["campaign"]["p50_us"] / 1e3, 3),
+                      "guarded_render": round(st["guarded_render"]["p50_us"] / 1e3, 3)},
+           "p99_ms": {"campaign": round(st["campaign"]["p99_us"] / 1e3, 3),
+                      "guarded_render": round(st["guarded_render"]["p99_us"] / 1e3, 3)},
+           "launches": st["launches"], "completed": st["completed"], "rejected": st["rejected"],
+           "resident_GB": round(st["resident_bytes"] / 1e9, 3)}
+    if plain_seconds > 0:
+        ps = sgb.Server(0, max_slots=1, plain=True)
+        pviews = build(ps)
+        pst = drive(ps, pviews, plain_seconds)
+        ps.close()
+        out["plain_fifo"] = {"seconds_of_arrivals": plain_seconds, "completed": pst["completed"],
+                             "throughput_inj_per_s": round(pst["inj_per_s"], 1),
+                             "p50_ms": {"campaign": round(pst["campaign"]["p50_us"] / 1e3, 3),
+                                        "guarded_render": round(pst["guarded_render"]["p50_us"] / 1e3, 3)},
+                             "p99_ms": {"campaign": round(pst["campaign"]["p99_us"] / 1e3, 3),
+                                        "guarded_render": round(pst["guarded_render"]["p99_us"] / 1e3, 3)}}
+    return out
+
+
+def run_serve(args):
+    out = {"metric": "serving: throughput and p50/p99 request latency, continuous batching vs plain FIFO",
+           **serve_workload(args.serve_seconds if args.serve_seconds > 0 else 5.0)}
     print(json.dumps(out), flush=True)
 
 

@@ -219,6 +219,9 @@ int64_t sg_prep_instances(const sg_prep* prep);
 /* Copy the prepared clean frame into dst (device, height*width*3 floats). */
 sg_status sg_prep_copy_frame(const sg_prep* prep, float* dst, void* stream);
 
+/* A prepared scene is read-only once made: contexts on the same device (for
+ * example one per host thread) may render batches of it concurrently. */
+
 /* Render B corrupted variants of a prepared scene and score each against the
  * clean frame (Sec. 5.12: many independently corrupted variants per launch;
  * Sec. 3 "Metrics"; Def. 1; Def. 2).  sites: HOST array of n_sites;
@@ -275,6 +278,79 @@ sg_status sg_ctx_pass_times(sg_ctx* ctx, double* ms, int64_t* launches);
  * any non-finite value in its frames.  out: B entries (device). */
 sg_status sg_metrics(sg_ctx* ctx, const float* images, const float* clean, int32_t B, int32_t K, int32_t H,
                      int32_t W, sg_metrics_t* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over resident scenes.  Scenes (and their guard
+ * boxes) are copied to the device once; each (scene, camera) view is
+ * prepared once, keeping its clean frame and tile lists resident.  Worker
+ * threads, each with its own context and HIP stream, take queued requests
+ * in arrival order; pending injection campaigns on the same view are merged
+ * into one batched launch (continuous batching), and launches of different
+ * workers run concurrently on the device.  A request is admitted only while
+ * the resident state plus the memory of running launches stays within the
+ * device budget.  Latencies are measured from each request's arrival time to
+ * the completion of its launch, on the host's monotonic clock. */
+typedef struct sg_server sg_server;
+typedef struct {
+  size_t hbm_budget_bytes;   /* device bytes for resident state + running launches; 0 = no cap */
+  int32_t max_slots;         /* worker threads / concurrent launches (0 = 4) */
+  int32_t max_batch;         /* variants per launch (0 = 64) */
+  int32_t queue_depth;       /* pending requests before submit returns SG_E_BUSY (0 = unbounded) */
+  int32_t plain;             /* 1: reference FIFO path: one worker, no merging, a full render per variant */
+} sg_serve_config;
+
+/* An injection campaign scores each site as its own single-upset variant
+ * (per_variant receives n_sites records); a guarded render applies all sites
+ * together, clamps the result into the scene's box (Alg. 1) and scores the
+ * frame (per_variant receives one record).  sites and per_variant are host
+ * arrays; sites are copied at submit, per_variant must stay valid until the
+ * request is done.  arrival_ns is a CLOCK_MONOTONIC time (0 = now). */
+enum { SG_REQ_CAMPAIGN = 0, SG_REQ_GUARDED_RENDER = 1 };
+typedef struct {
+  int32_t kind;
+  int32_t view_id;
+  const sg_site* sites;
+  int32_t n_sites;
+  int32_t _pad;
+  int64_t arrival_ns;
+  sg_metrics_t* per_variant;
+} sg_request;
+
+typedef struct {
+  sg_status status;         /* SG_OK, SG_E_NOMEM (no longer fits), SG_E_DEVICE */
+  int32_t _pad;
+  int64_t done_ns;
+  int64_t latency_ns;       /* done_ns - arrival_ns */
+  uint64_t clamps;
+} sg_result;
+
+typedef struct {
+  uint64_t submitted, completed, rejected, launches, variants;
+  double inj_per_s, req_per_s;             /* over first arrival .. last completion */
+  double p50_us[2], p99_us[2], mean_us[2]; /* per request kind */
+  uint64_t n[2];
+  size_t resident_bytes;
+} sg_serve_stats_t;
+
+sg_status sg_serve_create(int32_t device, const sg_serve_config* cfg, sg_server** out);
+/* Copy a scene (device or host memory, any strides) and optionally its box
+ * into the server.  Must precede the first submit. */
+sg_status sg_serve_add_scene(sg_server* srv, const sg_scene* scene, const sg_box* box, uint32_t box_mask,
+                             int32_t* scene_id);
+/* Prepare a scene for one camera (resident clean frame and tile lists).
+ * Returns SG_E_NOMEM if the view does not fit the budget. */
+sg_status sg_serve_add_view(sg_server* srv, int32_t scene_id, const sg_camera* cam, const sg_raster* raster,
+                            int32_t* view_id);
+/* Non-blocking.  SG_E_BUSY when the queue is full, SG_E_NOMEM when the
+ * request could never fit the budget.  Thread-safe. */
+sg_status sg_serve_submit(sg_server* srv, const sg_request* req, uint64_t* ticket);
+/* SG_E_PENDING until the request is done; then fills out and forgets the ticket. */
+sg_status sg_serve_poll(sg_server* srv, uint64_t ticket, sg_result* out);
+sg_status sg_serve_wait(sg_server* srv, uint64_t ticket, sg_result* out, int64_t timeout_us);
+sg_status sg_serve_stats(sg_server* srv, sg_serve_stats_t* out);
+const char* sg_serve_last_error(const sg_server* srv);
+/* Finishes queued work, then releases everything the server holds. */
+void sg_serve_destroy(sg_server* srv);
 
 #ifdef __cplusplus
 }

@@ -54,6 +54,31 @@ class SgBox(C.Structure):
     _fields_ = [("mode", C.c_int32), ("dtype", C.c_int32), ("lo", C.c_void_p * 6), ("hi", C.c_void_p * 6)]
 
 
+class SgServeConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("max_batch", C.c_int32),
+                ("queue_depth", C.c_int32), ("plain", C.c_int32)]
+
+
+class SgRequest(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("view_id", C.c_int32), ("sites", C.c_void_p), ("n_sites", C.c_int32),
+                ("_pad", C.c_int32), ("arrival_ns", C.c_int64), ("per_variant", C.c_void_p)]
+
+
+class SgResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("_pad", C.c_int32), ("done_ns", C.c_int64), ("latency_ns", C.c_int64),
+                ("clamps", C.c_uint64)]
+
+
+class SgServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
+                ("launches", C.c_uint64), ("variants", C.c_uint64), ("inj_per_s", C.c_double),
+                ("req_per_s", C.c_double), ("p50_us", C.c_double * 2), ("p99_us", C.c_double * 2),
+                ("mean_us", C.c_double * 2), ("n", C.c_uint64 * 2), ("resident_bytes", C.c_size_t)]
+
+
+SG_REQ_CAMPAIGN, SG_REQ_GUARDED_RENDER = 0, 1
+
+
 class SgError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libsg status {code}: {msg}")
@@ -61,6 +86,10 @@ class SgError(RuntimeError):
 
 
 def _load():
+    # torch ships its own HIP runtime under the same soname as ROCm's; loading
+    # torch first makes libsg resolve to that one copy, so device pointers,
+    # streams and the runtime state are shared by both.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
     lib = C.CDLL(LIB_PATH)
@@ -85,6 +114,15 @@ def _load():
         "sg_render_batch": (i32, [vp, vp, vp, i32, vp, i32, P(SgBox), u32, vp, vp, i32, vp]),
         "sg_metrics": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
         "sg_ctx_timing": (i32, [vp, i32]),
+        "sg_serve_create": (i32, [i32, P(SgServeConfig), P(vp)]),
+        "sg_serve_add_scene": (i32, [vp, P(SgScene), P(SgBox), u32, P(i32)]),
+        "sg_serve_add_view": (i32, [vp, i32, P(SgCamera), P(SgRaster), P(i32)]),
+        "sg_serve_submit": (i32, [vp, P(SgRequest), P(u64)]),
+        "sg_serve_poll": (i32, [vp, u64, P(SgResult)]),
+        "sg_serve_wait": (i32, [vp, u64, P(SgResult), i64]),
+        "sg_serve_stats": (i32, [vp, P(SgServeStats)]),
+        "sg_serve_last_error": (C.c_char_p, [vp]),
+        "sg_serve_destroy": (None, [vp]),
         "sg_ctx_set_persistent": (i32, [vp, i32]),
         "sg_ctx_set_graphs": (i32, [vp, i32]),
         "sg_ctx_pass_times": (i32, [vp, vp, vp]),
@@ -100,7 +138,9 @@ LIB = _load()
 EXPORTED = ("sg_ctx_create", "sg_ctx_destroy", "sg_last_error", "sg_ctx_bytes", "sg_cast", "sg_inject",
             "sg_restore", "sg_guard_box", "sg_guard", "sg_render", "sg_prepare", "sg_prep_destroy",
             "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_metrics",
-            "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_graphs")
+            "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_graphs", "sg_serve_create",
+            "sg_serve_add_scene", "sg_serve_add_view", "sg_serve_submit", "sg_serve_poll", "sg_serve_wait",
+            "sg_serve_stats", "sg_serve_last_error", "sg_serve_destroy")
 
 
 def check(code):
@@ -361,3 +401,83 @@ def metrics_tensor(B: int):
 
 def read_metrics(t) -> np.ndarray:
     return t.cpu().numpy().view(METRICS_DTYPE)
+
+
+class Server:
+    """sg_server: resident scenes and views, a request queue and worker threads."""
+
+    def __init__(self, device: int = 0, budget: int = 0, max_slots: int = 4, max_batch: int = 64,
+                 queue_depth: int = 0, plain: bool = False):
+        cfg = SgServeConfig(budget, max_slots, max_batch, queue_depth, 1 if plain else 0)
+        h = C.c_void_p()
+        check(LIB.sg_serve_create(device, C.byref(cfg), C.byref(h)))
+        self.h = h
+        self._live = {}
+
+    def _check(self, code):
+        if code != SG_OK:
+            raise SgError(code, LIB.sg_serve_last_error(self.h).decode(errors="replace"))
+
+    def add_scene(self, scene: "DeviceScene", box: "Box" = None, box_mask: int = SG_FIELD_MASK_GUARD) -> int:
+        sid = C.c_int32()
+        self._check(LIB.sg_serve_add_scene(self.h, C.byref(scene.st), C.byref(box.st) if box is not None else None,
+                                           box_mask if box is not None else 0, C.byref(sid)))
+        return sid.value
+
+    def add_view(self, scene_id: int, cam, raster=None) -> int:
+        vid = C.c_int32()
+        camst = camera_struct(cam)
+        self._check(LIB.sg_serve_add_view(self.h, scene_id, C.byref(camst),
+                                          C.byref(raster) if raster is not None else None, C.byref(vid)))
+        return vid.value
+
+    def submit(self, kind: int, view: int, sites: np.ndarray, arrival_ns: int = 0) -> int:
+        s = np.ascontiguousarray(sites, SITE_DTYPE)
+        out = np.zeros(len(s) if kind == SG_REQ_CAMPAIGN else 1, METRICS_DTYPE)
+        req = SgRequest(kind, view, s.ctypes.data_as(C.c_void_p), len(s), 0, int(arrival_ns),
+                        out.ctypes.data_as(C.c_void_p))
+        t = C.c_uint64()
+        self._check(LIB.sg_serve_submit(self.h, C.byref(req), C.byref(t)))
+        self._live[t.value] = (s, out)
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float = 60.0):
+        """(result dict, per-variant records) once the request is done."""
+        r = SgResult()
+        code = LIB.sg_serve_wait(self.h, ticket, C.byref(r), int(timeout_s * 1e6))
+        if code == SG_E_PENDING:
+            raise TimeoutError(f"request {ticket} not done after {timeout_s} s")
+        self._check(code)
+        _, out = self._live.pop(ticket)
+        return {"status": r.status, "latency_ns": r.latency_ns, "done_ns": r.done_ns, "clamps": r.clamps}, out
+
+    def poll(self, ticket: int):
+        r = SgResult()
+        code = LIB.sg_serve_poll(self.h, ticket, C.byref(r))
+        if code == SG_E_PENDING:
+            return None
+        self._check(code)
+        _, out = self._live.pop(ticket)
+        return {"status": r.status, "latency_ns": r.latency_ns, "done_ns": r.done_ns, "clamps": r.clamps}, out
+
+    def stats(self) -> dict:
+        st = SgServeStats()
+        self._check(LIB.sg_serve_stats(self.h, C.byref(st)))
+        return {"submitted": st.submitted, "completed": st.completed, "rejected": st.rejected,
+                "launches": st.launches, "variants": st.variants, "inj_per_s": st.inj_per_s,
+                "req_per_s": st.req_per_s,
+                "campaign": {"p50_us": st.p50_us[0], "p99_us": st.p99_us[0], "mean_us": st.mean_us[0], "n": st.n[0]},
+                "guarded_render": {"p50_us": st.p50_us[1], "p99_us": st.p99_us[1], "mean_us": st.mean_us[1],
+                                   "n": st.n[1]},
+                "resident_bytes": st.resident_bytes}
+
+    def close(self):
+        if getattr(self, "h", None):
+            LIB.sg_serve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -71,23 +71,40 @@ __global__ void k_box_finalize(const uint32_t* kmin, const uint32_t* kmax, int C
   }
 }
 
-// Guard clamp of one field in place (Alg. 1 per frame).  Only clamped words
-// are written.  Clamps are counted per wave with a ballot.
-__global__ void k_guard(DevScene s, DevBox b, int f, unsigned long long* __restrict__ count) {
+// Guard clamp of one field in place (Alg. 1 per frame).  Each thread keeps
+// four independent words (and their bounds) in flight; only clamped words are
+// written.  Clamps are counted per wave.
+__device__ __forceinline__ void guard_one(const DevScene& s, const DevBox& b, int f, int c, int64_t i, uint32_t w,
+                                          uint32_t lo, uint32_t hi, uint32_t* local) {
+  bool clamped;
+  const uint32_t g = clamp_word(w, lo, hi, s.dtype, &clamped);
+  if (clamped) {
+    const int64_t idx = i * s.ps[f] + (int64_t)c * s.cs[f];
+    if (s.dtype == SG_F32) const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(s.ptr[f]))[idx] = g;
+    else const_cast<uint16_t*>(reinterpret_cast<const uint16_t*>(s.ptr[f]))[idx] = (uint16_t)g;
+    ++*local;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_guard(DevScene s, DevBox b, int f, unsigned long long* __restrict__ count) {
   const int c = blockIdx.y;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   uint32_t local = 0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s.n; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t w = load_word(s, f, i, c);
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < s.n; i += 4 * stride) {
+    uint32_t w[4], lo[4], hi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      w[u] = load_word(s, f, i + u * stride, c);
+      box_words(b, f, i + u * stride, c, s.n, &lo[u], &hi[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) guard_one(s, b, f, c, i + u * stride, w[u], lo[u], hi[u], &local);
+  }
+  for (; i < s.n; i += stride) {
     uint32_t lo, hi;
     box_words(b, f, i, c, s.n, &lo, &hi);
-    bool clamped;
-    const uint32_t g = clamp_word(w, lo, hi, s.dtype, &clamped);
-    if (clamped) {
-      const int64_t idx = i * s.ps[f] + (int64_t)c * s.cs[f];
-      if (s.dtype == SG_F32) const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(s.ptr[f]))[idx] = g;
-      else const_cast<uint16_t*>(reinterpret_cast<const uint16_t*>(s.ptr[f]))[idx] = (uint16_t)g;
-      ++local;
-    }
+    guard_one(s, b, f, c, i, load_word(s, f, i, c), lo, hi, &local);
   }
   for (int o = 32; o > 0; o >>= 1) local += (uint32_t)__shfl_xor((int)local, o);
   if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, (unsigned long long)local);

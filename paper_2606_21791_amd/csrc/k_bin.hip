@@ -9,6 +9,8 @@
 #include "sg_device.h"
 #include "sg_kernels.h"
 
+#include <algorithm>
+
 namespace sg {
 
 constexpr int kSortCap = 4096;       // keys sorted in LDS by one block
@@ -86,6 +88,46 @@ __global__ void __launch_bounds__(256) k_emit_big(const uint32_t* __restrict__ d
     const int area = w * (ty1 - ty0 + 1);
     const uint64_t key = ((uint64_t)depth[i] << 32) | i;
     for (int k = threadIdx.x; k < area; k += blockDim.x) emit_one(bb, (ty0 + k / w) * ras.tiles_x + tx0 + k % w, key);
+  }
+}
+
+// Chunked emission: block b handles primitives [b*chunk, (b+1)*chunk).  It
+// counts its instances per tile in LDS, reserves each tile's range with one
+// global atomic, then scatters with LDS cursors.  Rectangles larger than
+// kEmitSmall tiles go to the per-instance path of k_emit_big.
+__global__ void __launch_bounds__(1024) k_emit_chunk(int n, int chunk, const uint32_t* __restrict__ depth,
+                                                     const uint2* __restrict__ rect, DevRaster ras, BinBuffers bb) {
+  extern __shared__ uint32_t s_pos[];
+  const int nt = ras.n_tiles;
+  for (int k = threadIdx.x; k < nt; k += blockDim.x) s_pos[k] = 0;
+  __syncthreads();
+  const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const uint2 r = rect[i];
+    if (r.x == 0xffffffffu) continue;
+    const int tx0 = r.x & 0xffff, ty0 = r.x >> 16, tx1 = r.y & 0xffff, ty1 = r.y >> 16;
+    if ((tx1 - tx0 + 1) * (ty1 - ty0 + 1) > kEmitSmall) {
+      const unsigned long long b = atomicAdd(bb.total + 1, 1ull);
+      bb.big_prims[b] = (uint32_t)i;
+      continue;
+    }
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(s_pos + ty * ras.tiles_x + tx, 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+    const uint32_t c = s_pos[t];
+    if (c) s_pos[t] = bb.tile_start[t] + atomicAdd(bb.cursor + t, c);
+  }
+  __syncthreads();
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const uint2 r = rect[i];
+    if (r.x == 0xffffffffu) continue;
+    const int tx0 = r.x & 0xffff, ty0 = r.x >> 16, tx1 = r.y & 0xffff, ty1 = r.y >> 16;
+    if ((tx1 - tx0 + 1) * (ty1 - ty0 + 1) > kEmitSmall) continue;
+    const uint64_t key = ((uint64_t)depth[i] << 32) | (uint32_t)i;
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) bb.keys[atomicAdd(s_pos + ty * ras.tiles_x + tx, 1u)] = key;
   }
 }
 
@@ -178,8 +220,14 @@ void launch_tile_prefix(const DevRaster& ras, const BinBuffers& bb, hipStream_t 
 }
 
 void launch_emit(int n, const uint32_t* depth, const uint2* rect, const DevRaster& ras, const BinBuffers& bb,
-                 hipStream_t st) {
-  k_emit_small<<<(n + 255) / 256, 256, 0, st>>>(n, depth, rect, ras, bb);
+                 int n_cu, hipStream_t st) {
+  if (ras.n_tiles <= 16384) {
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n + 255) / 256, (int64_t)n_cu * 4));
+    const int chunk = (int)(((int64_t)n + blocks - 1) / blocks);
+    k_emit_chunk<<<blocks, 1024, (size_t)ras.n_tiles * sizeof(uint32_t), st>>>(n, chunk, depth, rect, ras, bb);
+  } else {
+    k_emit_small<<<(n + 255) / 256, 256, 0, st>>>(n, depth, rect, ras, bb);
+  }
   k_emit_big<<<1024, 256, 0, st>>>(depth, rect, ras, bb);
 }
 

@@ -4,19 +4,30 @@
 #include "sg_device.h"
 #include "sg_kernels.h"
 
+#include <algorithm>
+
 namespace sg {
 
-// One thread per primitive.  All stored words of the primitive are loaded
-// first (independent, coalesced loads: field f, component c of primitives
-// i .. i+63 are consecutive in the component-major layout), then clamped in
-// registers if a box is given, then projected.
-template <int DEG>
+// Projection of every primitive, grid-stride.  All stored words of a
+// primitive are loaded first (independent, coalesced loads: field f,
+// component c of consecutive primitives are consecutive words in the
+// component-major layout), clamped in registers if a box is given, then
+// projected.  Each visible primitive adds its tile rectangle to a 2-D
+// difference grid; when the grid fits in LDS the block accumulates it there
+// and flushes its nonzero entries with one global atomic each.
+template <int DEG, bool LDS_GRID>
 __global__ void __launch_bounds__(256) k_project(DevScene s, DevBox box, DevCam cam, DevRaster ras, ProjBuffers pb) {
   using L = Layout<DEG>;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  extern __shared__ int s_diff[];
+  const int X = ras.tiles_x + 1;
+  const int nd = X * (ras.tiles_y + 1);
+  if (LDS_GRID) {
+    for (int k = threadIdx.x; k < nd; k += blockDim.x) s_diff[k] = 0;
+    __syncthreads();
+  }
   uint32_t clamps = 0;
   bool nonfin = false;
-  if (i < s.n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s.n; i += (int64_t)gridDim.x * blockDim.x) {
     uint32_t w[L::kWords];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
@@ -41,19 +52,25 @@ __global__ void __launch_bounds__(256) k_project(DevScene s, DevBox box, DevCam 
     }
     auto get = [&](int f, int c) -> uint32_t { return w[L::off(f) + c]; };
     const ProjOut o = project_prim<DEG>(get, s.dtype, cam, ras);
-    nonfin = o.nonfinite;
+    nonfin |= o.nonfinite;
     pb.r0[i] = o.rec.r0;
     pb.r1[i] = o.rec.r1;
     pb.r2[i] = o.rec.r2;
     pb.depth[i] = o.depth;
     pb.rect[i] = o.visible ? make_uint2(o.rect0, o.rect1) : make_uint2(0xffffffffu, 0u);
     if (o.visible) {
-      const int X = ras.tiles_x + 1;
       const int tx0 = o.rect0 & 0xffff, ty0 = o.rect0 >> 16, tx1 = o.rect1 & 0xffff, ty1 = o.rect1 >> 16;
-      atomicAdd(pb.diff + ty0 * X + tx0, 1);
-      atomicAdd(pb.diff + ty0 * X + tx1 + 1, -1);
-      atomicAdd(pb.diff + (ty1 + 1) * X + tx0, -1);
-      atomicAdd(pb.diff + (ty1 + 1) * X + tx1 + 1, 1);
+      if (LDS_GRID) {
+        atomicAdd(s_diff + ty0 * X + tx0, 1);
+        atomicAdd(s_diff + ty0 * X + tx1 + 1, -1);
+        atomicAdd(s_diff + (ty1 + 1) * X + tx0, -1);
+        atomicAdd(s_diff + (ty1 + 1) * X + tx1 + 1, 1);
+      } else {
+        atomicAdd(pb.diff + ty0 * X + tx0, 1);
+        atomicAdd(pb.diff + ty0 * X + tx1 + 1, -1);
+        atomicAdd(pb.diff + (ty1 + 1) * X + tx0, -1);
+        atomicAdd(pb.diff + (ty1 + 1) * X + tx1 + 1, 1);
+      }
     }
   }
   for (int o = 32; o > 0; o >>= 1) clamps += (uint32_t)__shfl_xor((int)clamps, o);
@@ -61,6 +78,13 @@ __global__ void __launch_bounds__(256) k_project(DevScene s, DevBox box, DevCam 
   if ((threadIdx.x & 63) == 0) {
     if (clamps && pb.clamps) atomicAdd(pb.clamps, (unsigned long long)clamps);
     if (nf) atomicOr(pb.flags, 1u);
+  }
+  if (LDS_GRID) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+      const int v = s_diff[k];
+      if (v) atomicAdd(pb.diff + k, v);
+    }
   }
 }
 
@@ -228,14 +252,22 @@ __global__ void __launch_bounds__(1024) k_plan(BatchBuffers bb, int tiles_x, uin
 }
 
 void launch_project(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
-                    const ProjBuffers& pb, hipStream_t st) {
-  const unsigned blocks = (unsigned)(((int64_t)s.n + 255) / 256);
+                    const ProjBuffers& pb, int n_cu, hipStream_t st) {
+  const int64_t need = ((int64_t)s.n + 255) / 256;
+  const int nd = (ras.tiles_x + 1) * (ras.tiles_y + 1);
+  const bool lds = nd <= 16384;
+  const unsigned blocks = (unsigned)(lds ? std::min<int64_t>(need, (int64_t)n_cu * 4) : need);
+  const size_t shm = lds ? (size_t)nd * sizeof(int) : 0;
+#define SG_PROJ(D)                                                                          \
+  if (lds) k_project<D, true><<<blocks, 256, shm, st>>>(s, box, cam, ras, pb);            \
+  else k_project<D, false><<<blocks, 256, 0, st>>>(s, box, cam, ras, pb);
   switch (s.sh_degree) {
-    case 0: k_project<0><<<blocks, 256, 0, st>>>(s, box, cam, ras, pb); break;
-    case 1: k_project<1><<<blocks, 256, 0, st>>>(s, box, cam, ras, pb); break;
-    case 2: k_project<2><<<blocks, 256, 0, st>>>(s, box, cam, ras, pb); break;
-    default: k_project<3><<<blocks, 256, 0, st>>>(s, box, cam, ras, pb); break;
+    case 0: SG_PROJ(0) break;
+    case 1: SG_PROJ(1) break;
+    case 2: SG_PROJ(2) break;
+    default: SG_PROJ(3) break;
   }
+#undef SG_PROJ
 }
 
 void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,

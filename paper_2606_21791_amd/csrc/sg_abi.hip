@@ -385,7 +385,7 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
                  P<int32_t>(W->diff), P<uint32_t>(W->flags), P<unsigned long long>(W->clamps)};
   {
     PassScope ps(ctx, SG_PASS_PROJECT, st);
-    launch_project(s, box, cam, ras, pb, st);
+    launch_project(s, box, cam, ras, pb, ctx->n_cu, st);
   }
   BinBuffers bb{P<int32_t>(W->diff), P<uint32_t>(tile_cnt), P<uint32_t>(tile_start), P<uint32_t>(W->cursor),
                 P<unsigned long long>(W->total), nullptr, nullptr, P<uint32_t>(W->big_prims),
@@ -406,7 +406,7 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
   bb.capacity = n_inst;
   {
     PassScope ps(ctx, SG_PASS_BIN, st);
-    launch_emit(s.n, P<uint32_t>(depth), P<uint2>(rect), ras, bb, st);
+    launch_emit(s.n, P<uint32_t>(depth), P<uint2>(rect), ras, bb, ctx->n_cu, st);
   }
   {
     PassScope ps(ctx, SG_PASS_SORT, st);
@@ -649,7 +649,7 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
                           int32_t B, const sg_box* box, uint32_t box_field_mask, float* images_out,
                           sg_metrics_t* metrics_out, int32_t mode, void* stream) {
   if (!ctx || !prep || !metrics_out) return fail(SG_E_INVAL, "ctx/prep/metrics_out is NULL");
-  if (prep->ctx != ctx) return fail(SG_E_INVAL, "prep belongs to another context");
+  if (prep->ctx != ctx && prep->ctx->device != ctx->device) return fail(SG_E_INVAL, "prep is on another device");
   if (B < 0 || (B > 0 && !variants)) return fail(SG_E_INVAL, "bad variants");
   if (mode != SG_INCREMENTAL && mode != SG_FULL) return fail(SG_E_INVAL, "bad mode");
   const DevScene& s = prep->scene;

@@ -69,7 +69,7 @@ struct ProjBuffers {
   unsigned long long* clamps;
 };
 void launch_project(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
-                    const ProjBuffers& pb, hipStream_t st);
+                    const ProjBuffers& pb, int n_cu, hipStream_t st);
 
 struct BatchBuffers {
   const sg_site* sites;
@@ -105,7 +105,7 @@ struct BinBuffers {
 };
 void launch_tile_prefix(const DevRaster& ras, const BinBuffers& bb, hipStream_t st);
 void launch_emit(int n, const uint32_t* depth, const uint2* rect, const DevRaster& ras, const BinBuffers& bb,
-                 hipStream_t st);
+                 int n_cu, hipStream_t st);
 void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, hipStream_t st);
 
 // k_composite.hip
