@@ -33,8 +33,26 @@ sys.path.insert(0, ROOT)
 N_HI = 134_826
 FLOPS_PER_EVAL = 20            # q-form and alpha test of one pixel-primitive evaluation
 FP32_PEAK_TFLOPS = 157.3       # MI355X fp32 vector peak
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "composite_items_w2hi_f32_b32_hbm_traffic.txt")
 PAPER_CONTEXT = {"inj_per_s": 2515, "hardware": "Blackwell-generation GPU (model not named), B=32, resolution not stated",
                  "l40s_inj_per_s": 1522}
+
+
+def _measured_traffic():
+    """HBM bytes per compositing launch from the committed counter summary,
+    valid only while the compositing source is the one that was measured."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = dict(line.strip().split(": ", 1) for line in txt.splitlines()
+                if line.strip().startswith(("traffic_bytes_per_launch:", "k_composite.hip sha256 at measurement:")))
+    src = os.path.join(ROOT, "paper_2606_21791_amd", "csrc", "k_composite.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if vals.get("k_composite.hip sha256 at measurement") != sha:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
 
 
 def _workload(fmt):
@@ -95,7 +113,7 @@ def main():
     ap.add_argument("--no-graphs", action="store_true", help="launch each batch eagerly instead of replaying a graph")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="seconds of Poisson arrivals for the serving measurement (0: skip)")
-    ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve"],
+    ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve", "copy"],
                     help="w2: the headline; guard: support guard and accumulated dose on the N=134,826 scene; "
                          "large: the 2,056,645-primitive bf16 scene at 1600x900; stress: one guarded render at "
                          "65,812,640 primitives")
@@ -104,7 +122,8 @@ def main():
         print("bench.py measures one GPU: every run here uses a single MI355X (--gpus 1).", file=sys.stderr)
         sys.exit(2)
     if args.workload != "w2":
-        {"guard": run_guard, "large": run_large, "stress": run_stress, "serve": run_serve}[args.workload](args)
+        {"guard": run_guard, "large": run_large, "stress": run_stress, "serve": run_serve,
+         "copy": run_copy}[args.workload](args)
         return
 
     import torch
@@ -220,7 +239,8 @@ def main():
         "dirty_tiles_per_injection": round(float(recs["dirty_tiles"].mean()), 2),
         "catastrophic_fraction": round(float(recs["catastrophic"].mean()), 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                     "traffic": (_measured_traffic() if (args.fmt == "f32" and B == 32 and args.tile == 16) else None),
                      "kernel": "k_composite_items", "avg_launch_ms": round(comp_avg_s * 1e3, 4),
                      "evals_per_launch": round(evals_per_launch), "flops_per_eval": FLOPS_PER_EVAL},
         "paper_context": PAPER_CONTEXT,
@@ -547,6 +567,29 @@ def run_serve(args):
     out = {"metric": "serving: throughput and p50/p99 request latency, continuous batching vs plain FIFO",
            **serve_workload(args.serve_seconds if args.serve_seconds > 0 else 5.0)}
     print(json.dumps(out), flush=True)
+
+
+def run_copy(args):
+    """Device-to-device copy of 1 GiB (fp32), 10 times: the stream-copy ceiling
+    of the HBM, and the calibration point of the FETCH_SIZE / WRITE_SIZE
+    counters (each launch reads and writes exactly 1 GiB)."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    print(json.dumps({"metric": "stream copy, 1 GiB read + 1 GiB write per launch", "bytes_per_launch": 2 * 4 * n,
+                      "ms_per_launch": round(ms, 4), "GB_s": round(2 * 4 * n / (ms * 1e-3) / 1e9, 1),
+                      "frac_of_8TB_s": round(2 * 4 * n / (ms * 1e-3) / 8e12, 4)}), flush=True)
 
 
 if __name__ == "__main__":
