@@ -20,6 +20,7 @@ vector peak; `cpu_baseline` is the FP64 oracle's plain path on the host.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -101,13 +102,15 @@ def cpu_baseline(sc, cam, sites, fmt, n_inj):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--streams", type=int, default=8, help="HIP streams the batches rotate over")
     ap.add_argument("--wgs-per-cu", type=int, default=2, help="persistent compositing workgroups per CU (0: default)")
+    ap.add_argument("--resume", type=int, default=64,
+                    help="checkpoint spacing of prepared scenes (0: walk every merged list from its start)")
     ap.add_argument("--plain", type=int, default=100, help="injections timed on the plain path")
     ap.add_argument("--cpu-inj", type=int, default=1, help="oracle injections timed on the host (0: skip)")
     ap.add_argument("--no-graphs", action="store_true", help="launch each batch eagerly instead of replaying a graph")
@@ -132,6 +135,7 @@ def main():
     sc, cam, sites = _workload(args.fmt)
     ctx = sgb.Context(0)
     ctx.set_persistent(args.wgs_per_cu)
+    ctx.set_resume(args.resume)
     ctx.set_graphs(not args.no_graphs)
     streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
     ds = sgb.DeviceScene.upload(ctx, sc, args.fmt)
@@ -146,7 +150,9 @@ def main():
         sa = sgb.sites_array(sites.field[idx], sites.comp[idx], sites.prim[idx], sites.bit[idx])
         batches.append(sa)
     va = sgb.variants_array(np.arange(B), np.ones(B, np.uint32))
-    mts = [sgb.metrics_tensor(B) for _ in range(steps_total)]
+    rec_bytes = B * sgb.METRICS_DTYPE.itemsize
+    mt_all = sgb.metrics_tensor(B * steps_total)
+    mts = [mt_all[i * rec_bytes:(i + 1) * rec_bytes] for i in range(steps_total)]
 
     def run(i):
         with torch.cuda.stream(streams[i % len(streams)]):
@@ -155,22 +161,24 @@ def main():
     for i in range(args.warmup):
         run(i)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.warmup, steps_total):
-        run(i)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    recs = np.concatenate([sgb.read_metrics(m) for m in mts[args.warmup:]])
+    with _no_gc():
+        t_start = time.perf_counter()
+        for i in range(args.warmup, steps_total):
+            run(i)
+        t_sub = time.perf_counter()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+    recs = sgb.read_metrics(mt_all)[args.warmup * B:]
     inj_per_s = args.steps * B / elapsed
 
     # the same steps again with per-pass HIP events (graphs are not used while
     # timing), for the per-pass breakdown and the compositing launch duration
     ctx.timing(True)
     ctx.pass_times()
-    for i in range(args.warmup, steps_total):
-        run(i)
-    torch.cuda.synchronize()
+    with _no_gc():
+        for i in range(args.warmup, steps_total):
+            run(i)
+        torch.cuda.synchronize()
     passes = ctx.pass_times()
     ctx.timing(False)
 
@@ -236,6 +244,7 @@ def main():
                   "records_agree_with_batched": agree},
         "speedup_vs_plain": round(inj_per_s / (P / plain_dt), 2),
         "pass_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in passes.items() if v[1]},
+        "host_submit_ms_per_step": round((t_sub - t_start) * 1e3 / args.steps, 4),
         "dirty_tiles_per_injection": round(float(recs["dirty_tiles"].mean()), 2),
         "catastrophic_fraction": round(float(recs["catastrophic"].mean()), 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -254,6 +263,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+class _no_gc:
+    """Keeps Python's cyclic collector out of a timed submission loop (a full
+    collection in a process holding torch stalls the host for tens of ms)."""
+
+    def __enter__(self):
+        gc.collect()
+        gc.disable()
+
+    def __exit__(self, *exc):
+        gc.enable()
+
+
 def _batched_rate(ctx, prep, sites, B, streams, steps, warmup, guard=0, box=None):
     """Batched incremental injections/s over `steps` batches (after `warmup`)
     and the concatenated per-variant records."""
@@ -266,7 +287,9 @@ def _batched_rate(ctx, prep, sites, B, streams, steps, warmup, guard=0, box=None
         idx = (np.arange(B) + i * B) % n
         batches.append(sgb.sites_array(sites.field[idx], sites.comp[idx], sites.prim[idx], sites.bit[idx]))
     va = sgb.variants_array(np.arange(B), np.ones(B, np.uint32), guard)
-    mts = [sgb.metrics_tensor(B) for _ in range(total)]
+    rec_bytes = B * sgb.METRICS_DTYPE.itemsize
+    mt_all = sgb.metrics_tensor(B * total)
+    mts = [mt_all[i * rec_bytes:(i + 1) * rec_bytes] for i in range(total)]
 
     def run(i):
         with torch.cuda.stream(streams[i % len(streams)]):
@@ -275,12 +298,13 @@ def _batched_rate(ctx, prep, sites, B, streams, steps, warmup, guard=0, box=None
     for i in range(warmup):
         run(i)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(warmup, total):
-        run(i)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    recs = np.concatenate([sgb.read_metrics(m) for m in mts[warmup:]])
+    with _no_gc():
+        t0 = time.perf_counter()
+        for i in range(warmup, total):
+            run(i)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    recs = sgb.read_metrics(mt_all)[warmup * B:]
     return steps * B / dt, recs
 
 
@@ -302,6 +326,7 @@ def run_guard(args):
     sc, cam, sites = _workload("f32")
     ctx = sgb.Context(0)
     ctx.set_persistent(args.wgs_per_cu)
+    ctx.set_resume(args.resume)
     streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
     lo32, hi32 = synth.make_box_jitter(sc, seed=4)
     ds = sgb.DeviceScene.upload(ctx, sc, "f32")
@@ -381,6 +406,7 @@ def run_large(args):
     sc, cam, sites = _large_scene()
     ctx = sgb.Context(0)
     ctx.set_persistent(args.wgs_per_cu)
+    ctx.set_resume(args.resume)
     streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
     ds = sgb.DeviceScene.upload(ctx, sc, "bf16")
     del sc

@@ -243,6 +243,18 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
  * other streams to run concurrently; this is one of the tuned parameters. */
 sg_status sg_ctx_set_persistent(sg_ctx* ctx, int32_t wgs_per_cu);
 
+/* Spacing, in tile-list entries, of the compositing checkpoints that
+ * sg_prepare keeps with a prepared scene (default 64; 0 = none).  With a
+ * spacing g, sg_prepare stores for every pixel the list index at which its
+ * clean walk stopped, and for every tile the exact (colour, transmittance)
+ * state of each pixel after every g entries: H*W*4 bytes plus
+ * sum over tiles of floor(count / g) * tile^2 * 16 bytes of device memory.
+ * The incremental path of sg_render_batch then skips pixels that stopped
+ * before the first list entry a variant changes and resumes the others from
+ * the nearest checkpoint; results are bit-identical either way.  Applies to
+ * scenes prepared after the call; g must be 0 or in [16, 65536]. */
+sg_status sg_ctx_set_resume(sg_ctx* ctx, int32_t spacing);
+
 /* Replay the incremental part of sg_render_batch as a captured HIP graph
  * (default on).  A graph is used when every variant is incremental, no
  * images are requested, timing is off and the stream is not the null stream;

@@ -124,6 +124,7 @@ def _load():
         "sg_serve_last_error": (C.c_char_p, [vp]),
         "sg_serve_destroy": (None, [vp]),
         "sg_ctx_set_persistent": (i32, [vp, i32]),
+        "sg_ctx_set_resume": (i32, [vp, i32]),
         "sg_ctx_set_graphs": (i32, [vp, i32]),
         "sg_ctx_pass_times": (i32, [vp, vp, vp]),
     }
@@ -138,7 +139,8 @@ LIB = _load()
 EXPORTED = ("sg_ctx_create", "sg_ctx_destroy", "sg_last_error", "sg_ctx_bytes", "sg_cast", "sg_inject",
             "sg_restore", "sg_guard_box", "sg_guard", "sg_render", "sg_prepare", "sg_prep_destroy",
             "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_metrics",
-            "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_graphs", "sg_serve_create",
+            "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_resume", "sg_ctx_set_graphs",
+            "sg_serve_create",
             "sg_serve_add_scene", "sg_serve_add_view", "sg_serve_submit", "sg_serve_poll", "sg_serve_wait",
             "sg_serve_stats", "sg_serve_last_error", "sg_serve_destroy")
 
@@ -212,6 +214,10 @@ class Context:
 
     def set_persistent(self, wgs_per_cu: int):
         check(LIB.sg_ctx_set_persistent(self.h, int(wgs_per_cu)))
+
+    def set_resume(self, spacing: int):
+        """Checkpoint spacing of scenes prepared from now on (0 = no resume state)."""
+        check(LIB.sg_ctx_set_resume(self.h, int(spacing)))
 
     def set_graphs(self, enable: bool):
         check(LIB.sg_ctx_set_graphs(self.h, 1 if enable else 0))

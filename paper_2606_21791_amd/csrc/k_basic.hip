@@ -161,23 +161,9 @@ __global__ void k_reduce_metrics(const Partial* __restrict__ parts, const uint32
   }
   __shared__ Partial red;
   block_reduce_partial(sse, changed, mx, nonfin, ev, &red);
-  if (threadIdx.x == 0) {
-    sg_metrics_t m;
-    m.sse = red.sse;
-    m.mse = red.sse / (3.0 * (double)n_pixels);
-    m.psnr = m.mse == 0.0 ? __longlong_as_double(0x7ff0000000000000ll) : 10.0 * log10(1.0 / m.mse);
-    m.changed_px = red.changed;
-    m.footprint = (float)((double)red.changed / (double)n_pixels);
-    m.max_abs = red.max_abs;
-    m.nonfinite = red.nonfinite | (vs ? vs[v].nonfinite : 0u) | (flags ? (flags[0] & 1u) : 0u);
-    m.catastrophic = (m.nonfinite || (double)red.changed > 0.01 * (double)n_pixels) ? 1u : 0u;
-    m.dirty_tiles = vs ? vs[v].n_dirty : n;
-    m.clamps = vs ? vs[v].clamps : (clamps ? *clamps : 0ull);
-    m.n_pixels = n_pixels;
-    m.path = path;
-    m.evals = red.evals;
-    out[v] = m;
-  }
+  if (threadIdx.x == 0)
+    out[v] = make_metrics(red, (vs ? vs[v].nonfinite : 0u) | (flags ? (flags[0] & 1u) : 0u), vs ? vs[v].n_dirty : n,
+                          vs ? vs[v].clamps : (clamps ? *clamps : 0ull), n_pixels, path);
 }
 
 // ----------------------------------------------------------------------------

@@ -12,6 +12,12 @@
 // and their new records inserted at their (depth, id) position.  Both paths
 // run this same code per pixel, so an incrementally re-composited tile is
 // bit-identical to a full render of the variant.
+//
+// Resume: the merged list equals the clean list up to its first differing
+// index m0.  A pixel whose clean walk stopped before m0 is unchanged and is
+// not walked at all; the others restart from the clean render's checkpoint at
+// the largest multiple of the checkpoint spacing not above m0, which holds the
+// exact (C, T) state after that many entries.
 #include "sg_device.h"
 #include "sg_kernels.h"
 
@@ -23,9 +29,15 @@ struct MergeSpec {
   uint32_t rm_pos[kMaxTouch];
   uint32_t ins_mpos[kMaxTouch];
   uint32_t ins_src[kMaxTouch];   // index into the override records
+  uint32_t m0;                   // first index at which merged and clean lists differ
+  uint32_t start;                // resume index (multiple of the checkpoint spacing, <= m0)
 };
 
-template <int TILE>
+// MODE: 0 full render, 1 full render writing the resume state, 2 merged list
+// of a (variant, tile) item resumed from the clean state
+enum { kFull = 0, kFullWrite = 1, kItem = 2 };
+
+template <int TILE, int MODE>
 __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, const MergeSpec* ms, const Rec* ovr,
                                                float* img, Partial* part, float4* s_r0, float4* s_r1,
                                                float4* s_r2) {
@@ -43,20 +55,35 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
   const float amax = A.ras.amax, amin = A.ras.amin, tmin = A.ras.tmin, qc = A.ras.qcut2;
 
-  uint32_t raw_start, mlen;
-  if (ms) { raw_start = ms->raw_start; mlen = ms->mlen; }
+  uint32_t raw_start, mlen, start = 0;
+  if (MODE == kItem) { raw_start = ms->raw_start; mlen = ms->mlen; }
   else { raw_start = A.tile_start[tile]; mlen = A.tile_cnt[tile]; }
 
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   bool done = !inside;
-  uint32_t evals = inside ? mlen : 0u;   // list entries this pixel evaluates
-  for (uint32_t base = 0; base < mlen; base += BS) {
+  bool same = false;                     // pixel provably equal to the clean frame
+  if (MODE == kItem && A.stop) {
+    start = ms->start;
+    if (inside) {
+      const uint32_t sp = A.stop[(int64_t)y * A.W + x];
+      if (sp < ms->m0) {
+        same = true;
+        done = true;
+      } else if (start) {
+        const float4 st = A.ck[((int64_t)A.ck_off[tile] + start / A.ck_group - 1) * BS + tid];
+        C0 = st.x; C1 = st.y; C2 = st.z; T = st.w;
+      }
+    }
+  }
+  uint32_t evals = done ? 0u : mlen - start;   // list entries this pixel evaluates
+  uint32_t next_ck = A.ck_group;               // kFullWrite: next checkpoint index
+  for (uint32_t base = start; base < mlen; base += BS) {
     if (__syncthreads_and(done)) break;
     const uint32_t m = base + tid;
     uint32_t mask = 0;                   // target waves whose block this entry may reach
     if (m < mlen) {
       float4 a, b, c;
-      if (!ms) {
+      if (MODE != kItem) {
         const uint32_t id = (uint32_t)A.keys[raw_start + m];
         a = A.r0[id]; b = A.r1[id]; c = A.r2[id];
       } else {
@@ -124,6 +151,13 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
       int en = idx[min(1u, len - 1)];
       float4 a = s_r0[e], b = s_r1[e], c = s_r2[e];
       for (uint32_t j = 0; j < len; ++j) {
+        if (MODE == kFullWrite) {
+          // the state before this entry is the state after every entry below it
+          while (base + (uint32_t)e >= next_ck) {
+            A.ck_out[((int64_t)A.ck_off[tile] + next_ck / A.ck_group - 1) * BS + tid] = make_float4(C0, C1, C2, T);
+            next_ck += A.ck_group;
+          }
+        }
         // while this entry is evaluated, the next entry's record and the
         // index of the one after it are read from LDS
         const int enn = idx[min(j + 2, len - 1)];
@@ -137,7 +171,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
           const float Tn = T * (1.f - alpha);
           if (Tn < tmin) {
             done = true;
-            evals = base + (uint32_t)e + 1u;
+            evals = base + (uint32_t)e + 1u - start;
           } else {
             const float w = alpha * T;
             C0 = fmaf(c.y, w, C0);
@@ -156,15 +190,23 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
     }
   }
 
+  if (MODE == kFullWrite && !__all(done)) {
+    // pixels that never stopped: their final state is every later checkpoint
+    for (; next_ck <= mlen; next_ck += A.ck_group)
+      A.ck_out[((int64_t)A.ck_off[tile] + next_ck / A.ck_group - 1) * BS + tid] = make_float4(C0, C1, C2, T);
+  }
+
   double sse = 0.0;
   uint32_t changed = 0, nonfin = 0;
   float mx = 0.f;
-  if (inside) {
+  if (inside && !same) {
     const float p0 = fmaf(T, A.ras.bg[0], C0), p1 = fmaf(T, A.ras.bg[1], C1), p2 = fmaf(T, A.ras.bg[2], C2);
     nonfin = (isfinite(p0) && isfinite(p1) && isfinite(p2)) ? 0u : 1u;
     const float i0 = fminf(p0, 1.f), i1 = fminf(p1, 1.f), i2 = fminf(p2, 1.f);
     const int64_t off = ((int64_t)y * A.W + x) * 3;
     if (img) { img[off] = i0; img[off + 1] = i1; img[off + 2] = i2; }
+    if (MODE == kFullWrite)
+      A.stop_out[(int64_t)y * A.W + x] = nonfin ? ~0u : (done ? evals - 1u : mlen);
     if (A.clean) {
       const double d0 = (double)i0 - (double)A.clean[off], d1 = (double)i1 - (double)A.clean[off + 1],
                    d2 = (double)i2 - (double)A.clean[off + 2];
@@ -181,7 +223,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
 // (b % 8) * chunk + b / 8 so the tiles that one XCD (which receives every
 // 8th workgroup) composites form a contiguous band of the frame whose
 // primitive records share that XCD's L2.
-template <int TILE>
+template <int TILE, int MODE>
 __global__ void __launch_bounds__(TILE * TILE) k_composite_full(CompArgs A) {
   __shared__ float4 s_r0[TILE * TILE], s_r1[TILE * TILE], s_r2[TILE * TILE];
   const int nt = A.ras.n_tiles;
@@ -189,7 +231,7 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_full(CompArgs A) {
   const int b = blockIdx.x;
   const int tile = (b % 8) * chunk + b / 8;
   if (tile >= nt) return;
-  composite_tile<TILE>(A, tile, nullptr, nullptr, A.image, A.parts ? A.parts + tile : nullptr, s_r0, s_r1, s_r2);
+  composite_tile<TILE, MODE>(A, tile, nullptr, nullptr, A.image, A.parts ? A.parts + tile : nullptr, s_r0, s_r1, s_r2);
 }
 
 __device__ __forceinline__ bool rect_has(uint32_t r0, uint32_t r1, int tx, int ty) {
@@ -284,10 +326,15 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
       ms.n_rm = n_rm;
       ms.n_ins = ni;
       ms.mlen = ms.raw_len - (uint32_t)n_rm + (uint32_t)ni;
+      uint32_t m0 = ms.raw_len;
+      if (n_rm) m0 = min(m0, ms.rm_pos[0]);
+      if (ni) m0 = min(m0, ms.ins_mpos[0]);
+      ms.m0 = m0;
+      ms.start = A.ck_group ? (m0 / A.ck_group) * A.ck_group : 0u;
     }
     __syncthreads();
     float* img = A.image ? A.image + (int64_t)v * I.image_stride : nullptr;
-    composite_tile<TILE>(A, tile, &ms, I.ovr, img, A.parts + item, s_r0, s_r1, s_r2);
+    composite_tile<TILE, kItem>(A, tile, &ms, I.ovr, img, A.parts + item, s_r0, s_r1, s_r2);
     __syncthreads();
   }
 }
@@ -295,10 +342,18 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
 void launch_composite_full(const CompArgs& a, hipStream_t st) {
   const int nt = a.ras.n_tiles;
   const int grid = ((nt + 7) / 8) * 8;
-  switch (a.ras.tile) {
-    case 8: k_composite_full<8><<<grid, 64, 0, st>>>(a); break;
-    case 32: k_composite_full<32><<<grid, 1024, 0, st>>>(a); break;
-    default: k_composite_full<16><<<grid, 256, 0, st>>>(a); break;
+  if (a.ck_out) {
+    switch (a.ras.tile) {
+      case 8: k_composite_full<8, kFullWrite><<<grid, 64, 0, st>>>(a); break;
+      case 32: k_composite_full<32, kFullWrite><<<grid, 1024, 0, st>>>(a); break;
+      default: k_composite_full<16, kFullWrite><<<grid, 256, 0, st>>>(a); break;
+    }
+  } else {
+    switch (a.ras.tile) {
+      case 8: k_composite_full<8, kFull><<<grid, 64, 0, st>>>(a); break;
+      case 32: k_composite_full<32, kFull><<<grid, 1024, 0, st>>>(a); break;
+      default: k_composite_full<16, kFull><<<grid, 256, 0, st>>>(a); break;
+    }
   }
 }
 

@@ -113,14 +113,19 @@ __global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, Dev
   using L = Layout<DEG>;
   const int v = blockIdx.x;
   const int lane = threadIdx.x;
+  // the batch's variants and sites may sit in pinned host memory: read each
+  // once, staging up to 64 sites of the variant in LDS
   const sg_variant var = bb.variants[v];
-  const sg_site* sites = bb.sites + var.site_off;
+  __shared__ sg_site s_sites[64];
+  if ((uint32_t)lane < var.n_sites && lane < 64) s_sites[lane] = bb.sites[var.site_off + lane];
+  const sg_site* sites = var.n_sites <= 64 ? s_sites : bb.sites + var.site_off;
   const bool guard = var.guard != 0 && box.mask != 0;
   __shared__ VariantState st;
   __shared__ uint32_t s_w[L::kWords];
   __shared__ uint32_t s_same;
   uint64_t* bm = bb.bitmap + (int64_t)v * bb.bm_words;
   for (int w = lane; w < bb.bm_words; w += 64) bm[w] = 0ull;
+  __syncthreads();
   if (lane == 0) {
     st.n_touch = 0; st.full = 0; st.nonfinite = 0; st.n_dirty = 0; st.clamps = 0; st.item_off = 0; st._pad = 0;
     for (uint32_t k = 0; k < var.n_sites; ++k) {
@@ -210,7 +215,7 @@ __global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, Dev
 // (variant-major, rows in order), so each set bit's item index is its rank;
 // write the (variant, tile) items, each variant's first item, the total, and
 // zero the compositing work counter.
-__global__ void __launch_bounds__(1024) k_plan(BatchBuffers bb, int tiles_x, uint32_t* counter) {
+__global__ void __launch_bounds__(1024) k_plan(BatchBuffers bb) {
   __shared__ uint32_t s[1024];
   const int64_t n_words = (int64_t)bb.B * bb.bm_words;
   uint32_t carry = 0;
@@ -239,7 +244,7 @@ __global__ void __launch_bounds__(1024) k_plan(BatchBuffers bb, int tiles_x, uin
       while (m) {
         const int b = __ffsll((long long)m) - 1;
         m &= m - 1ull;
-        bb.items[pos++] = make_uint2((uint32_t)v, (uint32_t)(row * tiles_x + col0 + b));
+        bb.items[pos++] = make_uint2((uint32_t)v, (uint32_t)(row * bb.tiles_x + col0 + b));
       }
     }
     carry += s[1023];
@@ -247,7 +252,7 @@ __global__ void __launch_bounds__(1024) k_plan(BatchBuffers bb, int tiles_x, uin
   }
   if (threadIdx.x == 0) {
     *bb.n_items_total = carry;
-    *counter = 0u;
+    *bb.counter = 0u;
   }
 }
 
@@ -281,8 +286,7 @@ void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam
   }
 }
 
-void launch_plan(const BatchBuffers& bb, int tiles_x, uint32_t* counter, hipStream_t st) {
-  k_plan<<<1, 1024, 0, st>>>(bb, tiles_x, counter);
-}
+void launch_plan(const BatchBuffers& bb, hipStream_t st) { k_plan<<<1, 1024, 0, st>>>(bb); }
+
 
 }  // namespace sg

@@ -59,15 +59,18 @@ struct Workspace {
   DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
       big_prims, big_tiles, parts, work_scene, sites_dev, box_keys, metrics_tmp;
   // batches of variants
-  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, bsites, vars, gmetrics;
+  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, gmetrics;
   unsigned long long* h_total = nullptr;   // pinned
-  // pinned staging ring for a batch's sites and variants; slot k may be
-  // rewritten once the copies of its previous use (event) have completed
-  static constexpr int kRing = 2;
-  sg_site* h_sites[kRing] = {nullptr, nullptr};
-  sg_variant* h_vars[kRing] = {nullptr, nullptr};
+  // pinned staging ring for a batch's sites and variants, read by the variant
+  // prep kernel in place; slot k may be rewritten once the batch that last
+  // used it (event) has completed
+  static constexpr int kRing = 4;
+  sg_site* h_sites[kRing] = {};
+  sg_variant* h_vars[kRing] = {};
+  const sg_site* d_sites[kRing] = {};      // the same memory as seen from the device
+  const sg_variant* d_vars[kRing] = {};
   size_t h_sites_cap = 0, h_vars_cap = 0;
-  hipEvent_t staged[kRing] = {nullptr, nullptr};
+  hipEvent_t staged[kRing] = {};
   int ring = 0;
   // captured incremental batches: one executable graph per shape and buffer set
   struct Graph {
@@ -83,6 +86,7 @@ struct sg_ctx {
   size_t in_use = 0;
   int n_cu = 256;
   int persistent_wgs_per_cu = 0;           // 0: default of the tile size
+  int resume_spacing = 64;                 // checkpoint spacing of prepared scenes (0: none)
   bool use_graphs = true;
   std::vector<Workspace*> ws;
   // per-pass event timing (sg_ctx_timing)
@@ -99,6 +103,8 @@ struct sg_prep {
   DevRaster ras;
   int64_t n_inst = 0;
   DevBuf r0, r1, r2, depth, rect, tile_cnt, tile_start, keys, frame;
+  DevBuf stop, ck, ck_off;                 // resume state of the clean render
+  uint32_t ck_group = 0;
   int bm_words = 0, row_words = 0;
 };
 
@@ -151,7 +157,7 @@ void free_workspace(sg_ctx* ctx, Workspace* w) {
                     &w->tile_start, &w->cursor, &w->total, &w->keys, &w->keys_tmp, &w->big_prims, &w->big_tiles,
                     &w->parts, &w->work_scene, &w->sites_dev, &w->box_keys, &w->metrics_tmp, &w->vs, &w->ovr,
                     &w->bitmap, &w->item_off, &w->n_items_v, &w->n_items_total, &w->items, &w->bparts,
-                    &w->counter, &w->bsites, &w->vars, &w->gmetrics};
+                    &w->counter, &w->gmetrics};
   for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);
   w->graphs.clear();
   for (DevBuf* b : bufs) dev_free(ctx, *b);
@@ -184,8 +190,13 @@ sg_status stage_batch(Workspace* w, const sg_site* sites, int n_sites, size_t si
     }
     const size_t sc = std::max(site_cap, w->h_sites_cap), vc = std::max((size_t)B, w->h_vars_cap);
     for (int j = 0; j < Workspace::kRing; ++j) {
-      HIP_TRY(hipHostMalloc((void**)&w->h_sites[j], sc * sizeof(sg_site), hipHostMallocDefault));
-      HIP_TRY(hipHostMalloc((void**)&w->h_vars[j], vc * sizeof(sg_variant), hipHostMallocDefault));
+      HIP_TRY(hipHostMalloc((void**)&w->h_sites[j], sc * sizeof(sg_site), hipHostMallocMapped));
+      HIP_TRY(hipHostMalloc((void**)&w->h_vars[j], vc * sizeof(sg_variant), hipHostMallocMapped));
+      void* d = nullptr;
+      HIP_TRY(hipHostGetDevicePointer(&d, w->h_sites[j], 0));
+      w->d_sites[j] = static_cast<const sg_site*>(d);
+      HIP_TRY(hipHostGetDevicePointer(&d, w->h_vars[j], 0));
+      w->d_vars[j] = static_cast<const sg_variant*>(d);
     }
     w->h_sites_cap = sc;
     w->h_vars_cap = vc;
@@ -361,7 +372,7 @@ struct RenderBufs {
 sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                       DevBuf& r0, DevBuf& r1, DevBuf& r2, DevBuf& depth, DevBuf& rect, DevBuf& tile_cnt,
                       DevBuf& tile_start, DevBuf& keys, float* image, const float* clean, Partial* parts,
-                      hipStream_t st, int64_t* n_inst_out) {
+                      hipStream_t st, int64_t* n_inst_out, sg_prep* resume = nullptr) {
   const int64_t n = s.n;
   SG_TRY(dev_alloc(ctx, r0, n * sizeof(float4)));
   SG_TRY(dev_alloc(ctx, r1, n * sizeof(float4)));
@@ -414,6 +425,29 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
   }
   CompArgs ca{P<float4>(r0), P<float4>(r1), P<float4>(r2), P<uint32_t>(tile_start), P<uint32_t>(tile_cnt),
               P<uint64_t>(keys), clean, image, parts, ras, cam.W, cam.H};
+  if (resume && resume->ck_group) {
+    // checkpoint slots per tile: floor(count / spacing), laid out tile after tile
+    const uint32_t g = resume->ck_group;
+    std::vector<uint32_t> cnt(ras.n_tiles), off(ras.n_tiles);
+    HIP_TRY(hipMemcpyAsync(cnt.data(), tile_cnt.p, ras.n_tiles * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    uint64_t slots = 0;
+    for (int t = 0; t < ras.n_tiles; ++t) {
+      off[t] = (uint32_t)slots;
+      slots += cnt[t] / g;
+    }
+    if (slots >= 0xffffffffull) return fail(SG_E_UNSUPPORTED, "too many checkpoints; raise the spacing");
+    const size_t bs = (size_t)ras.tile * ras.tile;
+    SG_TRY(dev_alloc(ctx, resume->stop, (size_t)cam.W * cam.H * sizeof(uint32_t)));
+    SG_TRY(dev_alloc(ctx, resume->ck_off, ras.n_tiles * sizeof(uint32_t)));
+    SG_TRY(dev_alloc(ctx, resume->ck, std::max<size_t>(slots, 1) * bs * sizeof(float4)));
+    HIP_TRY(hipMemcpyAsync(resume->ck_off.p, off.data(), ras.n_tiles * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));        // `off` is released on return
+    ca.stop_out = P<uint32_t>(resume->stop);
+    ca.ck_out = P<float4>(resume->ck);
+    ca.ck_off = P<uint32_t>(resume->ck_off);
+    ca.ck_group = g;
+  }
   {
     PassScope ps(ctx, SG_PASS_COMPOSITE_FULL, st);
     launch_composite_full(ca, st);
@@ -458,6 +492,13 @@ void sg_ctx_destroy(sg_ctx* c) {
 }
 
 size_t sg_ctx_bytes(const sg_ctx* c) { return c ? c->in_use : 0; }
+
+sg_status sg_ctx_set_resume(sg_ctx* c, int32_t spacing) {
+  if (!c) return fail(SG_E_INVAL, "ctx is NULL");
+  if (spacing != 0 && (spacing < 16 || spacing > 65536)) return fail(SG_E_INVAL, "resume spacing must be 0 or in [16, 65536]");
+  c->resume_spacing = spacing;
+  return SG_OK;
+}
 
 sg_status sg_ctx_set_persistent(sg_ctx* c, int32_t wgs_per_cu) {
   if (!c || wgs_per_cu < 0 || wgs_per_cu > 64) return fail(SG_E_INVAL, "wgs_per_cu must be 0..64");
@@ -608,6 +649,7 @@ sg_status sg_prepare(sg_ctx* ctx, const sg_scene* clean, const sg_camera* cam, c
     return rc;
   }
   p->host_scene = *clean;
+  p->ck_group = (uint32_t)ctx->resume_spacing;
   DevBox nobox;
   std::memset(&nobox, 0, sizeof(nobox));
   hipStream_t st = S(stream);
@@ -615,7 +657,7 @@ sg_status sg_prepare(sg_ctx* ctx, const sg_scene* clean, const sg_camera* cam, c
   rc = W ? dev_alloc(ctx, p->frame, (size_t)p->cam.W * p->cam.H * 3 * sizeof(float)) : SG_E_NOMEM;
   if (rc == SG_OK)
     rc = full_render(ctx, W, p->scene, nobox, p->cam, p->ras, p->r0, p->r1, p->r2, p->depth, p->rect, p->tile_cnt,
-                     p->tile_start, p->keys, P<float>(p->frame), nullptr, nullptr, st, &p->n_inst);
+                     p->tile_start, p->keys, P<float>(p->frame), nullptr, nullptr, st, &p->n_inst, p);
   if (rc != SG_OK) {
     sg_prep_destroy(p);
     return rc;
@@ -630,7 +672,8 @@ void sg_prep_destroy(sg_prep* p) {
   if (!p) return;
   sg_ctx* c = p->ctx;
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&p->r0, &p->r1, &p->r2, &p->depth, &p->rect, &p->tile_cnt, &p->tile_start, &p->keys, &p->frame};
+  DevBuf* bufs[] = {&p->r0,         &p->r1,   &p->r2,    &p->depth, &p->rect, &p->tile_cnt,
+                    &p->tile_start, &p->keys, &p->frame, &p->stop,  &p->ck,   &p->ck_off};
   for (DevBuf* b : bufs) dev_free(c, *b);
   delete p;
 }
@@ -690,8 +733,6 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
     SG_TRY(dev_alloc(ctx, W->counter, 16));
     SG_TRY(dev_alloc(ctx, W->items, (size_t)B * ras.n_tiles * sizeof(uint2)));
     SG_TRY(dev_alloc(ctx, W->bparts, (size_t)B * ras.n_tiles * sizeof(Partial)));
-    SG_TRY(dev_alloc(ctx, W->vars, (size_t)B * sizeof(sg_variant)));
-    SG_TRY(dev_alloc(ctx, W->bsites, site_cap * sizeof(sg_site)));
     SG_TRY(dev_alloc(ctx, W->gmetrics, (size_t)B * sizeof(sg_metrics_t)));
     int slot = 0;
     SG_TRY(stage_batch(W, sites, n_sites, site_cap, variants, B, &slot));
@@ -702,24 +743,29 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
     const bool graph = ctx->use_graphs && !ctx->timing && full_idx.empty() && !images_out && st != nullptr;
     sg_metrics_t* mout = graph ? P<sg_metrics_t>(W->gmetrics) : metrics_out;
     auto enqueue = [&]() -> sg_status {
-      HIP_TRY(hipMemcpyAsync(W->bsites.p, W->h_sites[slot], site_cap * sizeof(sg_site), hipMemcpyHostToDevice, st));
-      HIP_TRY(hipMemcpyAsync(W->vars.p, W->h_vars[slot], (size_t)B * sizeof(sg_variant), hipMemcpyHostToDevice, st));
       if (images_out)
         for (int v = 0; v < B; ++v)
           HIP_TRY(hipMemcpyAsync(images_out + v * frame_floats, prep->frame.p, frame_floats * sizeof(float),
                                  hipMemcpyDeviceToDevice, st));
-      BatchBuffers bb{P<sg_site>(W->bsites), P<sg_variant>(W->vars), B, P<VariantState>(W->vs), P<Rec>(W->ovr),
+      BatchBuffers bb{W->d_sites[slot], W->d_vars[slot], B, P<VariantState>(W->vs), P<Rec>(W->ovr),
                       P<uint64_t>(W->bitmap), prep->bm_words, prep->row_words, P<uint32_t>(W->item_off),
-                      P<uint32_t>(W->n_items_v), P<uint32_t>(W->n_items_total), P<uint2>(W->items)};
+                      P<uint32_t>(W->n_items_v), P<uint32_t>(W->n_items_total), P<uint2>(W->items),
+                      P<uint32_t>(W->counter), ras.tiles_x};
       {
         PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
         launch_variant_prep(s, b, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
                             P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
-        launch_plan(bb, ras.tiles_x, P<uint32_t>(W->counter), st);
+        launch_plan(bb, st);
       }
       CompArgs ca{P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2), P<uint32_t>(prep->tile_start),
                   P<uint32_t>(prep->tile_cnt), P<uint64_t>(prep->keys), P<float>(prep->frame), images_out,
                   P<Partial>(W->bparts), ras, prep->cam.W, prep->cam.H};
+      if (prep->ck_group) {
+        ca.stop = P<uint32_t>(prep->stop);
+        ca.ck = P<float4>(prep->ck);
+        ca.ck_off = P<uint32_t>(prep->ck_off);
+        ca.ck_group = prep->ck_group;
+      }
       ItemArgs it{P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint2>(W->items), P<uint32_t>(W->n_items_total),
                   P<uint32_t>(W->counter), frame_floats, ctx->n_cu * per_cu};
       {
@@ -738,7 +784,7 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
       std::vector<uintptr_t> key = {(uintptr_t)prep, (uintptr_t)B, site_cap, (uintptr_t)slot, (uintptr_t)per_cu,
                                     (uintptr_t)b.mask, (uintptr_t)b.mode, (uintptr_t)W->vs.p, (uintptr_t)W->ovr.p,
                                     (uintptr_t)W->bitmap.p, (uintptr_t)W->items.p, (uintptr_t)W->bparts.p,
-                                    (uintptr_t)W->bsites.p, (uintptr_t)W->vars.p, (uintptr_t)W->gmetrics.p,
+                                    (uintptr_t)W->h_sites[slot], (uintptr_t)W->h_vars[slot], (uintptr_t)W->gmetrics.p,
                                     (uintptr_t)W->counter.p, (uintptr_t)W->item_off.p, (uintptr_t)W->n_items_v.p,
                                     (uintptr_t)W->n_items_total.p};
       for (int f = 0; f < 6; ++f) { key.push_back((uintptr_t)b.lo[f]); key.push_back((uintptr_t)b.hi[f]); }

@@ -41,6 +41,27 @@ __device__ __forceinline__ void block_reduce_partial(double sse, uint32_t change
   __syncthreads();
 }
 
+// The record of one variant from its reduced partial (Def. 1 footprint,
+// Def. 2 catastrophe, PSNR on [0, 1] images over the three channels).
+__device__ __forceinline__ sg_metrics_t make_metrics(const Partial& red, uint32_t extra_nonfinite, uint32_t dirty,
+                                                     unsigned long long clamps, uint32_t n_pixels, uint32_t path) {
+  sg_metrics_t m;
+  m.sse = red.sse;
+  m.mse = red.sse / (3.0 * (double)n_pixels);
+  m.psnr = m.mse == 0.0 ? __longlong_as_double(0x7ff0000000000000ll) : 10.0 * log10(1.0 / m.mse);
+  m.changed_px = red.changed;
+  m.footprint = (float)((double)red.changed / (double)n_pixels);
+  m.max_abs = red.max_abs;
+  m.nonfinite = red.nonfinite | extra_nonfinite;
+  m.catastrophic = (m.nonfinite || (double)red.changed > 0.01 * (double)n_pixels) ? 1u : 0u;
+  m.dirty_tiles = dirty;
+  m.clamps = clamps;
+  m.n_pixels = n_pixels;
+  m.path = path;
+  m.evals = red.evals;
+  return m;
+}
+
 // k_basic.hip
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 void launch_cast(const float* src, void* dst, int64_t n, int dtype, int mode, hipStream_t st);
@@ -84,11 +105,13 @@ struct BatchBuffers {
   uint32_t* n_items_v;      // B (dirty tiles per variant)
   uint32_t* n_items_total;  // 1
   uint2* items;             // capacity B * n_tiles
+  uint32_t* counter;        // compositing work counter, zeroed by the plan
+  int tiles_x;
 };
 void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                          const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
                          const uint2* rect, const BatchBuffers& bb, hipStream_t st);
-void launch_plan(const BatchBuffers& bb, int tiles_x, uint32_t* counter, hipStream_t st);
+void launch_plan(const BatchBuffers& bb, hipStream_t st);
 
 // k_bin.hip
 struct BinBuffers {
@@ -121,6 +144,18 @@ struct CompArgs {
   Partial* parts;         // per tile / per item; nullable when clean is null
   DevRaster ras;
   int32_t W, H;
+  // Resume state of a prepared clean render.  stop[p]: index, in its tile's
+  // list, of the entry at which pixel p stopped (the list length if it never
+  // stopped, ~0u if its colour was not finite).  ck: per tile, the (C, T)
+  // state of every pixel after each multiple of ck_group list entries, in
+  // slots ck_off[tile] + k - 1 for k = 1 .. count / ck_group.  The clean
+  // render of sg_prepare writes them (*_out); the incremental path reads them.
+  const uint32_t* stop = nullptr;
+  const float4* ck = nullptr;
+  const uint32_t* ck_off = nullptr;
+  uint32_t* stop_out = nullptr;
+  float4* ck_out = nullptr;
+  uint32_t ck_group = 0;
 };
 void launch_composite_full(const CompArgs& a, hipStream_t st);
 struct ItemArgs {

@@ -127,6 +127,38 @@ def test_incremental_equals_full_render(ctx, fmt):
     assert np.all(mi["path"] == 0) and np.all(mf["path"] == 1)
 
 
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_resume_spacing_invariance(ctx, tile):
+    """Skipping pixels that stopped before the first changed list entry and
+    resuming the others from clean checkpoints gives the same images and the
+    same records as walking every merged list from its start, for every
+    checkpoint spacing, and evaluates fewer entries."""
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(6741, seed=3, sh_degree=3)
+    cam = synth.make_camera(200, 160)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    sites = synth.make_sites_stratified(sc.n, 3, 96, seed=17, width_bits=32)
+    groups = [np.array([k]) for k in range(len(sites))]
+    groups += [np.array([0, 1, 2]), np.array([5, 6]), np.array([7, 7])]
+    out = {}
+    try:
+        for g in (0, 16, 64, 4096):
+            ctx.set_resume(g)
+            prep = ctx.prepare(ds, cam, b.raster_struct(tile=tile))
+            out[g] = _batch(ctx, prep, sites, groups)
+    finally:
+        ctx.set_resume(64)
+    img0, m0 = out[0]
+    for g in (16, 64, 4096):
+        img, m = out[g]
+        assert np.array_equal(img, img0), g
+        for key in ("sse", "changed_px", "max_abs", "nonfinite", "dirty_tiles"):
+            assert np.array_equal(m[key], m0[key]), (g, key)
+        assert m["evals"].sum() < m0["evals"].sum(), g
+    full, mf = _batch(ctx, prep, sites, groups, mode=1)
+    assert np.array_equal(out[64][0], full)
+
+
 def test_tile_size_invariance(ctx):
     from paper_2606_21791_amd import binding as b
     sc = synth.make_scene(6000, seed=13, sh_degree=1)
