@@ -28,6 +28,14 @@ import time
 
 import numpy as np
 
+# Hardware queues the HIP runtime spreads streams over (read once, when the
+# runtime starts).  Batches of a campaign are chains of short launches whose
+# throughput comes from running many of them concurrently; HIP's default of 4
+# queues caps that at four chains.
+HW_QUEUES = 16
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < HW_QUEUES:
+    os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -106,14 +114,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use --tile/--streams/--threads/--wgs-per-cu/--resume/--graphs as given instead of the "
+                         "autotuner's choice at the fixed --batch")
     ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--streams", type=int, default=8, help="HIP streams the batches rotate over")
+    ap.add_argument("--streams", type=int, default=16, help="HIP streams the batches rotate over")
+    ap.add_argument("--threads", type=int, default=4,
+                    help="host threads of the native campaign call (0: a Python loop of sg_render_batch calls)")
     ap.add_argument("--wgs-per-cu", type=int, default=2, help="persistent compositing workgroups per CU (0: default)")
     ap.add_argument("--resume", type=int, default=64,
                     help="checkpoint spacing of prepared scenes (0: walk every merged list from its start)")
+    ap.add_argument("--graphs", action="store_true", help="replay each batch as a captured graph")
+    ap.add_argument("--free-batch", type=int, default=512,
+                    help="also tune B up to this bound and time that configuration (0: skip)")
     ap.add_argument("--plain", type=int, default=100, help="injections timed on the plain path")
     ap.add_argument("--cpu-inj", type=int, default=1, help="oracle injections timed on the host (0: skip)")
-    ap.add_argument("--no-graphs", action="store_true", help="launch each batch eagerly instead of replaying a graph")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="seconds of Poisson arrivals for the serving measurement (0: skip)")
     ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve", "copy"],
@@ -134,11 +149,19 @@ def main():
 
     sc, cam, sites = _workload(args.fmt)
     ctx = sgb.Context(0)
+    ds = sgb.DeviceScene.upload(ctx, sc, args.fmt)
+    tune_sample = sgb.sites_array(sites.field[:4096], sites.comp[:4096], sites.prim[:4096], sites.bit[:4096])
+    tuned = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tuned = ctx.autotune(ds, cam, tune_sample, fixed_batch=args.batch)
+        tuned["seconds"] = round(time.perf_counter() - t0, 2)
+        args.tile, args.streams, args.threads = tuned["tile"], tuned["streams"], tuned["threads"]
+        args.wgs_per_cu, args.resume, args.graphs = tuned["wgs_per_cu"], tuned["resume"], bool(tuned["graphs"])
     ctx.set_persistent(args.wgs_per_cu)
     ctx.set_resume(args.resume)
-    ctx.set_graphs(not args.no_graphs)
+    ctx.set_graphs(args.graphs)
     streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
-    ds = sgb.DeviceScene.upload(ctx, sc, args.fmt)
     prep = ctx.prepare(ds, cam, sgb.raster_struct(tile=args.tile))
     torch.cuda.synchronize()
     B = args.batch
@@ -158,17 +181,31 @@ def main():
         with torch.cuda.stream(streams[i % len(streams)]):
             ctx.render_batch(prep, batches[i], va, metrics=mts[i])
 
-    for i in range(args.warmup):
-        run(i)
+    # native campaign: every step's batch in one sg_campaign call (batches of
+    # B round-robin over the streams, enqueued by `threads` host threads)
+    all_idx = np.arange(steps_total * B) % n_sites
+    sa_all = sgb.sites_array(sites.field[all_idx], sites.comp[all_idx], sites.prim[all_idx], sites.bit[all_idx])
+    va_all = sgb.variants_array(np.arange(steps_total * B), np.ones(steps_total * B, np.uint32))
+    w_end = args.warmup * B
+
+    def run_steps(first, last):
+        """Steps [first, last): a campaign call, or a Python loop of batches."""
+        if args.threads > 0:
+            ctx.campaign(prep, sa_all, va_all[first * B:last * B], mt_all[first * rec_bytes:last * rec_bytes],
+                         batch=B, streams=len(streams), threads=args.threads)
+        else:
+            for i in range(first, last):
+                run(i)
+
+    run_steps(0, args.warmup)
     torch.cuda.synchronize()
     with _no_gc():
         t_start = time.perf_counter()
-        for i in range(args.warmup, steps_total):
-            run(i)
+        run_steps(args.warmup, steps_total)
         t_sub = time.perf_counter()
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
-    recs = sgb.read_metrics(mt_all)[args.warmup * B:]
+    recs = sgb.read_metrics(mt_all)[w_end:]
     inj_per_s = args.steps * B / elapsed
 
     # the same steps again with per-pass HIP events (graphs are not used while
@@ -176,17 +213,44 @@ def main():
     ctx.timing(True)
     ctx.pass_times()
     with _no_gc():
-        for i in range(args.warmup, steps_total):
-            run(i)
+        run_steps(args.warmup, steps_total)
         torch.cuda.synchronize()
     passes = ctx.pass_times()
     ctx.timing(False)
+    recs_timed = sgb.read_metrics(mt_all)[w_end:]
 
     # dominant kernel: the persistent compositing launch
     comp_ms, comp_n = passes["composite_items"]
     comp_avg_s = comp_ms / max(comp_n, 1) / 1e3
     evals_per_launch = float(recs["evals"].sum()) / args.steps
     achieved = evals_per_launch * FLOPS_PER_EVAL / comp_avg_s / 1e12 if comp_avg_s > 0 else 0.0
+
+    # the same injections with B tuned too (many variants per launch)
+    free = None
+    if args.free_batch > 0:
+        t0 = time.perf_counter()
+        tf = ctx.autotune(ds, cam, tune_sample, max_batch=args.free_batch)
+        tf["seconds"] = round(time.perf_counter() - t0, 2)
+        ctx_f = sgb.Context(0)
+        ctx_f.apply_tune(tf)
+        prep_f = ctx_f.prepare(ds, cam, sgb.raster_struct(tile=tf["tile"]))
+        n_inj = args.steps * B
+        mt_f = sgb.metrics_tensor(n_inj)
+        kw = dict(batch=tf["batch"], streams=tf["streams"], threads=tf["threads"])
+        ctx_f.campaign(prep_f, sa_all, va_all[w_end:w_end + min(n_inj, 4 * tf["batch"])], mt_f, **kw)
+        torch.cuda.synchronize()
+        with _no_gc():
+            t0 = time.perf_counter()
+            ctx_f.campaign(prep_f, sa_all, va_all[w_end:w_end + n_inj], mt_f, **kw)
+            torch.cuda.synchronize()
+            dt_f = time.perf_counter() - t0
+        rf = sgb.read_metrics(mt_f)
+        same = all(np.array_equal(rf[k], recs[k]) for k in ("changed_px", "max_abs", "nonfinite")) and \
+            bool(np.allclose(rf["sse"], recs["sse"], rtol=1e-12, atol=0.0))
+        free = {"value": round(n_inj / dt_f, 1), "unit": "injections/s", "injections": n_inj,
+                "config": {k: tf[k] for k in ("tile", "batch", "streams", "threads", "wgs_per_cu", "resume", "graphs")},
+                "tune_seconds": tf["seconds"], "records_identical_to_headline": same}
+        del prep_f, ctx_f
 
     # plain path: inject, full render with metrics against the clean frame, restore, read back
     frame = prep.frame()
@@ -237,12 +301,17 @@ def main():
                                f"800x800, {args.tile}x{args.tile} tiles, B={B} single-bit variants per launch, "
                                "incremental dirty-tile re-composite",
                    "global_batch": B, "n_sites": n_sites, "instances_clean": prep.instances(),
-                   "streams": len(streams), "wgs_per_cu": args.wgs_per_cu, "graphs": not args.no_graphs},
+                   "streams": len(streams), "host_threads": args.threads, "wgs_per_cu": args.wgs_per_cu,
+                   "graphs": args.graphs, "resume_spacing": args.resume,
+                   "tuned": tuned is not None, "gpu_max_hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"])},
+        "repeat_records_identical": bool(all(np.array_equal(recs[k], recs_timed[k])
+                                             for k in ("sse", "changed_px", "max_abs", "nonfinite", "evals"))),
         "plain": {"value": round(P / plain_dt, 1), "unit": "injections/s", "injections": P,
                   "ms_per_injection": round(plain_dt / P * 1e3, 4),
                   "pass_ms_per_injection": {k: round(v[0] / max(P, 1), 4) for k, v in plain_passes.items() if v[1]},
                   "records_agree_with_batched": agree},
         "speedup_vs_plain": round(inj_per_s / (P / plain_dt), 2),
+        "tuned_any_batch": free,
         "pass_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in passes.items() if v[1]},
         "host_submit_ms_per_step": round((t_sub - t_start) * 1e3 / args.steps, 4),
         "dirty_tiles_per_injection": round(float(recs["dirty_tiles"].mean()), 2),

@@ -238,6 +238,57 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
                           const sg_variant* variants, int32_t B, const sg_box* box, uint32_t box_field_mask,
                           float* images_out, sg_metrics_t* metrics_out, int32_t mode, void* stream);
 
+/* A campaign: n_variants variants of one prepared scene, rendered as
+ * consecutive batches of cfg->batch variants (the launch size B of
+ * sg_render_batch), the batches spread round-robin over cfg->streams device
+ * streams of the context, which cfg->threads host threads enqueue
+ * concurrently (the parallel injection engine of Sec. 3 run as one call).
+ * metrics_out (device, n_variants records) receives the same records as
+ * sg_render_batch on each batch in turn; no images.  sites and variants are
+ * host arrays as in sg_render_batch (offsets index `sites`).  The launches
+ * are ordered after earlier work on `stream`, and later work on `stream` is
+ * ordered after them; the call returns once everything is enqueued.  cfg may
+ * be NULL (batch 32, 8 streams, 2 threads).  Errors of any batch stop the
+ * campaign and are reported with the batch index. */
+typedef struct {
+  int32_t batch;     /* variants per launch; 0 = 32 */
+  int32_t streams;   /* device streams; 0 = 8 (at most 64) */
+  int32_t threads;   /* host threads; 0 = 2 (at most streams) */
+  int32_t _pad;
+} sg_campaign_cfg;
+sg_status sg_campaign(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites, const sg_variant* variants,
+                      int32_t n_variants, const sg_box* box, uint32_t box_field_mask, const sg_campaign_cfg* cfg,
+                      sg_metrics_t* metrics_out, void* stream);
+
+/* Autotuner.  Picks the launch configuration of injection campaigns on one
+ * scene and camera by measurement: tile size, variants per launch B,
+ * campaign streams and host threads, persistent compositing workgroups per
+ * CU, checkpoint spacing and graph replay.  It prepares the scene at each
+ * candidate tile size and spacing, times campaigns of single-site variants
+ * over `sites` (host, at least 64; the sample should follow the campaign's
+ * site distribution) and moves one parameter at a time to its best value
+ * until none improves (two sweeps at most).  fixed_batch > 0 keeps B at that
+ * value; otherwise B is tuned up to max_batch (0 = 512).  The rendered
+ * results never depend on the choice: every configuration is bit-identical.
+ *
+ * cache_path (nullable) names a text file of one JSON object per line, keyed
+ * by device architecture, primitive-count bucket (ceil log2 N), frame size,
+ * storage format, SH degree, fixed_batch and max_batch.  A hit fills *out
+ * with from_cache = 1 and touches no device; a miss measures, appends the
+ * result and sets from_cache = 0.  The context's settings are restored
+ * before returning; the caller applies the result (sg_ctx_set_persistent,
+ * sg_ctx_set_resume, sg_ctx_set_graphs before sg_prepare with the tile size,
+ * and batch/streams/threads in sg_campaign). */
+typedef struct {
+  int32_t tile, batch, streams, threads, wgs_per_cu, resume, graphs, from_cache;
+  double inj_per_s;   /* measured rate of the chosen configuration */
+  int32_t trials;     /* configurations measured */
+  int32_t _pad;
+} sg_tune_t;
+sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_camera* cam, const sg_raster* raster,
+                      const sg_site* sites, int32_t n_sites, int32_t fixed_batch, int32_t max_batch,
+                      const char* cache_path, sg_tune_t* out, void* stream);
+
 /* Workgroups per compute unit of the persistent incremental compositing
  * launch (0 = default for the tile size).  Fewer leave room for batches on
  * other streams to run concurrently; this is one of the tuned parameters. */

@@ -54,6 +54,16 @@ class SgBox(C.Structure):
     _fields_ = [("mode", C.c_int32), ("dtype", C.c_int32), ("lo", C.c_void_p * 6), ("hi", C.c_void_p * 6)]
 
 
+class SgCampaignCfg(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("streams", C.c_int32), ("threads", C.c_int32), ("_pad", C.c_int32)]
+
+
+class SgTune(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("batch", C.c_int32), ("streams", C.c_int32), ("threads", C.c_int32),
+                ("wgs_per_cu", C.c_int32), ("resume", C.c_int32), ("graphs", C.c_int32), ("from_cache", C.c_int32),
+                ("inj_per_s", C.c_double), ("trials", C.c_int32), ("_pad", C.c_int32)]
+
+
 class SgServeConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("max_batch", C.c_int32),
                 ("queue_depth", C.c_int32), ("plain", C.c_int32)]
@@ -112,7 +122,9 @@ def _load():
         "sg_prep_instances": (i64, [vp]),
         "sg_prep_copy_frame": (i32, [vp, vp, vp]),
         "sg_render_batch": (i32, [vp, vp, vp, i32, vp, i32, P(SgBox), u32, vp, vp, i32, vp]),
+        "sg_campaign": (i32, [vp, vp, vp, i32, vp, i32, P(SgBox), u32, P(SgCampaignCfg), vp, vp]),
         "sg_metrics": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
+        "sg_autotune": (i32, [vp, P(SgScene), P(SgCamera), P(SgRaster), vp, i32, i32, i32, C.c_char_p, P(SgTune), vp]),
         "sg_ctx_timing": (i32, [vp, i32]),
         "sg_serve_create": (i32, [i32, P(SgServeConfig), P(vp)]),
         "sg_serve_add_scene": (i32, [vp, P(SgScene), P(SgBox), u32, P(i32)]),
@@ -138,7 +150,7 @@ def _load():
 LIB = _load()
 EXPORTED = ("sg_ctx_create", "sg_ctx_destroy", "sg_last_error", "sg_ctx_bytes", "sg_cast", "sg_inject",
             "sg_restore", "sg_guard_box", "sg_guard", "sg_render", "sg_prepare", "sg_prep_destroy",
-            "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_metrics",
+            "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_campaign", "sg_autotune", "sg_metrics",
             "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_resume", "sg_ctx_set_graphs",
             "sg_serve_create",
             "sg_serve_add_scene", "sg_serve_add_view", "sg_serve_submit", "sg_serve_poll", "sg_serve_wait",
@@ -285,6 +297,35 @@ class Context:
         check(LIB.sg_render_batch(self.h, prep.h, s.ctypes.data_as(C.c_void_p), len(s), v.ctypes.data_as(C.c_void_p),
                                   len(v), C.byref(box.st) if box is not None else None,
                                   box_mask if box is not None else 0, _ptr(images), _ptr(metrics), mode, _stream()))
+
+    def campaign(self, prep, sites: np.ndarray, variants: np.ndarray, metrics, box=None,
+                 box_mask: int = SG_FIELD_MASK_GUARD, batch: int = 32, streams: int = 8, threads: int = 2):
+        """All variants of a campaign in batches of `batch`, over `streams` device
+        streams enqueued by `threads` host threads; records into `metrics`."""
+        s = np.ascontiguousarray(sites, SITE_DTYPE)
+        v = np.ascontiguousarray(variants, VARIANT_DTYPE)
+        cfg = SgCampaignCfg(int(batch), int(streams), int(threads), 0)
+        check(LIB.sg_campaign(self.h, prep.h, s.ctypes.data_as(C.c_void_p), len(s), v.ctypes.data_as(C.c_void_p),
+                              len(v), C.byref(box.st) if box is not None else None, box_mask if box is not None else 0,
+                              C.byref(cfg), _ptr(metrics), _stream()))
+
+    def autotune(self, scene, cam, sites: np.ndarray, raster=None, fixed_batch: int = 0, max_batch: int = 0,
+                 cache: str | None = None) -> dict:
+        """Measured launch configuration for campaigns on this scene and camera
+        (see sg_autotune); the context's own settings are left unchanged."""
+        s = np.ascontiguousarray(sites, SITE_DTYPE)
+        out = SgTune()
+        check(LIB.sg_autotune(self.h, C.byref(scene.st), C.byref(camera_struct(cam)),
+                              C.byref(raster) if raster is not None else None, s.ctypes.data_as(C.c_void_p), len(s),
+                              int(fixed_batch), int(max_batch), cache.encode() if cache else None, C.byref(out),
+                              _stream()))
+        return {k: getattr(out, k) for k, _ in SgTune._fields_ if not k.startswith("_")}
+
+    def apply_tune(self, t: dict):
+        """Context settings of a tuned configuration (prepare with tile=t["tile"] afterwards)."""
+        self.set_persistent(t["wgs_per_cu"])
+        self.set_resume(t["resume"])
+        self.set_graphs(bool(t["graphs"]))
 
     def metrics(self, images, clean, B, K, H, W, out):
         check(LIB.sg_metrics(self.h, _ptr(images), _ptr(clean), B, K, H, W, _ptr(out), _stream()))

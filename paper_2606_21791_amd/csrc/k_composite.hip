@@ -197,7 +197,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
   }
 
   double sse = 0.0;
-  uint32_t changed = 0, nonfin = 0;
+  uint32_t changed = 0, nonfin = 0, my_stop = 0;
   float mx = 0.f;
   if (inside && !same) {
     const float p0 = fmaf(T, A.ras.bg[0], C0), p1 = fmaf(T, A.ras.bg[1], C1), p2 = fmaf(T, A.ras.bg[2], C2);
@@ -205,8 +205,10 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
     const float i0 = fminf(p0, 1.f), i1 = fminf(p1, 1.f), i2 = fminf(p2, 1.f);
     const int64_t off = ((int64_t)y * A.W + x) * 3;
     if (img) { img[off] = i0; img[off + 1] = i1; img[off + 2] = i2; }
-    if (MODE == kFullWrite)
-      A.stop_out[(int64_t)y * A.W + x] = nonfin ? ~0u : (done ? evals - 1u : mlen);
+    if (MODE == kFullWrite) {
+      my_stop = nonfin ? ~0u : (done ? evals - 1u : mlen);
+      A.stop_out[(int64_t)y * A.W + x] = my_stop;
+    }
     if (A.clean) {
       const double d0 = (double)i0 - (double)A.clean[off], d1 = (double)i1 - (double)A.clean[off + 1],
                    d2 = (double)i2 - (double)A.clean[off + 2];
@@ -215,6 +217,15 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
       changed = dm > (1.0 / 255.0) ? 1u : 0u;
       mx = (float)dm;
     }
+  }
+  if (MODE == kFullWrite) {
+    // the key at which the tile's last pixel stopped
+    __shared__ uint32_t s_smax;
+    if (tid == 0) s_smax = 0;
+    __syncthreads();
+    if (inside) atomicMax(&s_smax, my_stop);
+    __syncthreads();
+    if (tid == 0) A.stop_key_out[tile] = s_smax >= mlen ? ~0ull : A.keys[raw_start + s_smax];
   }
   if (part) block_reduce_partial(sse, changed, mx, nonfin, (unsigned long long)evals, part);
 }
@@ -241,9 +252,14 @@ __device__ __forceinline__ bool rect_has(uint32_t r0, uint32_t r1, int tx, int t
 // Persistent incremental compositing: a fixed grid of workgroups pops
 // (variant, tile) work items from a device counter until the batch's item
 // count (known only on the device) is exhausted.  Per item, the positions of
-// the corrupted primitives' old keys and new keys in the tile's clean list are
-// found by one parallel counting pass over the list (the number of keys below
-// a target is its lower bound).
+// the corrupted primitives' old keys and new keys in the tile's sorted clean
+// list (each target's lower bound) are found by a two-round parallel search:
+// the last keys of TILE*TILE equal buckets locate each target's bucket, and
+// one pass over that bucket counts the keys below the target.
+//
+// An item is skipped outright when the merged list equals the clean list, or
+// when every target key lies after the key at which the tile's last pixel
+// stopped in the clean render: no pixel of the tile reaches a changed entry.
 template <int TILE>
 __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, ItemArgs I) {
   constexpr int BS = TILE * TILE;
@@ -252,8 +268,8 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
   __shared__ MergeSpec ms;
   __shared__ uint32_t s_item;
   __shared__ uint64_t s_tgt[NT];        // removal keys, then insertion keys (sorted)
-  __shared__ uint32_t s_cnt[NT], s_fnd[NT];
-  __shared__ int s_nr, s_ni;
+  __shared__ uint32_t s_cnt[NT], s_fnd[NT], s_bkt[NT];
+  __shared__ int s_nr, s_ni, s_skip;
   const uint32_t total = *I.n_items_total;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(I.counter, 1u);
@@ -263,7 +279,7 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
     const uint2 it = I.items[item];
     const uint32_t v = it.x;
     const int tile = (int)it.y;
-    if (threadIdx.x < NT) { s_cnt[threadIdx.x] = 0; s_fnd[threadIdx.x] = 0; }
+    if (threadIdx.x < NT) { s_cnt[threadIdx.x] = 0; s_fnd[threadIdx.x] = 0; s_bkt[threadIdx.x] = 0; }
     if (threadIdx.x == 0) {
       const VariantState& vs = I.vs[v];
       const int tx = tile % A.ras.tiles_x, ty = tile / A.ras.tiles_x;
@@ -290,22 +306,53 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
         }
       s_nr = nr;
       s_ni = ni;
+      uint64_t mn = ~0ull;
+      for (int j = 0; j < nr + ni; ++j) mn = min(mn, s_tgt[j]);
+      s_skip = (nr + ni == 0) || (A.stop_key && mn > A.stop_key[tile]);
     }
     __syncthreads();
-    const int nr = s_nr, nt = s_nr + s_ni;
-    // one pass over the list per target keeps the register footprint of the
-    // compositing loop unchanged (targets are few: usually one old, one new key)
-    for (int j = 0; j < nt; ++j) {
-      const uint64_t tgt = s_tgt[j];
-      const uint64_t* keys = A.keys + ms.raw_start;
-      uint32_t c = 0, f = 0;
-      for (uint32_t m = threadIdx.x; m < ms.raw_len; m += BS) {
-        const uint64_t key = keys[m];
-        c += key < tgt ? 1u : 0u;
-        f |= key == tgt ? 1u : 0u;
+    if (s_skip) {
+      if (threadIdx.x == 0) {
+        Partial z;
+        z.sse = 0.0; z.evals = 0; z.changed = 0; z.max_abs = 0.f; z.nonfinite = 0; z._pad = 0;
+        A.parts[item] = z;
       }
-      for (int o = 32; o > 0; o >>= 1) { c += (uint32_t)__shfl_xor((int)c, o); f |= (uint32_t)__shfl_xor((int)f, o); }
-      if ((threadIdx.x & 63) == 0 && (c | f)) { atomicAdd(&s_cnt[j], c); atomicOr(&s_fnd[j], f); }
+      __syncthreads();
+      continue;
+    }
+    const int nr = s_nr, nt = s_nr + s_ni;
+    {
+      const uint64_t* keys = A.keys + ms.raw_start;
+      const uint32_t L = ms.raw_len, G = (L + BS - 1) / BS;   // bucket width
+      const int lane = threadIdx.x & 63;
+      // round 1: a target's bucket is the number of buckets whose last key is below it
+      uint64_t last = ~0ull;
+      if (threadIdx.x * G < L) last = keys[min(L, (threadIdx.x + 1) * G) - 1];
+      for (int j = 0; j < nt; ++j) {
+        const unsigned long long m = __ballot(last < s_tgt[j]);
+        if (lane == 0 && m) atomicAdd(&s_bkt[j], (uint32_t)__popcll(m));
+      }
+      __syncthreads();
+      // round 2: keys below the target inside its bucket, and whether it is present
+      for (int j = 0; j < nt; ++j) {
+        const uint64_t tgt = s_tgt[j];
+        const uint32_t b0 = s_bkt[j] * G, b1 = min(L, b0 + G);
+        uint32_t c = 0;
+        bool eq = false;
+        for (uint32_t m = b0 + threadIdx.x; m < b1; m += BS) {
+          const uint64_t key = keys[m];
+          c += key < tgt ? 1u : 0u;
+          eq |= key == tgt;
+        }
+        for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o);
+        const unsigned long long me = __ballot(eq);
+        if (lane == 0) {
+          if (c) atomicAdd(&s_cnt[j], c);
+          if (me) atomicOr(&s_fnd[j], 1u);
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x < nt) s_cnt[threadIdx.x] += min(s_bkt[threadIdx.x] * G, L);
     }
     __syncthreads();
     if (threadIdx.x == 0) {

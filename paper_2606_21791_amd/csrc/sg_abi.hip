@@ -6,10 +6,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "sg_kernels.h"
+#include "sg_settings.h"
 
 using namespace sg;
 
@@ -89,6 +92,10 @@ struct sg_ctx {
   int resume_spacing = 64;                 // checkpoint spacing of prepared scenes (0: none)
   bool use_graphs = true;
   std::vector<Workspace*> ws;
+  std::vector<hipStream_t> campaign_streams;   // created by sg_campaign, default priority
+  // guards ws, in_use and the timing state: sg_campaign enqueues from several
+  // host threads, each on its own streams (so each on its own workspaces)
+  std::mutex mu;
   // per-pass event timing (sg_ctx_timing)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -103,7 +110,7 @@ struct sg_prep {
   DevRaster ras;
   int64_t n_inst = 0;
   DevBuf r0, r1, r2, depth, rect, tile_cnt, tile_start, keys, frame;
-  DevBuf stop, ck, ck_off;                 // resume state of the clean render
+  DevBuf stop, ck, ck_off, stop_key;       // resume state of the clean render
   uint32_t ck_group = 0;
   int bm_words = 0, row_words = 0;
 };
@@ -113,26 +120,31 @@ namespace {
 sg_status dev_alloc(sg_ctx* ctx, DevBuf& b, size_t bytes) {
   if (bytes <= b.bytes) return SG_OK;
   bytes = std::max<size_t>(bytes, 256);
-  if (ctx->budget && ctx->in_use - b.bytes + bytes > ctx->budget)
-    return fail(SG_E_NOMEM, "device budget exceeded");
-  if (b.p) {
-    (void)hipFree(b.p);
-    ctx->in_use -= b.bytes;
-    b.p = nullptr;
-    b.bytes = 0;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (ctx->budget && ctx->in_use - b.bytes + bytes > ctx->budget)
+      return fail(SG_E_NOMEM, "device budget exceeded");
+    ctx->in_use += bytes - b.bytes;
   }
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) return fail(SG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->in_use -= bytes;
+    return fail(SG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
   b.p = p;
   b.bytes = bytes;
-  ctx->in_use += bytes;
   return SG_OK;
 }
 
 void dev_free(sg_ctx* ctx, DevBuf& b) {
   if (b.p) {
     (void)hipFree(b.p);
+    std::lock_guard<std::mutex> g(ctx->mu);
     ctx->in_use -= b.bytes;
   }
   b.p = nullptr;
@@ -140,6 +152,7 @@ void dev_free(sg_ctx* ctx, DevBuf& b) {
 }
 
 Workspace* workspace(sg_ctx* ctx, hipStream_t st) {
+  std::lock_guard<std::mutex> g(ctx->mu);
   for (Workspace* w : ctx->ws)
     if (w->stream == st) return w;
   Workspace* w = new Workspace();
@@ -218,6 +231,7 @@ struct PassScope {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   static hipEvent_t get(sg_ctx* c) {
+    std::lock_guard<std::mutex> g(c->mu);
     if (!c->ev_pool.empty()) {
       hipEvent_t e = c->ev_pool.back();
       c->ev_pool.pop_back();
@@ -236,6 +250,7 @@ struct PassScope {
   ~PassScope() {
     if (a && b) {
       (void)hipEventRecord(b, st);
+      std::lock_guard<std::mutex> g(c->mu);
       c->pending[pass].push_back({a, b});
     }
   }
@@ -440,12 +455,14 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
     const size_t bs = (size_t)ras.tile * ras.tile;
     SG_TRY(dev_alloc(ctx, resume->stop, (size_t)cam.W * cam.H * sizeof(uint32_t)));
     SG_TRY(dev_alloc(ctx, resume->ck_off, ras.n_tiles * sizeof(uint32_t)));
+    SG_TRY(dev_alloc(ctx, resume->stop_key, ras.n_tiles * sizeof(uint64_t)));
     SG_TRY(dev_alloc(ctx, resume->ck, std::max<size_t>(slots, 1) * bs * sizeof(float4)));
     HIP_TRY(hipMemcpyAsync(resume->ck_off.p, off.data(), ras.n_tiles * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));        // `off` is released on return
     ca.stop_out = P<uint32_t>(resume->stop);
     ca.ck_out = P<float4>(resume->ck);
     ca.ck_off = P<uint32_t>(resume->ck_off);
+    ca.stop_key_out = P<uint64_t>(resume->stop_key);
     ca.ck_group = g;
   }
   {
@@ -485,6 +502,7 @@ void sg_ctx_destroy(sg_ctx* c) {
   (void)hipDeviceSynchronize();
   for (Workspace* w : c->ws) free_workspace(c, w);
   c->ws.clear();
+  for (hipStream_t st : c->campaign_streams) (void)hipStreamDestroy(st);
   for (int p = 0; p < SG_N_PASSES; ++p)
     for (auto& pr : c->pending[p]) c->ev_pool.insert(c->ev_pool.end(), {pr.first, pr.second});
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -492,6 +510,22 @@ void sg_ctx_destroy(sg_ctx* c) {
 }
 
 size_t sg_ctx_bytes(const sg_ctx* c) { return c ? c->in_use : 0; }
+
+}  // extern "C"
+
+SgSettings sg_settings_get(const sg_ctx* c) {
+  return {c->device, c->persistent_wgs_per_cu, c->resume_spacing, c->use_graphs ? 1 : 0};
+}
+
+sg_status sg_fail(sg_status code, const char* msg) { return fail(code, msg); }
+
+void sg_settings_set(sg_ctx* c, const SgSettings& s) {
+  c->persistent_wgs_per_cu = s.wgs_per_cu;
+  c->resume_spacing = s.resume_spacing;
+  c->use_graphs = s.graphs != 0;
+}
+
+extern "C" {
 
 sg_status sg_ctx_set_resume(sg_ctx* c, int32_t spacing) {
   if (!c) return fail(SG_E_INVAL, "ctx is NULL");
@@ -673,7 +707,7 @@ void sg_prep_destroy(sg_prep* p) {
   sg_ctx* c = p->ctx;
   (void)hipDeviceSynchronize();
   DevBuf* bufs[] = {&p->r0,         &p->r1,   &p->r2,    &p->depth, &p->rect, &p->tile_cnt,
-                    &p->tile_start, &p->keys, &p->frame, &p->stop,  &p->ck,   &p->ck_off};
+                    &p->tile_start, &p->keys, &p->frame, &p->stop,  &p->ck,   &p->ck_off, &p->stop_key};
   for (DevBuf* b : bufs) dev_free(c, *b);
   delete p;
 }
@@ -764,6 +798,7 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
         ca.stop = P<uint32_t>(prep->stop);
         ca.ck = P<float4>(prep->ck);
         ca.ck_off = P<uint32_t>(prep->ck_off);
+        ca.stop_key = P<uint64_t>(prep->stop_key);
         ca.ck_group = prep->ck_group;
       }
       ItemArgs it{P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint2>(W->items), P<uint32_t>(W->n_items_total),
@@ -848,6 +883,90 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
       SG_TRY(check_last("sg_render_batch full"));
     }
   }
+  return SG_OK;
+}
+
+sg_status sg_campaign(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites, const sg_variant* variants,
+                      int32_t n_variants, const sg_box* box, uint32_t box_field_mask, const sg_campaign_cfg* cfg,
+                      sg_metrics_t* metrics_out, void* stream) {
+  if (!ctx || !prep || !metrics_out) return fail(SG_E_INVAL, "ctx/prep/metrics_out is NULL");
+  if (n_variants < 0 || (n_variants > 0 && !variants)) return fail(SG_E_INVAL, "bad variants");
+  const int B = cfg && cfg->batch > 0 ? cfg->batch : 32;
+  const int NS = cfg && cfg->streams > 0 ? cfg->streams : 8;
+  const int NT = std::min(cfg && cfg->threads > 0 ? cfg->threads : 2, NS);
+  if (B > 65536 || NS > 64 || NT > 64) return fail(SG_E_INVAL, "campaign batch/streams/threads out of range");
+  SG_TRY(validate_sites(prep->scene, sites, n_sites));
+  for (int v = 0; v < n_variants; ++v)
+    if ((uint64_t)variants[v].site_off + variants[v].n_sites > (uint64_t)n_sites)
+      return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": sites out of range");
+  if (n_variants == 0) return SG_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    while ((int)ctx->campaign_streams.size() < NS) {
+      hipStream_t st = nullptr;
+      HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      ctx->campaign_streams.push_back(st);
+    }
+  }
+  // the campaign's launches follow the caller's earlier work on `stream` and
+  // the caller's later work follows all of them
+  hipStream_t caller = S(stream);
+  hipEvent_t start = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(start, caller));
+  for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(ctx->campaign_streams[k], start, 0));
+  (void)hipEventDestroy(start);
+
+  const int nb = (n_variants + B - 1) / B;
+  std::mutex err_mu;
+  sg_status first_rc = SG_OK;
+  std::string first_msg;
+  auto worker = [&](int t) {
+    (void)hipSetDevice(ctx->device);
+    std::vector<sg_variant> local;
+    for (int b = 0; b < nb; ++b) {
+      const int k = b % NS;
+      if (k % NT != t) continue;
+      {
+        std::lock_guard<std::mutex> g(err_mu);
+        if (first_rc != SG_OK) return;
+      }
+      const int v0 = b * B, nv = std::min(B, n_variants - v0);
+      // the sites this batch refers to, with its variants' offsets rebased
+      uint32_t lo = UINT32_MAX, hi = 0;
+      for (int v = v0; v < v0 + nv; ++v) {
+        lo = std::min(lo, variants[v].site_off);
+        hi = std::max(hi, variants[v].site_off + variants[v].n_sites);
+      }
+      if (lo > hi) lo = hi = 0;
+      local.assign(variants + v0, variants + v0 + nv);
+      for (sg_variant& x : local) x.site_off -= lo;
+      const sg_status rc = sg_render_batch(ctx, prep, sites + lo, (int32_t)(hi - lo), local.data(), nv, box,
+                                           box_field_mask, nullptr, metrics_out + v0, SG_INCREMENTAL,
+                                           ctx->campaign_streams[k]);
+      if (rc != SG_OK) {
+        std::lock_guard<std::mutex> g(err_mu);
+        if (first_rc == SG_OK) {
+          first_rc = rc;
+          first_msg = "batch " + std::to_string(b) + ": " + g_err;
+        }
+        return;
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < NT; ++t) pool.emplace_back(worker, t);
+  worker(0);
+  for (std::thread& th : pool) th.join();
+  for (int k = 0; k < NS; ++k) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(e, ctx->campaign_streams[k]));
+    HIP_TRY(hipStreamWaitEvent(caller, e, 0));
+    (void)hipEventDestroy(e);
+  }
+  if (first_rc != SG_OK) return fail(first_rc, first_msg);
   return SG_OK;
 }
 

@@ -150,11 +150,15 @@ struct CompArgs {
   // state of every pixel after each multiple of ck_group list entries, in
   // slots ck_off[tile] + k - 1 for k = 1 .. count / ck_group.  The clean
   // render of sg_prepare writes them (*_out); the incremental path reads them.
+  // stop_key[t]: the key of the entry at which the last pixel of tile t
+  // stopped (all ones if a pixel never stopped or was not finite).
   const uint32_t* stop = nullptr;
   const float4* ck = nullptr;
   const uint32_t* ck_off = nullptr;
+  const uint64_t* stop_key = nullptr;
   uint32_t* stop_out = nullptr;
   float4* ck_out = nullptr;
+  uint64_t* stop_key_out = nullptr;
   uint32_t ck_group = 0;
 };
 void launch_composite_full(const CompArgs& a, hipStream_t st);

@@ -201,6 +201,90 @@ def test_guarded_and_multi_upset_variants(ctx):
             assert np.max(ms["footprint"][:32]) < 0.2
 
 
+def test_campaign_matches_batches(ctx):
+    """sg_campaign over several streams and host threads gives, per variant,
+    exactly the records of sg_render_batch on the same batches one by one,
+    with guarded, multi-site and full-path variants and a ragged last batch."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(4000, seed=14, sh_degree=1)
+    cam = synth.make_camera(160, 128)
+    lo32, hi32 = synth.make_box_jitter(sc, seed=4)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    box = b.Box.per_prim(ctx, lo32, hi32, "f32")
+    prep = ctx.prepare(ds, cam)
+    single = synth.make_sites_stratified(sc.n, 1, 40, seed=19, width_bits=32)
+    dose = synth.make_sites_dose(sc.n, 1, 12, seed=20, width_bits=32)      # 12 primitives: full path
+    sites = synth.Sites(*(np.concatenate([a, c]) for a, c in zip(
+        (single.field, single.comp, single.prim, single.bit), (dose.field, dose.comp, dose.prim, dose.bit))))
+    ns = len(single.prim)
+    sa = b.sites_array(sites.field, sites.comp, sites.prim, sites.bit)
+    offs = list(range(ns)) + [0, ns]
+    cnts = [1] * ns + [3, len(dose.prim)]
+    guard = np.array([(k % 3 == 0) for k in range(len(offs))], np.uint32)
+    va = b.variants_array(np.array(offs), np.array(cnts), 0)
+    va["guard"] = guard
+    B = 7
+    ref = []
+    for v0 in range(0, len(va), B):
+        mt = b.metrics_tensor(len(va[v0:v0 + B]))
+        ctx.render_batch(prep, sa, va[v0:v0 + B], box=box, metrics=mt)
+        ref.append(b.read_metrics(mt))
+    ref = np.concatenate(ref)
+    for streams, threads in ((1, 1), (4, 2), (5, 3)):
+        mt = b.metrics_tensor(len(va))
+        ctx.campaign(prep, sa, va, mt, box=box, batch=B, streams=streams, threads=threads)
+        torch.cuda.synchronize()
+        got = b.read_metrics(mt)
+        for key in ("sse", "changed_px", "max_abs", "nonfinite", "dirty_tiles", "clamps", "path", "evals"):
+            assert np.array_equal(got[key], ref[key]), (streams, threads, key)
+    assert ref["path"][-1] == 1 and np.all(ref["path"][:-1] == 0)
+    with pytest.raises(b.SgError):
+        bad = va.copy()
+        bad["site_off"][3] = len(sa)
+        ctx.campaign(prep, sa, bad, b.metrics_tensor(len(va)), box=box, batch=B)
+
+
+def test_autotune_and_cache(ctx, tmp_path):
+    """The autotuner returns a valid configuration, caches it (a second call
+    is a hit and measures nothing), leaves the context's settings alone, and
+    the tuned configuration gives the same records as the defaults."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(6741, seed=3, sh_degree=3)
+    cam = synth.make_camera(200, 160)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    sites = synth.make_sites_stratified(sc.n, 3, 64, seed=23, width_bits=32)
+    sa = b.sites_array(sites.field, sites.comp, sites.prim, sites.bit)
+    cache = str(tmp_path / "tune.jsonl")
+    t = ctx.autotune(ds, cam, sa[:512], max_batch=128, cache=cache)
+    assert t["from_cache"] == 0 and t["trials"] >= 10 and t["inj_per_s"] > 0
+    assert t["tile"] in (8, 16, 32) and t["batch"] in (32, 64, 128) and t["resume"] in (32, 64, 128, 256)
+    assert 1 <= t["threads"] <= t["streams"] and t["wgs_per_cu"] in (1, 2, 4, 8) and t["graphs"] in (0, 1)
+    t2 = ctx.autotune(ds, cam, sa[:512], max_batch=128, cache=cache)
+    assert t2["from_cache"] == 1 and t2["trials"] == 0
+    assert {k: t2[k] for k in ("tile", "batch", "streams", "threads", "wgs_per_cu", "resume", "graphs")} == \
+        {k: t[k] for k in ("tile", "batch", "streams", "threads", "wgs_per_cu", "resume", "graphs")}
+    tf = ctx.autotune(ds, cam, sa[:512], fixed_batch=32, cache=cache)
+    assert tf["batch"] == 32 and tf["from_cache"] == 0
+    with pytest.raises(b.SgError):
+        ctx.autotune(ds, cam, sa[:10])
+    n = len(sa)
+    va = b.variants_array(np.arange(n), np.ones(n, np.uint32))
+    ref = b.metrics_tensor(n)
+    prep = ctx.prepare(ds, cam)
+    ctx.campaign(prep, sa, va, ref)
+    tuned = b.Context(0)
+    tuned.apply_tune(t)
+    prep_t = tuned.prepare(ds, cam, b.raster_struct(tile=t["tile"]))
+    got = b.metrics_tensor(n)
+    tuned.campaign(prep_t, sa, va, got, batch=t["batch"], streams=t["streams"], threads=t["threads"])
+    torch.cuda.synchronize()
+    r, g = b.read_metrics(ref), b.read_metrics(got)
+    for key in ("sse", "changed_px", "max_abs", "nonfinite"):
+        assert np.array_equal(r[key], g[key]) or key == "sse" and np.allclose(r[key], g[key], rtol=1e-12, atol=0), key
+
+
 def test_sg_metrics_matches_definition(ctx):
     import torch
     from paper_2606_21791_amd import binding as b
