@@ -43,6 +43,7 @@ N_HI = 134_826
 FLOPS_PER_EVAL = 20            # q-form and alpha test of one pixel-primitive evaluation
 FP32_PEAK_TFLOPS = 157.3       # MI355X fp32 vector peak
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "composite_items_w2hi_f32_b32_hbm_traffic.txt")
+DIRTY_BINS = [0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
 PAPER_CONTEXT = {"inj_per_s": 2515, "hardware": "Blackwell-generation GPU (model not named), B=32, resolution not stated",
                  "l40s_inj_per_s": 1522}
 
@@ -74,37 +75,73 @@ def _workload(fmt):
     return sc, cam, sites.take(order)
 
 
-def cpu_baseline(sc, cam, sites, fmt, n_inj):
-    """The oracle's plain path on one host thread, timed on a bounded sample:
-    each injection projects all primitives and composites the 400 x 400
-    top-left quadrant of the frame (same intrinsics); the per-injection time
-    is extrapolated as projection + 4 x quadrant compositing."""
+_CPU = {}   # inputs of the oracle baseline, shared with forked workers
+
+
+def _cpu_one(k):
+    """One oracle injection on the bounded sample: FP64 projection of every
+    primitive, then compositing and metrics of the 400 x 400 quadrant.
+    Returns (projection seconds, quadrant seconds)."""
     from threadpoolctl import threadpool_limits
     from oracle import formats, metrics as om, render as orender
+    d = _CPU
+    with threadpool_limits(limits=1):
+        w = [x.copy() for x in d["words"]]
+        st = d["sites"]
+        f, c, p, b = int(st.field[k]), int(st.comp[k]), int(st.prim[k]), int(st.bit[k])
+        w[f][c, p] = formats.flip(w[f][c, p:p + 1], b)[0]
+        t0 = time.perf_counter()
+        pr = orender.project(orender.decode_scene(w, d["fmt"]), 3, d["quad"])
+        t1 = time.perf_counter()
+        out = orender.render(pr, d["quad"])
+        om.frame_metrics(out["image"], d["clean"], out["nonfinite"])
+        t2 = time.perf_counter()
+    return t1 - t0, t2 - t1
+
+
+def cpu_baseline(sc, cam, sites, fmt, n_inj, procs):
+    """The oracle's plain path timed on the host on a bounded sample: each
+    injection projects all primitives and composites the 400 x 400 top-left
+    quadrant of the frame (same intrinsics); its time is extrapolated as
+    projection + 4 x quadrant.  First n_inj injections on one thread, then
+    `procs` injections at once in forked worker processes (one thread each);
+    the reported value is the all-process rate.  Runs before the GPU is
+    touched, so the workers fork from a process without a device context."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from oracle import formats, render as orender
     from paper_2606_21791_amd import synth
     quad = synth.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx, cam.cy, cam.width // 2, cam.height // 2)
     with threadpool_limits(limits=1):
         words = [formats.store(f, fmt) for f in sc.fields]
-        clean = orender.render(orender.project(orender.decode_scene(words, fmt), 3, quad), quad)
-        t_proj = t_rend = 0.0
-        for k in range(n_inj):
-            w = [x.copy() for x in words]
-            f, c, p, b = int(sites.field[k]), int(sites.comp[k]), int(sites.prim[k]), int(sites.bit[k])
-            w[f][c, p] = formats.flip(w[f][c, p:p + 1], b)[0]
+        clean = orender.render(orender.project(orender.decode_scene(words, fmt), 3, quad), quad)["image"]
+    _CPU.update(words=words, sites=sites, fmt=fmt, quad=quad, clean=clean)
+    one = [_cpu_one(k) for k in range(n_inj)]
+    t_proj = sum(a for a, _ in one) / n_inj
+    t_rend = sum(b for _, b in one) / n_inj
+    per_inj_1 = t_proj + 4.0 * t_rend
+    res = {"unit": "injections/s", "kind": "oracle", "single_thread_value": 1.0 / per_inj_1}
+    if procs > 1:
+        with mp.get_context("fork").Pool(procs) as pool:
             t0 = time.perf_counter()
-            pr = orender.project(orender.decode_scene(w, fmt), 3, quad)
-            t1 = time.perf_counter()
-            out = orender.render(pr, quad)
-            om.frame_metrics(out["image"], clean["image"], out["nonfinite"])
-            t2 = time.perf_counter()
-            t_proj += t1 - t0
-            t_rend += t2 - t1
-    per_inj = (t_proj + 4.0 * t_rend) / n_inj
-    return {"value": 1.0 / per_inj, "unit": "injections/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_inj} single-bit injection(s) of the same workload: FP64 projection of all "
-                      f"{sc.n} primitives ({t_proj / n_inj:.1f} s) plus compositing and metrics of the 400x400 "
-                      f"top-left quadrant ({t_rend / n_inj:.1f} s), extrapolated to the full frame as "
-                      f"projection + 4 x quadrant = {per_inj:.1f} s per injection, one host thread"}
+            many = pool.map(_cpu_one, range(n_inj, n_inj + procs), chunksize=1)
+            wall = time.perf_counter() - t0
+        worst = max(a + 4.0 * b for a, b in many)
+        res.update(value=procs / worst, cores=procs,
+                   sample=f"{procs} single-bit injections of the same workload run at once in {procs} forked "
+                          f"processes of one thread each ({wall:.1f} s wall): FP64 projection of all {sc.n} "
+                          f"primitives plus compositing and metrics of the 400x400 top-left quadrant, each "
+                          f"extrapolated to the full frame as projection + 4 x quadrant (slowest process "
+                          f"{worst:.1f} s per injection); on one thread alone: projection {t_proj:.1f} s, "
+                          f"quadrant {t_rend:.1f} s, {per_inj_1:.1f} s per injection")
+    else:
+        res.update(value=1.0 / per_inj_1, cores=1,
+                   sample=f"{n_inj} single-bit injection(s) of the same workload on one thread: FP64 projection "
+                          f"of all {sc.n} primitives ({t_proj:.1f} s) plus compositing and metrics of the "
+                          f"400x400 top-left quadrant ({t_rend:.1f} s), extrapolated as projection + 4 x "
+                          f"quadrant = {per_inj_1:.1f} s per injection")
+    _CPU.clear()
+    return res
 
 
 def main():
@@ -128,7 +165,11 @@ def main():
     ap.add_argument("--free-batch", type=int, default=512,
                     help="also tune B up to this bound and time that configuration (0: skip)")
     ap.add_argument("--plain", type=int, default=100, help="injections timed on the plain path")
-    ap.add_argument("--cpu-inj", type=int, default=1, help="oracle injections timed on the host (0: skip)")
+    ap.add_argument("--no-formats", dest="formats", action="store_false",
+                    help="skip the fp16/bf16 (or fp32) rates at the headline configuration")
+    ap.add_argument("--cpu-inj", type=int, default=1, help="oracle injections timed on one host thread (0: skip)")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle processes run at once for the all-core baseline (0: the host's cores, at most 16)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="seconds of Poisson arrivals for the serving measurement (0: skip)")
     ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve", "copy"],
@@ -144,10 +185,15 @@ def main():
          "copy": run_copy}[args.workload](args)
         return
 
+    sc, cam, sites = _workload(args.fmt)
+    cpu = None
+    if args.cpu_inj > 0:   # before the GPU is touched (the workers fork)
+        procs = args.cpu_procs if args.cpu_procs > 0 else min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(sc, cam, sites, args.fmt, args.cpu_inj, procs)
+
     import torch
     from paper_2606_21791_amd import binding as sgb
 
-    sc, cam, sites = _workload(args.fmt)
     ctx = sgb.Context(0)
     ds = sgb.DeviceScene.upload(ctx, sc, args.fmt)
     tune_sample = sgb.sites_array(sites.field[:4096], sites.comp[:4096], sites.prim[:4096], sites.bit[:4096])
@@ -199,14 +245,22 @@ def main():
 
     run_steps(0, args.warmup)
     torch.cuda.synchronize()
+    # the K timed steps as REPS equal campaigns, each bracketed by a
+    # synchronisation (the spread of their rates is reported beside the total)
+    REPS = 5
+    bounds = [args.warmup + (args.steps * r) // REPS for r in range(REPS + 1)]
+    rep_dt = []
     with _no_gc():
         t_start = time.perf_counter()
-        run_steps(args.warmup, steps_total)
-        t_sub = time.perf_counter()
-        torch.cuda.synchronize()
+        for r in range(REPS):
+            t0 = time.perf_counter()
+            run_steps(bounds[r], bounds[r + 1])
+            torch.cuda.synchronize()
+            rep_dt.append(time.perf_counter() - t0)
         elapsed = time.perf_counter() - t_start
     recs = sgb.read_metrics(mt_all)[w_end:]
     inj_per_s = args.steps * B / elapsed
+    rep_rates = np.array([(bounds[r + 1] - bounds[r]) * B / rep_dt[r] for r in range(REPS)])
 
     # the same steps again with per-pass HIP events (graphs are not used while
     # timing), for the per-pass breakdown and the compositing launch duration
@@ -224,6 +278,33 @@ def main():
     comp_avg_s = comp_ms / max(comp_n, 1) / 1e3
     evals_per_launch = float(recs["evals"].sum()) / args.steps
     achieved = evals_per_launch * FLOPS_PER_EVAL / comp_avg_s / 1e12 if comp_avg_s > 0 else 0.0
+
+    # the other storage formats at the same launch configuration
+    per_format = {}
+    for fmt in ("f32", "f16", "bf16"):
+        if fmt == args.fmt or not args.formats:
+            continue
+        sc_f, _, sites_f = _workload(fmt)
+        ds_f = sgb.DeviceScene.upload(ctx, sc_f, fmt)
+        prep_fm = ctx.prepare(ds_f, cam, sgb.raster_struct(tile=args.tile))
+        n_f = min(args.steps, 1000) * B
+        idx_f = np.arange(n_f) % len(sites_f)
+        sa_f = sgb.sites_array(sites_f.field[idx_f], sites_f.comp[idx_f], sites_f.prim[idx_f], sites_f.bit[idx_f])
+        va_f = sgb.variants_array(np.arange(n_f), np.ones(n_f, np.uint32))
+        mt_fm = sgb.metrics_tensor(n_f)
+        kw = dict(batch=B, streams=len(streams), threads=max(1, args.threads))
+        ctx.campaign(prep_fm, sa_f, va_f[:8 * B], mt_fm, **kw)
+        torch.cuda.synchronize()
+        with _no_gc():
+            t0 = time.perf_counter()
+            ctx.campaign(prep_fm, sa_f, va_f, mt_fm, **kw)
+            torch.cuda.synchronize()
+            dt_fm = time.perf_counter() - t0
+        r_f = sgb.read_metrics(mt_fm)
+        per_format[fmt] = {"value": round(n_f / dt_fm, 1), "injections": n_f,
+                           "dirty_tiles_per_injection": round(float(r_f["dirty_tiles"].mean()), 2),
+                           "catastrophic_fraction": round(float(r_f["catastrophic"].mean()), 4)}
+        del prep_fm, ds_f
 
     # the same injections with B tuned too (many variants per launch)
     free = None
@@ -309,16 +390,24 @@ def main():
         "plain": {"value": round(P / plain_dt, 1), "unit": "injections/s", "injections": P,
                   "ms_per_injection": round(plain_dt / P * 1e3, 4),
                   "pass_ms_per_injection": {k: round(v[0] / max(P, 1), 4) for k, v in plain_passes.items() if v[1]},
+                  "pass_gbps": _plain_pass_gbps(sc.n, prep.instances(), cam, args.fmt, plain_passes, P),
                   "records_agree_with_batched": agree},
         "speedup_vs_plain": round(inj_per_s / (P / plain_dt), 2),
         "tuned_any_batch": free,
         "pass_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in passes.items() if v[1]},
-        "host_submit_ms_per_step": round((t_sub - t_start) * 1e3 / args.steps, 4),
+        "repetitions": {"n": REPS, "median": round(float(np.median(rep_rates)), 1),
+                        "p10": round(float(np.percentile(rep_rates, 10)), 1),
+                        "p90": round(float(np.percentile(rep_rates, 90)), 1)},
+        "dirty_tile_histogram": {"bin_edges": DIRTY_BINS,
+                                 "counts": np.histogram(recs["dirty_tiles"], bins=DIRTY_BINS)[0].tolist()},
+        "per_format": per_format,
         "dirty_tiles_per_injection": round(float(recs["dirty_tiles"].mean()), 2),
         "catastrophic_fraction": round(float(recs["catastrophic"].mean()), 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                     "traffic": (_measured_traffic() if (args.fmt == "f32" and B == 32 and args.tile == 16) else None),
+                     "traffic": (_measured_traffic()
+                                 if (args.fmt == "f32" and B == 32 and args.tile == 16 and args.resume == 32) else None),
+                     "aggregate_achieved": round(evals_per_launch * args.steps * FLOPS_PER_EVAL / elapsed / 1e12, 3),
                      "kernel": "k_composite_items", "avg_launch_ms": round(comp_avg_s * 1e3, 4),
                      "evals_per_launch": round(evals_per_launch), "flops_per_eval": FLOPS_PER_EVAL},
         "paper_context": PAPER_CONTEXT,
@@ -327,9 +416,28 @@ def main():
         del prep, ds
         torch.cuda.synchronize()
         out["serving"] = serve_workload(args.serve_seconds)
-    if args.cpu_inj > 0:
-        out["cpu_baseline"] = cpu_baseline(sc, cam, sites, args.fmt, args.cpu_inj)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
+
+
+def _plain_pass_gbps(n, inst, cam, fmt, passes, P):
+    """Achieved GB/s of the plain path's passes from their algorithmic bytes:
+    project reads 59 stored words and writes a 48-B record, depth and
+    rectangle per primitive; binning reads depth and rectangle and writes an
+    8-B key per instance; the per-tile sort reads and writes each key once;
+    compositing reads each instance's key and record and the clean frame."""
+    w = 4 if fmt == "f32" else 2
+    px = cam.width * cam.height
+    alg = {"project": n * (59 * w + 48 + 4 + 8), "bin": n * 12 + inst * 8, "sort": inst * 16,
+           "composite_full": inst * (8 + 48) + px * 12}
+    out = {}
+    for k, b in alg.items():
+        ms, cnt = passes.get(k, (0.0, 0))
+        if cnt and ms > 0:
+            gbps = b / (ms / P / 1e3) / 1e9
+            out[k] = {"bytes": int(b), "GB_s": round(gbps, 1), "frac_of_8TB_s": round(gbps / 8000.0, 4)}
+    return out
 
 
 class _no_gc:
@@ -344,37 +452,46 @@ class _no_gc:
         gc.enable()
 
 
-def _batched_rate(ctx, prep, sites, B, streams, steps, warmup, guard=0, box=None):
-    """Batched incremental injections/s over `steps` batches (after `warmup`)
-    and the concatenated per-variant records."""
+def _batched_rate(ctx, prep, sites, B, streams, threads, steps, warmup, guard=0, box=None):
+    """Batched incremental injections/s of one campaign call over `steps`
+    batches of B (after `warmup` batches), and the per-variant records."""
     import torch
     from paper_2606_21791_amd import binding as sgb
     n = len(sites)
-    total = warmup + steps
-    batches = []
-    for i in range(total):
-        idx = (np.arange(B) + i * B) % n
-        batches.append(sgb.sites_array(sites.field[idx], sites.comp[idx], sites.prim[idx], sites.bit[idx]))
-    va = sgb.variants_array(np.arange(B), np.ones(B, np.uint32), guard)
-    rec_bytes = B * sgb.METRICS_DTYPE.itemsize
-    mt_all = sgb.metrics_tensor(B * total)
-    mts = [mt_all[i * rec_bytes:(i + 1) * rec_bytes] for i in range(total)]
-
-    def run(i):
-        with torch.cuda.stream(streams[i % len(streams)]):
-            ctx.render_batch(prep, batches[i], va, box=box, metrics=mts[i])
-
-    for i in range(warmup):
-        run(i)
+    total = (warmup + steps) * B
+    idx = np.arange(total) % n
+    sa = sgb.sites_array(sites.field[idx], sites.comp[idx], sites.prim[idx], sites.bit[idx])
+    va = sgb.variants_array(np.arange(total), np.ones(total, np.uint32), guard)
+    mt = sgb.metrics_tensor(total)
+    rb = sgb.METRICS_DTYPE.itemsize
+    kw = dict(box=box, batch=B, streams=streams, threads=threads)
+    ctx.campaign(prep, sa, va[:warmup * B], mt[:warmup * B * rb], **kw)
     torch.cuda.synchronize()
     with _no_gc():
         t0 = time.perf_counter()
-        for i in range(warmup, total):
-            run(i)
+        ctx.campaign(prep, sa, va[warmup * B:], mt[warmup * B * rb:], **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-    recs = sgb.read_metrics(mt_all)[warmup * B:]
+    recs = sgb.read_metrics(mt)[warmup * B:]
     return steps * B / dt, recs
+
+
+def _tune_into(ctx, args, ds, cam, sites):
+    """Autotune at the fixed --batch (unless --no-tune) and apply the result to
+    ctx and args; returns the tuner's record or None."""
+    from paper_2606_21791_amd import binding as sgb
+    if args.no_tune:
+        ctx.set_persistent(args.wgs_per_cu)
+        ctx.set_resume(args.resume)
+        ctx.set_graphs(args.graphs)
+        return None
+    k = min(4096, len(sites))
+    sample = sgb.sites_array(sites.field[:k], sites.comp[:k], sites.prim[:k], sites.bit[:k])
+    t = ctx.autotune(ds, cam, sample, fixed_batch=args.batch)
+    args.tile, args.streams, args.threads = t["tile"], t["streams"], t["threads"]
+    args.wgs_per_cu, args.resume, args.graphs = t["wgs_per_cu"], t["resume"], bool(t["graphs"])
+    ctx.apply_tune(t)
+    return t
 
 
 def _summ(recs):
@@ -394,17 +511,16 @@ def run_guard(args):
     from paper_2606_21791_amd import binding as sgb, synth
     sc, cam, sites = _workload("f32")
     ctx = sgb.Context(0)
-    ctx.set_persistent(args.wgs_per_cu)
-    ctx.set_resume(args.resume)
-    streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
     lo32, hi32 = synth.make_box_jitter(sc, seed=4)
     ds = sgb.DeviceScene.upload(ctx, sc, "f32")
     box = sgb.Box.per_prim(ctx, lo32, hi32, "f32")
-    prep = ctx.prepare(ds, cam)
+    tuned = _tune_into(ctx, args, ds, cam, sites)
+    prep = ctx.prepare(ds, cam, sgb.raster_struct(tile=args.tile))
     torch.cuda.synchronize()
     out = {"metric": "support guard: cost per frame, guarded vs unguarded injections, accumulated dose",
            "config": {"workload": "N=134,826 Gaussians, SH degree 3, fp32, 800x800, per-primitive box "
-                                  "(value -/+ |N(0,0.2)|, rounded outward)", "B": args.batch}}
+                                  "(value -/+ |N(0,0.2)|, rounded outward)", "B": args.batch, "tile": args.tile,
+                      "streams": args.streams, "host_threads": args.threads, "tuned": tuned is not None}}
     # guard cost: the scrub pass over the resident scene (identity on the clean scene)
     work = ds.clone()
     for _ in range(3):
@@ -435,7 +551,8 @@ def run_guard(args):
                          "projection_us_without_guard": round(proj["without"] * 1e3, 2)}
     # single flips, unguarded and guarded
     for guard in (0, 1):
-        rate, recs = _batched_rate(ctx, prep, sites, args.batch, streams, args.steps, args.warmup, guard, box)
+        rate, recs = _batched_rate(ctx, prep, sites, args.batch, args.streams, max(1, args.threads),
+                                   min(args.steps, 2000), args.warmup, guard, box)
         out["guarded" if guard else "unguarded"] = {"inj_per_s": round(rate, 1), **_summ(recs)}
     # accumulated dose: k simultaneous flips over all stored bits, 16 frames each
     dose = {}
@@ -474,16 +591,15 @@ def run_large(args):
     from paper_2606_21791_amd import binding as sgb
     sc, cam, sites = _large_scene()
     ctx = sgb.Context(0)
-    ctx.set_persistent(args.wgs_per_cu)
-    ctx.set_resume(args.resume)
-    streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
     ds = sgb.DeviceScene.upload(ctx, sc, "bf16")
     del sc
+    tuned = _tune_into(ctx, args, ds, cam, sites)
     t0 = time.perf_counter()
-    prep = ctx.prepare(ds, cam)
+    prep = ctx.prepare(ds, cam, sgb.raster_struct(tile=args.tile))
     torch.cuda.synchronize()
     prep_s = time.perf_counter() - t0
-    rate, recs = _batched_rate(ctx, prep, sites, args.batch, streams, args.steps, args.warmup)
+    rate, recs = _batched_rate(ctx, prep, sites, args.batch, args.streams, max(1, args.threads),
+                               min(args.steps, 2000), args.warmup)
     frame = prep.frame()
     mt1 = sgb.metrics_tensor(1)
     P = max(5, args.plain // 4)
@@ -504,8 +620,10 @@ def run_large(args):
            "value": round(rate, 1), "unit": "injections/s",
            "config": {"workload": "N=2,056,645 Gaussians in 64 anisotropic clusters, SH degree 3, bf16 storage, "
                                   f"1600x900, B={args.batch}, 6 fields x 1,024 stratified sites",
-                      "streams": len(streams), "instances_clean": prep.instances(),
-                      "prepare_s": round(prep_s, 3)},
+                      "tile": args.tile, "streams": args.streams, "host_threads": args.threads,
+                      "wgs_per_cu": args.wgs_per_cu, "resume_spacing": args.resume, "tuned": tuned is not None,
+                      "instances_clean": prep.instances(), "prepare_s": round(prep_s, 3),
+                      "device_bytes": ctx.bytes()},
            "plain": {"value": round(P / plain_dt, 1), "unit": "injections/s",
                      "pass_ms_per_injection": {k: round(v[0] / P, 4) for k, v in pp.items() if v[1]}},
            "speedup_vs_plain": round(rate / (P / plain_dt), 2),

@@ -51,7 +51,50 @@ __global__ void __launch_bounds__(1024) k_tile_prefix(DevRaster ras, BinBuffers 
     carry += s[1023];
     __syncthreads();
   }
-  if (threadIdx.x == 0) { bb.total[0] = carry; bb.total[1] = 0; bb.total[2] = 0; }
+  // tiles whose lists exceed one LDS sort, in tile order, with the prefix
+  // counts of their LDS chunks and of their 8-key merge groups
+  __shared__ unsigned long long s_acc[3];
+  __shared__ uint32_t s_max;
+  if (threadIdx.x == 0) { s_acc[0] = s_acc[1] = s_acc[2] = 0; s_max = 0; }
+  __syncthreads();
+  for (int base = 0; base < ras.n_tiles; base += 1024) {
+    const int t = base + threadIdx.x;
+    const uint32_t c = t < ras.n_tiles ? bb.tile_cnt[t] : 0u;
+    const bool big = c > (uint32_t)kSortCap;
+    const uint32_t nch = big ? (c + kSortCap - 1) / kSortCap : 0u, ngr = big ? (c + 7) / 8 : 0u;
+    // three inclusive scans over the 1024 tiles of this round, in one LDS pass each
+    uint32_t v[3] = {big ? 1u : 0u, nch, ngr}, excl[3];
+    for (int q = 0; q < 3; ++q) {
+      s[threadIdx.x] = v[q];
+      __syncthreads();
+      for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t y = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += y;
+        __syncthreads();
+      }
+      excl[q] = s[threadIdx.x] - v[q];
+      v[q] = s[1023];
+      __syncthreads();
+    }
+    if (big) {
+      const uint32_t k = (uint32_t)(s_acc[0] + excl[0]);
+      bb.big_tiles[k] = (uint32_t)t;
+      bb.big_choff[k] = (uint32_t)(s_acc[1] + excl[1]);
+      bb.big_goff[k] = (uint32_t)(s_acc[2] + excl[2]);
+      atomicMax(&s_max, c);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) { s_acc[0] += v[0]; s_acc[1] += v[1]; s_acc[2] += v[2]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const uint32_t nb = (uint32_t)s_acc[0];
+    bb.big_choff[nb] = (uint32_t)s_acc[1];
+    bb.big_goff[nb] = (uint32_t)s_acc[2];
+    bb.total[0] = carry; bb.total[1] = 0; bb.total[2] = nb; bb.total[3] = s_max;
+    bb.total[4] = s_acc[1]; bb.total[5] = s_acc[2];
+  }
 }
 
 __device__ __forceinline__ void emit_one(const BinBuffers& bb, int t, uint64_t key) {
@@ -152,10 +195,7 @@ __global__ void __launch_bounds__(256) k_tile_sort(DevRaster ras, BinBuffers bb)
   const int t = blockIdx.x;
   const uint32_t n = bb.tile_cnt[t];
   if (n <= 1) return;
-  if (n > (uint32_t)kSortCap) {
-    if (threadIdx.x == 0) bb.big_tiles[atomicAdd(bb.total + 2, 1ull)] = (uint32_t)t;
-    return;
-  }
+  if (n > (uint32_t)kSortCap) return;   // sorted by k_big_chunks and k_big_merge
   __shared__ uint64_t sk[kSortCap];
   int P = 2;
   while (P < (int)n) P <<= 1;
@@ -166,52 +206,73 @@ __global__ void __launch_bounds__(256) k_tile_sort(DevRaster ras, BinBuffers bb)
   for (int i = threadIdx.x; i < (int)n; i += blockDim.x) g[i] = sk[i];
 }
 
-// Tiles with more than kSortCap instances: sort chunks of kSortCap in LDS,
-// then merge runs pairwise (merge path per 8 outputs) between keys and keys_tmp.
-__global__ void __launch_bounds__(1024) k_tile_sort_big(BinBuffers bb) {
+// Tiles with more than kSortCap instances are sorted by the whole grid:
+// every LDS-sized chunk of every such tile is sorted by one block, then runs
+// are merged pairwise in passes of doubling width, each pass spreading its
+// 8-key output groups over all threads (merge path per group).  Passes
+// alternate between keys and keys_tmp at the tile's own offset.
+
+// The big tile holding global item g (off has nb + 1 prefix entries).
+__device__ __forceinline__ int big_of(const uint32_t* off, int nb, uint32_t g) {
+  int lo = 0, hi = nb;   // largest k with off[k] <= g
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(1024) k_big_chunks(BinBuffers bb) {
   __shared__ uint64_t sk[kSortCap];
-  const unsigned long long nbt = bb.total[2];
-  for (unsigned long long bt = blockIdx.x; bt < nbt; bt += gridDim.x) {
-    const uint32_t t = bb.big_tiles[bt];
+  const int nb = (int)bb.total[2];
+  const uint32_t nch = (uint32_t)bb.total[4];
+  for (uint32_t g = blockIdx.x; g < nch; g += gridDim.x) {
+    const int k = big_of(bb.big_choff, nb, g);
+    const uint32_t t = bb.big_tiles[k];
     const int n = (int)bb.tile_cnt[t];
-    uint64_t* a = bb.keys + bb.tile_start[t];
-    uint64_t* b = bb.keys_tmp + bb.tile_start[t];
-    for (int c0 = 0; c0 < n; c0 += kSortCap) {
-      const int m = min(kSortCap, n - c0);
-      __syncthreads();
-      for (int i = threadIdx.x; i < kSortCap; i += blockDim.x) sk[i] = i < m ? a[c0 + i] : ~0ull;
-      __syncthreads();
-      lds_bitonic(sk, kSortCap);
-      for (int i = threadIdx.x; i < m; i += blockDim.x) a[c0 + i] = sk[i];
-    }
+    const int c0 = (int)(g - bb.big_choff[k]) * kSortCap;
+    const int m = min(kSortCap, n - c0);
+    uint64_t* a = bb.keys + bb.tile_start[t] + c0;
     __syncthreads();
-    uint64_t* src = a;
-    uint64_t* dst = b;
-    for (int w = kSortCap; w < n; w <<= 1) {
-      for (int pos0 = threadIdx.x * 8; pos0 < n; pos0 += blockDim.x * 8) {
-        const int p = pos0 / (2 * w);
-        const int a0 = p * 2 * w, na = min(w, n - a0);
-        const int b0 = a0 + na, nb = max(0, min(w, n - b0));
-        const int d = pos0 - a0;
-        int lo = max(0, d - nb), hi = min(d, na);
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (src[a0 + mid] < src[b0 + d - 1 - mid]) lo = mid + 1; else hi = mid;
-        }
-        int i = lo, j = d - lo;
-        const int end = min(pos0 + 8, a0 + na + nb);
-        for (int o = pos0; o < end; ++o) {
-          if (j >= nb || (i < na && src[a0 + i] < src[b0 + j])) dst[o] = src[a0 + i++];
-          else dst[o] = src[b0 + j++];
-        }
-      }
-      __syncthreads();
-      uint64_t* tmp = src; src = dst; dst = tmp;
-    }
-    if (src != a) {
-      for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = src[i];
-    }
+    for (int i = threadIdx.x; i < kSortCap; i += blockDim.x) sk[i] = i < m ? a[i] : ~0ull;
     __syncthreads();
+    lds_bitonic(sk, kSortCap);
+    for (int i = threadIdx.x; i < m; i += blockDim.x) a[i] = sk[i];
+  }
+}
+
+// One pass: runs of width w are merged into runs of 2w (tiles whose list is
+// not longer than w are copied).  `src` and `dst` are keys / keys_tmp.
+__global__ void __launch_bounds__(256) k_big_merge(BinBuffers bb, uint32_t w, const uint64_t* __restrict__ src_all,
+                                                   uint64_t* __restrict__ dst_all) {
+  const int nb = (int)bb.total[2];
+  const uint32_t ngr = (uint32_t)bb.total[5];
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ngr; g += gridDim.x * blockDim.x) {
+    const int k = big_of(bb.big_goff, nb, g);
+    const uint32_t t = bb.big_tiles[k];
+    const uint32_t n = bb.tile_cnt[t];
+    const uint64_t* src = src_all + bb.tile_start[t];
+    uint64_t* dst = dst_all + bb.tile_start[t];
+    const uint32_t pos0 = (g - bb.big_goff[k]) * 8u;
+    const uint32_t end = min(pos0 + 8u, n);
+    if (n <= w) {
+      for (uint32_t o = pos0; o < end; ++o) dst[o] = src[o];
+      continue;
+    }
+    const uint32_t a0 = pos0 / (2u * w) * (2u * w);
+    const uint32_t na = min(w, n - a0);
+    const uint32_t b0 = a0 + na, nbk = b0 < n ? min(w, n - b0) : 0u;
+    const uint32_t d = pos0 - a0;
+    uint32_t lo = d > nbk ? d - nbk : 0u, hi = min(d, na);
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (src[a0 + mid] < src[b0 + d - 1 - mid]) lo = mid + 1; else hi = mid;
+    }
+    uint32_t i = lo, j = d - lo;
+    for (uint32_t o = pos0; o < end; ++o) {
+      if (j >= nbk || (i < na && src[a0 + i] < src[b0 + j])) dst[o] = src[a0 + i++];
+      else dst[o] = src[b0 + j++];
+    }
   }
 }
 
@@ -231,9 +292,22 @@ void launch_emit(int n, const uint32_t* depth, const uint2* rect, const DevRaste
   k_emit_big<<<1024, 256, 0, st>>>(depth, rect, ras, bb);
 }
 
-void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, hipStream_t st) {
+void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, const unsigned long long* totals, int n_cu,
+                      hipStream_t st) {
   k_tile_sort<<<ras.n_tiles, 256, 0, st>>>(ras, bb);
-  k_tile_sort_big<<<256, 1024, 0, st>>>(bb);
+  if (totals[2] == 0) return;
+  const unsigned long long nch = totals[4], ngr = totals[5], maxn = totals[3];
+  k_big_chunks<<<(unsigned)std::min<unsigned long long>(nch, (unsigned long long)n_cu * 2), 1024, 0, st>>>(bb);
+  const unsigned grid = (unsigned)std::max<unsigned long long>(
+      1, std::min<unsigned long long>((ngr + 255) / 256, (unsigned long long)n_cu * 8));
+  uint64_t* src = bb.keys;
+  uint64_t* dst = bb.keys_tmp;
+  int passes = 0;
+  for (unsigned long long w = kSortCap; w < maxn; w <<= 1, ++passes) {
+    k_big_merge<<<grid, 256, 0, st>>>(bb, (uint32_t)w, src, dst);
+    std::swap(src, dst);
+  }
+  if (passes & 1) k_big_merge<<<grid, 256, 0, st>>>(bb, 0xffffffffu, src, dst);   // back into keys
 }
 
 }  // namespace sg

@@ -60,7 +60,7 @@ struct Workspace {
   hipStream_t stream = nullptr;
   // full renders
   DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
-      big_prims, big_tiles, parts, work_scene, sites_dev, box_keys, metrics_tmp;
+      big_prims, big_tiles, big_choff, big_goff, parts, work_scene, sites_dev, box_keys, metrics_tmp;
   // batches of variants
   DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, gmetrics;
   unsigned long long* h_total = nullptr;   // pinned
@@ -168,6 +168,7 @@ Workspace* workspace(sg_ctx* ctx, hipStream_t st) {
 void free_workspace(sg_ctx* ctx, Workspace* w) {
   DevBuf* bufs[] = {&w->r0, &w->r1, &w->r2, &w->depth, &w->rect, &w->diff, &w->flags, &w->clamps, &w->tile_cnt,
                     &w->tile_start, &w->cursor, &w->total, &w->keys, &w->keys_tmp, &w->big_prims, &w->big_tiles,
+                    &w->big_choff, &w->big_goff,
                     &w->parts, &w->work_scene, &w->sites_dev, &w->box_keys, &w->metrics_tmp, &w->vs, &w->ovr,
                     &w->bitmap, &w->item_off, &w->n_items_v, &w->n_items_total, &w->items, &w->bparts,
                     &w->counter, &w->gmetrics};
@@ -401,9 +402,11 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
   SG_TRY(dev_alloc(ctx, tile_cnt, ras.n_tiles * sizeof(uint32_t)));
   SG_TRY(dev_alloc(ctx, tile_start, ras.n_tiles * sizeof(uint32_t)));
   SG_TRY(dev_alloc(ctx, W->cursor, ras.n_tiles * sizeof(uint32_t)));
-  SG_TRY(dev_alloc(ctx, W->total, 4 * sizeof(unsigned long long)));
+  SG_TRY(dev_alloc(ctx, W->total, 8 * sizeof(unsigned long long)));
   SG_TRY(dev_alloc(ctx, W->big_prims, n * sizeof(uint32_t)));
   SG_TRY(dev_alloc(ctx, W->big_tiles, ras.n_tiles * sizeof(uint32_t)));
+  SG_TRY(dev_alloc(ctx, W->big_choff, (ras.n_tiles + 1) * sizeof(uint32_t)));
+  SG_TRY(dev_alloc(ctx, W->big_goff, (ras.n_tiles + 1) * sizeof(uint32_t)));
   launch_fill_u32(P<uint32_t>(W->diff), 0u, diff_n, st);
   launch_fill_u32(P<uint32_t>(W->flags), 0u, 4, st);
   launch_fill_u32(P<uint32_t>(W->clamps), 0u, 4, st);
@@ -415,13 +418,13 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
   }
   BinBuffers bb{P<int32_t>(W->diff), P<uint32_t>(tile_cnt), P<uint32_t>(tile_start), P<uint32_t>(W->cursor),
                 P<unsigned long long>(W->total), nullptr, nullptr, P<uint32_t>(W->big_prims),
-                P<uint32_t>(W->big_tiles), 0};
+                P<uint32_t>(W->big_tiles), P<uint32_t>(W->big_choff), P<uint32_t>(W->big_goff), 0};
   {
     PassScope ps(ctx, SG_PASS_BIN, st);
     launch_tile_prefix(ras, bb, st);
   }
   SG_TRY(check_last("project/binning launch"));
-  HIP_TRY(hipMemcpyAsync(W->h_total, W->total.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(W->h_total, W->total.p, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const int64_t n_inst = (int64_t)W->h_total[0];
   if (n_inst >= (int64_t)0xffffffffu) return fail(SG_E_UNSUPPORTED, "more than 2^32 primitive-tile instances");
@@ -436,7 +439,8 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
   }
   {
     PassScope ps(ctx, SG_PASS_SORT, st);
-    launch_tile_sort(ras, bb, st);
+    if (W->h_total[3] > (1ull << 31)) return fail(SG_E_UNSUPPORTED, "a tile list longer than 2^31 entries");
+    launch_tile_sort(ras, bb, W->h_total, ctx->n_cu, st);
   }
   CompArgs ca{P<float4>(r0), P<float4>(r1), P<float4>(r2), P<uint32_t>(tile_start), P<uint32_t>(tile_cnt),
               P<uint64_t>(keys), clean, image, parts, ras, cam.W, cam.H};

@@ -119,17 +119,24 @@ struct BinBuffers {
   uint32_t* tile_cnt;
   uint32_t* tile_start;
   uint32_t* cursor;
-  unsigned long long* total;   // [0] instances, [1] big prims, [2] big tiles
+  // [0] instances, [1] big prims, [2] big tiles (lists longer than one LDS
+  // sort), [3] longest big list, [4] LDS chunks of big tiles, [5] 8-key merge
+  // groups of big tiles
+  unsigned long long* total;
   uint64_t* keys;
   uint64_t* keys_tmp;
   uint32_t* big_prims;
-  uint32_t* big_tiles;
+  uint32_t* big_tiles;        // big tiles in tile order
+  uint32_t* big_choff;        // per big tile (+1): first LDS chunk
+  uint32_t* big_goff;         // per big tile (+1): first merge group
   int64_t capacity;
 };
 void launch_tile_prefix(const DevRaster& ras, const BinBuffers& bb, hipStream_t st);
 void launch_emit(int n, const uint32_t* depth, const uint2* rect, const DevRaster& ras, const BinBuffers& bb,
                  int n_cu, hipStream_t st);
-void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, hipStream_t st);
+// totals: host copy of bb.total[0..5] after k_tile_prefix
+void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, const unsigned long long* totals, int n_cu,
+                      hipStream_t st);
 
 // k_composite.hip
 struct CompArgs {
