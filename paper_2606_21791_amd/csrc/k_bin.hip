@@ -14,6 +14,7 @@
 namespace sg {
 
 constexpr int kSortCap = 4096;       // keys sorted in LDS by one block
+constexpr int kMergeTile = 2048;     // outputs of one block in a merge pass
 constexpr int kEmitSmall = 32;       // rectangles up to this many tiles are emitted by one thread
 
 __global__ void __launch_bounds__(1024) k_tile_prefix(DevRaster ras, BinBuffers bb) {
@@ -52,7 +53,7 @@ __global__ void __launch_bounds__(1024) k_tile_prefix(DevRaster ras, BinBuffers 
     __syncthreads();
   }
   // tiles whose lists exceed one LDS sort, in tile order, with the prefix
-  // counts of their LDS chunks and of their 8-key merge groups
+  // counts of their LDS chunks and of their merge blocks
   __shared__ unsigned long long s_acc[3];
   __shared__ uint32_t s_max;
   if (threadIdx.x == 0) { s_acc[0] = s_acc[1] = s_acc[2] = 0; s_max = 0; }
@@ -61,7 +62,7 @@ __global__ void __launch_bounds__(1024) k_tile_prefix(DevRaster ras, BinBuffers 
     const int t = base + threadIdx.x;
     const uint32_t c = t < ras.n_tiles ? bb.tile_cnt[t] : 0u;
     const bool big = c > (uint32_t)kSortCap;
-    const uint32_t nch = big ? (c + kSortCap - 1) / kSortCap : 0u, ngr = big ? (c + 7) / 8 : 0u;
+    const uint32_t nch = big ? (c + kSortCap - 1) / kSortCap : 0u, ngr = big ? (c + kMergeTile - 1) / kMergeTile : 0u;
     // three inclusive scans over the 1024 tiles of this round, in one LDS pass each
     uint32_t v[3] = {big ? 1u : 0u, nch, ngr}, excl[3];
     for (int q = 0; q < 3; ++q) {
@@ -208,9 +209,11 @@ __global__ void __launch_bounds__(256) k_tile_sort(DevRaster ras, BinBuffers bb)
 
 // Tiles with more than kSortCap instances are sorted by the whole grid:
 // every LDS-sized chunk of every such tile is sorted by one block, then runs
-// are merged pairwise in passes of doubling width, each pass spreading its
-// 8-key output groups over all threads (merge path per group).  Passes
-// alternate between keys and keys_tmp at the tile's own offset.
+// are merged pairwise in passes of doubling width.  A pass first finds, for
+// every kMergeTile-output block, where its outputs start in the two runs
+// (merge path, one thread per block), then each block stages its inputs in
+// LDS and merges them.  Passes alternate between keys and keys_tmp at the
+// tile's own offset.
 
 // The big tile holding global item g (off has nb + 1 prefix entries).
 __device__ __forceinline__ int big_of(const uint32_t* off, int nb, uint32_t g) {
@@ -220,6 +223,54 @@ __device__ __forceinline__ int big_of(const uint32_t* off, int nb, uint32_t g) {
     if (off[mid] <= g) lo = mid; else hi = mid;
   }
   return lo;
+}
+
+// Element i of a bitonic stage (k, j) keeps min(own, partner) when it is the
+// lower element of an ascending pair or the upper one of a descending pair.
+__device__ __forceinline__ uint64_t bitonic_keep(uint64_t v, uint64_t p, int i, int k, int j) {
+  const bool take_min = ((i & k) == 0) == ((i & j) == 0);
+  return take_min ? (v < p ? v : p) : (v < p ? p : v);
+}
+
+__device__ __forceinline__ void bitonic_pair(uint64_t& lo, uint64_t& hi, bool asc) {
+  if ((lo > hi) == asc) { const uint64_t t = lo; lo = hi; hi = t; }
+}
+
+// Ascending sort of 4096 keys by 1024 threads, four keys per thread in
+// registers (thread t holds elements 4t..4t+3): partners in the same thread
+// are exchanged in registers, partners in the same wave by lane shuffles,
+// and the rest through LDS (element i at sk[(i & 3) * 1024 + (i >> 2)]).
+__device__ void sort4096(uint64_t* sk, uint64_t& v0, uint64_t& v1, uint64_t& v2, uint64_t& v3) {
+  const int t = threadIdx.x;
+  const int i0 = 4 * t;
+  for (int k = 2; k <= kSortCap; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 256) {
+        __syncthreads();
+        sk[t] = v0; sk[1024 + t] = v1; sk[2048 + t] = v2; sk[3072 + t] = v3;
+        __syncthreads();
+        const int pt = t ^ (j >> 2);
+        v0 = bitonic_keep(v0, sk[pt], i0, k, j);
+        v1 = bitonic_keep(v1, sk[1024 + pt], i0 + 1, k, j);
+        v2 = bitonic_keep(v2, sk[2048 + pt], i0 + 2, k, j);
+        v3 = bitonic_keep(v3, sk[3072 + pt], i0 + 3, k, j);
+      } else if (j >= 4) {
+        const int m = j >> 2;
+        const uint64_t p0 = __shfl_xor(v0, m), p1 = __shfl_xor(v1, m), p2 = __shfl_xor(v2, m), p3 = __shfl_xor(v3, m);
+        v0 = bitonic_keep(v0, p0, i0, k, j);
+        v1 = bitonic_keep(v1, p1, i0 + 1, k, j);
+        v2 = bitonic_keep(v2, p2, i0 + 2, k, j);
+        v3 = bitonic_keep(v3, p3, i0 + 3, k, j);
+      } else if (j == 2) {
+        bitonic_pair(v0, v2, (i0 & k) == 0);
+        bitonic_pair(v1, v3, ((i0 + 1) & k) == 0);
+      } else {
+        bitonic_pair(v0, v1, (i0 & k) == 0);
+        bitonic_pair(v2, v3, ((i0 + 2) & k) == 0);
+      }
+    }
+  }
+  __syncthreads();   // the caller may reuse sk
 }
 
 __global__ void __launch_bounds__(1024) k_big_chunks(BinBuffers bb) {
@@ -233,45 +284,92 @@ __global__ void __launch_bounds__(1024) k_big_chunks(BinBuffers bb) {
     const int c0 = (int)(g - bb.big_choff[k]) * kSortCap;
     const int m = min(kSortCap, n - c0);
     uint64_t* a = bb.keys + bb.tile_start[t] + c0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < kSortCap; i += blockDim.x) sk[i] = i < m ? a[i] : ~0ull;
-    __syncthreads();
-    lds_bitonic(sk, kSortCap);
-    for (int i = threadIdx.x; i < m; i += blockDim.x) a[i] = sk[i];
+    const int e = 4 * threadIdx.x;
+    uint64_t v0 = e < m ? a[e] : ~0ull, v1 = e + 1 < m ? a[e + 1] : ~0ull, v2 = e + 2 < m ? a[e + 2] : ~0ull,
+             v3 = e + 3 < m ? a[e + 3] : ~0ull;
+    sort4096(sk, v0, v1, v2, v3);
+    if (e < m) a[e] = v0;
+    if (e + 1 < m) a[e + 1] = v1;
+    if (e + 2 < m) a[e + 2] = v2;
+    if (e + 3 < m) a[e + 3] = v3;
   }
 }
 
-// One pass: runs of width w are merged into runs of 2w (tiles whose list is
-// not longer than w are copied).  `src` and `dst` are keys / keys_tmp.
+// Position of one merge block in its tile and run pair for a pass of width w.
+struct MergeBlock {
+  uint32_t t, n, o0, o1, a0, na, b0, nb;
+};
+
+__device__ __forceinline__ MergeBlock merge_block(const BinBuffers& bb, int nbig, uint32_t g, uint32_t w) {
+  MergeBlock m;
+  const int k = big_of(bb.big_goff, nbig, g);
+  m.t = bb.big_tiles[k];
+  m.n = bb.tile_cnt[m.t];
+  m.o0 = (g - bb.big_goff[k]) * (uint32_t)kMergeTile;
+  m.o1 = min(m.o0 + (uint32_t)kMergeTile, m.n);
+  if (m.n <= w) {   // a single run: copied
+    m.a0 = 0; m.na = m.n; m.b0 = m.n; m.nb = 0;
+    return m;
+  }
+  m.a0 = m.o0 / (2u * w) * (2u * w);
+  m.na = min(w, m.n - m.a0);
+  m.b0 = m.a0 + m.na;
+  m.nb = m.b0 < m.n ? min(w, m.n - m.b0) : 0u;
+  return m;
+}
+
+// Number of outputs before diagonal d of the merge of A (na) and B (nb) that come from A.
+__device__ __forceinline__ uint32_t merge_split(const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb,
+                                                uint32_t d) {
+  uint32_t lo = d > nb ? d - nb : 0u, hi = min(d, na);
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (A[mid] < B[d - 1 - mid]) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256) k_big_partition(BinBuffers bb, uint32_t w, const uint64_t* __restrict__ src_all) {
+  const int nbig = (int)bb.total[2];
+  const uint32_t nblk = (uint32_t)bb.total[5];
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nblk; g += gridDim.x * blockDim.x) {
+    const MergeBlock m = merge_block(bb, nbig, g, w);
+    const uint64_t* src = src_all + bb.tile_start[m.t];
+    bb.big_split[g] = m.nb ? merge_split(src + m.a0, m.na, src + m.b0, m.nb, m.o0 - m.a0) : m.o0 - m.a0;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_big_merge(BinBuffers bb, uint32_t w, const uint64_t* __restrict__ src_all,
                                                    uint64_t* __restrict__ dst_all) {
-  const int nb = (int)bb.total[2];
-  const uint32_t ngr = (uint32_t)bb.total[5];
-  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ngr; g += gridDim.x * blockDim.x) {
-    const int k = big_of(bb.big_goff, nb, g);
-    const uint32_t t = bb.big_tiles[k];
-    const uint32_t n = bb.tile_cnt[t];
-    const uint64_t* src = src_all + bb.tile_start[t];
-    uint64_t* dst = dst_all + bb.tile_start[t];
-    const uint32_t pos0 = (g - bb.big_goff[k]) * 8u;
-    const uint32_t end = min(pos0 + 8u, n);
-    if (n <= w) {
-      for (uint32_t o = pos0; o < end; ++o) dst[o] = src[o];
+  __shared__ uint64_t s[kMergeTile];
+  const int nbig = (int)bb.total[2];
+  const uint32_t nblk = (uint32_t)bb.total[5];
+  for (uint32_t g = blockIdx.x; g < nblk; g += gridDim.x) {
+    const MergeBlock m = merge_block(bb, nbig, g, w);
+    const uint64_t* src = src_all + bb.tile_start[m.t];
+    uint64_t* dst = dst_all + bb.tile_start[m.t];
+    const uint32_t cnt = m.o1 - m.o0;
+    if (m.nb == 0) {
+      for (uint32_t o = threadIdx.x; o < cnt; o += blockDim.x) dst[m.o0 + o] = src[m.o0 + o];
       continue;
     }
-    const uint32_t a0 = pos0 / (2u * w) * (2u * w);
-    const uint32_t na = min(w, n - a0);
-    const uint32_t b0 = a0 + na, nbk = b0 < n ? min(w, n - b0) : 0u;
-    const uint32_t d = pos0 - a0;
-    uint32_t lo = d > nbk ? d - nbk : 0u, hi = min(d, na);
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (src[a0 + mid] < src[b0 + d - 1 - mid]) lo = mid + 1; else hi = mid;
-    }
-    uint32_t i = lo, j = d - lo;
-    for (uint32_t o = pos0; o < end; ++o) {
-      if (j >= nbk || (i < na && src[a0 + i] < src[b0 + j])) dst[o] = src[a0 + i++];
-      else dst[o] = src[b0 + j++];
+    // this block's inputs: A[ia0, ia1) and B[ib0, ib1)
+    const uint32_t ia0 = bb.big_split[g];
+    const uint32_t ia1 = m.o1 == m.a0 + m.na + m.nb ? m.na : bb.big_split[g + 1];
+    const uint32_t ib0 = (m.o0 - m.a0) - ia0, ib1 = (m.o1 - m.a0) - ia1;
+    const uint32_t nA = ia1 - ia0, nB = ib1 - ib0;
+    __syncthreads();
+    for (uint32_t x = threadIdx.x; x < nA; x += blockDim.x) s[x] = src[m.a0 + ia0 + x];
+    for (uint32_t x = threadIdx.x; x < nB; x += blockDim.x) s[nA + x] = src[m.b0 + ib0 + x];
+    __syncthreads();
+    const uint32_t d = 8u * threadIdx.x;
+    if (d < cnt) {
+      uint32_t i = merge_split(s, nA, s + nA, nB, d), j = d - i;
+      const uint32_t end = min(d + 8u, cnt);
+      for (uint32_t o = d; o < end; ++o) {
+        if (j >= nB || (i < nA && s[i] < s[nA + j])) dst[m.o0 + o] = s[i++];
+        else dst[m.o0 + o] = s[nA + j++];
+      }
     }
   }
 }
@@ -296,18 +394,19 @@ void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, const unsigned
                       hipStream_t st) {
   k_tile_sort<<<ras.n_tiles, 256, 0, st>>>(ras, bb);
   if (totals[2] == 0) return;
-  const unsigned long long nch = totals[4], ngr = totals[5], maxn = totals[3];
+  const unsigned long long nch = totals[4], nblk = totals[5], maxn = totals[3];
   k_big_chunks<<<(unsigned)std::min<unsigned long long>(nch, (unsigned long long)n_cu * 2), 1024, 0, st>>>(bb);
-  const unsigned grid = (unsigned)std::max<unsigned long long>(
-      1, std::min<unsigned long long>((ngr + 255) / 256, (unsigned long long)n_cu * 8));
+  const unsigned pgrid = (unsigned)std::max<unsigned long long>(1, (nblk + 255) / 256);
+  const unsigned mgrid = (unsigned)std::min<unsigned long long>(nblk, (unsigned long long)n_cu * 8);
   uint64_t* src = bb.keys;
   uint64_t* dst = bb.keys_tmp;
   int passes = 0;
   for (unsigned long long w = kSortCap; w < maxn; w <<= 1, ++passes) {
-    k_big_merge<<<grid, 256, 0, st>>>(bb, (uint32_t)w, src, dst);
+    k_big_partition<<<pgrid, 256, 0, st>>>(bb, (uint32_t)w, src);
+    k_big_merge<<<mgrid, 256, 0, st>>>(bb, (uint32_t)w, src, dst);
     std::swap(src, dst);
   }
-  if (passes & 1) k_big_merge<<<grid, 256, 0, st>>>(bb, 0xffffffffu, src, dst);   // back into keys
+  if (passes & 1) k_big_merge<<<mgrid, 256, 0, st>>>(bb, 0xffffffffu, src, dst);   // back into keys
 }
 
 }  // namespace sg

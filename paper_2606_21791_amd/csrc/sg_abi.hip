@@ -60,7 +60,7 @@ struct Workspace {
   hipStream_t stream = nullptr;
   // full renders
   DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
-      big_prims, big_tiles, big_choff, big_goff, parts, work_scene, sites_dev, box_keys, metrics_tmp;
+      big_prims, big_tiles, big_choff, big_goff, big_split, parts, work_scene, sites_dev, box_keys, metrics_tmp;
   // batches of variants
   DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, gmetrics;
   unsigned long long* h_total = nullptr;   // pinned
@@ -168,7 +168,7 @@ Workspace* workspace(sg_ctx* ctx, hipStream_t st) {
 void free_workspace(sg_ctx* ctx, Workspace* w) {
   DevBuf* bufs[] = {&w->r0, &w->r1, &w->r2, &w->depth, &w->rect, &w->diff, &w->flags, &w->clamps, &w->tile_cnt,
                     &w->tile_start, &w->cursor, &w->total, &w->keys, &w->keys_tmp, &w->big_prims, &w->big_tiles,
-                    &w->big_choff, &w->big_goff,
+                    &w->big_choff, &w->big_goff, &w->big_split,
                     &w->parts, &w->work_scene, &w->sites_dev, &w->box_keys, &w->metrics_tmp, &w->vs, &w->ovr,
                     &w->bitmap, &w->item_off, &w->n_items_v, &w->n_items_total, &w->items, &w->bparts,
                     &w->counter, &w->gmetrics};
@@ -418,7 +418,7 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
   }
   BinBuffers bb{P<int32_t>(W->diff), P<uint32_t>(tile_cnt), P<uint32_t>(tile_start), P<uint32_t>(W->cursor),
                 P<unsigned long long>(W->total), nullptr, nullptr, P<uint32_t>(W->big_prims),
-                P<uint32_t>(W->big_tiles), P<uint32_t>(W->big_choff), P<uint32_t>(W->big_goff), 0};
+                P<uint32_t>(W->big_tiles), P<uint32_t>(W->big_choff), P<uint32_t>(W->big_goff), nullptr, 0};
   {
     PassScope ps(ctx, SG_PASS_BIN, st);
     launch_tile_prefix(ras, bb, st);
@@ -440,6 +440,8 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
   {
     PassScope ps(ctx, SG_PASS_SORT, st);
     if (W->h_total[3] > (1ull << 31)) return fail(SG_E_UNSUPPORTED, "a tile list longer than 2^31 entries");
+    SG_TRY(dev_alloc(ctx, W->big_split, (W->h_total[5] + 1) * sizeof(uint32_t)));
+    bb.big_split = P<uint32_t>(W->big_split);
     launch_tile_sort(ras, bb, W->h_total, ctx->n_cu, st);
   }
   CompArgs ca{P<float4>(r0), P<float4>(r1), P<float4>(r2), P<uint32_t>(tile_start), P<uint32_t>(tile_cnt),

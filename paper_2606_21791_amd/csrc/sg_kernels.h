@@ -120,15 +120,16 @@ struct BinBuffers {
   uint32_t* tile_start;
   uint32_t* cursor;
   // [0] instances, [1] big prims, [2] big tiles (lists longer than one LDS
-  // sort), [3] longest big list, [4] LDS chunks of big tiles, [5] 8-key merge
-  // groups of big tiles
+  // sort), [3] longest big list, [4] LDS chunks of big tiles, [5] merge blocks
+  // of big tiles
   unsigned long long* total;
   uint64_t* keys;
   uint64_t* keys_tmp;
   uint32_t* big_prims;
   uint32_t* big_tiles;        // big tiles in tile order
   uint32_t* big_choff;        // per big tile (+1): first LDS chunk
-  uint32_t* big_goff;         // per big tile (+1): first merge group
+  uint32_t* big_goff;         // per big tile (+1): first merge block
+  uint32_t* big_split;        // per merge block: its first output's position in run A
   int64_t capacity;
 };
 void launch_tile_prefix(const DevRaster& ras, const BinBuffers& bb, hipStream_t st);
