@@ -172,7 +172,7 @@ def main():
                     help="oracle processes run at once for the all-core baseline (0: the host's cores, at most 16)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="seconds of Poisson arrivals for the serving measurement (0: skip)")
-    ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve", "copy"],
+    ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve", "copy", "views"],
                     help="w2: the headline; guard: support guard and accumulated dose on the N=134,826 scene; "
                          "large: the 2,056,645-primitive bf16 scene at 1600x900; stress: one guarded render at "
                          "65,812,640 primitives")
@@ -182,7 +182,7 @@ def main():
         sys.exit(2)
     if args.workload != "w2":
         {"guard": run_guard, "large": run_large, "stress": run_stress, "serve": run_serve,
-         "copy": run_copy}[args.workload](args)
+         "copy": run_copy, "views": run_views}[args.workload](args)
         return
 
     sc, cam, sites = _workload(args.fmt)
@@ -676,6 +676,54 @@ def run_stress(args):
            "pass_ms": {k: round(v[0] / reps, 3) for k, v in pp.items() if v[1]},
            "clamps_clean": int(cnt[0]), "device_bytes": ctx.bytes(),
            "paper_context": {"guard_ms": 9.66, "guard_fraction": 0.183, "hardware": "Blackwell-generation GPU"}}
+    print(json.dumps(out), flush=True)
+
+
+def run_views(args):
+    """K views per injection (Def. 1 pools the footprint over K views): the
+    scaling-sweep scene (N=134,826, SH3, fp32) seen by K orbit cameras at
+    800x800, batched campaigns of B variants for K in 1, 2, 4, 8, 16;
+    injections/s and view-pixels composited per second (K x 800 x 800 per
+    injection, the unit of the paper's multi-view throughput)."""
+    import torch
+    from paper_2606_21791_amd import binding as sgb, synth
+    sc, cam, sites = _workload("f32")
+    ctx = sgb.Context(0)
+    ds = sgb.DeviceScene.upload(ctx, sc, "f32")
+    tuned = _tune_into(ctx, args, ds, cam, sites)
+    B = args.batch
+    n_inj = min(args.steps, 1000) * B
+    idx = np.arange(n_inj) % len(sites)
+    sa = sgb.sites_array(sites.field[idx], sites.comp[idx], sites.prim[idx], sites.bit[idx])
+    va = sgb.variants_array(np.arange(n_inj), np.ones(n_inj, np.uint32))
+    curve = []
+    for K in (1, 2, 4, 8, 16):
+        cams = synth.make_orbit_cameras(K, 800, 800)
+        preps = [ctx.prepare(ds, c, sgb.raster_struct(tile=args.tile)) for c in cams]
+        n = max(B, (n_inj // K) // B * B)
+        mt = sgb.metrics_tensor(n)
+        kw = dict(batch=B, streams=args.streams, threads=max(1, args.threads))
+        ctx.campaign(preps, sa, va[:4 * B], mt, **kw)
+        torch.cuda.synchronize()
+        with _no_gc():
+            t0 = time.perf_counter()
+            ctx.campaign(preps, sa, va[:n], mt, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        r = sgb.read_metrics(mt)
+        curve.append({"K": K, "inj_per_s": round(n / dt, 1), "view_mpix_per_s": round(n * K * 0.64 / dt, 1),
+                      "mean_footprint": round(float(r["footprint"].mean()), 6),
+                      "catastrophic_fraction": round(float(r["catastrophic"].mean()), 4),
+                      "dirty_tiles_per_injection": round(float(r["dirty_tiles"].mean()), 2)})
+        del preps
+        torch.cuda.synchronize()
+    out = {"metric": "K-view injections: injections/s and view-Mpix/s vs K",
+           "config": {"workload": "N=134,826 Gaussians, SH degree 3, fp32, K orbit views at 800x800 "
+                                  f"(elevation 15 deg), B={B}", "tile": args.tile, "streams": args.streams,
+                      "host_threads": args.threads, "resume_spacing": args.resume, "tuned": tuned is not None},
+           "curve": curve,
+           "paper_context": {"view_mpix_per_s": 837, "saturation_views": 16, "hardware": "Blackwell-generation GPU, "
+                             "full renders of K views per injection"}}
     print(json.dumps(out), flush=True)
 
 

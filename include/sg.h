@@ -238,6 +238,20 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
                           const sg_variant* variants, int32_t B, const sg_box* box, uint32_t box_field_mask,
                           float* images_out, sg_metrics_t* metrics_out, int32_t mode, void* stream);
 
+/* K views per injection (Def. 1 averages the footprint over the K views;
+ * Sec. 3, "Parallel injection engine", renders them per injection).  preps[k]
+ * are views of one scene (prepared from the same sg_scene).  Every variant
+ * is rendered in each view as by sg_render_batch; per_view_out (nullable,
+ * device, K x B records, view-major) receives the per-view records and
+ * metrics_out (device, B records) the pooled ones: SSE, changed pixels,
+ * evaluations, dirty tiles and pixels summed over the views, the largest
+ * delta, the non-finite flag of any view, the footprint as the mean of the
+ * per-view footprints, PSNR from the pooled MSE and the catastrophe rule on
+ * the pooled footprint.  1 <= K <= 64. */
+sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const sg_site* sites, int32_t n_sites,
+                                const sg_variant* variants, int32_t B, const sg_box* box, uint32_t box_field_mask,
+                                sg_metrics_t* metrics_out, sg_metrics_t* per_view_out, int32_t mode, void* stream);
+
 /* A campaign: n_variants variants of one prepared scene, rendered as
  * consecutive batches of cfg->batch variants (the launch size B of
  * sg_render_batch), the batches spread round-robin over cfg->streams device
@@ -259,6 +273,11 @@ typedef struct {
 sg_status sg_campaign(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites, const sg_variant* variants,
                       int32_t n_variants, const sg_box* box, uint32_t box_field_mask, const sg_campaign_cfg* cfg,
                       sg_metrics_t* metrics_out, void* stream);
+/* The same over K views of one scene: each batch is rendered in every view
+ * as by sg_render_batch_views and metrics_out receives the pooled records. */
+sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const sg_site* sites, int32_t n_sites,
+                            const sg_variant* variants, int32_t n_variants, const sg_box* box, uint32_t box_field_mask,
+                            const sg_campaign_cfg* cfg, sg_metrics_t* metrics_out, void* stream);
 
 /* Autotuner.  Picks the launch configuration of injection campaigns on one
  * scene and camera by measurement: tile size, variants per launch B,

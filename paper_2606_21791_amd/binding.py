@@ -123,6 +123,8 @@ def _load():
         "sg_prep_copy_frame": (i32, [vp, vp, vp]),
         "sg_render_batch": (i32, [vp, vp, vp, i32, vp, i32, P(SgBox), u32, vp, vp, i32, vp]),
         "sg_campaign": (i32, [vp, vp, vp, i32, vp, i32, P(SgBox), u32, P(SgCampaignCfg), vp, vp]),
+        "sg_campaign_views": (i32, [vp, vp, i32, vp, i32, vp, i32, P(SgBox), u32, P(SgCampaignCfg), vp, vp]),
+        "sg_render_batch_views": (i32, [vp, vp, i32, vp, i32, vp, i32, P(SgBox), u32, vp, vp, i32, vp]),
         "sg_metrics": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
         "sg_autotune": (i32, [vp, P(SgScene), P(SgCamera), P(SgRaster), vp, i32, i32, i32, C.c_char_p, P(SgTune), vp]),
         "sg_ctx_timing": (i32, [vp, i32]),
@@ -150,7 +152,8 @@ def _load():
 LIB = _load()
 EXPORTED = ("sg_ctx_create", "sg_ctx_destroy", "sg_last_error", "sg_ctx_bytes", "sg_cast", "sg_inject",
             "sg_restore", "sg_guard_box", "sg_guard", "sg_render", "sg_prepare", "sg_prep_destroy",
-            "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_campaign", "sg_autotune", "sg_metrics",
+            "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_render_batch_views", "sg_campaign",
+            "sg_campaign_views", "sg_autotune", "sg_metrics",
             "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_resume", "sg_ctx_set_graphs",
             "sg_serve_create",
             "sg_serve_add_scene", "sg_serve_add_view", "sg_serve_submit", "sg_serve_poll", "sg_serve_wait",
@@ -301,13 +304,34 @@ class Context:
     def campaign(self, prep, sites: np.ndarray, variants: np.ndarray, metrics, box=None,
                  box_mask: int = SG_FIELD_MASK_GUARD, batch: int = 32, streams: int = 8, threads: int = 2):
         """All variants of a campaign in batches of `batch`, over `streams` device
-        streams enqueued by `threads` host threads; records into `metrics`."""
+        streams enqueued by `threads` host threads; records into `metrics`.
+        `prep` may be a list of views of one scene (pooled records)."""
         s = np.ascontiguousarray(sites, SITE_DTYPE)
         v = np.ascontiguousarray(variants, VARIANT_DTYPE)
         cfg = SgCampaignCfg(int(batch), int(streams), int(threads), 0)
-        check(LIB.sg_campaign(self.h, prep.h, s.ctypes.data_as(C.c_void_p), len(s), v.ctypes.data_as(C.c_void_p),
-                              len(v), C.byref(box.st) if box is not None else None, box_mask if box is not None else 0,
-                              C.byref(cfg), _ptr(metrics), _stream()))
+        bx = C.byref(box.st) if box is not None else None
+        mask = box_mask if box is not None else 0
+        if isinstance(prep, (list, tuple)):
+            hs = (C.c_void_p * len(prep))(*[p.h for p in prep])
+            check(LIB.sg_campaign_views(self.h, hs, len(prep), s.ctypes.data_as(C.c_void_p), len(s),
+                                        v.ctypes.data_as(C.c_void_p), len(v), bx, mask, C.byref(cfg), _ptr(metrics),
+                                        _stream()))
+        else:
+            check(LIB.sg_campaign(self.h, prep.h, s.ctypes.data_as(C.c_void_p), len(s), v.ctypes.data_as(C.c_void_p),
+                                  len(v), bx, mask, C.byref(cfg), _ptr(metrics), _stream()))
+
+    def render_batch_views(self, preps, sites: np.ndarray, variants: np.ndarray, metrics, per_view=None, box=None,
+                           box_mask: int = SG_FIELD_MASK_GUARD, mode: int = SG_INCREMENTAL):
+        """Every variant in each of the K views `preps`; pooled records into
+        `metrics` (B), per-view records into `per_view` (K x B) when given."""
+        s = np.ascontiguousarray(sites, SITE_DTYPE)
+        v = np.ascontiguousarray(variants, VARIANT_DTYPE)
+        hs = (C.c_void_p * len(preps))(*[p.h for p in preps])
+        check(LIB.sg_render_batch_views(self.h, hs, len(preps), s.ctypes.data_as(C.c_void_p), len(s),
+                                        v.ctypes.data_as(C.c_void_p), len(v),
+                                        C.byref(box.st) if box is not None else None,
+                                        box_mask if box is not None else 0, _ptr(metrics), _ptr(per_view), mode,
+                                        _stream()))
 
     def autotune(self, scene, cam, sites: np.ndarray, raster=None, fixed_batch: int = 0, max_batch: int = 0,
                  cache: str | None = None) -> dict:

@@ -166,6 +166,35 @@ __global__ void k_reduce_metrics(const Partial* __restrict__ parts, const uint32
                           vs ? vs[v].clamps : (clamps ? *clamps : 0ull), n_pixels, path);
 }
 
+// Pools the records of K views per variant (view-major input, K x B): SSE,
+// changed pixels, evaluations, dirty tiles and pixels add up, the largest
+// delta and the non-finite flag are kept, the footprint is the mean of the
+// per-view footprints (Def. 1), PSNR follows from the pooled MSE, and the
+// catastrophe rule (Def. 2) is applied to the pooled footprint.
+__global__ void k_pool_views(const sg_metrics_t* __restrict__ views, int K, int B, sg_metrics_t* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= B) return;
+  Partial r;
+  r.sse = 0.0; r.evals = 0; r.changed = 0; r.max_abs = 0.f; r.nonfinite = 0; r._pad = 0;
+  uint32_t dirty = 0, px = 0;
+  double foot = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const sg_metrics_t& m = views[(int64_t)k * B + v];
+    r.sse += m.sse;
+    r.evals += m.evals;
+    r.changed += m.changed_px;
+    r.max_abs = fmaxf(r.max_abs, m.max_abs);
+    r.nonfinite |= m.nonfinite;
+    dirty += m.dirty_tiles;
+    px += m.n_pixels;
+    foot += (double)m.changed_px / (double)m.n_pixels;
+  }
+  sg_metrics_t o = make_metrics(r, 0u, dirty, views[v].clamps, px, views[v].path);
+  o.footprint = (float)(foot / K);
+  o.catastrophic = (o.nonfinite || foot / K > 0.01) ? 1u : 0u;
+  out[v] = o;
+}
+
 // ----------------------------------------------------------------------------
 // host launchers
 
@@ -213,6 +242,11 @@ void launch_reduce_metrics(const Partial* parts, const uint32_t* item_off, const
   if (B <= 0) return;
   k_reduce_metrics<<<B, 256, 0, st>>>(parts, item_off, n_items, uniform_items, vs, flags, clamps, n_pixels, out,
                                       path);
+}
+
+void launch_pool_views(const sg_metrics_t* views, int K, int B, sg_metrics_t* out, hipStream_t st) {
+  if (B <= 0) return;
+  k_pool_views<<<(B + 255) / 256, 256, 0, st>>>(views, K, B, out);
 }
 
 }  // namespace sg

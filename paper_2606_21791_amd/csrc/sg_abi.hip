@@ -39,6 +39,8 @@ sg_status fail(sg_status code, const std::string& msg) {
 
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+constexpr int kMaxViews = 64;
+
 int n_components(int f, int sh_degree) {
   static const int base[5] = {3, 3, 4, 1, 3};
   if (f < 5) return base[f];
@@ -62,7 +64,7 @@ struct Workspace {
   DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
       big_prims, big_tiles, big_choff, big_goff, big_split, parts, work_scene, sites_dev, box_keys, metrics_tmp;
   // batches of variants
-  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, gmetrics;
+  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, gmetrics, views_tmp;
   unsigned long long* h_total = nullptr;   // pinned
   // pinned staging ring for a batch's sites and variants, read by the variant
   // prep kernel in place; slot k may be rewritten once the batch that last
@@ -171,7 +173,7 @@ void free_workspace(sg_ctx* ctx, Workspace* w) {
                     &w->big_choff, &w->big_goff, &w->big_split,
                     &w->parts, &w->work_scene, &w->sites_dev, &w->box_keys, &w->metrics_tmp, &w->vs, &w->ovr,
                     &w->bitmap, &w->item_off, &w->n_items_v, &w->n_items_total, &w->items, &w->bparts,
-                    &w->counter, &w->gmetrics};
+                    &w->counter, &w->gmetrics, &w->views_tmp};
   for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);
   w->graphs.clear();
   for (DevBuf* b : bufs) dev_free(ctx, *b);
@@ -892,10 +894,41 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
   return SG_OK;
 }
 
-sg_status sg_campaign(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites, const sg_variant* variants,
-                      int32_t n_variants, const sg_box* box, uint32_t box_field_mask, const sg_campaign_cfg* cfg,
-                      sg_metrics_t* metrics_out, void* stream) {
-  if (!ctx || !prep || !metrics_out) return fail(SG_E_INVAL, "ctx/prep/metrics_out is NULL");
+sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const sg_site* sites, int32_t n_sites,
+                                const sg_variant* variants, int32_t B, const sg_box* box, uint32_t box_field_mask,
+                                sg_metrics_t* metrics_out, sg_metrics_t* per_view_out, int32_t mode, void* stream) {
+  if (!ctx || !preps || !metrics_out) return fail(SG_E_INVAL, "ctx/preps/metrics_out is NULL");
+  if (K < 1 || K > kMaxViews) return fail(SG_E_INVAL, "K must be in [1, 64]");
+  for (int k = 0; k < K; ++k) {
+    if (!preps[k]) return fail(SG_E_INVAL, "preps[" + std::to_string(k) + "] is NULL");
+    const sg_scene& a = preps[0]->host_scene;
+    const sg_scene& b = preps[k]->host_scene;
+    bool same = a.n == b.n && a.sh_degree == b.sh_degree && a.dtype == b.dtype;
+    for (int f = 0; f < 6 && same; ++f) same = a.ptr[f] == b.ptr[f];
+    if (!same) return fail(SG_E_INVAL, "the views are not prepared from one scene");
+  }
+  if (B == 0) return SG_OK;
+  hipStream_t st = S(stream);
+  WS_OR_FAIL(W, ctx, st);
+  sg_metrics_t* pv = per_view_out;
+  if (!pv) {
+    SG_TRY(dev_alloc(ctx, W->views_tmp, (size_t)K * B * sizeof(sg_metrics_t)));
+    pv = P<sg_metrics_t>(W->views_tmp);
+  }
+  for (int k = 0; k < K; ++k)
+    SG_TRY(sg_render_batch(ctx, preps[k], sites, n_sites, variants, B, box, box_field_mask, nullptr,
+                           pv + (int64_t)k * B, mode, stream));
+  launch_pool_views(pv, K, B, metrics_out, st);
+  return check_last("sg_render_batch_views");
+}
+
+sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const sg_site* sites, int32_t n_sites,
+                            const sg_variant* variants, int32_t n_variants, const sg_box* box, uint32_t box_field_mask,
+                            const sg_campaign_cfg* cfg, sg_metrics_t* metrics_out, void* stream) {
+  if (!ctx || !preps || !metrics_out) return fail(SG_E_INVAL, "ctx/preps/metrics_out is NULL");
+  if (K < 1 || K > kMaxViews) return fail(SG_E_INVAL, "K must be in [1, 64]");
+  sg_prep* prep = preps[0];
+  if (!prep) return fail(SG_E_INVAL, "preps[0] is NULL");
   if (n_variants < 0 || (n_variants > 0 && !variants)) return fail(SG_E_INVAL, "bad variants");
   const int B = cfg && cfg->batch > 0 ? cfg->batch : 32;
   const int NS = cfg && cfg->streams > 0 ? cfg->streams : 8;
@@ -948,9 +981,12 @@ sg_status sg_campaign(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t 
       if (lo > hi) lo = hi = 0;
       local.assign(variants + v0, variants + v0 + nv);
       for (sg_variant& x : local) x.site_off -= lo;
-      const sg_status rc = sg_render_batch(ctx, prep, sites + lo, (int32_t)(hi - lo), local.data(), nv, box,
-                                           box_field_mask, nullptr, metrics_out + v0, SG_INCREMENTAL,
-                                           ctx->campaign_streams[k]);
+      const sg_status rc =
+          K == 1 ? sg_render_batch(ctx, prep, sites + lo, (int32_t)(hi - lo), local.data(), nv, box, box_field_mask,
+                                   nullptr, metrics_out + v0, SG_INCREMENTAL, ctx->campaign_streams[k])
+                 : sg_render_batch_views(ctx, preps, K, sites + lo, (int32_t)(hi - lo), local.data(), nv, box,
+                                         box_field_mask, metrics_out + v0, nullptr, SG_INCREMENTAL,
+                                         ctx->campaign_streams[k]);
       if (rc != SG_OK) {
         std::lock_guard<std::mutex> g(err_mu);
         if (first_rc == SG_OK) {
@@ -974,6 +1010,13 @@ sg_status sg_campaign(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t 
   }
   if (first_rc != SG_OK) return fail(first_rc, first_msg);
   return SG_OK;
+}
+
+sg_status sg_campaign(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites, const sg_variant* variants,
+                      int32_t n_variants, const sg_box* box, uint32_t box_field_mask, const sg_campaign_cfg* cfg,
+                      sg_metrics_t* metrics_out, void* stream) {
+  return sg_campaign_views(ctx, &prep, 1, sites, n_sites, variants, n_variants, box, box_field_mask, cfg, metrics_out,
+                           stream);
 }
 
 sg_status sg_metrics(sg_ctx* ctx, const float* images, const float* clean, int32_t B, int32_t K, int32_t H, int32_t W,

@@ -73,6 +73,7 @@ void launch_guard(const DevScene& s, const DevBox& b, int f, unsigned long long*
 void launch_health(const unsigned long long* count, unsigned long long thr, uint32_t* alert, hipStream_t st);
 void launch_metrics_partials(const float* img, const float* clean, int64_t px_per_var, int nchunks, int B,
                              Partial* out, hipStream_t st);
+void launch_pool_views(const sg_metrics_t* views, int K, int B, sg_metrics_t* out, hipStream_t st);
 void launch_reduce_metrics(const Partial* parts, const uint32_t* item_off, const uint32_t* n_items,
                            uint32_t uniform_items, const VariantState* vs, const uint32_t* flags,
                            const unsigned long long* clamps, uint32_t n_pixels, sg_metrics_t* out, int B,

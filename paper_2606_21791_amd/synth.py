@@ -121,6 +121,22 @@ def make_camera(width: int, height: int, distance: float = 3.0, fov_x_deg: float
                   int(width), int(height))
 
 
+def make_orbit_cameras(k: int, width: int, height: int, distance: float = 3.0, fov_x_deg: float = 60.0,
+                       elevation_deg: float = 15.0) -> list:
+    """k cameras evenly spaced in azimuth around the origin, each tilted by
+    elevation_deg and looking at the origin from the given distance (R is a
+    rotation about x by the elevation times a rotation about y by 2 pi j / k)."""
+    base = make_camera(width, height, distance, fov_x_deg)
+    e = math.radians(elevation_deg)
+    rx = np.array([[1.0, 0.0, 0.0], [0.0, math.cos(e), -math.sin(e)], [0.0, math.sin(e), math.cos(e)]])
+    cams = []
+    for j in range(k):
+        a = 2.0 * math.pi * j / k
+        ry = np.array([[math.cos(a), 0.0, math.sin(a)], [0.0, 1.0, 0.0], [-math.sin(a), 0.0, math.cos(a)]])
+        cams.append(Camera(rx @ ry, base.t.copy(), base.fx, base.fy, base.cx, base.cy, base.width, base.height))
+    return cams
+
+
 @dataclass
 class Sites:
     """Fault sites (field, primitive, component, bit), Sec. 3 "Single-bit upset model"."""

@@ -313,6 +313,69 @@ def test_autotune_and_cache(ctx, tmp_path):
         assert np.array_equal(r[key], g[key]) or key == "sse" and np.allclose(r[key], g[key], rtol=1e-12, atol=0), key
 
 
+def test_k_views_pooling(ctx):
+    """K views per injection (Def. 1: footprint averaged over the views): the
+    per-view records equal single-view batches exactly, the pooled record is
+    the pooling of the per-view ones, and a K-view campaign over several
+    streams equals the batch-by-batch calls."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(4000, seed=14, sh_degree=1)
+    cams = synth.make_orbit_cameras(3, 96, 80)
+    lo32, hi32 = synth.make_box_jitter(sc, seed=4)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    box = b.Box.per_prim(ctx, lo32, hi32, "f32")
+    preps = [ctx.prepare(ds, c) for c in cams]
+    single = synth.make_sites_stratified(sc.n, 1, 20, seed=31, width_bits=32)
+    dose = synth.make_sites_dose(sc.n, 1, 12, seed=32, width_bits=32)
+    sites = synth.Sites(*(np.concatenate([a, c]) for a, c in zip(
+        (single.field, single.comp, single.prim, single.bit), (dose.field, dose.comp, dose.prim, dose.bit))))
+    ns = len(single.prim)
+    sa = b.sites_array(sites.field, sites.comp, sites.prim, sites.bit)
+    va = b.variants_array(np.array(list(range(ns)) + [0, ns]), np.array([1] * ns + [3, len(dose.prim)]), 0)
+    va["guard"] = np.arange(len(va)) % 2
+    B, K = len(va), len(preps)
+    pooled, per_view = b.metrics_tensor(B), b.metrics_tensor(K * B)
+    ctx.render_batch_views(preps, sa, va, pooled, per_view=per_view, box=box)
+    torch.cuda.synchronize()
+    P, V = b.read_metrics(pooled), b.read_metrics(per_view).reshape(K, B)
+    for k in range(K):
+        mt = b.metrics_tensor(B)
+        ctx.render_batch(preps[k], sa, va, box=box, metrics=mt)
+        ref = b.read_metrics(mt)
+        for key in ref.dtype.names:
+            assert np.array_equal(V[k][key], ref[key]), (k, key)
+    sse = V["sse"][0].copy()
+    for k in range(1, K):
+        sse = sse + V["sse"][k]
+    assert np.array_equal(P["sse"], sse)
+    for key in ("changed_px", "dirty_tiles", "n_pixels", "evals"):
+        assert np.array_equal(P[key], V[key].sum(axis=0)), key
+    assert np.array_equal(P["max_abs"], V["max_abs"].max(axis=0))
+    assert np.array_equal(P["nonfinite"], V["nonfinite"].max(axis=0))
+    assert np.array_equal(P["clamps"], V["clamps"][0])
+    foot = (V["changed_px"] / V["n_pixels"]).mean(axis=0)
+    assert np.array_equal(P["footprint"], foot.astype(np.float32))
+    assert np.allclose(P["mse"], sse / (3.0 * V["n_pixels"].sum(axis=0)), rtol=1e-15, atol=0)
+    assert np.array_equal(P["catastrophic"], ((P["nonfinite"] > 0) | (foot > 0.01)).astype(np.uint32))
+    assert P["path"][-1] == 1 and V["n_pixels"][0][0] == 96 * 80
+    got = b.metrics_tensor(B)
+    ctx.campaign(preps, sa, va, got, box=box, batch=7, streams=4, threads=2)
+    torch.cuda.synchronize()
+    G = b.read_metrics(got)
+    ref = []
+    for v0 in range(0, B, 7):
+        mt = b.metrics_tensor(len(va[v0:v0 + 7]))
+        ctx.render_batch_views(preps, sa, va[v0:v0 + 7], mt, box=box)
+        ref.append(b.read_metrics(mt))
+    ref = np.concatenate(ref)
+    for key in ref.dtype.names:
+        assert np.array_equal(G[key], ref[key]), key
+    with pytest.raises(b.SgError):   # views of different scenes
+        other = b.DeviceScene.upload(ctx, sc, "f32")
+        ctx.render_batch_views([preps[0], ctx.prepare(other, cams[1])], sa, va, pooled)
+
+
 def test_sg_metrics_matches_definition(ctx):
     import torch
     from paper_2606_21791_amd import binding as b
