@@ -494,6 +494,37 @@ def _tune_into(ctx, args, ds, cam, sites):
     return t
 
 
+def _coarsen(mask, s):
+    """Region mask of the 8 x 8 grid coarsened to (8/s) x (8/s) regions."""
+    out = 0
+    for b in range(64):
+        if (mask >> b) & 1:
+            ry, rx = divmod(b, 8)
+            out |= 1 << ((ry // s) * (8 // s) + rx // s)
+    return out
+
+
+def _contamination(recs, sel=None):
+    """Sort-first contamination (Sec. 5.10) per partition of 4, 16 and 64
+    regions: mean fraction of regions whose pixels change (rendered) and
+    whose primitive sets change (predicted), and the mean intersection over
+    union of the two region sets (variants with a non-empty union)."""
+    pred = [int(x) for x in recs["predicted_regions"]]
+    rend = [int(x) for x in recs["rendered_regions"]]
+    if sel is not None:
+        pred = [pred[i] for i in sel]
+        rend = [rend[i] for i in sel]
+    out = {"variants": len(pred)}
+    for s, R in ((4, 4), (2, 16), (1, 64)):
+        p = [_coarsen(m, s) if s > 1 else m for m in pred]
+        r = [_coarsen(m, s) if s > 1 else m for m in rend]
+        ious = [bin(a & b).count("1") / bin(a | b).count("1") for a, b in zip(p, r) if a | b]
+        out[f"R{R}"] = {"rendered_frac": round(float(np.mean([bin(x).count("1") / R for x in r])) if r else 0.0, 4),
+                        "predicted_frac": round(float(np.mean([bin(x).count("1") / R for x in p])) if p else 0.0, 4),
+                        "iou": round(float(np.mean(ious)), 4) if ious else None}
+    return out
+
+
 def _summ(recs):
     ps = recs["psnr"][np.isfinite(recs["psnr"])]
     return {"mean_psnr_db": round(float(ps.mean()), 3) if ps.size else None,
@@ -550,10 +581,16 @@ def run_guard(args):
                          "clamp_on_load_extra_us": round((proj["with"] - proj["without"]) * 1e3, 2),
                          "projection_us_without_guard": round(proj["without"] * 1e3, 2)}
     # single flips, unguarded and guarded
+    steps_g = min(args.steps, 2000)
+    site_of = (np.arange(steps_g * args.batch) + args.warmup * args.batch) % len(sites)
+    scale_sign = np.nonzero((sites.field[site_of] == 1) & (sites.bit[site_of] == 31))[0]
     for guard in (0, 1):
         rate, recs = _batched_rate(ctx, prep, sites, args.batch, args.streams, max(1, args.threads),
-                                   min(args.steps, 2000), args.warmup, guard, box)
-        out["guarded" if guard else "unguarded"] = {"inj_per_s": round(rate, 1), **_summ(recs)}
+                                   steps_g, args.warmup, guard, box)
+        out["guarded" if guard else "unguarded"] = {
+            "inj_per_s": round(rate, 1), **_summ(recs),
+            "contamination_all": _contamination(recs),
+            "contamination_scale_sign": _contamination(recs, scale_sign)}
     # accumulated dose: k simultaneous flips over all stored bits, 16 frames each
     dose = {}
     mt = sgb.metrics_tensor(1)

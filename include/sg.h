@@ -128,7 +128,17 @@ typedef struct {
 
 /* Per-variant result (Sec. 3 "Metrics"; Def. 1; Def. 2).  footprint is the
  * fraction of pixels with max over RGB |delta| > 1/255; catastrophic is
- * nonfinite || footprint > 0.01; psnr is +Inf when mse == 0. */
+ * nonfinite || footprint > 0.01; psnr is +Inf when mse == 0.
+ *
+ * Contamination of a sort-first partition (Sec. 5.10): the frame's tiles are
+ * grouped into an 8 x 8 grid of regions, tile (tx, ty) belonging to region
+ * (8 tx / tiles_x, 8 ty / tiles_y), bit 8 ry + rx.  predicted_regions holds
+ * the regions of the variant's dirty tiles (the old and new footprints of its
+ * corrupted primitives: the nodes whose primitive sets change), and
+ * rendered_regions the regions holding a tile with a changed pixel.  Coarser
+ * partitions (4 x 4, 2 x 2) are unions of 2 x 2 or 4 x 4 bit blocks.  A
+ * variant on the full-render path reports every region as predicted; K-view
+ * records hold the union over the views; sg_metrics leaves both at 0. */
 typedef struct {
   double sse;
   double mse;
@@ -145,6 +155,8 @@ typedef struct {
   uint64_t evals;         /* pixel-primitive evaluations of the front-to-back loop
                              (per pixel: list entries up to and including the one
                              that stops it) over the re-composited tiles */
+  uint64_t predicted_regions;
+  uint64_t rendered_regions;
 } sg_metrics_t;
 
 typedef struct sg_ctx sg_ctx;

@@ -29,8 +29,9 @@ VARIANT_DTYPE = np.dtype([("site_off", "<u4"), ("n_sites", "<u4"), ("guard", "<u
 METRICS_DTYPE = np.dtype([("sse", "<f8"), ("mse", "<f8"), ("psnr", "<f8"), ("footprint", "<f4"),
                           ("max_abs", "<f4"), ("nonfinite", "<u4"), ("catastrophic", "<u4"),
                           ("changed_px", "<u4"), ("dirty_tiles", "<u4"), ("clamps", "<u8"),
-                          ("n_pixels", "<u4"), ("path", "<u4"), ("evals", "<u8")])
-assert SITE_DTYPE.itemsize == 8 and VARIANT_DTYPE.itemsize == 16 and METRICS_DTYPE.itemsize == 72
+                          ("n_pixels", "<u4"), ("path", "<u4"), ("evals", "<u8"),
+                          ("predicted_regions", "<u8"), ("rendered_regions", "<u8")])
+assert SITE_DTYPE.itemsize == 8 and VARIANT_DTYPE.itemsize == 16 and METRICS_DTYPE.itemsize == 88
 PASSES = ("variant_prep", "composite_items", "reduce", "project", "bin", "sort", "composite_full", "guard")
 
 

@@ -143,7 +143,7 @@ __global__ void k_metrics_partials(const float* __restrict__ img, const float* _
 __global__ void k_reduce_metrics(const Partial* __restrict__ parts, const uint32_t* __restrict__ item_off,
                                  const uint32_t* __restrict__ n_items, uint32_t uniform_items, const VariantState* vs,
                                  const uint32_t* flags, const unsigned long long* clamps, uint32_t n_pixels,
-                                 sg_metrics_t* __restrict__ out, uint32_t path) {
+                                 sg_metrics_t* __restrict__ out, uint32_t path, int tiles_x, int tiles_y) {
   const int v = blockIdx.x;
   const uint32_t off = item_off ? item_off[v] : v * uniform_items;
   const uint32_t n = n_items ? n_items[v] : uniform_items;
@@ -151,8 +151,10 @@ __global__ void k_reduce_metrics(const Partial* __restrict__ parts, const uint32
   uint32_t changed = 0, nonfin = 0;
   float mx = 0.f;
   unsigned long long ev = 0;
+  uint64_t rend = 0;   // full render with per-tile partials: regions of the changed tiles
   for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
     const Partial p = parts[off + k];
+    if (tiles_x > 0 && p.changed) rend |= region_bit((int)k % tiles_x, (int)k / tiles_x, tiles_x, tiles_y);
     sse += p.sse;
     changed += p.changed;
     mx = fmaxf(mx, p.max_abs);
@@ -160,10 +162,18 @@ __global__ void k_reduce_metrics(const Partial* __restrict__ parts, const uint32
     ev += p.evals;
   }
   __shared__ Partial red;
-  block_reduce_partial(sse, changed, mx, nonfin, ev, &red);
-  if (threadIdx.x == 0)
+  __shared__ unsigned long long s_rend;
+  if (threadIdx.x == 0) s_rend = 0;
+  block_reduce_partial(sse, changed, mx, nonfin, ev, &red);   // its barriers order s_rend's reset
+  if (rend) atomicOr(&s_rend, (unsigned long long)rend);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t pr = 0, rr = 0;
+    if (vs) { pr = vs[v].pred_regions; rr = vs[v].rend_regions; }
+    else if (tiles_x > 0) { pr = ~0ull; rr = s_rend; }
     out[v] = make_metrics(red, (vs ? vs[v].nonfinite : 0u) | (flags ? (flags[0] & 1u) : 0u), vs ? vs[v].n_dirty : n,
-                          vs ? vs[v].clamps : (clamps ? *clamps : 0ull), n_pixels, path);
+                          vs ? vs[v].clamps : (clamps ? *clamps : 0ull), n_pixels, path, pr, rr);
+  }
 }
 
 // Pools the records of K views per variant (view-major input, K x B): SSE,
@@ -178,8 +188,11 @@ __global__ void k_pool_views(const sg_metrics_t* __restrict__ views, int K, int 
   r.sse = 0.0; r.evals = 0; r.changed = 0; r.max_abs = 0.f; r.nonfinite = 0; r._pad = 0;
   uint32_t dirty = 0, px = 0;
   double foot = 0.0;
+  uint64_t pr = 0, rr = 0;
   for (int k = 0; k < K; ++k) {
     const sg_metrics_t& m = views[(int64_t)k * B + v];
+    pr |= m.predicted_regions;
+    rr |= m.rendered_regions;
     r.sse += m.sse;
     r.evals += m.evals;
     r.changed += m.changed_px;
@@ -189,7 +202,7 @@ __global__ void k_pool_views(const sg_metrics_t* __restrict__ views, int K, int 
     px += m.n_pixels;
     foot += (double)m.changed_px / (double)m.n_pixels;
   }
-  sg_metrics_t o = make_metrics(r, 0u, dirty, views[v].clamps, px, views[v].path);
+  sg_metrics_t o = make_metrics(r, 0u, dirty, views[v].clamps, px, views[v].path, pr, rr);
   o.footprint = (float)(foot / K);
   o.catastrophic = (o.nonfinite || foot / K > 0.01) ? 1u : 0u;
   out[v] = o;
@@ -238,10 +251,10 @@ void launch_metrics_partials(const float* img, const float* clean, int64_t px_pe
 void launch_reduce_metrics(const Partial* parts, const uint32_t* item_off, const uint32_t* n_items,
                            uint32_t uniform_items, const VariantState* vs, const uint32_t* flags,
                            const unsigned long long* clamps, uint32_t n_pixels, sg_metrics_t* out, int B,
-                           uint32_t path, hipStream_t st) {
+                           uint32_t path, hipStream_t st, int tiles_x, int tiles_y) {
   if (B <= 0) return;
   k_reduce_metrics<<<B, 256, 0, st>>>(parts, item_off, n_items, uniform_items, vs, flags, clamps, n_pixels, out,
-                                      path);
+                                      path, tiles_x, tiles_y);
 }
 
 void launch_pool_views(const sg_metrics_t* views, int K, int B, sg_metrics_t* out, hipStream_t st) {

@@ -311,11 +311,13 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
       s_skip = (nr + ni == 0) || (A.stop_key && mn > A.stop_key[tile]);
     }
     __syncthreads();
+    const uint64_t region = region_bit(tile % A.ras.tiles_x, tile / A.ras.tiles_x, A.ras.tiles_x, A.ras.tiles_y);
     if (s_skip) {
       if (threadIdx.x == 0) {
         Partial z;
         z.sse = 0.0; z.evals = 0; z.changed = 0; z.max_abs = 0.f; z.nonfinite = 0; z._pad = 0;
         A.parts[item] = z;
+        atomicOr((unsigned long long*)&I.vs[v].pred_regions, (unsigned long long)region);
       }
       __syncthreads();
       continue;
@@ -382,6 +384,10 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
     __syncthreads();
     float* img = A.image ? A.image + (int64_t)v * I.image_stride : nullptr;
     composite_tile<TILE, kItem>(A, tile, &ms, I.ovr, img, A.parts + item, s_r0, s_r1, s_r2);
+    if (threadIdx.x == 0) {   // thread 0 wrote the item's partial
+      atomicOr((unsigned long long*)&I.vs[v].pred_regions, (unsigned long long)region);
+      if (A.parts[item].changed) atomicOr((unsigned long long*)&I.vs[v].rend_regions, (unsigned long long)region);
+    }
     __syncthreads();
   }
 }

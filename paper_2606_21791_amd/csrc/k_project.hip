@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, Dev
   __syncthreads();
   if (lane == 0) {
     st.n_touch = 0; st.full = 0; st.nonfinite = 0; st.n_dirty = 0; st.clamps = 0; st.item_off = 0; st._pad = 0;
+    st.pred_regions = 0; st.rend_regions = 0;
     for (uint32_t k = 0; k < var.n_sites; ++k) {
       const uint32_t p = sites[k].prim;
       bool seen = false;

@@ -673,7 +673,8 @@ sg_status sg_render(sg_ctx* ctx, const sg_scene* scene, const sg_camera* cam, co
                      W->keys, image_out, clean_frame, parts, st, nullptr));
   if (metrics_out)
     launch_reduce_metrics(parts, nullptr, nullptr, (uint32_t)r.n_tiles, nullptr, P<uint32_t>(W->flags),
-                          P<unsigned long long>(W->clamps), (uint32_t)(c.W * c.H), metrics_out, 1, 1u, st);
+                          P<unsigned long long>(W->clamps), (uint32_t)(c.W * c.H), metrics_out, 1, 1u, st,
+                          r.tiles_x, r.tiles_y);
   return check_last("sg_render");
 }
 
@@ -887,7 +888,7 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
                          P<float>(prep->frame), P<Partial>(W->parts), st, nullptr));
       launch_reduce_metrics(P<Partial>(W->parts), nullptr, nullptr, (uint32_t)ras.n_tiles, nullptr,
                             P<uint32_t>(W->flags), P<unsigned long long>(W->clamps),
-                            (uint32_t)(prep->cam.W * prep->cam.H), metrics_out + v, 1, 1u, st);
+                            (uint32_t)(prep->cam.W * prep->cam.H), metrics_out + v, 1, 1u, st, ras.tiles_x, ras.tiles_y);
       SG_TRY(check_last("sg_render_batch full"));
     }
   }

@@ -44,7 +44,8 @@ __device__ __forceinline__ void block_reduce_partial(double sse, uint32_t change
 // The record of one variant from its reduced partial (Def. 1 footprint,
 // Def. 2 catastrophe, PSNR on [0, 1] images over the three channels).
 __device__ __forceinline__ sg_metrics_t make_metrics(const Partial& red, uint32_t extra_nonfinite, uint32_t dirty,
-                                                     unsigned long long clamps, uint32_t n_pixels, uint32_t path) {
+                                                     unsigned long long clamps, uint32_t n_pixels, uint32_t path,
+                                                     uint64_t pred_regions = 0, uint64_t rend_regions = 0) {
   sg_metrics_t m;
   m.sse = red.sse;
   m.mse = red.sse / (3.0 * (double)n_pixels);
@@ -59,6 +60,8 @@ __device__ __forceinline__ sg_metrics_t make_metrics(const Partial& red, uint32_
   m.n_pixels = n_pixels;
   m.path = path;
   m.evals = red.evals;
+  m.predicted_regions = pred_regions;
+  m.rendered_regions = rend_regions;
   return m;
 }
 
@@ -74,10 +77,12 @@ void launch_health(const unsigned long long* count, unsigned long long thr, uint
 void launch_metrics_partials(const float* img, const float* clean, int64_t px_per_var, int nchunks, int B,
                              Partial* out, hipStream_t st);
 void launch_pool_views(const sg_metrics_t* views, int K, int B, sg_metrics_t* out, hipStream_t st);
+// tiles_x > 0 marks per-tile partials of a full render (uniform_items tiles):
+// their rendered regions are derived from the tiles with a changed pixel.
 void launch_reduce_metrics(const Partial* parts, const uint32_t* item_off, const uint32_t* n_items,
                            uint32_t uniform_items, const VariantState* vs, const uint32_t* flags,
                            const unsigned long long* clamps, uint32_t n_pixels, sg_metrics_t* out, int B,
-                           uint32_t path, hipStream_t st);
+                           uint32_t path, hipStream_t st, int tiles_x = 0, int tiles_y = 0);
 
 // k_project.hip
 struct ProjBuffers {
@@ -172,7 +177,7 @@ struct CompArgs {
 };
 void launch_composite_full(const CompArgs& a, hipStream_t st);
 struct ItemArgs {
-  const VariantState* vs;
+  VariantState* vs;         // the items OR their regions into it
   const Rec* ovr;
   const uint2* items;
   const uint32_t* n_items_total;

@@ -77,7 +77,14 @@ struct VariantState {
   uint64_t clamps;
   uint32_t item_off;    // first work item
   uint32_t _pad;
+  uint64_t pred_regions;   // regions of the dirty tiles (sg_metrics_t::predicted_regions)
+  uint64_t rend_regions;   // regions with a changed pixel
   Touch touch[kMaxTouch];
 };
+
+// Region bit of tile (tx, ty) in the 8 x 8 partition of the frame's tiles.
+__host__ __device__ inline uint64_t region_bit(int tx, int ty, int tiles_x, int tiles_y) {
+  return 1ull << ((ty * 8 / tiles_y) * 8 + (tx * 8 / tiles_x));
+}
 
 }  // namespace sg

@@ -354,6 +354,8 @@ def test_k_views_pooling(ctx):
     assert np.array_equal(P["max_abs"], V["max_abs"].max(axis=0))
     assert np.array_equal(P["nonfinite"], V["nonfinite"].max(axis=0))
     assert np.array_equal(P["clamps"], V["clamps"][0])
+    for key in ("predicted_regions", "rendered_regions"):
+        assert np.array_equal(P[key], np.bitwise_or.reduce(V[key], axis=0)), key
     foot = (V["changed_px"] / V["n_pixels"]).mean(axis=0)
     assert np.array_equal(P["footprint"], foot.astype(np.float32))
     assert np.allclose(P["mse"], sse / (3.0 * V["n_pixels"].sum(axis=0)), rtol=1e-15, atol=0)
@@ -374,6 +376,50 @@ def test_k_views_pooling(ctx):
     with pytest.raises(b.SgError):   # views of different scenes
         other = b.DeviceScene.upload(ctx, sc, "f32")
         ctx.render_batch_views([preps[0], ctx.prepare(other, cams[1])], sa, va, pooled)
+
+
+def _region_mask(changed_tiles, tiles_x, tiles_y):
+    m = 0
+    for ty, tx in zip(*np.nonzero(changed_tiles)):
+        m |= 1 << int((ty * 8 // tiles_y) * 8 + (tx * 8 // tiles_x))
+    return m
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+def test_contamination_regions(ctx, tile):
+    """Sort-first contamination (Sec. 5.10) on the 8 x 8 region grid: the
+    rendered regions are exactly those holding a tile with a pixel changed by
+    more than one level in the variant's image, they lie inside the predicted
+    (dirty-tile) regions, and full-path variants predict every region."""
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(6741, seed=3, sh_degree=3)
+    cam = synth.make_camera(200, 160)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam, b.raster_struct(tile=tile))
+    clean = prep.frame().cpu().numpy().astype(np.float64)
+    sites = synth.make_sites_stratified(sc.n, 3, 24, seed=33, width_bits=32)
+    dose = synth.make_sites_dose(sc.n, 3, 20, seed=34, width_bits=32)
+    allsites = synth.Sites(*(np.concatenate([a, c]) for a, c in zip(
+        (sites.field, sites.comp, sites.prim, sites.bit), (dose.field, dose.comp, dose.prim, dose.bit))))
+    groups = [np.array([k]) for k in range(len(sites))] + [np.arange(len(sites), len(allsites))]
+    imgs, ms = _batch(ctx, prep, allsites, groups)
+    tx_n, ty_n = -(-200 // tile), -(-160 // tile)
+    n_nonempty = 0
+    for j in range(len(groups)):
+        d = np.abs(imgs[j].astype(np.float64) - clean).max(axis=2) > LEVEL
+        pad = np.zeros((ty_n * tile, tx_n * tile), bool)
+        pad[:160, :200] = d
+        changed_tiles = pad.reshape(ty_n, tile, tx_n, tile).any(axis=(1, 3))
+        rend = int(ms["rendered_regions"][j])
+        pred = int(ms["predicted_regions"][j])
+        assert rend == _region_mask(changed_tiles, tx_n, ty_n), j
+        assert rend & ~pred == 0, j
+        n_nonempty += rend != 0
+        if ms["path"][j] == 0:
+            assert bin(pred).count("1") <= int(ms["dirty_tiles"][j])
+        else:
+            assert pred == (1 << 64) - 1
+    assert n_nonempty >= 5 and ms["path"][-1] == 1
 
 
 def test_sg_metrics_matches_definition(ctx):
