@@ -452,7 +452,7 @@ class _no_gc:
         gc.enable()
 
 
-def _batched_rate(ctx, prep, sites, B, streams, threads, steps, warmup, guard=0, box=None):
+def _batched_rate(ctx, prep, sites, B, streams, threads, steps, warmup, guard=0, box=None, box_mask=0x1F, protect=0):
     """Batched incremental injections/s of one campaign call over `steps`
     batches of B (after `warmup` batches), and the per-variant records."""
     import torch
@@ -461,10 +461,10 @@ def _batched_rate(ctx, prep, sites, B, streams, threads, steps, warmup, guard=0,
     total = (warmup + steps) * B
     idx = np.arange(total) % n
     sa = sgb.sites_array(sites.field[idx], sites.comp[idx], sites.prim[idx], sites.bit[idx])
-    va = sgb.variants_array(np.arange(total), np.ones(total, np.uint32), guard)
+    va = sgb.variants_array(np.arange(total), np.ones(total, np.uint32), guard, protect)
     mt = sgb.metrics_tensor(total)
     rb = sgb.METRICS_DTYPE.itemsize
-    kw = dict(box=box, batch=B, streams=streams, threads=threads)
+    kw = dict(box=box, box_mask=box_mask, batch=B, streams=streams, threads=threads)
     ctx.campaign(prep, sa, va[:warmup * B], mt[:warmup * B * rb], **kw)
     torch.cuda.synchronize()
     with _no_gc():
@@ -591,6 +591,23 @@ def run_guard(args):
             "inj_per_s": round(rate, 1), **_summ(recs),
             "contamination_all": _contamination(recs),
             "contamination_scale_sign": _contamination(recs, scale_sign)}
+    # Table 3: the alternative defenses on the same fault grid
+    grid = {}
+    for name, kw in (("none", {}), ("support_guard", {"guard": 1}),
+                     ("selective_guard", {"guard": 1, "box_mask": (1 << 1) | (1 << 3)}),
+                     ("ecc_sign_exp", {"protect": sgb.SG_PROTECT_SIGN_EXP}),
+                     ("vote_3_copies", {"protect": sgb.SG_PROTECT_VOTE})):
+        rate, recs = _batched_rate(ctx, prep, sites, args.batch, args.streams, max(1, args.threads), steps_g,
+                                   args.warmup, box=box, **kw)
+        grid[name] = {"catastrophe_pct": round(100.0 * float(recs["catastrophic"].mean()), 4),
+                      "mean_footprint_pct": round(100.0 * float(recs["footprint"].mean()), 5),
+                      "inj_per_s": round(rate, 1)}
+    grid["memory_factor"] = {"none": 1.0, "support_guard": 1.0, "selective_guard": 1.0,
+                             "ecc_sign_exp": round(1.0 + 9.0 / 32.0, 3), "vote_3_copies": 3.0,
+                             "model": "the code stores one check bit per protected bit (9 of 32); the vote "
+                                      "stores three copies"}
+    out["mitigation_grid"] = grid
+
     # accumulated dose: k simultaneous flips over all stored bits, 16 frames each
     dose = {}
     mt = sgb.metrics_tensor(1)

@@ -118,12 +118,20 @@ typedef struct {
 
 /* One corrupted variant of a prepared scene: sites[site_off .. site_off+n_sites)
  * of the batch's site array are applied together; guard != 0 clamps the
- * variant into the batch's box before it is rendered. */
+ * variant into the batch's box before it is rendered.
+ *
+ * protect emulates the alternative defenses of Table 3 on the same fault
+ * grid: SG_PROTECT_SIGN_EXP, a code over the sign and exponent bits of every
+ * stored word (fp32 bits 23-31, fp16 bits 10-15, bf16 bits 7-15), corrects
+ * the sites on those bits and lets the others through; SG_PROTECT_VOTE,
+ * three copies with a majority vote, corrects every site (each upset hits
+ * one copy). */
+enum { SG_PROTECT_NONE = 0, SG_PROTECT_SIGN_EXP = 1, SG_PROTECT_VOTE = 2 };
 typedef struct {
   uint32_t site_off;
   uint32_t n_sites;
   uint32_t guard;
-  uint32_t _pad;
+  uint32_t protect;
 } sg_variant;
 
 /* Per-variant result (Sec. 3 "Metrics"; Def. 1; Def. 2).  footprint is the

@@ -25,7 +25,8 @@ SG_FIELD_MASK_GUARD = 0x1F
 DTYPES = {"f32": SG_F32, "f16": SG_F16, "bf16": SG_BF16}
 
 SITE_DTYPE = np.dtype([("field", "u1"), ("bit", "u1"), ("comp", "<u2"), ("prim", "<u4")])
-VARIANT_DTYPE = np.dtype([("site_off", "<u4"), ("n_sites", "<u4"), ("guard", "<u4"), ("_pad", "<u4")])
+VARIANT_DTYPE = np.dtype([("site_off", "<u4"), ("n_sites", "<u4"), ("guard", "<u4"), ("protect", "<u4")])
+SG_PROTECT_NONE, SG_PROTECT_SIGN_EXP, SG_PROTECT_VOTE = 0, 1, 2
 METRICS_DTYPE = np.dtype([("sse", "<f8"), ("mse", "<f8"), ("psnr", "<f8"), ("footprint", "<f4"),
                           ("max_abs", "<f4"), ("nonfinite", "<u4"), ("catastrophic", "<u4"),
                           ("changed_px", "<u4"), ("dirty_tiles", "<u4"), ("clamps", "<u8"),
@@ -199,9 +200,9 @@ def sites_array(field, comp, prim, bit) -> np.ndarray:
     return a
 
 
-def variants_array(site_off, n_sites, guard=0) -> np.ndarray:
+def variants_array(site_off, n_sites, guard=0, protect=0) -> np.ndarray:
     a = np.zeros(len(site_off), VARIANT_DTYPE)
-    a["site_off"], a["n_sites"], a["guard"] = site_off, n_sites, guard
+    a["site_off"], a["n_sites"], a["guard"], a["protect"] = site_off, n_sites, guard, protect
     return a
 
 

@@ -150,7 +150,8 @@ __global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, Dev
       uint32_t w = load_word(s, f, p, c);
       for (uint32_t k = 0; k < var.n_sites; ++k) {
         const sg_site x = sites[k];
-        if (x.prim == p && x.field == f && x.comp == c) w ^= 1u << x.bit;
+        if (x.prim == p && x.field == f && x.comp == c && !site_corrected(var.protect, x.bit, s.dtype))
+          w ^= 1u << x.bit;
       }
       if (guard && ((box.mask >> f) & 1u)) {
         uint32_t lo, hi;

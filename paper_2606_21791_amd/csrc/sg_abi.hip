@@ -747,6 +747,7 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
     const sg_variant& x = variants[v];
     if ((uint64_t)x.site_off + x.n_sites > (uint64_t)n_sites) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": sites out of range");
     if (x.guard && !b.mask) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": guard requested without a box");
+    if (x.protect > SG_PROTECT_VOTE) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": unknown protect mode");
     std::vector<uint32_t> prims;
     bool full = mode == SG_FULL;
     for (uint32_t k = 0; k < x.n_sites && !full; ++k) {
@@ -879,8 +880,16 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
         if (s.ncomp[f])
           HIP_TRY(hipMemcpyAsync(const_cast<void*>(w.ptr[f]), s.ptr[f], field_extent(s, f) * wb, hipMemcpyDeviceToDevice, st));
       const sg_variant& x = variants[v];
-      SG_TRY(stage_sites(ctx, sites + x.site_off, (int)x.n_sites, W->sites_dev, st));
-      launch_inject(w, P<sg_site>(W->sites_dev), (int)x.n_sites, nullptr, st);
+      // sites the variant's emulated defense corrects are not applied
+      const int first_protected = s.dtype == SG_F32 ? 23 : (s.dtype == SG_F16 ? 10 : 7);
+      std::vector<sg_site> applied;
+      for (uint32_t k = 0; k < x.n_sites; ++k) {
+        const sg_site& y = sites[x.site_off + k];
+        if (x.protect == SG_PROTECT_VOTE || (x.protect == SG_PROTECT_SIGN_EXP && y.bit >= first_protected)) continue;
+        applied.push_back(y);
+      }
+      SG_TRY(stage_sites(ctx, applied.data(), (int)applied.size(), W->sites_dev, st));
+      launch_inject(w, P<sg_site>(W->sites_dev), (int)applied.size(), nullptr, st);
       DevBox bx = b;
       if (!x.guard) bx.mask = 0;
       SG_TRY(full_render(ctx, W, w, bx, prep->cam, ras, W->r0, W->r1, W->r2, W->depth, W->rect, W->tile_cnt,

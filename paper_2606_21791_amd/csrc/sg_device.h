@@ -331,4 +331,14 @@ __device__ __forceinline__ ProjOut project_prim(Get get, int dtype, const DevCam
   return o;
 }
 
+// Whether a site is corrected by the variant's emulated defense (the
+// protect field of sg_variant): the sign and exponent bits of the storage
+// format, or every bit.
+__device__ __forceinline__ bool site_corrected(uint32_t protect, int bit, int dtype) {
+  if (protect == SG_PROTECT_VOTE) return true;
+  if (protect != SG_PROTECT_SIGN_EXP) return false;
+  const int first = dtype == SG_F32 ? 23 : (dtype == SG_F16 ? 10 : 7);
+  return bit >= first;
+}
+
 }  // namespace sg

@@ -16,7 +16,7 @@ int main() {
   F(sg_camera, height);
   Z(sg_raster); F(sg_raster, tile); F(sg_raster, alpha_max); F(sg_raster, bg);
   Z(sg_box); F(sg_box, mode); F(sg_box, dtype); F(sg_box, lo); F(sg_box, hi);
-  Z(sg_variant); F(sg_variant, site_off); F(sg_variant, n_sites); F(sg_variant, guard);
+  Z(sg_variant); F(sg_variant, site_off); F(sg_variant, n_sites); F(sg_variant, guard); F(sg_variant, protect);
   Z(sg_metrics_t); F(sg_metrics_t, sse); F(sg_metrics_t, mse); F(sg_metrics_t, psnr); F(sg_metrics_t, footprint);
   F(sg_metrics_t, max_abs); F(sg_metrics_t, nonfinite); F(sg_metrics_t, catastrophic); F(sg_metrics_t, changed_px);
   F(sg_metrics_t, dirty_tiles); F(sg_metrics_t, clamps); F(sg_metrics_t, n_pixels); F(sg_metrics_t, path);

@@ -422,6 +422,69 @@ def test_contamination_regions(ctx, tile):
     assert n_nonempty >= 5 and ms["path"][-1] == 1
 
 
+def test_emulated_defenses(ctx):
+    """Table 3's alternatives on one fault grid: the sign+exponent code
+    removes exactly the sites on sign and exponent bits (incremental and
+    full-path variants), the three-copy vote removes every site, and the
+    selective guard (log-scales and opacity only) matches the oracle's guard
+    restricted to those fields."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(4000, seed=14)
+    cam = synth.make_camera(128, 128)
+    lo32, hi32 = synth.make_box_jitter(sc, seed=4)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    box = b.Box.per_prim(ctx, lo32, hi32, "f32")
+    prep = ctx.prepare(ds, cam)
+    single = synth.make_sites_stratified(sc.n, 0, 16, seed=35, width_bits=32, fields=(0, 1, 2, 3, 4))
+    dose = synth.make_sites_dose(sc.n, 0, 12, seed=36, width_bits=32)
+    sites = synth.Sites(*(np.concatenate([a, c]) for a, c in zip(
+        (single.field, single.comp, single.prim, single.bit), (dose.field, dose.comp, dose.prim, dose.bit))))
+    sa = b.sites_array(sites.field, sites.comp, sites.prim, sites.bit)
+    ns, nd = len(single.prim), len(dose.prim)
+
+    def run(offs, cnts, protect=0, guard=0, mask=b.SG_FIELD_MASK_GUARD, sarr=sa):
+        va = b.variants_array(np.asarray(offs), np.asarray(cnts), guard, protect)
+        mt = b.metrics_tensor(len(va))
+        imgs = torch.zeros((len(va), 128, 128, 3), dtype=torch.float32, device="cuda")
+        ctx.render_batch(prep, sarr, va, box=box, box_mask=mask, images=imgs, metrics=mt)
+        torch.cuda.synchronize()
+        return imgs.cpu().numpy(), b.read_metrics(mt)
+
+    offs, cnts = list(range(ns)) + [ns], [1] * ns + [nd]
+    _, plain = run(offs, cnts)
+    _, ecc = run(offs, cnts, protect=b.SG_PROTECT_SIGN_EXP)
+    _, vote = run(offs, cnts, protect=b.SG_PROTECT_VOTE)
+    assert np.all(vote["sse"] == 0) and np.all(vote["changed_px"] == 0) and np.all(vote["nonfinite"] == 0)
+    low = sites.bit < 23
+    for j in range(ns):
+        if low[j]:
+            for key in ("sse", "changed_px", "max_abs", "nonfinite", "dirty_tiles"):
+                assert ecc[key][j] == plain[key][j], (j, key)
+        else:
+            assert ecc["sse"][j] == 0 and ecc["changed_px"][j] == 0 and ecc["nonfinite"][j] == 0, j
+    # the full-path variant under the code equals the variant of its low-bit sites alone
+    keep = np.nonzero(low[ns:])[0] + ns
+    sk = b.sites_array(sites.field[keep], sites.comp[keep], sites.prim[keep], sites.bit[keep])
+    _, low_only = run([0], [len(keep)], sarr=sk)
+    assert ecc["path"][-1] == 1
+    for key in ("sse", "changed_px", "max_abs", "nonfinite"):
+        assert ecc[key][-1] == low_only[key][0], key
+    # selective guard: log-scales (1) and opacity (3) only
+    words = stored(sc, "f32")
+    lo = [None if a is None else formats.f32_words(a) for a in lo32]
+    hi = [None if a is None else formats.f32_words(a) for a in hi32]
+    pick = [j for j in range(ns) if sites.field[j] in (1, 3)][:6] + [j for j in range(ns) if sites.field[j] == 0][:2]
+    imgs, ms = run(pick, [1] * len(pick), guard=1, mask=(1 << 1) | (1 << 3))
+    clean_gpu = prep.frame().cpu().numpy()
+    clean_ref = oracle_render(words, "f32", 0, cam)
+    for k, j in enumerate(pick):
+        w, n_cl = oguard.guard_scene(apply_sites(words, sites, j), lo, hi, "f32", fields=(1, 3))
+        ref = oracle_render(w, "f32", 0, cam)
+        _check_variant(imgs[k], ms[k], ref, clean_ref, clean_gpu)
+        assert int(ms["clamps"][k]) == n_cl
+
+
 def test_sg_metrics_matches_definition(ctx):
     import torch
     from paper_2606_21791_amd import binding as b
