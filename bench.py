@@ -165,6 +165,9 @@ def main():
     ap.add_argument("--free-batch", type=int, default=512,
                     help="also tune B up to this bound and time that configuration (0: skip)")
     ap.add_argument("--plain", type=int, default=100, help="injections timed on the plain path")
+    ap.add_argument("--storm-n", type=int, default=32 * 2_056_645, help="primitives of the fault-storm scene")
+    ap.add_argument("--storm-k", type=int, default=1000, help="upsets written per storm frame")
+    ap.add_argument("--storm-frames", type=int, default=300, help="frames of the fault storm")
     ap.add_argument("--no-formats", dest="formats", action="store_false",
                     help="skip the fp16/bf16 (or fp32) rates at the headline configuration")
     ap.add_argument("--cpu-inj", type=int, default=1, help="oracle injections timed on one host thread (0: skip)")
@@ -172,7 +175,7 @@ def main():
                     help="oracle processes run at once for the all-core baseline (0: the host's cores, at most 16)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="seconds of Poisson arrivals for the serving measurement (0: skip)")
-    ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve", "copy", "views"],
+    ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve", "copy", "views", "storm"],
                     help="w2: the headline; guard: support guard and accumulated dose on the N=134,826 scene; "
                          "large: the 2,056,645-primitive bf16 scene at 1600x900; stress: one guarded render at "
                          "65,812,640 primitives")
@@ -182,7 +185,7 @@ def main():
         sys.exit(2)
     if args.workload != "w2":
         {"guard": run_guard, "large": run_large, "stress": run_stress, "serve": run_serve,
-         "copy": run_copy, "views": run_views}[args.workload](args)
+         "copy": run_copy, "views": run_views, "storm": run_storm}[args.workload](args)
         return
 
     sc, cam, sites = _workload(args.fmt)
@@ -778,6 +781,72 @@ def run_views(args):
            "curve": curve,
            "paper_context": {"view_mpix_per_s": 837, "saturation_views": 16, "hardware": "Blackwell-generation GPU, "
                              "full renders of K views per injection"}}
+    print(json.dumps(out), flush=True)
+
+
+def run_storm(args):
+    """Fault storm on the largest model (Sec. 5.9): k random upsets over every
+    stored bit are written into the resident scene every frame, for F frames;
+    each frame is rendered from the corrupted scene, unguarded, guarded every
+    frame, or scrubbed every M frames (Cor. 2's periodic scrub).  Reports
+    per-frame latency (inject + guard + render) and the PSNR / SSIM of the
+    frames against the clean frame."""
+    import torch
+    from paper_2606_21791_amd import binding as sgb, synth
+    n = args.storm_n
+    t0 = time.perf_counter()
+    sc = synth.make_scene(n, seed=6, sh_degree=0, means="clusters")
+    gen_s = time.perf_counter() - t0
+    cam = synth.make_camera(1600, 900, distance=25.0)
+    ctx = sgb.Context(0)
+    clean_ds = sgb.DeviceScene.upload(ctx, sc, "f32")
+    del sc
+    box = ctx.guard_box(clean_ds)
+    H, W = cam.height, cam.width
+    clean = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    ctx.render(clean_ds, cam, image=clean)
+    img = torch.empty((1, H, W, 3), dtype=torch.float32, device="cuda")
+    mt = sgb.metrics_tensor(1)
+    k, F = args.storm_k, args.storm_frames
+    # the same upsets for every mode
+    storm = [synth.make_sites_dose(n, 0, k, seed=10_000 + f, width_bits=32) for f in range(F)]
+    storm = [sgb.sites_array(x.field, x.comp, x.prim, x.bit) for x in storm]
+    modes = (("unguarded", 0), ("guard_every_frame", 1), ("scrub_every_10", 10), ("scrub_every_100", 100))
+    out = {"metric": "fault storm: per-frame latency and fidelity under k upsets per frame",
+           "config": {"workload": f"N={n:,} Gaussians (64 clusters), SH degree 0, fp32, 1600x900, {k} random "
+                                  f"upsets over all stored bits per frame, {F} frames, global box",
+                      "generate_s": round(gen_s, 1)},
+           "paper_context": {"guarded_ms": 22.9, "unguarded_ms": 20.5, "k": 1000, "frames": 300,
+                             "hardware": "Blackwell-generation GPU"}}
+    sample = set(range(0, F, max(1, F // 10))) | {F - 1}
+    for name, every in modes:
+        work = clean_ds.clone()
+        torch.cuda.synchronize()
+        lat, psnr, ssim, nonfinite, clamps = [], [], [], 0, 0
+        for f in range(F):
+            t0 = time.perf_counter()
+            ctx.inject(work, storm[f])
+            if every and (f + 1) % every == 0:
+                cnt, _ = ctx.guard(work, box)
+            ctx.render(work, cam, image=img[0], clean=clean, metrics=mt)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+            if every and (f + 1) % every == 0:
+                clamps += int(cnt[0])
+            if f in sample:
+                r = sgb.read_metrics(mt)[0]
+                psnr.append(float(r["psnr"]))
+                ssim.append(float(ctx.ssim(img, clean).cpu()[0]))
+                nonfinite += int(r["nonfinite"])
+        lat_ms = np.array(lat) * 1e3
+        out[name] = {"ms_per_frame_mean": round(float(lat_ms.mean()), 3),
+                     "ms_per_frame_p50": round(float(np.median(lat_ms)), 3),
+                     "ms_per_frame_p99": round(float(np.percentile(lat_ms, 99)), 3),
+                     "psnr_db_sampled": [round(x, 2) for x in psnr], "ssim_sampled": [round(x, 5) for x in ssim],
+                     "final_psnr_db": round(psnr[-1], 3), "final_ssim": round(ssim[-1], 5),
+                     "nonfinite_sampled_frames": nonfinite, "clamps": clamps}
+        del work
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

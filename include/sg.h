@@ -374,6 +374,16 @@ enum {
 sg_status sg_ctx_timing(sg_ctx* ctx, int32_t enable);
 sg_status sg_ctx_pass_times(sg_ctx* ctx, double* ms, int64_t* launches);
 
+/* Structural similarity (Sec. 3 "Metrics", after Wang et al. 2004) of B
+ * frames `images` (device, B x H x W x 3 fp32 in [0, 1]) against `clean`
+ * (device, H x W x 3): 11 x 11 Gaussian window of standard deviation 1.5,
+ * C1 = 0.01^2, C2 = 0.03^2, biased local variance and covariance, the index
+ * at every window position wholly inside the frame, averaged over positions
+ * and channels, computed in fp64.  out (device) receives B doubles.  H and W
+ * must be at least 11. */
+sg_status sg_ssim(sg_ctx* ctx, const float* images, const float* clean, int32_t B, int32_t H, int32_t W, double* out,
+                  void* stream);
+
 /* Metrics of B*K frames against K clean frames (Sec. 3; Def. 1; Def. 2):
  * images is [B][K][H][W][3], clean is [K][H][W][3]; MSE and the footprint are
  * pooled over the K views of a variant.  nonfinite is set for a variant with

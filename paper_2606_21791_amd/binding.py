@@ -128,6 +128,7 @@ def _load():
         "sg_campaign_views": (i32, [vp, vp, i32, vp, i32, vp, i32, P(SgBox), u32, P(SgCampaignCfg), vp, vp]),
         "sg_render_batch_views": (i32, [vp, vp, i32, vp, i32, vp, i32, P(SgBox), u32, vp, vp, i32, vp]),
         "sg_metrics": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
+        "sg_ssim": (i32, [vp, vp, vp, i32, i32, i32, vp, vp]),
         "sg_autotune": (i32, [vp, P(SgScene), P(SgCamera), P(SgRaster), vp, i32, i32, i32, C.c_char_p, P(SgTune), vp]),
         "sg_ctx_timing": (i32, [vp, i32]),
         "sg_serve_create": (i32, [i32, P(SgServeConfig), P(vp)]),
@@ -155,7 +156,7 @@ LIB = _load()
 EXPORTED = ("sg_ctx_create", "sg_ctx_destroy", "sg_last_error", "sg_ctx_bytes", "sg_cast", "sg_inject",
             "sg_restore", "sg_guard_box", "sg_guard", "sg_render", "sg_prepare", "sg_prep_destroy",
             "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_render_batch_views", "sg_campaign",
-            "sg_campaign_views", "sg_autotune", "sg_metrics",
+            "sg_campaign_views", "sg_autotune", "sg_metrics", "sg_ssim",
             "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_resume", "sg_ctx_set_graphs",
             "sg_serve_create",
             "sg_serve_add_scene", "sg_serve_add_view", "sg_serve_submit", "sg_serve_poll", "sg_serve_wait",
@@ -352,6 +353,16 @@ class Context:
         self.set_persistent(t["wgs_per_cu"])
         self.set_resume(t["resume"])
         self.set_graphs(bool(t["graphs"]))
+
+    def ssim(self, images, clean, out=None):
+        """SSIM of each frame of `images` (B, H, W, 3) against `clean` (H, W, 3);
+        returns a float64 device tensor of B values."""
+        import torch
+        B, H, W = images.shape[0], images.shape[1], images.shape[2]
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=images.device)
+        check(LIB.sg_ssim(self.h, _ptr(images), _ptr(clean), B, H, W, _ptr(out), _stream()))
+        return out
 
     def metrics(self, images, clean, B, K, H, W, out):
         check(LIB.sg_metrics(self.h, _ptr(images), _ptr(clean), B, K, H, W, _ptr(out), _stream()))

@@ -64,7 +64,7 @@ struct Workspace {
   DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
       big_prims, big_tiles, big_choff, big_goff, big_split, parts, work_scene, sites_dev, box_keys, metrics_tmp;
   // batches of variants
-  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, gmetrics, views_tmp;
+  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, gmetrics, views_tmp, ssim_tmp;
   unsigned long long* h_total = nullptr;   // pinned
   // pinned staging ring for a batch's sites and variants, read by the variant
   // prep kernel in place; slot k may be rewritten once the batch that last
@@ -122,8 +122,13 @@ namespace {
 sg_status dev_alloc(sg_ctx* ctx, DevBuf& b, size_t bytes) {
   if (bytes <= b.bytes) return SG_OK;
   bytes = std::max<size_t>(bytes, 256);
+  // a buffer that has to grow again grows by half as much more, so that
+  // sizes creeping up call after call (instance counts under a fault storm)
+  // reallocate a logarithmic number of times
   {
     std::lock_guard<std::mutex> g(ctx->mu);
+    const size_t grown = b.p ? std::max(bytes, b.bytes + b.bytes / 2) : bytes;
+    if (!ctx->budget || ctx->in_use - b.bytes + grown <= ctx->budget) bytes = grown;
     if (ctx->budget && ctx->in_use - b.bytes + bytes > ctx->budget)
       return fail(SG_E_NOMEM, "device budget exceeded");
     ctx->in_use += bytes - b.bytes;
@@ -173,7 +178,7 @@ void free_workspace(sg_ctx* ctx, Workspace* w) {
                     &w->big_choff, &w->big_goff, &w->big_split,
                     &w->parts, &w->work_scene, &w->sites_dev, &w->box_keys, &w->metrics_tmp, &w->vs, &w->ovr,
                     &w->bitmap, &w->item_off, &w->n_items_v, &w->n_items_total, &w->items, &w->bparts,
-                    &w->counter, &w->gmetrics, &w->views_tmp};
+                    &w->counter, &w->gmetrics, &w->views_tmp, &w->ssim_tmp};
   for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);
   w->graphs.clear();
   for (DevBuf* b : bufs) dev_free(ctx, *b);
@@ -1027,6 +1032,26 @@ sg_status sg_campaign(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t 
                       sg_metrics_t* metrics_out, void* stream) {
   return sg_campaign_views(ctx, &prep, 1, sites, n_sites, variants, n_variants, box, box_field_mask, cfg, metrics_out,
                            stream);
+}
+
+sg_status sg_ssim(sg_ctx* ctx, const float* images, const float* clean, int32_t B, int32_t H, int32_t W, double* out,
+                  void* stream) {
+  if (!ctx || !images || !clean || !out) return fail(SG_E_INVAL, "NULL argument");
+  if (B < 1 || B > 65535 || H < 11 || W < 11)
+    return fail(SG_E_INVAL, "B must be in [1, 65535] and the frame at least 11 x 11");
+  SsimWeights gw;
+  double sum = 0.0;
+  for (int t = 0; t < 11; ++t) {
+    const double r = (double)(t - 5);
+    gw.w[t] = std::exp(-r * r / (2.0 * 1.5 * 1.5));
+    sum += gw.w[t];
+  }
+  for (int t = 0; t < 11; ++t) gw.w[t] /= sum;
+  hipStream_t st = S(stream);
+  WS_OR_FAIL(WS, ctx, st);
+  SG_TRY(dev_alloc(ctx, WS->ssim_tmp, (size_t)B * ssim_blocks(H, W) * sizeof(double)));
+  launch_ssim(images, clean, B, H, W, gw, P<double>(WS->ssim_tmp), out, st);
+  return check_last("sg_ssim");
 }
 
 sg_status sg_metrics(sg_ctx* ctx, const float* images, const float* clean, int32_t B, int32_t K, int32_t H, int32_t W,

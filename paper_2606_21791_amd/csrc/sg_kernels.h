@@ -65,6 +65,14 @@ __device__ __forceinline__ sg_metrics_t make_metrics(const Partial& red, uint32_
   return m;
 }
 
+// k_ssim.hip: the normalised 1-D Gaussian taps of the SSIM window
+struct SsimWeights {
+  double w[11];
+};
+int ssim_blocks(int H, int W);
+void launch_ssim(const float* imgs, const float* clean, int B, int H, int W, const SsimWeights& gw, double* partial,
+                 double* out, hipStream_t st);
+
 // k_basic.hip
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 void launch_cast(const float* src, void* dst, int64_t n, int dtype, int mode, hipStream_t st);

@@ -161,3 +161,39 @@ def test_per_primitive_box_guard(ctx):
         torch.cuda.synchronize()
         assert int(cnt[0]) == n_ref
         assert all(np.array_equal(a, c) for a, c in zip(ds.host_words(), ref))
+
+
+def test_ssim_matches_oracle(ctx):
+    """sg_ssim against the oracle's SSIM on the same float32 frames: random
+    frames with ragged tiles, identical frames, and corrupted renders."""
+    import torch
+    from oracle import ssim as oss
+    from paper_2606_21791_amd import binding as b, synth
+    rng = np.random.default_rng(7)
+    H, W = 37, 45
+    clean = rng.uniform(size=(H, W, 3)).astype(np.float32)
+    imgs = np.stack([clean, np.clip(clean + rng.normal(0, 0.05, size=clean.shape), 0, 1),
+                     rng.uniform(size=clean.shape), np.full(clean.shape, 0.5)]).astype(np.float32)
+    got = ctx.ssim(torch.from_numpy(imgs).cuda(), torch.from_numpy(clean).cuda()).cpu().numpy()
+    ref = np.array([oss.ssim(imgs[k], clean) for k in range(len(imgs))])
+    assert abs(got[0] - 1.0) < 1e-12
+    assert np.allclose(got, ref, rtol=0, atol=1e-10), (got, ref)
+    # corrupted renders of a small scene
+    sc = synth.make_scene(3000, seed=5)
+    cam = synth.make_camera(96, 72)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam)
+    s = synth.make_sites_stratified(sc.n, 0, 4, seed=8, width_bits=32, fields=(0, 1, 3))
+    sa = b.sites_array(s.field, s.comp, s.prim, s.bit)
+    B = len(sa)
+    out = torch.zeros((B, 72, 96, 3), dtype=torch.float32, device="cuda")
+    ctx.render_batch(prep, sa, b.variants_array(np.arange(B), np.ones(B)), images=out, metrics=b.metrics_tensor(B))
+    frame = prep.frame()
+    got = ctx.ssim(out, frame).cpu().numpy()
+    o, f = out.cpu().numpy(), frame.cpu().numpy()
+    ref = np.array([oss.ssim(o[k], f) for k in range(B)])
+    assert np.allclose(got, ref, rtol=0, atol=1e-10)
+    assert got.min() < 1.0
+    with pytest.raises(b.SgError):
+        ctx.ssim(out[:, :10], frame[:10])
+
