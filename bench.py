@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--threads", type=int, default=4,
                     help="host threads of the native campaign call (0: a Python loop of sg_render_batch calls)")
     ap.add_argument("--wgs-per-cu", type=int, default=2, help="persistent compositing workgroups per CU (0: default)")
+    ap.add_argument("--grid", type=int, default=0,
+                    help="total persistent compositing workgroups, overriding --wgs-per-cu (0: per CU)")
     ap.add_argument("--resume", type=int, default=64,
                     help="checkpoint spacing of prepared scenes (0: walk every merged list from its start)")
     ap.add_argument("--graphs", action="store_true", help="replay each batch as a captured graph")
@@ -207,7 +209,9 @@ def main():
         tuned["seconds"] = round(time.perf_counter() - t0, 2)
         args.tile, args.streams, args.threads = tuned["tile"], tuned["streams"], tuned["threads"]
         args.wgs_per_cu, args.resume, args.graphs = tuned["wgs_per_cu"], tuned["resume"], bool(tuned["graphs"])
+        args.grid = tuned["grid"]
     ctx.set_persistent(args.wgs_per_cu)
+    ctx.set_persistent_grid(args.grid)
     ctx.set_resume(args.resume)
     ctx.set_graphs(args.graphs)
     streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
@@ -332,7 +336,8 @@ def main():
         same = all(np.array_equal(rf[k], recs[k]) for k in ("changed_px", "max_abs", "nonfinite")) and \
             bool(np.allclose(rf["sse"], recs["sse"], rtol=1e-12, atol=0.0))
         free = {"value": round(n_inj / dt_f, 1), "unit": "injections/s", "injections": n_inj,
-                "config": {k: tf[k] for k in ("tile", "batch", "streams", "threads", "wgs_per_cu", "resume", "graphs")},
+                "config": {k: tf[k] for k in ("tile", "batch", "streams", "threads", "wgs_per_cu", "grid", "resume",
+                                              "graphs")},
                 "tune_seconds": tf["seconds"], "records_identical_to_headline": same}
         del prep_f, ctx_f
 
@@ -386,6 +391,7 @@ def main():
                                "incremental dirty-tile re-composite",
                    "global_batch": B, "n_sites": n_sites, "instances_clean": prep.instances(),
                    "streams": len(streams), "host_threads": args.threads, "wgs_per_cu": args.wgs_per_cu,
+                   "grid": args.grid,
                    "graphs": args.graphs, "resume_spacing": args.resume,
                    "tuned": tuned is not None, "gpu_max_hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"])},
         "repeat_records_identical": bool(all(np.array_equal(recs[k], recs_timed[k])
@@ -485,6 +491,7 @@ def _tune_into(ctx, args, ds, cam, sites):
     from paper_2606_21791_amd import binding as sgb
     if args.no_tune:
         ctx.set_persistent(args.wgs_per_cu)
+        ctx.set_persistent_grid(args.grid)
         ctx.set_resume(args.resume)
         ctx.set_graphs(args.graphs)
         return None
@@ -493,6 +500,7 @@ def _tune_into(ctx, args, ds, cam, sites):
     t = ctx.autotune(ds, cam, sample, fixed_batch=args.batch)
     args.tile, args.streams, args.threads = t["tile"], t["streams"], t["threads"]
     args.wgs_per_cu, args.resume, args.graphs = t["wgs_per_cu"], t["resume"], bool(t["graphs"])
+    args.grid = t["grid"]
     ctx.apply_tune(t)
     return t
 

@@ -254,6 +254,7 @@ sg_status sg_prep_copy_frame(const sg_prep* prep, float* dst, void* stream);
  * images_out (nullable) receives B*height*width*3 floats; metrics_out
  * (device) receives B entries.  The scene is never modified. */
 enum { SG_INCREMENTAL = 0, SG_FULL = 1 };
+#define SG_MAX_BATCH 2048   /* variants per sg_render_batch call */
 sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites,
                           const sg_variant* variants, int32_t B, const sg_box* box, uint32_t box_field_mask,
                           float* images_out, sg_metrics_t* metrics_out, int32_t mode, void* stream);
@@ -285,7 +286,7 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
  * be NULL (batch 32, 8 streams, 2 threads).  Errors of any batch stop the
  * campaign and are reported with the batch index. */
 typedef struct {
-  int32_t batch;     /* variants per launch; 0 = 32 */
+  int32_t batch;     /* variants per launch; 0 = 32; at most SG_MAX_BATCH */
   int32_t streams;   /* device streams; 0 = 8 (at most 64) */
   int32_t threads;   /* host threads; 0 = 2 (at most streams) */
   int32_t _pad;
@@ -302,12 +303,12 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
 /* Autotuner.  Picks the launch configuration of injection campaigns on one
  * scene and camera by measurement: tile size, variants per launch B,
  * campaign streams and host threads, persistent compositing workgroups per
- * CU, checkpoint spacing and graph replay.  It prepares the scene at each
+ * CU (or a total grid), checkpoint spacing and graph replay.  It prepares the scene at each
  * candidate tile size and spacing, times campaigns of single-site variants
  * over `sites` (host, at least 64; the sample should follow the campaign's
  * site distribution) and moves one parameter at a time to its best value
  * until none improves (two sweeps at most).  fixed_batch > 0 keeps B at that
- * value; otherwise B is tuned up to max_batch (0 = 512).  The rendered
+ * value; otherwise B is tuned up to max_batch (0 = 512; at most SG_MAX_BATCH).  The rendered
  * results never depend on the choice: every configuration is bit-identical.
  *
  * cache_path (nullable) names a text file of one JSON object per line, keyed
@@ -316,13 +317,14 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
  * with from_cache = 1 and touches no device; a miss measures, appends the
  * result and sets from_cache = 0.  The context's settings are restored
  * before returning; the caller applies the result (sg_ctx_set_persistent,
- * sg_ctx_set_resume, sg_ctx_set_graphs before sg_prepare with the tile size,
+ * sg_ctx_set_persistent_grid, sg_ctx_set_resume, sg_ctx_set_graphs before
+ * sg_prepare with the tile size,
  * and batch/streams/threads in sg_campaign). */
 typedef struct {
   int32_t tile, batch, streams, threads, wgs_per_cu, resume, graphs, from_cache;
   double inj_per_s;   /* measured rate of the chosen configuration */
   int32_t trials;     /* configurations measured */
-  int32_t _pad;
+  int32_t grid;       /* total persistent workgroups (0: wgs_per_cu per CU) */
 } sg_tune_t;
 sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_camera* cam, const sg_raster* raster,
                       const sg_site* sites, int32_t n_sites, int32_t fixed_batch, int32_t max_batch,
@@ -332,6 +334,10 @@ sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_camera* cam, 
  * launch (0 = default for the tile size).  Fewer leave room for batches on
  * other streams to run concurrently; this is one of the tuned parameters. */
 sg_status sg_ctx_set_persistent(sg_ctx* ctx, int32_t wgs_per_cu);
+/* Total workgroups of that launch, overriding the per-CU count (0 = use the
+ * per-CU count; at most 65536).  A grid smaller than the device lets more
+ * launches from other streams be resident at once. */
+sg_status sg_ctx_set_persistent_grid(sg_ctx* ctx, int32_t total_wgs);
 
 /* Spacing, in tile-list entries, of the compositing checkpoints that
  * sg_prepare keeps with a prepared scene (default 64; 0 = none).  With a

@@ -63,7 +63,7 @@ class SgCampaignCfg(C.Structure):
 class SgTune(C.Structure):
     _fields_ = [("tile", C.c_int32), ("batch", C.c_int32), ("streams", C.c_int32), ("threads", C.c_int32),
                 ("wgs_per_cu", C.c_int32), ("resume", C.c_int32), ("graphs", C.c_int32), ("from_cache", C.c_int32),
-                ("inj_per_s", C.c_double), ("trials", C.c_int32), ("_pad", C.c_int32)]
+                ("inj_per_s", C.c_double), ("trials", C.c_int32), ("grid", C.c_int32)]
 
 
 class SgServeConfig(C.Structure):
@@ -141,6 +141,7 @@ def _load():
         "sg_serve_last_error": (C.c_char_p, [vp]),
         "sg_serve_destroy": (None, [vp]),
         "sg_ctx_set_persistent": (i32, [vp, i32]),
+        "sg_ctx_set_persistent_grid": (i32, [vp, i32]),
         "sg_ctx_set_resume": (i32, [vp, i32]),
         "sg_ctx_set_graphs": (i32, [vp, i32]),
         "sg_ctx_pass_times": (i32, [vp, vp, vp]),
@@ -157,7 +158,7 @@ EXPORTED = ("sg_ctx_create", "sg_ctx_destroy", "sg_last_error", "sg_ctx_bytes", 
             "sg_restore", "sg_guard_box", "sg_guard", "sg_render", "sg_prepare", "sg_prep_destroy",
             "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_render_batch_views", "sg_campaign",
             "sg_campaign_views", "sg_autotune", "sg_metrics", "sg_ssim",
-            "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_resume", "sg_ctx_set_graphs",
+            "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_persistent_grid", "sg_ctx_set_resume", "sg_ctx_set_graphs",
             "sg_serve_create",
             "sg_serve_add_scene", "sg_serve_add_view", "sg_serve_submit", "sg_serve_poll", "sg_serve_wait",
             "sg_serve_stats", "sg_serve_last_error", "sg_serve_destroy")
@@ -232,6 +233,9 @@ class Context:
 
     def set_persistent(self, wgs_per_cu: int):
         check(LIB.sg_ctx_set_persistent(self.h, int(wgs_per_cu)))
+
+    def set_persistent_grid(self, total_wgs: int):
+        check(LIB.sg_ctx_set_persistent_grid(self.h, int(total_wgs)))
 
     def set_resume(self, spacing: int):
         """Checkpoint spacing of scenes prepared from now on (0 = no resume state)."""
@@ -351,6 +355,7 @@ class Context:
     def apply_tune(self, t: dict):
         """Context settings of a tuned configuration (prepare with tile=t["tile"] afterwards)."""
         self.set_persistent(t["wgs_per_cu"])
+        self.set_persistent_grid(t.get("grid", 0))
         self.set_resume(t["resume"])
         self.set_graphs(bool(t["graphs"]))
 

@@ -37,6 +37,7 @@ struct MergeSpec {
 // of a (variant, tile) item resumed from the clean state
 enum { kFull = 0, kFullWrite = 1, kItem = 2 };
 
+
 template <int TILE, int MODE>
 __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, const MergeSpec* ms, const Rec* ovr,
                                                float* img, Partial* part, float4* s_r0, float4* s_r1,
@@ -270,15 +271,26 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
   __shared__ uint64_t s_tgt[NT];        // removal keys, then insertion keys (sorted)
   __shared__ uint32_t s_cnt[NT], s_fnd[NT], s_bkt[NT];
   __shared__ int s_nr, s_ni, s_skip;
-  const uint32_t total = *I.n_items_total;
+  // the variants' first items (B + 1 offsets; B <= kMaxBatch)
+  __shared__ uint32_t off[kMaxBatch + 1];
+  for (int k = threadIdx.x; k <= I.B; k += BS) off[k] = I.item_off[k];
+  __syncthreads();
+  const uint32_t total = off[I.B];
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(I.counter, 1u);
     __syncthreads();
     const uint32_t item = s_item;
     if (item >= total) break;
-    const uint2 it = I.items[item];
-    const uint32_t v = it.x;
-    const int tile = (int)it.y;
+    uint32_t v = 0;
+    {
+      int lo = 0, hi = I.B;   // largest v with off[v] <= item
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= item) lo = mid; else hi = mid;
+      }
+      v = (uint32_t)lo;
+    }
+    const int tile = (int)I.tiles[(int64_t)v * A.ras.n_tiles + (item - off[v])];
     if (threadIdx.x < NT) { s_cnt[threadIdx.x] = 0; s_fnd[threadIdx.x] = 0; s_bkt[threadIdx.x] = 0; }
     if (threadIdx.x == 0) {
       const VariantState& vs = I.vs[v];
@@ -311,13 +323,11 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
       s_skip = (nr + ni == 0) || (A.stop_key && mn > A.stop_key[tile]);
     }
     __syncthreads();
-    const uint64_t region = region_bit(tile % A.ras.tiles_x, tile / A.ras.tiles_x, A.ras.tiles_x, A.ras.tiles_y);
     if (s_skip) {
       if (threadIdx.x == 0) {
         Partial z;
         z.sse = 0.0; z.evals = 0; z.changed = 0; z.max_abs = 0.f; z.nonfinite = 0; z._pad = 0;
         A.parts[item] = z;
-        atomicOr((unsigned long long*)&I.vs[v].pred_regions, (unsigned long long)region);
       }
       __syncthreads();
       continue;
@@ -383,11 +393,10 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
     }
     __syncthreads();
     float* img = A.image ? A.image + (int64_t)v * I.image_stride : nullptr;
+    const uint64_t region = region_bit(tile % A.ras.tiles_x, tile / A.ras.tiles_x, A.ras.tiles_x, A.ras.tiles_y);
     composite_tile<TILE, kItem>(A, tile, &ms, I.ovr, img, A.parts + item, s_r0, s_r1, s_r2);
-    if (threadIdx.x == 0) {   // thread 0 wrote the item's partial
-      atomicOr((unsigned long long*)&I.vs[v].pred_regions, (unsigned long long)region);
-      if (A.parts[item].changed) atomicOr((unsigned long long*)&I.vs[v].rend_regions, (unsigned long long)region);
-    }
+    if (threadIdx.x == 0 && A.parts[item].changed)   // thread 0 wrote the item's partial
+      atomicOr((unsigned long long*)&I.vs[v].rend_regions, (unsigned long long)region);
     __syncthreads();
   }
 }

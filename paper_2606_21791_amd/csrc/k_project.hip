@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, Dev
   for (int w = lane; w < bb.bm_words; w += 64) bm[w] = 0ull;
   __syncthreads();
   if (lane == 0) {
-    st.n_touch = 0; st.full = 0; st.nonfinite = 0; st.n_dirty = 0; st.clamps = 0; st.item_off = 0; st._pad = 0;
+    st.n_touch = 0; st.full = 0; st.nonfinite = 0; st.n_dirty = 0; st.clamps = 0; st._pad0 = 0; st._pad = 0;
     st.pred_regions = 0; st.rend_regions = 0;
     for (uint32_t k = 0; k < var.n_sites; ++k) {
       const uint32_t p = sites[k].prim;
@@ -202,59 +202,94 @@ __global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, Dev
     }
     __syncthreads();
   }
-  uint32_t nd = 0;
-  for (int w = lane; w < bb.bm_words; w += 64) nd += (uint32_t)__popcll(bm[w]);
-  for (int o = 32; o > 0; o >>= 1) nd += (uint32_t)__shfl_xor((int)nd, o);
+  // The dirty tiles are the variant's predicted regions.  A dirty tile whose
+  // last pixel stopped, in the clean render, before every key the variant
+  // removes or inserts cannot change and gets no work item.  The variant's
+  // items (its remaining dirty tiles in row order) go to its own slice of the
+  // item list.
+  __shared__ unsigned long long s_minkey;
+  if (lane == 0) {
+    unsigned long long mk = ~0ull;
+    for (uint32_t j = 0; j < n_touch; ++j) {
+      const Touch& t = st.touch[j];
+      if (t.flags & 4u) continue;
+      if (t.flags & 1u) mk = min(mk, ((unsigned long long)t.old_depth << 32) | t.prim);
+      if (t.flags & 2u) mk = min(mk, ((unsigned long long)t.new_depth << 32) | t.prim);
+    }
+    s_minkey = mk;
+  }
+  __syncthreads();
+  const unsigned long long minkey = s_minkey;
+  uint32_t* my_tiles = bb.tiles + (int64_t)v * bb.n_tiles;
+  uint32_t nd = 0, ni = 0;
+  unsigned long long pred = 0;
+  for (int base = 0; base < bb.bm_words; base += 64) {
+    const int w = base + lane;
+    const uint64_t word = w < bb.bm_words ? bm[w] : 0ull;
+    uint64_t keep = word, m = word;
+    const int row = w / bb.row_words, col0 = (w % bb.row_words) * 64;
+    while (m) {
+      const int b = __ffsll((long long)m) - 1;
+      m &= m - 1ull;
+      const int tx = col0 + b;
+      pred |= region_bit(tx, row, bb.tiles_x, bb.tiles_y);
+      if (bb.stop_key && minkey > bb.stop_key[row * bb.tiles_x + tx]) keep &= ~(1ull << b);
+    }
+    nd += (uint32_t)__popcll(word);
+    // positions of this word's items: an exclusive scan of the kept counts over the lanes
+    const uint32_t c = (uint32_t)__popcll(keep);
+    uint32_t incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
+      if (lane >= o) incl += y;
+    }
+    uint32_t pos = ni + incl - c;
+    while (keep) {
+      const int b = __ffsll((long long)keep) - 1;
+      keep &= keep - 1ull;
+      my_tiles[pos++] = (uint32_t)(row * bb.tiles_x + col0 + b);
+    }
+    ni += (uint32_t)__shfl((int)incl, 63);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    nd += (uint32_t)__shfl_xor((int)nd, o);
+    pred |= __shfl_xor(pred, o);
+  }
   __syncthreads();
   if (lane == 0) {
     st.n_dirty = nd;
+    st.pred_regions = pred;
     bb.vs[v] = st;
-    bb.n_items_v[v] = nd;
+    bb.n_items_v[v] = ni;
   }
-}
-
-// One block: scan the popcounts of all dirty-tile bitmap words of the batch
-// (variant-major, rows in order), so each set bit's item index is its rank;
-// write the (variant, tile) items, each variant's first item, the total, and
-// zero the compositing work counter.
-__global__ void __launch_bounds__(1024) k_plan(BatchBuffers bb) {
-  __shared__ uint32_t s[1024];
-  const int64_t n_words = (int64_t)bb.B * bb.bm_words;
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < n_words; base += 1024) {
-    const int64_t w = base + threadIdx.x;
-    const uint64_t word = w < n_words ? bb.bitmap[w] : 0ull;
-    const uint32_t c = (uint32_t)__popcll(word);
-    s[threadIdx.x] = c;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const uint32_t y = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
-      __syncthreads();
-      s[threadIdx.x] += y;
-      __syncthreads();
-    }
-    if (w < n_words) {
-      uint32_t pos = carry + s[threadIdx.x] - c;
-      const int v = (int)(w / bb.bm_words);
-      const int wl = (int)(w % bb.bm_words);
-      if (wl == 0) {
-        bb.item_off[v] = pos;
-        bb.vs[v].item_off = pos;
+  // The workgroup that finishes last turns the per-variant item counts into
+  // offsets (a scan over B counts) and arms the compositing work counter.
+  // Every lane releases its stores before the arrival is counted; the last
+  // workgroup acquires them before reading.
+  __shared__ uint32_t s_last;
+  __threadfence();
+  __syncthreads();
+  if (lane == 0) s_last = atomicAdd(bb.arrive, 1u) == gridDim.x - 1 ? 1u : 0u;
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    uint32_t carry = 0;
+    for (int base = 0; base < bb.B; base += 64) {
+      const int u = base + lane;
+      const uint32_t c = u < bb.B ? bb.n_items_v[u] : 0u;
+      uint32_t incl = c;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
+        if (lane >= o) incl += y;
       }
-      uint64_t m = word;
-      const int row = wl / bb.row_words, col0 = (wl % bb.row_words) * 64;
-      while (m) {
-        const int b = __ffsll((long long)m) - 1;
-        m &= m - 1ull;
-        bb.items[pos++] = make_uint2((uint32_t)v, (uint32_t)(row * bb.tiles_x + col0 + b));
-      }
+      if (u < bb.B) bb.item_off[u] = carry + incl - c;
+      carry += (uint32_t)__shfl((int)incl, 63);
     }
-    carry += s[1023];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    *bb.n_items_total = carry;
-    *bb.counter = 0u;
+    if (lane == 0) {
+      bb.item_off[bb.B] = carry;
+      *bb.counter = 0u;
+      *bb.arrive = 0u;   // ready for the next batch on this workspace
+    }
   }
 }
 
@@ -287,8 +322,6 @@ void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam
     default: k_variant_prep<3><<<bb.B, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, bb); break;
   }
 }
-
-void launch_plan(const BatchBuffers& bb, hipStream_t st) { k_plan<<<1, 1024, 0, st>>>(bb); }
 
 
 }  // namespace sg

@@ -64,7 +64,7 @@ struct Workspace {
   DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
       big_prims, big_tiles, big_choff, big_goff, big_split, parts, work_scene, sites_dev, box_keys, metrics_tmp;
   // batches of variants
-  DevBuf vs, ovr, bitmap, item_off, n_items_v, n_items_total, items, bparts, counter, gmetrics, views_tmp, ssim_tmp;
+  DevBuf vs, ovr, bitmap, item_off, n_items_v, tiles, bparts, counter, arrive, gmetrics, views_tmp, ssim_tmp;
   unsigned long long* h_total = nullptr;   // pinned
   // pinned staging ring for a batch's sites and variants, read by the variant
   // prep kernel in place; slot k may be rewritten once the batch that last
@@ -91,6 +91,7 @@ struct sg_ctx {
   size_t in_use = 0;
   int n_cu = 256;
   int persistent_wgs_per_cu = 0;           // 0: default of the tile size
+  int persistent_grid = 0;                 // total workgroups (0: per-CU count)
   int resume_spacing = 64;                 // checkpoint spacing of prepared scenes (0: none)
   bool use_graphs = true;
   std::vector<Workspace*> ws;
@@ -177,8 +178,8 @@ void free_workspace(sg_ctx* ctx, Workspace* w) {
                     &w->tile_start, &w->cursor, &w->total, &w->keys, &w->keys_tmp, &w->big_prims, &w->big_tiles,
                     &w->big_choff, &w->big_goff, &w->big_split,
                     &w->parts, &w->work_scene, &w->sites_dev, &w->box_keys, &w->metrics_tmp, &w->vs, &w->ovr,
-                    &w->bitmap, &w->item_off, &w->n_items_v, &w->n_items_total, &w->items, &w->bparts,
-                    &w->counter, &w->gmetrics, &w->views_tmp, &w->ssim_tmp};
+                    &w->bitmap, &w->item_off, &w->n_items_v, &w->tiles, &w->bparts,
+                    &w->counter, &w->arrive, &w->gmetrics, &w->views_tmp, &w->ssim_tmp};
   for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);
   w->graphs.clear();
   for (DevBuf* b : bufs) dev_free(ctx, *b);
@@ -527,13 +528,14 @@ size_t sg_ctx_bytes(const sg_ctx* c) { return c ? c->in_use : 0; }
 }  // extern "C"
 
 SgSettings sg_settings_get(const sg_ctx* c) {
-  return {c->device, c->persistent_wgs_per_cu, c->resume_spacing, c->use_graphs ? 1 : 0};
+  return {c->device, c->persistent_wgs_per_cu, c->resume_spacing, c->use_graphs ? 1 : 0, c->persistent_grid};
 }
 
 sg_status sg_fail(sg_status code, const char* msg) { return fail(code, msg); }
 
 void sg_settings_set(sg_ctx* c, const SgSettings& s) {
   c->persistent_wgs_per_cu = s.wgs_per_cu;
+  c->persistent_grid = s.grid;
   c->resume_spacing = s.resume_spacing;
   c->use_graphs = s.graphs != 0;
 }
@@ -544,6 +546,12 @@ sg_status sg_ctx_set_resume(sg_ctx* c, int32_t spacing) {
   if (!c) return fail(SG_E_INVAL, "ctx is NULL");
   if (spacing != 0 && (spacing < 16 || spacing > 65536)) return fail(SG_E_INVAL, "resume spacing must be 0 or in [16, 65536]");
   c->resume_spacing = spacing;
+  return SG_OK;
+}
+
+sg_status sg_ctx_set_persistent_grid(sg_ctx* c, int32_t total_wgs) {
+  if (!c || total_wgs < 0 || total_wgs > 65536) return fail(SG_E_INVAL, "total_wgs must be 0..65536");
+  c->persistent_grid = total_wgs;
   return SG_OK;
 }
 
@@ -742,6 +750,7 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
   if (!ctx || !prep || !metrics_out) return fail(SG_E_INVAL, "ctx/prep/metrics_out is NULL");
   if (prep->ctx != ctx && prep->ctx->device != ctx->device) return fail(SG_E_INVAL, "prep is on another device");
   if (B < 0 || (B > 0 && !variants)) return fail(SG_E_INVAL, "bad variants");
+  if (B > kMaxBatch) return fail(SG_E_INVAL, "at most 2048 variants per launch (sg_campaign splits larger sets)");
   if (mode != SG_INCREMENTAL && mode != SG_FULL) return fail(SG_E_INVAL, "bad mode");
   const DevScene& s = prep->scene;
   SG_TRY(validate_sites(s, sites, n_sites));
@@ -776,11 +785,14 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
     SG_TRY(dev_alloc(ctx, W->vs, (size_t)B * sizeof(VariantState)));
     SG_TRY(dev_alloc(ctx, W->ovr, (size_t)B * kMaxTouch * sizeof(Rec)));
     SG_TRY(dev_alloc(ctx, W->bitmap, (size_t)B * prep->bm_words * sizeof(uint64_t)));
-    SG_TRY(dev_alloc(ctx, W->item_off, (size_t)B * sizeof(uint32_t)));
+    SG_TRY(dev_alloc(ctx, W->item_off, (size_t)(B + 1) * sizeof(uint32_t)));
     SG_TRY(dev_alloc(ctx, W->n_items_v, (size_t)B * sizeof(uint32_t)));
-    SG_TRY(dev_alloc(ctx, W->n_items_total, 16));
     SG_TRY(dev_alloc(ctx, W->counter, 16));
-    SG_TRY(dev_alloc(ctx, W->items, (size_t)B * ras.n_tiles * sizeof(uint2)));
+    SG_TRY(dev_alloc(ctx, W->tiles, (size_t)B * ras.n_tiles * sizeof(uint32_t)));
+    if (!W->arrive.p) {
+      SG_TRY(dev_alloc(ctx, W->arrive, 16));
+      launch_fill_u32(P<uint32_t>(W->arrive), 0u, 4, st);   // the variant prep returns it to zero
+    }
     SG_TRY(dev_alloc(ctx, W->bparts, (size_t)B * ras.n_tiles * sizeof(Partial)));
     SG_TRY(dev_alloc(ctx, W->gmetrics, (size_t)B * sizeof(sg_metrics_t)));
     int slot = 0;
@@ -798,13 +810,13 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
                                  hipMemcpyDeviceToDevice, st));
       BatchBuffers bb{W->d_sites[slot], W->d_vars[slot], B, P<VariantState>(W->vs), P<Rec>(W->ovr),
                       P<uint64_t>(W->bitmap), prep->bm_words, prep->row_words, P<uint32_t>(W->item_off),
-                      P<uint32_t>(W->n_items_v), P<uint32_t>(W->n_items_total), P<uint2>(W->items),
-                      P<uint32_t>(W->counter), ras.tiles_x};
+                      P<uint32_t>(W->n_items_v), P<uint32_t>(W->tiles), P<uint32_t>(W->counter),
+                      P<uint32_t>(W->arrive), ras.tiles_x, ras.tiles_y, ras.n_tiles,
+                      prep->ck_group ? P<uint64_t>(prep->stop_key) : nullptr};
       {
         PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
         launch_variant_prep(s, b, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
                             P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
-        launch_plan(bb, st);
       }
       CompArgs ca{P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2), P<uint32_t>(prep->tile_start),
                   P<uint32_t>(prep->tile_cnt), P<uint64_t>(prep->keys), P<float>(prep->frame), images_out,
@@ -816,8 +828,9 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
         ca.stop_key = P<uint64_t>(prep->stop_key);
         ca.ck_group = prep->ck_group;
       }
-      ItemArgs it{P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint2>(W->items), P<uint32_t>(W->n_items_total),
-                  P<uint32_t>(W->counter), frame_floats, ctx->n_cu * per_cu};
+      ItemArgs it{P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint32_t>(W->tiles), P<uint32_t>(W->item_off),
+                  P<uint32_t>(W->counter), frame_floats,
+                  ctx->persistent_grid > 0 ? ctx->persistent_grid : ctx->n_cu * per_cu, B};
       {
         PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st);
         launch_composite_items(ca, it, st);
@@ -832,11 +845,12 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
     };
     if (graph) {
       std::vector<uintptr_t> key = {(uintptr_t)prep, (uintptr_t)B, site_cap, (uintptr_t)slot, (uintptr_t)per_cu,
+                                    (uintptr_t)ctx->persistent_grid,
                                     (uintptr_t)b.mask, (uintptr_t)b.mode, (uintptr_t)W->vs.p, (uintptr_t)W->ovr.p,
-                                    (uintptr_t)W->bitmap.p, (uintptr_t)W->items.p, (uintptr_t)W->bparts.p,
+                                    (uintptr_t)W->bitmap.p, (uintptr_t)W->tiles.p, (uintptr_t)W->bparts.p,
                                     (uintptr_t)W->h_sites[slot], (uintptr_t)W->h_vars[slot], (uintptr_t)W->gmetrics.p,
                                     (uintptr_t)W->counter.p, (uintptr_t)W->item_off.p, (uintptr_t)W->n_items_v.p,
-                                    (uintptr_t)W->n_items_total.p};
+                                    (uintptr_t)W->arrive.p};
       for (int f = 0; f < 6; ++f) { key.push_back((uintptr_t)b.lo[f]); key.push_back((uintptr_t)b.hi[f]); }
       hipGraphExec_t exec = nullptr;
       for (auto& g : W->graphs)
@@ -948,7 +962,7 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
   const int B = cfg && cfg->batch > 0 ? cfg->batch : 32;
   const int NS = cfg && cfg->streams > 0 ? cfg->streams : 8;
   const int NT = std::min(cfg && cfg->threads > 0 ? cfg->threads : 2, NS);
-  if (B > 65536 || NS > 64 || NT > 64) return fail(SG_E_INVAL, "campaign batch/streams/threads out of range");
+  if (B > kMaxBatch || NS > 64 || NT > 64) return fail(SG_E_INVAL, "campaign batch/streams/threads out of range");
   SG_TRY(validate_sites(prep->scene, sites, n_sites));
   for (int v = 0; v < n_variants; ++v)
     if ((uint64_t)variants[v].site_off + variants[v].n_sites > (uint64_t)n_sites)

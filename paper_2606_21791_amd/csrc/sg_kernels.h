@@ -115,17 +115,17 @@ struct BatchBuffers {
   uint64_t* bitmap;         // B * bm_words dirty-tile bitmaps
   int bm_words;             // words per variant bitmap
   int row_words;            // words per tile row
-  uint32_t* item_off;       // B
-  uint32_t* n_items_v;      // B (dirty tiles per variant)
-  uint32_t* n_items_total;  // 1
-  uint2* items;             // capacity B * n_tiles
-  uint32_t* counter;        // compositing work counter, zeroed by the plan
-  int tiles_x;
+  uint32_t* item_off;       // B + 1: first item of each variant, then the total
+  uint32_t* n_items_v;      // B: work items (dirty tiles that can change) per variant
+  uint32_t* tiles;          // B x n_tiles: variant v's item tiles at [v * n_tiles, ...)
+  uint32_t* counter;        // compositing work counter, armed by the last prep workgroup
+  uint32_t* arrive;         // prep workgroups that have finished (zero between batches)
+  int tiles_x, tiles_y, n_tiles;
+  const uint64_t* stop_key; // per tile of the prepared view (nullable): see CompArgs
 };
 void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                          const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
                          const uint2* rect, const BatchBuffers& bb, hipStream_t st);
-void launch_plan(const BatchBuffers& bb, hipStream_t st);
 
 // k_bin.hip
 struct BinBuffers {
@@ -187,11 +187,12 @@ void launch_composite_full(const CompArgs& a, hipStream_t st);
 struct ItemArgs {
   VariantState* vs;         // the items OR their regions into it
   const Rec* ovr;
-  const uint2* items;
-  const uint32_t* n_items_total;
+  const uint32_t* tiles;    // see BatchBuffers
+  const uint32_t* item_off; // B + 1
   uint32_t* counter;
   int64_t image_stride;   // floats per variant image (when a.image != null)
   int grid;
+  int B;
 };
 void launch_composite_items(const CompArgs& a, const ItemArgs& it, hipStream_t st);
 

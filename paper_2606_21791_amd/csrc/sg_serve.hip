@@ -212,7 +212,8 @@ extern "C" {
 sg_status sg_serve_create(int32_t device, const sg_serve_config* cfg, sg_server** out) {
   if (!cfg || !out) return SG_E_INVAL;
   *out = nullptr;
-  if (cfg->max_slots < 0 || cfg->max_batch < 0 || cfg->queue_depth < 0) return SG_E_INVAL;
+  if (cfg->max_slots < 0 || cfg->max_batch < 0 || cfg->max_batch > SG_MAX_BATCH || cfg->queue_depth < 0)
+    return SG_E_INVAL;
   sg_server* S = new sg_server();
   S->cfg = *cfg;
   if (S->cfg.max_batch == 0) S->cfg.max_batch = 64;

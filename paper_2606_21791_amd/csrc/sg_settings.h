@@ -9,6 +9,7 @@ struct SgSettings {
   int wgs_per_cu;
   int resume_spacing;
   int graphs;
+  int grid;
 };
 SgSettings sg_settings_get(const sg_ctx* ctx);
 void sg_settings_set(sg_ctx* ctx, const SgSettings& s);

@@ -41,6 +41,7 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
   if (fixed_batch < 0 || max_batch < 0 || fixed_batch > 65536 || max_batch > 65536)
     return sg_fail(SG_E_INVAL, "fixed_batch/max_batch out of range");
   if (max_batch == 0) max_batch = 512;
+  if (fixed_batch > 2048 || max_batch > 2048) return sg_fail(SG_E_INVAL, "B is at most 2048 per launch");
   std::memset(out, 0, sizeof(*out));
   const SgSettings saved = sg_settings_get(ctx);
   const std::string key = sgtune::make_key(device_arch(saved.device), scene->n, cam->width, cam->height,
@@ -49,7 +50,7 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
   double best_rate = 0.0;
   if (cache_path && sgtune::lookup(cache_path, key, &best, &best_rate)) {
     *out = {best.tile, best.batch, best.streams, best.threads, best.wgs, best.resume, best.graphs, 1,
-            best_rate, 0, 0};
+            best_rate, 0, best.grid};
     return SG_OK;
   }
   sg_raster base = raster ? *raster : sg_raster{16, 0.99f, 1.0f / 255.0f, 1e-4f, 9.0f, 0.3f, {1.f, 1.f, 1.f}};
@@ -84,30 +85,34 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
     if (!p) return -1.0;
     SgSettings s = saved;
     s.wgs_per_cu = c.wgs;
+    s.grid = c.grid;
     s.resume_spacing = c.resume;
     s.graphs = c.graphs;
     sg_settings_set(ctx, s);
     sg_campaign_cfg cc{c.batch, c.streams, c.threads, 0};
     const int nv = std::max(c.batch, (n_sites / c.batch) * c.batch);
     const int use = std::min(nv, n_sites);
-    double best_dt = 1e30;
-    for (int rep = 0; rep < 3; ++rep) {   // the first repetition also warms graphs and workspaces
+    // one untimed campaign warms graphs and workspaces; then campaigns are
+    // timed until at least 40 ms (and two campaigns) have elapsed
+    double total = 0.0;
+    int64_t done = 0;
+    for (int rep = 0; rep < 200 && (rep < 3 || total < 0.04); ++rep) {
       if (hipStreamSynchronize(st) != hipSuccess) { rc = sg_fail(SG_E_DEVICE, "stream synchronize failed"); return -1.0; }
       const auto t0 = std::chrono::steady_clock::now();
       rc = sg_campaign(ctx, p, sites, n_sites, vars.data(), use, nullptr, 0, &cc, met, stream);
       if (rc != SG_OK) return -1.0;
       if (hipStreamSynchronize(st) != hipSuccess) { rc = sg_fail(SG_E_DEVICE, "stream synchronize failed"); return -1.0; }
       const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      if (rep > 0) best_dt = std::min(best_dt, dt);
+      if (rep > 0) { total += dt; done += use; }
     }
     ++trials;
-    return use / best_dt;
+    return (double)done / total;
   };
 
   Cfg cur;
   cur.batch = fixed_batch > 0 ? fixed_batch : std::min(32, max_batch);
   double cur_rate = measure(cur);
-  const std::vector<int> tiles = {8, 16, 32}, resumes = {32, 64, 128, 256}, wgss = {1, 2, 4, 8},
+  const std::vector<int> tiles = {8, 16, 32}, resumes = {32, 64, 128, 256}, wgss = {1, 2, 4, 8}, grids = {0, 64, 128},
                          streams = {4, 8, 16, 32}, threads = {1, 2, 4}, graphs = {0, 1};
   std::vector<int> batches;
   if (fixed_batch > 0) batches = {fixed_batch};
@@ -134,6 +139,7 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
     try_axis(&Cfg::tile, tiles);
     try_axis(&Cfg::resume, resumes);
     try_axis(&Cfg::wgs, wgss);
+    try_axis(&Cfg::grid, grids);
     try_axis(&Cfg::streams, streams);
     try_axis(&Cfg::threads, threads);
     try_axis(&Cfg::graphs, graphs);
@@ -144,6 +150,6 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
   sg_settings_set(ctx, saved);
   if (rc != SG_OK) return rc;
   if (cache_path) (void)sgtune::append(cache_path, key, cur, cur_rate);
-  *out = {cur.tile, cur.batch, cur.streams, cur.threads, cur.wgs, cur.resume, cur.graphs, 0, cur_rate, trials, 0};
+  *out = {cur.tile, cur.batch, cur.streams, cur.threads, cur.wgs, cur.resume, cur.graphs, 0, cur_rate, trials, cur.grid};
   return SG_OK;
 }

@@ -68,6 +68,7 @@ struct Touch {
 };
 
 constexpr int kMaxTouch = 8;
+constexpr int kMaxBatch = 2048;   // variants per sg_render_batch launch
 
 struct VariantState {
   uint32_t n_touch;
@@ -75,7 +76,7 @@ struct VariantState {
   uint32_t nonfinite;   // a corrupted stored component is Inf/NaN after the guard
   uint32_t n_dirty;     // dirty tiles
   uint64_t clamps;
-  uint32_t item_off;    // first work item
+  uint32_t _pad0;
   uint32_t _pad;
   uint64_t pred_regions;   // regions of the dirty tiles (sg_metrics_t::predicted_regions)
   uint64_t rend_regions;   // regions with a changed pixel

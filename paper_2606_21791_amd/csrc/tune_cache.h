@@ -2,7 +2,8 @@
 // API so that it can be unit-tested on the host.  One object per line:
 //   {"key": "<arch>|n<ceil log2 N>|<W>x<H>|<format>|sh<degree>|fb<fixed B>|mb<max B>",
 //    "tile": .., "batch": .., "streams": .., "threads": .., "wgs_per_cu": ..,
-//    "resume": .., "graphs": .., "inj_per_s": ..}
+//    "resume": .., "graphs": .., "grid": .., "inj_per_s": ..}
+// ("grid" may be absent in older lines: 0).
 // Later lines for the same key override earlier ones.
 #pragma once
 
@@ -14,7 +15,7 @@
 namespace sgtune {
 
 struct Cfg {
-  int tile = 16, batch = 32, streams = 16, threads = 2, wgs = 2, resume = 64, graphs = 0;
+  int tile = 16, batch = 32, streams = 16, threads = 2, wgs = 2, resume = 64, graphs = 0, grid = 0;
 };
 
 inline const char* dtype_name(int d) { return d == 0 ? "f32" : d == 1 ? "f16" : "bf16"; }
@@ -50,6 +51,7 @@ inline bool lookup(const char* path, const std::string& key, Cfg* c, double* rat
         !json_int(line, "wgs_per_cu", &x.wgs) || !json_int(line, "resume", &x.resume) ||
         !json_int(line, "graphs", &x.graphs))
       continue;
+    if (!json_int(line, "grid", &x.grid)) x.grid = 0;
     const size_t p = line.find("\"inj_per_s\": ");
     double r = 0.0;
     if (p != std::string::npos) std::sscanf(line.c_str() + p + 13, "%lf", &r);
@@ -66,7 +68,8 @@ inline bool append(const char* path, const std::string& key, const Cfg& c, doubl
   f.precision(12);
   f << "{\"key\": \"" << key << "\", \"tile\": " << c.tile << ", \"batch\": " << c.batch
     << ", \"streams\": " << c.streams << ", \"threads\": " << c.threads << ", \"wgs_per_cu\": " << c.wgs
-    << ", \"resume\": " << c.resume << ", \"graphs\": " << c.graphs << ", \"inj_per_s\": " << rate << "}\n";
+    << ", \"resume\": " << c.resume << ", \"graphs\": " << c.graphs << ", \"grid\": " << c.grid
+    << ", \"inj_per_s\": " << rate << "}\n";
   return (bool)f;
 }
 

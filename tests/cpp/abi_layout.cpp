@@ -22,7 +22,7 @@ int main() {
   F(sg_metrics_t, dirty_tiles); F(sg_metrics_t, clamps); F(sg_metrics_t, n_pixels); F(sg_metrics_t, path);
   F(sg_metrics_t, evals); F(sg_metrics_t, predicted_regions); F(sg_metrics_t, rendered_regions);
   Z(sg_campaign_cfg); F(sg_campaign_cfg, batch); F(sg_campaign_cfg, streams); F(sg_campaign_cfg, threads);
-  Z(sg_tune_t); F(sg_tune_t, tile); F(sg_tune_t, from_cache); F(sg_tune_t, inj_per_s); F(sg_tune_t, trials);
+  Z(sg_tune_t); F(sg_tune_t, tile); F(sg_tune_t, from_cache); F(sg_tune_t, inj_per_s); F(sg_tune_t, trials); F(sg_tune_t, grid);
   Z(sg_serve_config); F(sg_serve_config, hbm_budget_bytes); F(sg_serve_config, max_slots);
   F(sg_serve_config, plain);
   Z(sg_request); F(sg_request, kind); F(sg_request, sites); F(sg_request, n_sites); F(sg_request, arrival_ns);

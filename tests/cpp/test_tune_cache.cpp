@@ -25,14 +25,14 @@ int main(int argc, char** argv) {
   double r = 0.0;
   CHECK(!sgtune::lookup(path, "k1", &c, &r));            // no file yet
   sgtune::Cfg a;
-  a.tile = 8; a.batch = 128; a.streams = 32; a.threads = 4; a.wgs = 1; a.resume = 128; a.graphs = 1;
+  a.tile = 8; a.batch = 128; a.streams = 32; a.threads = 4; a.wgs = 1; a.resume = 128; a.graphs = 1; a.grid = 64;
   CHECK(sgtune::append(path, "k1", a, 1234567.5));
   sgtune::Cfg b;
   b.tile = 32;
   CHECK(sgtune::append(path, "k2", b, 10.0));
   CHECK(sgtune::lookup(path, "k1", &c, &r));
   CHECK(c.tile == 8 && c.batch == 128 && c.streams == 32 && c.threads == 4 && c.wgs == 1 && c.resume == 128 &&
-        c.graphs == 1 && r > 1234567.0 && r < 1234568.0);
+        c.graphs == 1 && c.grid == 64 && r > 1234567.0 && r < 1234568.0);
   CHECK(sgtune::lookup(path, "k2", &c, &r) && c.tile == 32 && c.batch == 32 && r == 10.0);
   CHECK(!sgtune::lookup(path, "k", &c, &r));             // keys match whole, not by prefix
   a.batch = 256;
@@ -40,8 +40,12 @@ int main(int argc, char** argv) {
   CHECK(sgtune::lookup(path, "k1", &c, &r) && c.batch == 256 && r == 5.0);
   std::FILE* f = std::fopen(path, "a");                  // a damaged line is skipped
   std::fputs("{\"key\": \"k2\", \"tile\": 8}\n", f);
+  // a line without "grid" reads as grid 0
+  std::fputs("{\"key\": \"k3\", \"tile\": 16, \"batch\": 64, \"streams\": 8, \"threads\": 2, "
+             "\"wgs_per_cu\": 2, \"resume\": 64, \"graphs\": 0, \"inj_per_s\": 7}\n", f);
   std::fclose(f);
   CHECK(sgtune::lookup(path, "k2", &c, &r) && c.tile == 32);
+  CHECK(sgtune::lookup(path, "k3", &c, &r) && c.batch == 64 && c.grid == 0 && r == 7.0);
   std::printf("tune cache ok\n");
   return 0;
 }

@@ -152,8 +152,11 @@ def test_resume_spacing_invariance(ctx, tile):
     for g in (16, 64, 4096):
         img, m = out[g]
         assert np.array_equal(img, img0), g
-        for key in ("sse", "changed_px", "max_abs", "nonfinite", "dirty_tiles"):
+        for key in ("changed_px", "max_abs", "nonfinite", "dirty_tiles"):
             assert np.array_equal(m[key], m0[key]), (g, key)
+        # the same per-tile terms; tiles that cannot change get no item here,
+        # so the double sums group them differently
+        assert np.allclose(m["sse"], m0["sse"], rtol=1e-12, atol=0.0), g
         assert m["evals"].sum() < m0["evals"].sum(), g
     full, mf = _batch(ctx, prep, sites, groups, mode=1)
     assert np.array_equal(out[64][0], full)
