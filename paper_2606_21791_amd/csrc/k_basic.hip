@@ -110,6 +110,68 @@ __global__ void __launch_bounds__(256) k_guard(DevScene s, DevBox b, int f, unsi
   if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, (unsigned long long)local);
 }
 
+// Guard of whole component rows against a global box, for rows whose
+// primitives are contiguous: 16-byte loads of 4 fp32 or 8 16-bit words, the
+// clamp decision per word as in guard_one, a vector written back only when
+// one of its words changed.  Block y serves row y of the plan; the few words
+// before the row's first 16-byte boundary and after its last are done one by
+// one by block x = 0.
+template <int ES>
+__global__ void __launch_bounds__(256) k_guard_rows(DevScene s, DevBox b, GuardRows gr,
+                                                    unsigned long long* __restrict__ count) {
+  constexpr int PER = 16 / ES;   // words per vector
+  const int f = gr.f[blockIdx.y], c = gr.c[blockIdx.y];
+  uint32_t lo, hi;
+  box_words(b, f, 0, c, s.n, &lo, &hi);
+  char* row = const_cast<char*>(reinterpret_cast<const char*>(s.ptr[f])) + (int64_t)c * s.cs[f] * ES;
+  const int64_t n = s.n;
+  const int64_t head = (int64_t)(((16 - ((uintptr_t)row & 15)) & 15) / ES);   // words before alignment
+  const int64_t h = head < n ? head : n;
+  const int64_t nvec = (n - h) / PER;
+  const int64_t tail0 = h + nvec * PER;
+  uint32_t local = 0;
+  auto one = [&](int64_t i) {
+    uint32_t w = ES == 4 ? reinterpret_cast<uint32_t*>(row)[i] : reinterpret_cast<uint16_t*>(row)[i];
+    bool cl;
+    const uint32_t g = clamp_word(w, lo, hi, s.dtype, &cl);
+    if (cl) {
+      if (ES == 4) reinterpret_cast<uint32_t*>(row)[i] = g;
+      else reinterpret_cast<uint16_t*>(row)[i] = (uint16_t)g;
+      ++local;
+    }
+  };
+  if (blockIdx.x == 0) {
+    for (int64_t i = threadIdx.x; i < h; i += blockDim.x) one(i);
+    for (int64_t i = tail0 + threadIdx.x; i < n; i += blockDim.x) one(i);
+  }
+  uint4* vec = reinterpret_cast<uint4*>(row + h * ES);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nvec; j += stride) {
+    const uint4 v = vec[j];
+    uint32_t words[4] = {v.x, v.y, v.z, v.w};
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (ES == 4) {
+        bool cl;
+        words[q] = clamp_word(words[q], lo, hi, s.dtype, &cl);
+        any |= cl;
+        local += cl ? 1u : 0u;
+      } else {
+        bool c0, c1;
+        const uint32_t a = clamp_word(words[q] & 0xffffu, lo, hi, s.dtype, &c0);
+        const uint32_t d = clamp_word(words[q] >> 16, lo, hi, s.dtype, &c1);
+        words[q] = (a & 0xffffu) | (d << 16);
+        any |= c0 | c1;
+        local += (c0 ? 1u : 0u) + (c1 ? 1u : 0u);
+      }
+    }
+    if (any) vec[j] = make_uint4(words[0], words[1], words[2], words[3]);
+  }
+  for (int o = 32; o > 0; o >>= 1) local += (uint32_t)__shfl_xor((int)local, o);
+  if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, (unsigned long long)local);
+}
+
 __global__ void k_health(const unsigned long long* count, unsigned long long threshold, uint32_t* alert) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *alert = (*count > threshold) ? 1u : 0u;
 }
@@ -238,6 +300,16 @@ void launch_box_finalize(const uint32_t* kmin, const uint32_t* kmax, int C, int 
 void launch_guard(const DevScene& s, const DevBox& b, int f, unsigned long long* count, hipStream_t st) {
   dim3 g(blocks_for(s.n, 256, 2048), s.ncomp[f]);
   k_guard<<<g, 256, 0, st>>>(s, b, f, count);
+}
+void launch_guard_rows(const DevScene& s, const DevBox& b, const GuardRows& gr, unsigned long long* count,
+                       hipStream_t st) {
+  if (gr.n_rows == 0) return;
+  const int es = s.dtype == SG_F32 ? 4 : 2;
+  const int64_t nvec = (int64_t)s.n * es / 16;
+  // enough blocks per row for several vectors in flight per thread across the device
+  dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((nvec + 1023) / 1024, 2048)), gr.n_rows);
+  if (es == 4) k_guard_rows<4><<<g, 256, 0, st>>>(s, b, gr, count);
+  else k_guard_rows<2><<<g, 256, 0, st>>>(s, b, gr, count);
 }
 void launch_health(const unsigned long long* count, unsigned long long thr, uint32_t* alert, hipStream_t st) {
   k_health<<<1, 64, 0, st>>>(count, thr, alert);

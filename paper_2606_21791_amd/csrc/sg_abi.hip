@@ -655,8 +655,23 @@ sg_status sg_guard(sg_ctx* ctx, const sg_scene* scene, const sg_box* box, uint32
   launch_fill_u32(reinterpret_cast<uint32_t*>(clamp_count), 0u, 2, st);
   {
     PassScope ps(ctx, SG_PASS_GUARD, st);
-    for (int f = 0; f < 6; ++f)
-      if ((b.mask >> f) & 1u) launch_guard(s, b, f, reinterpret_cast<unsigned long long*>(clamp_count), st);
+    // rows of contiguous primitives against a global box: one vectorised
+    // launch; anything else: the per-field kernel
+    GuardRows gr;
+    gr.n_rows = 0;
+    for (int f = 0; f < 6; ++f) {
+      if (!((b.mask >> f) & 1u)) continue;
+      if (b.mode == SG_BOX_GLOBAL && s.ps[f] == 1 && gr.n_rows + s.ncomp[f] <= 64) {
+        for (int c = 0; c < s.ncomp[f]; ++c) {
+          gr.f[gr.n_rows] = f;
+          gr.c[gr.n_rows] = c;
+          ++gr.n_rows;
+        }
+      } else {
+        launch_guard(s, b, f, reinterpret_cast<unsigned long long*>(clamp_count), st);
+      }
+    }
+    launch_guard_rows(s, b, gr, reinterpret_cast<unsigned long long*>(clamp_count), st);
   }
   if (health_alert) launch_health(reinterpret_cast<unsigned long long*>(clamp_count), health_threshold, health_alert, st);
   return check_last("sg_guard");

@@ -81,6 +81,15 @@ void launch_box_reduce(const DevScene& s, int f, uint32_t* kmin, uint32_t* kmax,
 void launch_box_finalize(const uint32_t* kmin, const uint32_t* kmax, int C, int dtype, void* lo, void* hi,
                          hipStream_t st);
 void launch_guard(const DevScene& s, const DevBox& b, int f, unsigned long long* count, hipStream_t st);
+// Component rows (field, component) guarded by one launch; global box and
+// contiguous primitives only.
+struct GuardRows {
+  int n_rows;
+  int f[64];
+  int c[64];
+};
+void launch_guard_rows(const DevScene& s, const DevBox& b, const GuardRows& gr, unsigned long long* count,
+                       hipStream_t st);
 void launch_health(const unsigned long long* count, unsigned long long thr, uint32_t* alert, hipStream_t st);
 void launch_metrics_partials(const float* img, const float* clean, int64_t px_per_var, int nchunks, int B,
                              Partial* out, hipStream_t st);

@@ -99,10 +99,11 @@ def test_invalid_site_rejected_without_mutation(ctx):
 
 
 @pytest.mark.parametrize("fmt", FMTS)
-def test_guard_box_and_clamp_bit_exact(ctx, fmt):
+@pytest.mark.parametrize("n", [20_000, 20_003])   # 20,003: rows start off the 16-byte grid, ragged ends
+def test_guard_box_and_clamp_bit_exact(ctx, fmt, n):
     import torch
     from paper_2606_21791_amd import binding as b
-    sc = synth.make_scene(20_000, seed=6, sh_degree=1)
+    sc = synth.make_scene(n, seed=6, sh_degree=1)
     ds = b.DeviceScene.upload(ctx, sc, fmt)
     words = stored(sc, fmt)
     box = ctx.guard_box(ds)
