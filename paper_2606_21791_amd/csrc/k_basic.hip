@@ -116,22 +116,29 @@ __global__ void __launch_bounds__(256) k_guard(DevScene s, DevBox b, int f, unsi
 // one of its words changed.  Block y serves row y of the plan; the few words
 // before the row's first 16-byte boundary and after its last are done one by
 // one by block x = 0.
-template <int ES>
+template <int ES, bool PER_PRIM>
 __global__ void __launch_bounds__(256) k_guard_rows(DevScene s, DevBox b, GuardRows gr,
                                                     unsigned long long* __restrict__ count) {
   constexpr int PER = 16 / ES;   // words per vector
   const int f = gr.f[blockIdx.y], c = gr.c[blockIdx.y];
-  uint32_t lo, hi;
-  box_words(b, f, 0, c, s.n, &lo, &hi);
-  char* row = const_cast<char*>(reinterpret_cast<const char*>(s.ptr[f])) + (int64_t)c * s.cs[f] * ES;
   const int64_t n = s.n;
+  uint32_t glo = 0, ghi = 0;     // global box of this row
+  if (!PER_PRIM) box_words(b, f, 0, c, n, &glo, &ghi);
+  char* row = const_cast<char*>(reinterpret_cast<const char*>(s.ptr[f])) + (int64_t)c * s.cs[f] * ES;
+  // per-primitive bounds: rows of the box arrays, laid out like the scene's
+  const char* lrow = PER_PRIM ? reinterpret_cast<const char*>(b.lo[f]) + (int64_t)c * n * ES : nullptr;
+  const char* hrow = PER_PRIM ? reinterpret_cast<const char*>(b.hi[f]) + (int64_t)c * n * ES : nullptr;
   const int64_t head = (int64_t)(((16 - ((uintptr_t)row & 15)) & 15) / ES);   // words before alignment
   const int64_t h = head < n ? head : n;
   const int64_t nvec = (n - h) / PER;
   const int64_t tail0 = h + nvec * PER;
   uint32_t local = 0;
+  auto word_at = [](const char* r, int64_t i) -> uint32_t {
+    return ES == 4 ? reinterpret_cast<const uint32_t*>(r)[i] : reinterpret_cast<const uint16_t*>(r)[i];
+  };
   auto one = [&](int64_t i) {
-    uint32_t w = ES == 4 ? reinterpret_cast<uint32_t*>(row)[i] : reinterpret_cast<uint16_t*>(row)[i];
+    const uint32_t w = word_at(row, i);
+    const uint32_t lo = PER_PRIM ? word_at(lrow, i) : glo, hi = PER_PRIM ? word_at(hrow, i) : ghi;
     bool cl;
     const uint32_t g = clamp_word(w, lo, hi, s.dtype, &cl);
     if (cl) {
@@ -145,22 +152,32 @@ __global__ void __launch_bounds__(256) k_guard_rows(DevScene s, DevBox b, GuardR
     for (int64_t i = tail0 + threadIdx.x; i < n; i += blockDim.x) one(i);
   }
   uint4* vec = reinterpret_cast<uint4*>(row + h * ES);
+  const uint4* lvec = PER_PRIM ? reinterpret_cast<const uint4*>(lrow + h * ES) : nullptr;
+  const uint4* hvec = PER_PRIM ? reinterpret_cast<const uint4*>(hrow + h * ES) : nullptr;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nvec; j += stride) {
     const uint4 v = vec[j];
     uint32_t words[4] = {v.x, v.y, v.z, v.w};
+    uint32_t los[4] = {glo, glo, glo, glo}, his[4] = {ghi, ghi, ghi, ghi};
+    if (PER_PRIM) {
+      const uint4 l = lvec[j], u = hvec[j];
+      los[0] = l.x; los[1] = l.y; los[2] = l.z; los[3] = l.w;
+      his[0] = u.x; his[1] = u.y; his[2] = u.z; his[3] = u.w;
+    }
     bool any = false;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (ES == 4) {
         bool cl;
-        words[q] = clamp_word(words[q], lo, hi, s.dtype, &cl);
+        words[q] = clamp_word(words[q], los[q], his[q], s.dtype, &cl);
         any |= cl;
         local += cl ? 1u : 0u;
       } else {
         bool c0, c1;
-        const uint32_t a = clamp_word(words[q] & 0xffffu, lo, hi, s.dtype, &c0);
-        const uint32_t d = clamp_word(words[q] >> 16, lo, hi, s.dtype, &c1);
+        const uint32_t lo0 = PER_PRIM ? (los[q] & 0xffffu) : glo, hi0 = PER_PRIM ? (his[q] & 0xffffu) : ghi;
+        const uint32_t lo1 = PER_PRIM ? (los[q] >> 16) : glo, hi1 = PER_PRIM ? (his[q] >> 16) : ghi;
+        const uint32_t a = clamp_word(words[q] & 0xffffu, lo0, hi0, s.dtype, &c0);
+        const uint32_t d = clamp_word(words[q] >> 16, lo1, hi1, s.dtype, &c1);
         words[q] = (a & 0xffffu) | (d << 16);
         any |= c0 | c1;
         local += (c0 ? 1u : 0u) + (c1 ? 1u : 0u);
@@ -308,8 +325,14 @@ void launch_guard_rows(const DevScene& s, const DevBox& b, const GuardRows& gr, 
   const int64_t nvec = (int64_t)s.n * es / 16;
   // enough blocks per row for several vectors in flight per thread across the device
   dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((nvec + 1023) / 1024, 2048)), gr.n_rows);
-  if (es == 4) k_guard_rows<4><<<g, 256, 0, st>>>(s, b, gr, count);
-  else k_guard_rows<2><<<g, 256, 0, st>>>(s, b, gr, count);
+  const bool pp = b.mode == SG_BOX_PER_PRIM;
+  if (es == 4) {
+    if (pp) k_guard_rows<4, true><<<g, 256, 0, st>>>(s, b, gr, count);
+    else k_guard_rows<4, false><<<g, 256, 0, st>>>(s, b, gr, count);
+  } else {
+    if (pp) k_guard_rows<2, true><<<g, 256, 0, st>>>(s, b, gr, count);
+    else k_guard_rows<2, false><<<g, 256, 0, st>>>(s, b, gr, count);
+  }
 }
 void launch_health(const unsigned long long* count, unsigned long long thr, uint32_t* alert, hipStream_t st) {
   k_health<<<1, 64, 0, st>>>(count, thr, alert);

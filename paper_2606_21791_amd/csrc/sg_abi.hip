@@ -655,13 +655,18 @@ sg_status sg_guard(sg_ctx* ctx, const sg_scene* scene, const sg_box* box, uint32
   launch_fill_u32(reinterpret_cast<uint32_t*>(clamp_count), 0u, 2, st);
   {
     PassScope ps(ctx, SG_PASS_GUARD, st);
-    // rows of contiguous primitives against a global box: one vectorised
-    // launch; anything else: the per-field kernel
+    // rows of contiguous primitives: one vectorised launch (with a
+    // per-primitive box, when its rows share the scene rows' alignment);
+    // anything else: the per-field kernel
     GuardRows gr;
     gr.n_rows = 0;
     for (int f = 0; f < 6; ++f) {
       if (!((b.mask >> f) & 1u)) continue;
-      if (b.mode == SG_BOX_GLOBAL && s.ps[f] == 1 && gr.n_rows + s.ncomp[f] <= 64) {
+      bool rows = s.ps[f] == 1 && gr.n_rows + s.ncomp[f] <= 64;
+      if (b.mode == SG_BOX_PER_PRIM)
+        rows = rows && s.cs[f] == s.n && ((uintptr_t)s.ptr[f] & 15) == 0 && ((uintptr_t)b.lo[f] & 15) == 0 &&
+               ((uintptr_t)b.hi[f] & 15) == 0;
+      if (rows) {
         for (int c = 0; c < s.ncomp[f]; ++c) {
           gr.f[gr.n_rows] = f;
           gr.c[gr.n_rows] = c;

@@ -136,10 +136,11 @@ def test_guard_box_and_clamp_bit_exact(ctx, fmt, n):
     assert int(cnt[0]) == 0 and int(alert[0]) == 0
 
 
-def test_per_primitive_box_guard(ctx):
+@pytest.mark.parametrize("n", [5000, 5003])   # 5,003: rows off the 16-byte grid, ragged ends
+def test_per_primitive_box_guard(ctx, n):
     import torch
     from paper_2606_21791_amd import binding as b
-    sc = synth.make_scene(5000, seed=8)
+    sc = synth.make_scene(n, seed=8)
     lo32, hi32 = synth.make_box_jitter(sc, seed=4)
     for fmt in FMTS:
         ds = b.DeviceScene.upload(ctx, sc, fmt)
