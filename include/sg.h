@@ -284,7 +284,15 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
  * are ordered after earlier work on `stream`, and later work on `stream` is
  * ordered after them; the call returns once everything is enqueued.  cfg may
  * be NULL (batch 32, 8 streams, 2 threads).  Errors of any batch stop the
- * campaign and are reported with the batch index. */
+ * campaign and are reported with the batch index.
+ *
+ * When every variant is incremental (at most 8 distinct primitives), the
+ * campaign copies sites and variants to device memory once and enqueues two
+ * launches per batch: the variant prep, which also reduces the metrics of
+ * the previous batch of its stream, and the persistent compositing; one
+ * reduction per stream ends it.  Campaigns on one context run one at a
+ * time (a second call waits until the first one's device copies are no
+ * longer read). */
 typedef struct {
   int32_t batch;     /* variants per launch; 0 = 32; at most SG_MAX_BATCH */
   int32_t streams;   /* device streams; 0 = 8 (at most 64) */
@@ -303,7 +311,7 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
 /* Autotuner.  Picks the launch configuration of injection campaigns on one
  * scene and camera by measurement: tile size, variants per launch B,
  * campaign streams and host threads, persistent compositing workgroups per
- * CU (or a total grid), checkpoint spacing and graph replay.  It prepares the scene at each
+ * CU (or a total grid) and checkpoint spacing.  It prepares the scene at each
  * candidate tile size and spacing, times campaigns of single-site variants
  * over `sites` (host, at least 64; the sample should follow the campaign's
  * site distribution) and moves one parameter at a time to its best value
@@ -317,9 +325,9 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
  * with from_cache = 1 and touches no device; a miss measures, appends the
  * result and sets from_cache = 0.  The context's settings are restored
  * before returning; the caller applies the result (sg_ctx_set_persistent,
- * sg_ctx_set_persistent_grid, sg_ctx_set_resume, sg_ctx_set_graphs before
- * sg_prepare with the tile size,
- * and batch/streams/threads in sg_campaign). */
+ * sg_ctx_set_persistent_grid, sg_ctx_set_resume before sg_prepare with the
+ * tile size, and batch/streams/threads in sg_campaign).  graphs is 0:
+ * campaigns do not replay graphs. */
 typedef struct {
   int32_t tile, batch, streams, threads, wgs_per_cu, resume, graphs, from_cache;
   double inj_per_s;   /* measured rate of the chosen configuration */

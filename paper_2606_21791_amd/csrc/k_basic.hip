@@ -218,38 +218,30 @@ __global__ void k_metrics_partials(const float* __restrict__ img, const float* _
   block_reduce_partial(sse, changed, mx, nonfin, 0ull, out + (int64_t)v * gridDim.x + blockIdx.x);
 }
 
-// Per variant: partials[item_off[v] .. + n_items[v]) in a fixed order -> metrics.
-__global__ void k_reduce_metrics(const Partial* __restrict__ parts, const uint32_t* __restrict__ item_off,
-                                 const uint32_t* __restrict__ n_items, uint32_t uniform_items, const VariantState* vs,
-                                 const uint32_t* flags, const unsigned long long* clamps, uint32_t n_pixels,
-                                 sg_metrics_t* __restrict__ out, uint32_t path, int tiles_x, int tiles_y) {
+// Per variant (one wave): partials[item_off[v] .. + n_items[v]) in a fixed
+// order -> metrics.  With vs, the partials are a batch's item partials and
+// the record is the one the fused reduction of the next batch's variant prep
+// writes (reduce_batch_variant); without, they are per tile (tiles_x > 0) or
+// per pixel chunk.
+__global__ void __launch_bounds__(64) k_reduce_metrics(const Partial* __restrict__ parts, const uint32_t* __restrict__ item_off,
+                                                       const uint32_t* __restrict__ n_items, uint32_t uniform_items,
+                                                       const VariantState* vs, const uint32_t* flags,
+                                                       const unsigned long long* clamps, uint32_t n_pixels,
+                                                       sg_metrics_t* __restrict__ out, uint32_t path, int tiles_x,
+                                                       int tiles_y) {
   const int v = blockIdx.x;
+  if (vs && item_off && n_items && !flags && path == 0u) {
+    reduce_batch_variant(parts, item_off, n_items, vs, n_pixels, v, out);
+    return;
+  }
   const uint32_t off = item_off ? item_off[v] : v * uniform_items;
   const uint32_t n = n_items ? n_items[v] : uniform_items;
-  double sse = 0.0;
-  uint32_t changed = 0, nonfin = 0;
-  float mx = 0.f;
-  unsigned long long ev = 0;
   uint64_t rend = 0;   // full render with per-tile partials: regions of the changed tiles
-  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
-    const Partial p = parts[off + k];
-    if (tiles_x > 0 && p.changed) rend |= region_bit((int)k % tiles_x, (int)k / tiles_x, tiles_x, tiles_y);
-    sse += p.sse;
-    changed += p.changed;
-    mx = fmaxf(mx, p.max_abs);
-    nonfin |= p.nonfinite;
-    ev += p.evals;
-  }
-  __shared__ Partial red;
-  __shared__ unsigned long long s_rend;
-  if (threadIdx.x == 0) s_rend = 0;
-  block_reduce_partial(sse, changed, mx, nonfin, ev, &red);   // its barriers order s_rend's reset
-  if (rend) atomicOr(&s_rend, (unsigned long long)rend);
-  __syncthreads();
+  const Partial red = wave_reduce_parts(parts, off, n, tiles_x, tiles_y, &rend);
   if (threadIdx.x == 0) {
     uint64_t pr = 0, rr = 0;
     if (vs) { pr = vs[v].pred_regions; rr = vs[v].rend_regions; }
-    else if (tiles_x > 0) { pr = ~0ull; rr = s_rend; }
+    else if (tiles_x > 0) { pr = ~0ull; rr = rend; }
     out[v] = make_metrics(red, (vs ? vs[v].nonfinite : 0u) | (flags ? (flags[0] & 1u) : 0u), vs ? vs[v].n_dirty : n,
                           vs ? vs[v].clamps : (clamps ? *clamps : 0ull), n_pixels, path, pr, rr);
   }
@@ -348,8 +340,8 @@ void launch_reduce_metrics(const Partial* parts, const uint32_t* item_off, const
                            const unsigned long long* clamps, uint32_t n_pixels, sg_metrics_t* out, int B,
                            uint32_t path, hipStream_t st, int tiles_x, int tiles_y) {
   if (B <= 0) return;
-  k_reduce_metrics<<<B, 256, 0, st>>>(parts, item_off, n_items, uniform_items, vs, flags, clamps, n_pixels, out,
-                                      path, tiles_x, tiles_y);
+  k_reduce_metrics<<<B, 64, 0, st>>>(parts, item_off, n_items, uniform_items, vs, flags, clamps, n_pixels, out,
+                                     path, tiles_x, tiles_y);
 }
 
 void launch_pool_views(const sg_metrics_t* views, int K, int B, sg_metrics_t* out, hipStream_t st) {

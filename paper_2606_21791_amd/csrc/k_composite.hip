@@ -38,10 +38,15 @@ struct MergeSpec {
 enum { kFull = 0, kFullWrite = 1, kItem = 2 };
 
 
+// kItem: s_ids (nullable) holds the ids of the tile's whole clean list;
+// sp_in and cl*_in are the pixel's stop index and clean colour, read by the
+// caller.  Returns the tile's changed-pixel count in thread 0 (0 elsewhere,
+// and when part is null).
 template <int TILE, int MODE>
-__device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, const MergeSpec* ms, const Rec* ovr,
-                                               float* img, Partial* part, float4* s_r0, float4* s_r1,
-                                               float4* s_r2) {
+__device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, const MergeSpec* ms, const Rec* ovr,
+                                                   float* img, Partial* part, float4* s_r0, float4* s_r1,
+                                                   float4* s_r2, const uint32_t* s_ids = nullptr, uint32_t sp_in = 0,
+                                                   float cl0_in = 0.f, float cl1_in = 0.f, float cl2_in = 0.f) {
   constexpr int BS = TILE * TILE;
   constexpr int NW = BS / 64;            // waves per tile; wave w covers an 8 x 8 pixel block
   constexpr int BPR = TILE / 8;          // blocks per tile row
@@ -66,7 +71,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
   if (MODE == kItem && A.stop) {
     start = ms->start;
     if (inside) {
-      const uint32_t sp = A.stop[(int64_t)y * A.W + x];
+      const uint32_t sp = sp_in;
       if (sp < ms->m0) {
         same = true;
         done = true;
@@ -99,7 +104,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
         } else {
           uint32_t raw = m - before;
           for (int k = 0; k < ms->n_rm; ++k) raw += ms->rm_pos[k] <= raw ? 1u : 0u;
-          const uint32_t id = (uint32_t)A.keys[raw_start + raw];
+          const uint32_t id = s_ids ? s_ids[raw] : (uint32_t)A.keys[raw_start + raw];
           a = A.r0[id]; b = A.r1[id]; c = A.r2[id];
         }
       }
@@ -211,8 +216,9 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
       A.stop_out[(int64_t)y * A.W + x] = my_stop;
     }
     if (A.clean) {
-      const double d0 = (double)i0 - (double)A.clean[off], d1 = (double)i1 - (double)A.clean[off + 1],
-                   d2 = (double)i2 - (double)A.clean[off + 2];
+      const float c0 = MODE == kItem ? cl0_in : A.clean[off], c1 = MODE == kItem ? cl1_in : A.clean[off + 1],
+                  c2 = MODE == kItem ? cl2_in : A.clean[off + 2];
+      const double d0 = (double)i0 - (double)c0, d1 = (double)i1 - (double)c1, d2 = (double)i2 - (double)c2;
       sse = d0 * d0 + d1 * d1 + d2 * d2;
       const double dm = fmax(fabs(d0), fmax(fabs(d1), fabs(d2)));
       changed = dm > (1.0 / 255.0) ? 1u : 0u;
@@ -228,7 +234,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& A, int tile, cons
     __syncthreads();
     if (tid == 0) A.stop_key_out[tile] = s_smax >= mlen ? ~0ull : A.keys[raw_start + s_smax];
   }
-  if (part) block_reduce_partial(sse, changed, mx, nonfin, (unsigned long long)evals, part);
+  return part ? block_reduce_partial(sse, changed, mx, nonfin, (unsigned long long)evals, part) : 0u;
 }
 
 // Full render: one workgroup per tile.  Block b of the grid serves tile
@@ -246,41 +252,52 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_full(CompArgs A) {
   composite_tile<TILE, MODE>(A, tile, nullptr, nullptr, A.image, A.parts ? A.parts + tile : nullptr, s_r0, s_r1, s_r2);
 }
 
-__device__ __forceinline__ bool rect_has(uint32_t r0, uint32_t r1, int tx, int ty) {
-  return tx >= (int)(r0 & 0xffff) && tx <= (int)(r1 & 0xffff) && ty >= (int)(r0 >> 16) && ty <= (int)(r1 >> 16);
-}
-
 // Persistent incremental compositing: a fixed grid of workgroups pops
 // (variant, tile) work items from a device counter until the batch's item
 // count (known only on the device) is exhausted.  Per item, the positions of
 // the corrupted primitives' old keys and new keys in the tile's sorted clean
-// list (each target's lower bound) are found by a two-round parallel search:
-// the last keys of TILE*TILE equal buckets locate each target's bucket, and
-// one pass over that bucket counts the keys below the target.
+// list (each target's lower bound) are counted over the whole list, which a
+// list of at most KCAP entries brings into registers in one round of loads
+// (its ids then stay in LDS for the compositing); a longer list is searched
+// in two rounds: the last keys of TILE*TILE equal buckets locate each
+// target's bucket, and one pass over that bucket counts the keys below the
+// target.  The next item is popped, and the pixel's stop index and clean
+// colour are read, while the current item's list is searched.
 //
-// An item is skipped outright when the merged list equals the clean list, or
-// when every target key lies after the key at which the tile's last pixel
-// stopped in the clean render: no pixel of the tile reaches a changed entry.
+// The variant prep has already dropped every dirty tile whose last pixel
+// stopped, in the clean render, before all of the tile's target keys.
+// 16 x 16 tiles: registers are held to five resident workgroups per CU, the
+// number their LDS allows.
 template <int TILE>
-__global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, ItemArgs I) {
+__global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_composite_items(CompArgs A, ItemArgs I) {
   constexpr int BS = TILE * TILE;
   constexpr int NT = 2 * kMaxTouch;
+  constexpr int KPT = TILE == 8 ? 8 : (TILE == 16 ? 4 : 2);   // staged list keys per thread
+  constexpr int KCAP = KPT * BS;
+  constexpr int VSW = (int)(sizeof(VariantState) / sizeof(uint32_t));
+  constexpr int BPR = TILE / 8;
   __shared__ float4 s_r0[BS], s_r1[BS], s_r2[BS];
   __shared__ MergeSpec ms;
   __shared__ uint32_t s_item;
+  __shared__ uint32_t s_vs[VSW];        // the item's VariantState
+  __shared__ uint32_t s_ids[KCAP];      // ids of a staged clean list
   __shared__ uint64_t s_tgt[NT];        // removal keys, then insertion keys (sorted)
   __shared__ uint32_t s_cnt[NT], s_fnd[NT], s_bkt[NT];
-  __shared__ int s_nr, s_ni, s_skip;
+  __shared__ int s_nr, s_ni;
   // the variants' first items (B + 1 offsets; B <= kMaxBatch)
   __shared__ uint32_t off[kMaxBatch + 1];
-  for (int k = threadIdx.x; k <= I.B; k += BS) off[k] = I.item_off[k];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int pxo = (wave % BPR) * 8 + (lane & 7), pyo = (wave / BPR) * 8 + (lane >> 3);   // as in composite_tile
+  for (int k = tid; k <= I.B; k += BS) off[k] = I.item_off[k];
+  if (tid == 0) s_item = atomicAdd(I.counter, 1u);
   __syncthreads();
   const uint32_t total = off[I.B];
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(I.counter, 1u);
-    __syncthreads();
-    const uint32_t item = s_item;
+    // item, variant and tile are uniform over the workgroup: keep them scalar
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
     if (item >= total) break;
+    uint32_t next = 0;
+    if (tid == 0) next = atomicAdd(I.counter, 1u);
     uint32_t v = 0;
     {
       int lo = 0, hi = I.B;   // largest v with off[v] <= item
@@ -288,15 +305,34 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
         const int mid = (lo + hi) >> 1;
         if (off[mid] <= item) lo = mid; else hi = mid;
       }
-      v = (uint32_t)lo;
+      v = (uint32_t)__builtin_amdgcn_readfirstlane(lo);
     }
-    const int tile = (int)I.tiles[(int64_t)v * A.ras.n_tiles + (item - off[v])];
-    if (threadIdx.x < NT) { s_cnt[threadIdx.x] = 0; s_fnd[threadIdx.x] = 0; s_bkt[threadIdx.x] = 0; }
-    if (threadIdx.x == 0) {
-      const VariantState& vs = I.vs[v];
-      const int tx = tile % A.ras.tiles_x, ty = tile / A.ras.tiles_x;
-      ms.raw_start = A.tile_start[tile];
-      ms.raw_len = A.tile_cnt[tile];
+    const uint32_t first = __builtin_amdgcn_readfirstlane(off[v]);
+    const uint4 ent = I.items[(int64_t)v * A.ras.n_tiles + (item - first)];
+    for (int k = tid; k < VSW; k += BS) s_vs[k] = reinterpret_cast<const uint32_t*>(I.vs + v)[k];
+    const int tile = (int)ent.x;
+    const uint32_t raw_start = ent.y, L = ent.z;
+    const int tx = tile % A.ras.tiles_x, ty = tile / A.ras.tiles_x;
+    const int x = tx * TILE + pxo, y = ty * TILE + pyo;
+    uint32_t sp = 0;
+    float cl0 = 0.f, cl1 = 0.f, cl2 = 0.f;
+    if (x < A.W && y < A.H) {
+      const int64_t p = (int64_t)y * A.W + x;
+      if (A.stop) sp = A.stop[p];
+      if (A.clean) { cl0 = A.clean[3 * p]; cl1 = A.clean[3 * p + 1]; cl2 = A.clean[3 * p + 2]; }
+    }
+    const bool staged = L <= (uint32_t)KCAP;
+    const uint64_t* keys = A.keys + raw_start;
+    uint64_t kr[KPT];
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+      const uint32_t m = (uint32_t)(tid + k * BS);
+      kr[k] = staged && m < L ? keys[m] : ~0ull;   // padding compares above every key
+    }
+    if (tid < NT) { s_cnt[tid] = 0; s_fnd[tid] = 0; s_bkt[tid] = 0; }
+    __syncthreads();
+    if (tid == 0) {
+      const VariantState& vs = *reinterpret_cast<const VariantState*>(s_vs);
       int nr = 0, ni = 0;
       // removal keys fill s_tgt from the front, insertion keys from the back
       for (uint32_t j = 0; j < vs.n_touch; ++j) {
@@ -314,32 +350,50 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
       for (int a = 1; a < ni; ++a)
         for (int b = a; b > 0 && s_tgt[nr + b - 1] > s_tgt[nr + b]; --b) {
           const uint64_t k = s_tgt[nr + b]; s_tgt[nr + b] = s_tgt[nr + b - 1]; s_tgt[nr + b - 1] = k;
-          const uint32_t x = ms.ins_src[b]; ms.ins_src[b] = ms.ins_src[b - 1]; ms.ins_src[b - 1] = x;
+          const uint32_t z = ms.ins_src[b]; ms.ins_src[b] = ms.ins_src[b - 1]; ms.ins_src[b - 1] = z;
         }
       s_nr = nr;
       s_ni = ni;
-      uint64_t mn = ~0ull;
-      for (int j = 0; j < nr + ni; ++j) mn = min(mn, s_tgt[j]);
-      s_skip = (nr + ni == 0) || (A.stop_key && mn > A.stop_key[tile]);
     }
     __syncthreads();
-    if (s_skip) {
-      if (threadIdx.x == 0) {
+    const int nr = __builtin_amdgcn_readfirstlane(s_nr), nt = nr + __builtin_amdgcn_readfirstlane(s_ni);
+    if (nt == 0) {   // the variant changes nothing in this tile
+      if (tid == 0) {
         Partial z;
         z.sse = 0.0; z.evals = 0; z.changed = 0; z.max_abs = 0.f; z.nonfinite = 0; z._pad = 0;
         A.parts[item] = z;
+        s_item = next;
       }
       __syncthreads();
       continue;
     }
-    const int nr = s_nr, nt = s_nr + s_ni;
-    {
-      const uint64_t* keys = A.keys + ms.raw_start;
-      const uint32_t L = ms.raw_len, G = (L + BS - 1) / BS;   // bucket width
-      const int lane = threadIdx.x & 63;
+    const uint32_t G = (L + BS - 1) / BS;   // bucket width of a long list
+    if (staged) {
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        const uint32_t m = (uint32_t)(tid + k * BS);
+        if (m < L) s_ids[m] = (uint32_t)kr[k];
+      }
+      for (int j = 0; j < nt; ++j) {
+        const uint64_t tgt = s_tgt[j];
+        uint32_t c = 0;
+        bool eq = false;
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) {
+          c += kr[k] < tgt ? 1u : 0u;
+          eq |= kr[k] == tgt;
+        }
+        for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o);
+        const unsigned long long me = __ballot(eq);
+        if (lane == 0) {
+          if (c) atomicAdd(&s_cnt[j], c);
+          if (me) atomicOr(&s_fnd[j], 1u);
+        }
+      }
+    } else {
       // round 1: a target's bucket is the number of buckets whose last key is below it
       uint64_t last = ~0ull;
-      if (threadIdx.x * G < L) last = keys[min(L, (threadIdx.x + 1) * G) - 1];
+      if (tid * G < L) last = keys[min(L, (tid + 1) * G) - 1];
       for (int j = 0; j < nt; ++j) {
         const unsigned long long m = __ballot(last < s_tgt[j]);
         if (lane == 0 && m) atomicAdd(&s_bkt[j], (uint32_t)__popcll(m));
@@ -351,7 +405,7 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
         const uint32_t b0 = s_bkt[j] * G, b1 = min(L, b0 + G);
         uint32_t c = 0;
         bool eq = false;
-        for (uint32_t m = b0 + threadIdx.x; m < b1; m += BS) {
+        for (uint32_t m = b0 + tid; m < b1; m += BS) {
           const uint64_t key = keys[m];
           c += key < tgt ? 1u : 0u;
           eq |= key == tgt;
@@ -363,29 +417,31 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
           if (me) atomicOr(&s_fnd[j], 1u);
         }
       }
-      __syncthreads();
-      if (threadIdx.x < nt) s_cnt[threadIdx.x] += min(s_bkt[threadIdx.x] * G, L);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
+      // lower bound of target j: the keys below it in its bucket plus the
+      // buckets before it (no buckets for a staged list)
       int n_rm = 0;
       for (int j = 0; j < nr; ++j)
-        if (s_fnd[j]) ms.rm_pos[n_rm++] = s_cnt[j];
+        if (s_fnd[j]) ms.rm_pos[n_rm++] = s_cnt[j] + min(s_bkt[j] * G, L);
       for (int a = 1; a < n_rm; ++a)
         for (int b = a; b > 0 && ms.rm_pos[b - 1] > ms.rm_pos[b]; --b) {
-          const uint32_t x = ms.rm_pos[b]; ms.rm_pos[b] = ms.rm_pos[b - 1]; ms.rm_pos[b - 1] = x;
+          const uint32_t z = ms.rm_pos[b]; ms.rm_pos[b] = ms.rm_pos[b - 1]; ms.rm_pos[b - 1] = z;
         }
       const int ni = nt - nr;
       for (int j = 0; j < ni; ++j) {
-        const uint32_t praw = s_cnt[nr + j];
+        const uint32_t praw = s_cnt[nr + j] + min(s_bkt[nr + j] * G, L);
         uint32_t rm_before = 0;
         for (int k = 0; k < n_rm; ++k) rm_before += ms.rm_pos[k] < praw ? 1u : 0u;
         ms.ins_mpos[j] = praw - rm_before + (uint32_t)j;
       }
+      ms.raw_start = raw_start;
+      ms.raw_len = L;
       ms.n_rm = n_rm;
       ms.n_ins = ni;
-      ms.mlen = ms.raw_len - (uint32_t)n_rm + (uint32_t)ni;
-      uint32_t m0 = ms.raw_len;
+      ms.mlen = L - (uint32_t)n_rm + (uint32_t)ni;
+      uint32_t m0 = L;
       if (n_rm) m0 = min(m0, ms.rm_pos[0]);
       if (ni) m0 = min(m0, ms.ins_mpos[0]);
       ms.m0 = m0;
@@ -393,10 +449,14 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_items(CompArgs A, Ite
     }
     __syncthreads();
     float* img = A.image ? A.image + (int64_t)v * I.image_stride : nullptr;
-    const uint64_t region = region_bit(tile % A.ras.tiles_x, tile / A.ras.tiles_x, A.ras.tiles_x, A.ras.tiles_y);
-    composite_tile<TILE, kItem>(A, tile, &ms, I.ovr, img, A.parts + item, s_r0, s_r1, s_r2);
-    if (threadIdx.x == 0 && A.parts[item].changed)   // thread 0 wrote the item's partial
-      atomicOr((unsigned long long*)&I.vs[v].rend_regions, (unsigned long long)region);
+    const uint32_t changed = composite_tile<TILE, kItem>(A, tile, &ms, I.ovr, img, A.parts + item, s_r0, s_r1, s_r2,
+                                                         staged ? s_ids : nullptr, sp, cl0, cl1, cl2);
+    if (tid == 0) {
+      if (changed)
+        atomicOr((unsigned long long*)&I.vs[v].rend_regions,
+                 (unsigned long long)region_bit(tx, ty, A.ras.tiles_x, A.ras.tiles_y));
+      s_item = next;
+    }
     __syncthreads();
   }
 }

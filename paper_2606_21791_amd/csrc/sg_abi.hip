@@ -77,6 +77,10 @@ struct Workspace {
   size_t h_sites_cap = 0, h_vars_cap = 0;
   hipEvent_t staged[kRing] = {};
   int ring = 0;
+  // pipelined campaign: the batch whose metrics the next variant prep on
+  // this workspace reduces (pend_B = 0: none)
+  sg_metrics_t* pend_out = nullptr;
+  int pend_B = 0;
   // captured incremental batches: one executable graph per shape and buffer set
   struct Graph {
     std::vector<uintptr_t> key;
@@ -96,6 +100,12 @@ struct sg_ctx {
   bool use_graphs = true;
   std::vector<Workspace*> ws;
   std::vector<hipStream_t> campaign_streams;   // created by sg_campaign, default priority
+  // device copies of a pipelined campaign's sites and variants; camp_done
+  // marks the end of the campaign that last used them; camp_mu serialises
+  // campaigns on one context
+  DevBuf camp_sites, camp_vars;
+  hipEvent_t camp_done = nullptr;
+  std::mutex camp_mu;
   // guards ws, in_use and the timing state: sg_campaign enqueues from several
   // host threads, each on its own streams (so each on its own workspaces)
   std::mutex mu;
@@ -266,7 +276,7 @@ struct PassScope {
 };
 
 template <class T>
-T* P(DevBuf& b) {
+T* P(const DevBuf& b) {
   return reinterpret_cast<T*>(b.p);
 }
 
@@ -517,6 +527,9 @@ void sg_ctx_destroy(sg_ctx* c) {
   for (Workspace* w : c->ws) free_workspace(c, w);
   c->ws.clear();
   for (hipStream_t st : c->campaign_streams) (void)hipStreamDestroy(st);
+  dev_free(c, c->camp_sites);
+  dev_free(c, c->camp_vars);
+  if (c->camp_done) (void)hipEventDestroy(c->camp_done);
   for (int p = 0; p < SG_N_PASSES; ++p)
     for (auto& pr : c->pending[p]) c->ev_pool.insert(c->ev_pool.end(), {pr.first, pr.second});
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -764,6 +777,59 @@ sg_status sg_prep_copy_frame(const sg_prep* p, float* dst, void* stream) {
   return SG_OK;
 }
 
+// Device buffers of an incremental batch of up to B variants on workspace W.
+static sg_status alloc_batch(sg_ctx* ctx, Workspace* W, const sg_prep* prep, int B, hipStream_t st) {
+  const DevRaster& ras = prep->ras;
+  SG_TRY(dev_alloc(ctx, W->vs, (size_t)B * sizeof(VariantState)));
+  SG_TRY(dev_alloc(ctx, W->ovr, (size_t)B * kMaxTouch * sizeof(Rec)));
+  SG_TRY(dev_alloc(ctx, W->bitmap, (size_t)B * prep->bm_words * sizeof(uint64_t)));
+  SG_TRY(dev_alloc(ctx, W->item_off, (size_t)(B + 1) * sizeof(uint32_t)));
+  SG_TRY(dev_alloc(ctx, W->n_items_v, (size_t)B * sizeof(uint32_t)));
+  SG_TRY(dev_alloc(ctx, W->counter, 16));
+  SG_TRY(dev_alloc(ctx, W->tiles, (size_t)B * ras.n_tiles * sizeof(uint4)));
+  if (!W->arrive.p) {
+    SG_TRY(dev_alloc(ctx, W->arrive, 16));
+    launch_fill_u32(P<uint32_t>(W->arrive), 0u, 4, st);   // the variant prep returns it to zero
+  }
+  SG_TRY(dev_alloc(ctx, W->bparts, (size_t)B * ras.n_tiles * sizeof(Partial)));
+  return SG_OK;
+}
+
+static BatchBuffers batch_buffers(Workspace* W, const sg_prep* prep, const sg_site* d_sites, const sg_variant* d_vars,
+                                  int B) {
+  const DevRaster& ras = prep->ras;
+  BatchBuffers bb{d_sites, d_vars, B, P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint64_t>(W->bitmap),
+                  prep->bm_words, prep->row_words, P<uint32_t>(W->item_off), P<uint32_t>(W->n_items_v),
+                  P<uint4>(W->tiles), P<uint32_t>(W->counter), P<uint32_t>(W->arrive), ras.tiles_x, ras.tiles_y,
+                  ras.n_tiles, prep->ck_group ? P<uint64_t>(prep->stop_key) : nullptr, P<uint32_t>(prep->tile_start),
+                  P<uint32_t>(prep->tile_cnt), nullptr, nullptr, 0, (uint32_t)(prep->cam.W * prep->cam.H)};
+  return bb;
+}
+
+static CompArgs item_comp_args(Workspace* W, const sg_prep* prep, float* images_out) {
+  CompArgs ca{P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2), P<uint32_t>(prep->tile_start),
+              P<uint32_t>(prep->tile_cnt), P<uint64_t>(prep->keys), P<float>(prep->frame), images_out,
+              P<Partial>(W->bparts), prep->ras, prep->cam.W, prep->cam.H};
+  if (prep->ck_group) {
+    ca.stop = P<uint32_t>(prep->stop);
+    ca.ck = P<float4>(prep->ck);
+    ca.ck_off = P<uint32_t>(prep->ck_off);
+    ca.stop_key = P<uint64_t>(prep->stop_key);
+    ca.ck_group = prep->ck_group;
+  }
+  return ca;
+}
+
+static ItemArgs item_args(const sg_ctx* ctx, Workspace* W, const sg_prep* prep, int B) {
+  const int tile = prep->ras.tile;
+  const int per_cu = ctx->persistent_wgs_per_cu > 0 ? ctx->persistent_wgs_per_cu
+                                                    : (tile == 32 ? 2 : (tile == 16 ? 8 : 16));
+  ItemArgs it{P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint4>(W->tiles), P<uint32_t>(W->item_off),
+              P<uint32_t>(W->counter), (int64_t)prep->cam.W * prep->cam.H * 3,
+              ctx->persistent_grid > 0 ? ctx->persistent_grid : ctx->n_cu * per_cu, B};
+  return it;
+}
+
 sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites, const sg_variant* variants,
                           int32_t B, const sg_box* box, uint32_t box_field_mask, float* images_out,
                           sg_metrics_t* metrics_out, int32_t mode, void* stream) {
@@ -802,23 +868,11 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
   // incremental pipeline over all B (variants needing the full path get no items)
   if ((int)full_idx.size() < B) {
     const size_t site_cap = std::max<size_t>((size_t)n_sites, std::max<size_t>(64, (size_t)4 * B));
-    SG_TRY(dev_alloc(ctx, W->vs, (size_t)B * sizeof(VariantState)));
-    SG_TRY(dev_alloc(ctx, W->ovr, (size_t)B * kMaxTouch * sizeof(Rec)));
-    SG_TRY(dev_alloc(ctx, W->bitmap, (size_t)B * prep->bm_words * sizeof(uint64_t)));
-    SG_TRY(dev_alloc(ctx, W->item_off, (size_t)(B + 1) * sizeof(uint32_t)));
-    SG_TRY(dev_alloc(ctx, W->n_items_v, (size_t)B * sizeof(uint32_t)));
-    SG_TRY(dev_alloc(ctx, W->counter, 16));
-    SG_TRY(dev_alloc(ctx, W->tiles, (size_t)B * ras.n_tiles * sizeof(uint32_t)));
-    if (!W->arrive.p) {
-      SG_TRY(dev_alloc(ctx, W->arrive, 16));
-      launch_fill_u32(P<uint32_t>(W->arrive), 0u, 4, st);   // the variant prep returns it to zero
-    }
-    SG_TRY(dev_alloc(ctx, W->bparts, (size_t)B * ras.n_tiles * sizeof(Partial)));
+    SG_TRY(alloc_batch(ctx, W, prep, B, st));
     SG_TRY(dev_alloc(ctx, W->gmetrics, (size_t)B * sizeof(sg_metrics_t)));
     int slot = 0;
     SG_TRY(stage_batch(W, sites, n_sites, site_cap, variants, B, &slot));
-    const int per_cu = ctx->persistent_wgs_per_cu > 0 ? ctx->persistent_wgs_per_cu
-                                                      : (ras.tile == 32 ? 2 : (ras.tile == 16 ? 8 : 16));
+    const int per_cu = ctx->persistent_wgs_per_cu;
     // a graph is replayed when every variant is incremental, no images are
     // requested and timing is off; it writes its metrics to the workspace
     const bool graph = ctx->use_graphs && !ctx->timing && full_idx.empty() && !images_out && st != nullptr;
@@ -828,29 +882,14 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
         for (int v = 0; v < B; ++v)
           HIP_TRY(hipMemcpyAsync(images_out + v * frame_floats, prep->frame.p, frame_floats * sizeof(float),
                                  hipMemcpyDeviceToDevice, st));
-      BatchBuffers bb{W->d_sites[slot], W->d_vars[slot], B, P<VariantState>(W->vs), P<Rec>(W->ovr),
-                      P<uint64_t>(W->bitmap), prep->bm_words, prep->row_words, P<uint32_t>(W->item_off),
-                      P<uint32_t>(W->n_items_v), P<uint32_t>(W->tiles), P<uint32_t>(W->counter),
-                      P<uint32_t>(W->arrive), ras.tiles_x, ras.tiles_y, ras.n_tiles,
-                      prep->ck_group ? P<uint64_t>(prep->stop_key) : nullptr};
+      const BatchBuffers bb = batch_buffers(W, prep, W->d_sites[slot], W->d_vars[slot], B);
       {
         PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
         launch_variant_prep(s, b, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
                             P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
       }
-      CompArgs ca{P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2), P<uint32_t>(prep->tile_start),
-                  P<uint32_t>(prep->tile_cnt), P<uint64_t>(prep->keys), P<float>(prep->frame), images_out,
-                  P<Partial>(W->bparts), ras, prep->cam.W, prep->cam.H};
-      if (prep->ck_group) {
-        ca.stop = P<uint32_t>(prep->stop);
-        ca.ck = P<float4>(prep->ck);
-        ca.ck_off = P<uint32_t>(prep->ck_off);
-        ca.stop_key = P<uint64_t>(prep->stop_key);
-        ca.ck_group = prep->ck_group;
-      }
-      ItemArgs it{P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint32_t>(W->tiles), P<uint32_t>(W->item_off),
-                  P<uint32_t>(W->counter), frame_floats,
-                  ctx->persistent_grid > 0 ? ctx->persistent_grid : ctx->n_cu * per_cu, B};
+      const CompArgs ca = item_comp_args(W, prep, images_out);
+      const ItemArgs it = item_args(ctx, W, prep, B);
       {
         PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st);
         launch_composite_items(ca, it, st);
@@ -971,6 +1010,94 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
   return check_last("sg_render_batch_views");
 }
 
+// sg_campaign with one view and every variant incremental.  The campaign's
+// sites and variants are copied to the device once, and a batch is two
+// launches on its stream: the variant prep, which also reduces the metrics of
+// the stream's previous batch, and the persistent compositing.  One
+// reduction per stream closes the campaign.  The records are those of
+// sg_render_batch on the same batches (the same per-variant reduction).
+static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites,
+                                    const sg_variant* variants, int32_t n_variants, const DevBox& box, int B, int NS,
+                                    int NT, sg_metrics_t* metrics_out, hipStream_t caller) {
+  std::lock_guard<std::mutex> cg(ctx->camp_mu);
+  if (ctx->camp_done) HIP_TRY(hipEventSynchronize(ctx->camp_done));   // the previous campaign's copies are free
+  else HIP_TRY(hipEventCreateWithFlags(&ctx->camp_done, hipEventDisableTiming));
+  SG_TRY(dev_alloc(ctx, ctx->camp_sites, std::max<size_t>(1, (size_t)n_sites) * sizeof(sg_site)));
+  SG_TRY(dev_alloc(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant)));
+  if (n_sites)
+    HIP_TRY(hipMemcpyAsync(ctx->camp_sites.p, sites, (size_t)n_sites * sizeof(sg_site), hipMemcpyHostToDevice, caller));
+  HIP_TRY(hipMemcpyAsync(ctx->camp_vars.p, variants, (size_t)n_variants * sizeof(sg_variant), hipMemcpyHostToDevice,
+                         caller));
+  std::vector<Workspace*> ws(NS);
+  for (int k = 0; k < NS; ++k) {
+    ws[k] = workspace(ctx, ctx->campaign_streams[k]);
+    if (!ws[k]) return fail(SG_E_NOMEM, "pinned allocation for a workspace failed");
+    SG_TRY(alloc_batch(ctx, ws[k], prep, B, ctx->campaign_streams[k]));
+    if (ws[k]->pend_B) return fail(SG_E_INVAL, "a campaign stream has an unreduced batch");
+  }
+  hipEvent_t start = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(start, caller));
+  for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(ctx->campaign_streams[k], start, 0));
+  (void)hipEventDestroy(start);
+
+  const sg_site* d_sites = P<sg_site>(ctx->camp_sites);
+  const sg_variant* d_vars = P<sg_variant>(ctx->camp_vars);
+  const DevScene& s = prep->scene;
+  const CompArgs ca0 = item_comp_args(ws[0], prep, nullptr);
+  const int nb = (n_variants + B - 1) / B;
+  auto worker = [&](int t) {
+    (void)hipSetDevice(ctx->device);
+    for (int b = 0; b < nb; ++b) {
+      const int k = b % NS;
+      if (k % NT != t) continue;
+      Workspace* W = ws[k];
+      hipStream_t st = ctx->campaign_streams[k];
+      const int v0 = b * B, nv = std::min(B, n_variants - v0);
+      BatchBuffers bb = batch_buffers(W, prep, d_sites, d_vars + v0, nv);
+      bb.prev_parts = P<Partial>(W->bparts);
+      bb.prev_out = W->pend_out;
+      bb.prev_B = W->pend_B;
+      {
+        PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
+        launch_variant_prep(s, box, prep->cam, prep->ras, P<float4>(prep->r0), P<float4>(prep->r1),
+                            P<float4>(prep->r2), P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
+      }
+      CompArgs ca = ca0;
+      ca.parts = P<Partial>(W->bparts);
+      {
+        PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st);
+        launch_composite_items(ca, item_args(ctx, W, prep, nv), st);
+      }
+      W->pend_out = metrics_out + v0;
+      W->pend_B = nv;
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < NT; ++t) pool.emplace_back(worker, t);
+  worker(0);
+  for (std::thread& th : pool) th.join();
+  const uint32_t n_pixels = (uint32_t)(prep->cam.W * prep->cam.H);
+  for (int k = 0; k < NS; ++k) {
+    Workspace* W = ws[k];
+    hipStream_t st = ctx->campaign_streams[k];
+    if (W->pend_B) {
+      PassScope ps(ctx, SG_PASS_REDUCE, st);
+      launch_reduce_metrics(P<Partial>(W->bparts), P<uint32_t>(W->item_off), P<uint32_t>(W->n_items_v), 0,
+                            P<VariantState>(W->vs), nullptr, nullptr, n_pixels, W->pend_out, W->pend_B, 0u, st);
+      W->pend_B = 0;
+      W->pend_out = nullptr;
+    }
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(e, st));
+    HIP_TRY(hipStreamWaitEvent(caller, e, 0));
+    (void)hipEventDestroy(e);
+  }
+  HIP_TRY(hipEventRecord(ctx->camp_done, caller));
+  return check_last("sg_campaign");
+}
+
 sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const sg_site* sites, int32_t n_sites,
                             const sg_variant* variants, int32_t n_variants, const sg_box* box, uint32_t box_field_mask,
                             const sg_campaign_cfg* cfg, sg_metrics_t* metrics_out, void* stream) {
@@ -1000,6 +1127,28 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
   // the campaign's launches follow the caller's earlier work on `stream` and
   // the caller's later work follows all of them
   hipStream_t caller = S(stream);
+  if (K == 1) {
+    // the pipelined path takes campaigns whose variants all stay incremental
+    DevBox b;
+    SG_TRY(to_dev_box(box, box_field_mask, prep->scene, &b));
+    bool incremental = true;
+    std::vector<uint32_t> prims;
+    for (int v = 0; v < n_variants && incremental; ++v) {
+      const sg_variant& x = variants[v];
+      if (x.guard && !b.mask) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": guard requested without a box");
+      if (x.protect > SG_PROTECT_VOTE) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": unknown protect mode");
+      prims.clear();
+      for (uint32_t k = 0; k < x.n_sites && incremental; ++k) {
+        const uint32_t pr = sites[x.site_off + k].prim;
+        if (std::find(prims.begin(), prims.end(), pr) == prims.end()) {
+          prims.push_back(pr);
+          if ((int)prims.size() > kMaxTouch) incremental = false;
+        }
+      }
+    }
+    if (incremental)
+      return campaign_pipelined(ctx, prep, sites, n_sites, variants, n_variants, b, B, NS, NT, metrics_out, caller);
+  }
   hipEvent_t start = nullptr;
   HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
   HIP_TRY(hipEventRecord(start, caller));

@@ -331,6 +331,28 @@ __device__ __forceinline__ ProjOut project_prim(Get get, int dtype, const DevCam
   return o;
 }
 
+// Whether tile (tx, ty) lies in the packed tile rectangle [r0, r1].
+__device__ __forceinline__ bool rect_has(uint32_t r0, uint32_t r1, int tx, int ty) {
+  return tx >= (int)(r0 & 0xffff) && tx <= (int)(r1 & 0xffff) && ty >= (int)(r0 >> 16) && ty <= (int)(r1 >> 16);
+}
+
+// Smallest (depth, id) key that a variant removes from or inserts into the
+// list of tile (tx, ty): the old key of each changed primitive whose clean
+// rectangle holds the tile, the new key of each whose corrupted one does.
+// All ones when the variant changes nothing in the tile.
+__device__ __forceinline__ unsigned long long tile_min_key(const Touch* touch, uint32_t n_touch, int tx, int ty) {
+  unsigned long long mk = ~0ull;
+  for (uint32_t j = 0; j < n_touch; ++j) {
+    const Touch& t = touch[j];
+    if (t.flags & 4u) continue;
+    if ((t.flags & 1u) && rect_has(t.old_rect0, t.old_rect1, tx, ty))
+      mk = min(mk, ((unsigned long long)t.old_depth << 32) | t.prim);
+    if ((t.flags & 2u) && rect_has(t.new_rect0, t.new_rect1, tx, ty))
+      mk = min(mk, ((unsigned long long)t.new_depth << 32) | t.prim);
+  }
+  return mk;
+}
+
 // Whether a site is corrected by the variant's emulated defense (the
 // protect field of sg_variant): the sign and exponent bits of the storage
 // format, or every bit.

@@ -10,9 +10,10 @@ namespace sg {
 
 // Block-wide reduction of a metric partial in a fixed order (wave butterflies,
 // then waves in index order), so the result does not depend on scheduling.
-// Every thread of the block must call it; thread 0 writes *out.
-__device__ __forceinline__ void block_reduce_partial(double sse, uint32_t changed, float mx, uint32_t nonfin,
-                                                     unsigned long long evals, Partial* out) {
+// Every thread of the block must call it; thread 0 writes *out and gets the
+// changed-pixel total as the return value (0 elsewhere).
+__device__ __forceinline__ uint32_t block_reduce_partial(double sse, uint32_t changed, float mx, uint32_t nonfin,
+                                                         unsigned long long evals, Partial* out) {
   for (int o = 32; o > 0; o >>= 1) {
     sse += __shfl_xor(sse, o);
     changed += (uint32_t)__shfl_xor((int)changed, o);
@@ -37,8 +38,41 @@ __device__ __forceinline__ void block_reduce_partial(double sse, uint32_t change
       p.evals += s_ev[i];
     }
     *out = p;
+    changed = p.changed;
   }
   __syncthreads();
+  return threadIdx.x == 0 ? changed : 0u;
+}
+
+// One wave's sum of the partials parts[off .. off + n) in a fixed order (lane
+// j takes entries j, j + 64, ...; then xor butterflies, whose results are
+// the same in every lane).  rend (nullable; tiles_x > 0): regions of the
+// entries, taken as the tiles of a full frame, that hold a changed pixel.
+__device__ __forceinline__ Partial wave_reduce_parts(const Partial* __restrict__ parts, uint32_t off, uint32_t n,
+                                                     int tiles_x, int tiles_y, uint64_t* rend) {
+  const int lane = threadIdx.x & 63;
+  Partial r;
+  r.sse = 0.0; r.evals = 0; r.changed = 0; r.max_abs = 0.f; r.nonfinite = 0; r._pad = 0;
+  uint64_t rg = 0;
+  for (uint32_t k = lane; k < n; k += 64) {
+    const Partial p = parts[off + k];
+    if (tiles_x > 0 && p.changed) rg |= region_bit((int)k % tiles_x, (int)k / tiles_x, tiles_x, tiles_y);
+    r.sse += p.sse;
+    r.changed += p.changed;
+    r.max_abs = fmaxf(r.max_abs, p.max_abs);
+    r.nonfinite |= p.nonfinite;
+    r.evals += p.evals;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    r.sse += __shfl_xor(r.sse, o);
+    r.changed += (uint32_t)__shfl_xor((int)r.changed, o);
+    r.max_abs = fmaxf(r.max_abs, __shfl_xor(r.max_abs, o));
+    r.nonfinite |= (uint32_t)__shfl_xor((int)r.nonfinite, o);
+    r.evals += __shfl_xor(r.evals, o);
+    rg |= __shfl_xor(rg, o);
+  }
+  if (rend) *rend = rg;
+  return r;
 }
 
 // The record of one variant from its reduced partial (Def. 1 footprint,
@@ -63,6 +97,18 @@ __device__ __forceinline__ sg_metrics_t make_metrics(const Partial& red, uint32_
   m.predicted_regions = pred_regions;
   m.rendered_regions = rend_regions;
   return m;
+}
+
+// The record of variant v of an incremental batch from its item partials
+// and its state (one wave; lane 0 writes out[v]).
+__device__ __forceinline__ void reduce_batch_variant(const Partial* __restrict__ parts, const uint32_t* item_off,
+                                                     const uint32_t* n_items, const VariantState* vs,
+                                                     uint32_t n_pixels, int v, sg_metrics_t* __restrict__ out) {
+  const Partial red = wave_reduce_parts(parts, item_off[v], n_items[v], 0, 0, nullptr);
+  if ((threadIdx.x & 63) == 0) {
+    const VariantState& s = vs[v];
+    out[v] = make_metrics(red, s.nonfinite, s.n_dirty, s.clamps, n_pixels, 0u, s.pred_regions, s.rend_regions);
+  }
 }
 
 // k_ssim.hip: the normalised 1-D Gaussian taps of the SSIM window
@@ -126,11 +172,23 @@ struct BatchBuffers {
   int row_words;            // words per tile row
   uint32_t* item_off;       // B + 1: first item of each variant, then the total
   uint32_t* n_items_v;      // B: work items (dirty tiles that can change) per variant
-  uint32_t* tiles;          // B x n_tiles: variant v's item tiles at [v * n_tiles, ...)
+  // B x n_tiles work items: variant v's at [v * n_tiles, ...), each
+  // {tile, first entry of its clean list, clean list length, 0}
+  uint4* items;
   uint32_t* counter;        // compositing work counter, armed by the last prep workgroup
   uint32_t* arrive;         // prep workgroups that have finished (zero between batches)
   int tiles_x, tiles_y, n_tiles;
   const uint64_t* stop_key; // per tile of the prepared view (nullable): see CompArgs
+  const uint32_t* tile_start;
+  const uint32_t* tile_cnt;
+  // The previous batch of this workspace, whose metrics are still to be
+  // reduced (prev_B = 0: none): its item partials, per-variant item ranges
+  // (item_off, n_items_v) and states (vs) are read before this batch
+  // overwrites them.
+  const Partial* prev_parts;
+  sg_metrics_t* prev_out;
+  int prev_B;
+  uint32_t n_pixels;
 };
 void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                          const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
@@ -196,7 +254,7 @@ void launch_composite_full(const CompArgs& a, hipStream_t st);
 struct ItemArgs {
   VariantState* vs;         // the items OR their regions into it
   const Rec* ovr;
-  const uint32_t* tiles;    // see BatchBuffers
+  const uint4* items;       // see BatchBuffers
   const uint32_t* item_off; // B + 1
   uint32_t* counter;
   int64_t image_stride;   // floats per variant image (when a.image != null)

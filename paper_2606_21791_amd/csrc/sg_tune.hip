@@ -92,7 +92,7 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
     sg_campaign_cfg cc{c.batch, c.streams, c.threads, 0};
     const int nv = std::max(c.batch, (n_sites / c.batch) * c.batch);
     const int use = std::min(nv, n_sites);
-    // one untimed campaign warms graphs and workspaces; then campaigns are
+    // one untimed campaign warms the workspaces; then campaigns are
     // timed until at least 40 ms (and two campaigns) have elapsed
     double total = 0.0;
     int64_t done = 0;
@@ -113,7 +113,7 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
   cur.batch = fixed_batch > 0 ? fixed_batch : std::min(32, max_batch);
   double cur_rate = measure(cur);
   const std::vector<int> tiles = {8, 16, 32}, resumes = {32, 64, 128, 256}, wgss = {1, 2, 4, 8}, grids = {0, 64, 128},
-                         streams = {4, 8, 16, 32}, threads = {1, 2, 4}, graphs = {0, 1};
+                         streams = {4, 8, 16, 32, 64}, threads = {1, 2, 4};
   std::vector<int> batches;
   if (fixed_batch > 0) batches = {fixed_batch};
   else
@@ -142,7 +142,6 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
     try_axis(&Cfg::grid, grids);
     try_axis(&Cfg::streams, streams);
     try_axis(&Cfg::threads, threads);
-    try_axis(&Cfg::graphs, graphs);
     if (!moved) break;
   }
   for (auto& kv : preps) sg_prep_destroy(kv.second);
