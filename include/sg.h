@@ -287,12 +287,14 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
  * campaign and are reported with the batch index.
  *
  * When every variant is incremental (at most 8 distinct primitives), the
- * campaign copies sites and variants to device memory once and enqueues two
- * launches per batch: the variant prep, which also reduces the metrics of
- * the previous batch of its stream, and the persistent compositing; one
- * reduction per stream ends it.  Campaigns on one context run one at a
- * time (a second call waits until the first one's device copies are no
- * longer read). */
+ * campaign copies sites and variants to device memory once, stages and
+ * projects the corrupted primitives of up to 131,072 variants in one
+ * pre-pass launch, and then enqueues one launch per batch on its stream:
+ * launch i lists the work items of the stream's batch i, composites batch
+ * i - 1 and reduces the metrics of batch i - 2 (two more launches per
+ * stream drain the pipeline).  Campaigns on one context run one at a time
+ * (a second call waits until the first one's device buffers are no longer
+ * read). */
 typedef struct {
   int32_t batch;     /* variants per launch; 0 = 32; at most SG_MAX_BATCH */
   int32_t streams;   /* device streams; 0 = 8 (at most 64) */
@@ -375,8 +377,10 @@ sg_status sg_ctx_set_graphs(sg_ctx* ctx, int32_t enable);
  * and the number of timed launches into launches[SG_N_PASSES] (both host),
  * and clears the record. */
 enum {
-  SG_PASS_VARIANT_PREP = 0,     /* corrupted-primitive projection and dirty-tile planning */
-  SG_PASS_COMPOSITE_ITEMS = 1,  /* persistent incremental compositing */
+  SG_PASS_VARIANT_PREP = 0,     /* corrupted-primitive projection and dirty-tile planning
+                                   (a campaign: its pre-pass over all variants) */
+  SG_PASS_COMPOSITE_ITEMS = 1,  /* persistent incremental compositing (a campaign: its fused
+                                   per-batch step, which also plans and reduces) */
   SG_PASS_REDUCE = 2,           /* per-variant metric reduction */
   SG_PASS_PROJECT = 3,          /* full projection */
   SG_PASS_BIN = 4,              /* tile counts, offsets and instance scatter */

@@ -18,6 +18,7 @@
 // not walked at all; the others restart from the clean render's checkpoint at
 // the largest multiple of the checkpoint spacing not above m0, which holds the
 // exact (C, T) state after that many entries.
+#include "sg_batch.h"
 #include "sg_device.h"
 #include "sg_kernels.h"
 
@@ -269,7 +270,7 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_full(CompArgs A) {
 // 16 x 16 tiles: registers are held to five resident workgroups per CU, the
 // number their LDS allows.
 template <int TILE>
-__global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_composite_items(CompArgs A, ItemArgs I) {
+__device__ __forceinline__ void items_role(const CompArgs& A, const ItemArgs& I) {
   constexpr int BS = TILE * TILE;
   constexpr int NT = 2 * kMaxTouch;
   constexpr int KPT = TILE == 8 ? 8 : (TILE == 16 ? 4 : 2);   // staged list keys per thread
@@ -279,7 +280,7 @@ __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_composite_i
   __shared__ float4 s_r0[BS], s_r1[BS], s_r2[BS];
   __shared__ MergeSpec ms;
   __shared__ uint32_t s_item;
-  __shared__ uint32_t s_vs[VSW];        // the item's VariantState
+  __shared__ __align__(8) uint32_t s_vs[VSW];   // the item's VariantState
   __shared__ uint32_t s_ids[KCAP];      // ids of a staged clean list
   __shared__ uint64_t s_tgt[NT];        // removal keys, then insertion keys (sorted)
   __shared__ uint32_t s_cnt[NT], s_fnd[NT], s_bkt[NT];
@@ -458,6 +459,64 @@ __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_composite_i
       s_item = next;
     }
     __syncthreads();
+  }
+}
+
+template <int TILE>
+__global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_composite_items(CompArgs A, ItemArgs I) {
+  items_role<TILE>(A, I);
+}
+
+// The work items of variant v of a campaign's next batch (first wave only).
+__device__ __forceinline__ void tiles_role(const StepArgs& S, int v) {
+  constexpr int VSW = (int)(sizeof(VariantState) / sizeof(uint32_t));
+  __shared__ VariantState s_tv;
+  const int lane = threadIdx.x & 63;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(S.t_vs + v);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&s_tv);
+  for (int k = lane; k < VSW; k += 64) dst[k] = src[k];
+  wave_sync();
+  uint32_t nd, ni;
+  uint64_t pred;
+  enumerate_items(s_tv.touch, s_tv.n_touch, S.tiles_x, S.tiles_y, S.stop_key, S.tile_start, S.tile_cnt,
+                  S.t_items + (int64_t)v * S.n_tiles, &nd, &ni, &pred);
+  if (lane == 0) {
+    S.t_vs[v].n_dirty = nd;
+    S.t_vs[v].pred_regions = pred;
+    S.t_n_items[v] = ni;
+  }
+  finish_batch(S.t_arrive, (uint32_t)S.tB, S.t_n_items, S.t_item_off, S.tB, S.t_counter);
+}
+
+// Workgroups [0, tB): work items of the next batch, one variant each (its
+// other waves leave at once); then ceil(rB / waves) workgroups reducing the
+// previous batch's metrics, a variant per wave; then the persistent
+// compositing of the current batch.
+template <int TILE>
+__global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_campaign_step(StepArgs S) {
+  constexpr int NW = TILE * TILE / 64;
+  const int nt = S.tB, nr = (S.rB + NW - 1) / NW;
+  const int b = blockIdx.x;
+  if (b < nt) {
+    if (threadIdx.x < 64) tiles_role(S, b);
+    return;
+  }
+  if (b < nt + nr) {
+    const int v = (b - nt) * NW + (int)(threadIdx.x >> 6);
+    if (v < S.rB) reduce_batch_variant(S.r_parts, S.r_item_off, S.r_n_items, S.r_vs, S.n_pixels, v, S.r_out);
+    return;
+  }
+  items_role<TILE>(S.A, S.I);
+}
+
+void launch_campaign_step(const StepArgs& a, hipStream_t st) {
+  const int bs = a.A.ras.tile * a.A.ras.tile;
+  const int grid = a.tB + (a.rB + bs / 64 - 1) / (bs / 64) + (a.I.B > 0 ? a.I.grid : 0);
+  if (grid <= 0) return;
+  switch (a.A.ras.tile) {
+    case 8: k_campaign_step<8><<<grid, 64, 0, st>>>(a); break;
+    case 32: k_campaign_step<32><<<grid, 1024, 0, st>>>(a); break;
+    default: k_campaign_step<16><<<grid, 256, 0, st>>>(a); break;
   }
 }
 

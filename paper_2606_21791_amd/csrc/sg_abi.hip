@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -64,7 +65,7 @@ struct Workspace {
   DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
       big_prims, big_tiles, big_choff, big_goff, big_split, parts, work_scene, sites_dev, box_keys, metrics_tmp;
   // batches of variants
-  DevBuf vs, ovr, bitmap, item_off, n_items_v, tiles, bparts, counter, arrive, gmetrics, views_tmp, ssim_tmp;
+  DevBuf vs, ovr, item_off, n_items_v, tiles, bparts, counter, arrive, gmetrics, views_tmp, ssim_tmp;
   unsigned long long* h_total = nullptr;   // pinned
   // pinned staging ring for a batch's sites and variants, read by the variant
   // prep kernel in place; slot k may be rewritten once the batch that last
@@ -77,10 +78,10 @@ struct Workspace {
   size_t h_sites_cap = 0, h_vars_cap = 0;
   hipEvent_t staged[kRing] = {};
   int ring = 0;
-  // pipelined campaign: the batch whose metrics the next variant prep on
-  // this workspace reduces (pend_B = 0: none)
-  sg_metrics_t* pend_out = nullptr;
-  int pend_B = 0;
+  // pipelined campaign: three buffer sets of batch work items, their
+  // partials, per-variant counts and offsets, and a work counter and an
+  // arrival counter each (ctl: set s at words 4s and 4s + 1)
+  DevBuf st_items[3], st_parts[3], st_off[3], st_n[3], st_ctl;
   // captured incremental batches: one executable graph per shape and buffer set
   struct Graph {
     std::vector<uintptr_t> key;
@@ -100,10 +101,11 @@ struct sg_ctx {
   bool use_graphs = true;
   std::vector<Workspace*> ws;
   std::vector<hipStream_t> campaign_streams;   // created by sg_campaign, default priority
-  // device copies of a pipelined campaign's sites and variants; camp_done
-  // marks the end of the campaign that last used them; camp_mu serialises
+  // device copies of a pipelined campaign's sites and variants, and the
+  // states and override records of a chunk of its variants; camp_done marks
+  // the end of the campaign that last used them; camp_mu serialises
   // campaigns on one context
-  DevBuf camp_sites, camp_vars;
+  DevBuf camp_sites, camp_vars, camp_vs, camp_ovr;
   hipEvent_t camp_done = nullptr;
   std::mutex camp_mu;
   // guards ws, in_use and the timing state: sg_campaign enqueues from several
@@ -117,6 +119,10 @@ struct sg_ctx {
 
 struct sg_prep {
   sg_ctx* ctx;
+  // never reused, unlike the object's address: captured graphs of the
+  // incremental path are keyed on it, so a graph recorded for a destroyed
+  // prepared view (its device buffers freed) never matches a new one
+  uint64_t serial = 0;
   DevScene scene;
   sg_scene host_scene;
   DevCam cam;
@@ -125,7 +131,6 @@ struct sg_prep {
   DevBuf r0, r1, r2, depth, rect, tile_cnt, tile_start, keys, frame;
   DevBuf stop, ck, ck_off, stop_key;       // resume state of the clean render
   uint32_t ck_group = 0;
-  int bm_words = 0, row_words = 0;
 };
 
 namespace {
@@ -188,11 +193,17 @@ void free_workspace(sg_ctx* ctx, Workspace* w) {
                     &w->tile_start, &w->cursor, &w->total, &w->keys, &w->keys_tmp, &w->big_prims, &w->big_tiles,
                     &w->big_choff, &w->big_goff, &w->big_split,
                     &w->parts, &w->work_scene, &w->sites_dev, &w->box_keys, &w->metrics_tmp, &w->vs, &w->ovr,
-                    &w->bitmap, &w->item_off, &w->n_items_v, &w->tiles, &w->bparts,
-                    &w->counter, &w->arrive, &w->gmetrics, &w->views_tmp, &w->ssim_tmp};
+                    &w->item_off, &w->n_items_v, &w->tiles, &w->bparts,
+                    &w->counter, &w->arrive, &w->gmetrics, &w->views_tmp, &w->ssim_tmp, &w->st_ctl};
   for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);
   w->graphs.clear();
   for (DevBuf* b : bufs) dev_free(ctx, *b);
+  for (int k = 0; k < 3; ++k) {
+    dev_free(ctx, w->st_items[k]);
+    dev_free(ctx, w->st_parts[k]);
+    dev_free(ctx, w->st_off[k]);
+    dev_free(ctx, w->st_n[k]);
+  }
   if (w->h_total) (void)hipHostFree(w->h_total);
   for (int k = 0; k < Workspace::kRing; ++k) {
     if (w->h_sites[k]) (void)hipHostFree(w->h_sites[k]);
@@ -529,6 +540,8 @@ void sg_ctx_destroy(sg_ctx* c) {
   for (hipStream_t st : c->campaign_streams) (void)hipStreamDestroy(st);
   dev_free(c, c->camp_sites);
   dev_free(c, c->camp_vars);
+  dev_free(c, c->camp_vs);
+  dev_free(c, c->camp_ovr);
   if (c->camp_done) (void)hipEventDestroy(c->camp_done);
   for (int p = 0; p < SG_N_PASSES; ++p)
     for (auto& pr : c->pending[p]) c->ev_pool.insert(c->ev_pool.end(), {pr.first, pr.second});
@@ -728,8 +741,10 @@ sg_status sg_prepare(sg_ctx* ctx, const sg_scene* clean, const sg_camera* cam, c
                      void* stream) {
   if (!ctx || !out) return fail(SG_E_INVAL, "ctx/out is NULL");
   *out = nullptr;
+  static std::atomic<uint64_t> next_serial{1};
   sg_prep* p = new sg_prep();
   p->ctx = ctx;
+  p->serial = next_serial.fetch_add(1);
   sg_status rc = to_dev_scene(clean, &p->scene);
   if (rc == SG_OK) rc = to_dev_cam(cam, &p->cam);
   if (rc == SG_OK) rc = to_dev_raster(raster, p->cam.W, p->cam.H, &p->ras);
@@ -751,8 +766,6 @@ sg_status sg_prepare(sg_ctx* ctx, const sg_scene* clean, const sg_camera* cam, c
     sg_prep_destroy(p);
     return rc;
   }
-  p->row_words = (p->ras.tiles_x + 63) / 64;
-  p->bm_words = p->row_words * p->ras.tiles_y;
   *out = p;
   return SG_OK;
 }
@@ -782,7 +795,6 @@ static sg_status alloc_batch(sg_ctx* ctx, Workspace* W, const sg_prep* prep, int
   const DevRaster& ras = prep->ras;
   SG_TRY(dev_alloc(ctx, W->vs, (size_t)B * sizeof(VariantState)));
   SG_TRY(dev_alloc(ctx, W->ovr, (size_t)B * kMaxTouch * sizeof(Rec)));
-  SG_TRY(dev_alloc(ctx, W->bitmap, (size_t)B * prep->bm_words * sizeof(uint64_t)));
   SG_TRY(dev_alloc(ctx, W->item_off, (size_t)(B + 1) * sizeof(uint32_t)));
   SG_TRY(dev_alloc(ctx, W->n_items_v, (size_t)B * sizeof(uint32_t)));
   SG_TRY(dev_alloc(ctx, W->counter, 16));
@@ -798,11 +810,11 @@ static sg_status alloc_batch(sg_ctx* ctx, Workspace* W, const sg_prep* prep, int
 static BatchBuffers batch_buffers(Workspace* W, const sg_prep* prep, const sg_site* d_sites, const sg_variant* d_vars,
                                   int B) {
   const DevRaster& ras = prep->ras;
-  BatchBuffers bb{d_sites, d_vars, B, P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint64_t>(W->bitmap),
-                  prep->bm_words, prep->row_words, P<uint32_t>(W->item_off), P<uint32_t>(W->n_items_v),
+  BatchBuffers bb{d_sites, d_vars, B, P<VariantState>(W->vs), P<Rec>(W->ovr), P<uint32_t>(W->item_off),
+                  P<uint32_t>(W->n_items_v),
                   P<uint4>(W->tiles), P<uint32_t>(W->counter), P<uint32_t>(W->arrive), ras.tiles_x, ras.tiles_y,
                   ras.n_tiles, prep->ck_group ? P<uint64_t>(prep->stop_key) : nullptr, P<uint32_t>(prep->tile_start),
-                  P<uint32_t>(prep->tile_cnt), nullptr, nullptr, 0, (uint32_t)(prep->cam.W * prep->cam.H)};
+                  P<uint32_t>(prep->tile_cnt)};
   return bb;
 }
 
@@ -903,10 +915,10 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
       return SG_OK;
     };
     if (graph) {
-      std::vector<uintptr_t> key = {(uintptr_t)prep, (uintptr_t)B, site_cap, (uintptr_t)slot, (uintptr_t)per_cu,
+      std::vector<uintptr_t> key = {(uintptr_t)prep->serial, (uintptr_t)B, site_cap, (uintptr_t)slot, (uintptr_t)per_cu,
                                     (uintptr_t)ctx->persistent_grid,
                                     (uintptr_t)b.mask, (uintptr_t)b.mode, (uintptr_t)W->vs.p, (uintptr_t)W->ovr.p,
-                                    (uintptr_t)W->bitmap.p, (uintptr_t)W->tiles.p, (uintptr_t)W->bparts.p,
+                                    (uintptr_t)W->tiles.p, (uintptr_t)W->bparts.p,
                                     (uintptr_t)W->h_sites[slot], (uintptr_t)W->h_vars[slot], (uintptr_t)W->gmetrics.p,
                                     (uintptr_t)W->counter.p, (uintptr_t)W->item_off.p, (uintptr_t)W->n_items_v.p,
                                     (uintptr_t)W->arrive.p};
@@ -1011,88 +1023,137 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
 }
 
 // sg_campaign with one view and every variant incremental.  The campaign's
-// sites and variants are copied to the device once, and a batch is two
-// launches on its stream: the variant prep, which also reduces the metrics of
-// the stream's previous batch, and the persistent compositing.  One
-// reduction per stream closes the campaign.  The records are those of
-// sg_render_batch on the same batches (the same per-variant reduction).
+// sites and variants are copied to the device once, and the corrupted
+// primitives of a chunk of variants are staged and projected by one
+// pre-pass launch.  Each stream then runs its batches as a pipeline of one
+// launch per batch: launch i lists the work items of the stream's batch i,
+// composites batch i - 1 and reduces the metrics of batch i - 2, on three
+// rotating buffer sets; two more launches drain it.  The records are those
+// of sg_render_batch on the same batches.
 static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites,
                                     const sg_variant* variants, int32_t n_variants, const DevBox& box, int B, int NS,
                                     int NT, sg_metrics_t* metrics_out, hipStream_t caller) {
+  constexpr int kChunk = 1 << 17;   // variants staged per pre-pass
   std::lock_guard<std::mutex> cg(ctx->camp_mu);
-  if (ctx->camp_done) HIP_TRY(hipEventSynchronize(ctx->camp_done));   // the previous campaign's copies are free
+  if (ctx->camp_done) HIP_TRY(hipEventSynchronize(ctx->camp_done));   // the previous campaign's buffers are free
   else HIP_TRY(hipEventCreateWithFlags(&ctx->camp_done, hipEventDisableTiming));
+  const int chunk = std::min(n_variants, (kChunk / B) * B);
+  const DevRaster& ras = prep->ras;
   SG_TRY(dev_alloc(ctx, ctx->camp_sites, std::max<size_t>(1, (size_t)n_sites) * sizeof(sg_site)));
   SG_TRY(dev_alloc(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant)));
+  SG_TRY(dev_alloc(ctx, ctx->camp_vs, (size_t)chunk * sizeof(VariantState)));
+  SG_TRY(dev_alloc(ctx, ctx->camp_ovr, (size_t)chunk * kMaxTouch * sizeof(Rec)));
   if (n_sites)
     HIP_TRY(hipMemcpyAsync(ctx->camp_sites.p, sites, (size_t)n_sites * sizeof(sg_site), hipMemcpyHostToDevice, caller));
   HIP_TRY(hipMemcpyAsync(ctx->camp_vars.p, variants, (size_t)n_variants * sizeof(sg_variant), hipMemcpyHostToDevice,
                          caller));
   std::vector<Workspace*> ws(NS);
   for (int k = 0; k < NS; ++k) {
-    ws[k] = workspace(ctx, ctx->campaign_streams[k]);
-    if (!ws[k]) return fail(SG_E_NOMEM, "pinned allocation for a workspace failed");
-    SG_TRY(alloc_batch(ctx, ws[k], prep, B, ctx->campaign_streams[k]));
-    if (ws[k]->pend_B) return fail(SG_E_INVAL, "a campaign stream has an unreduced batch");
+    hipStream_t st = ctx->campaign_streams[k];
+    Workspace* W = workspace(ctx, st);
+    if (!W) return fail(SG_E_NOMEM, "pinned allocation for a workspace failed");
+    for (int q = 0; q < 3; ++q) {
+      SG_TRY(dev_alloc(ctx, W->st_items[q], (size_t)B * ras.n_tiles * sizeof(uint4)));
+      SG_TRY(dev_alloc(ctx, W->st_parts[q], (size_t)B * ras.n_tiles * sizeof(Partial)));
+      SG_TRY(dev_alloc(ctx, W->st_off[q], (size_t)(B + 1) * sizeof(uint32_t)));
+      SG_TRY(dev_alloc(ctx, W->st_n[q], (size_t)B * sizeof(uint32_t)));
+    }
+    if (!W->st_ctl.p) {
+      SG_TRY(dev_alloc(ctx, W->st_ctl, 3 * 4 * sizeof(uint32_t)));
+      launch_fill_u32(P<uint32_t>(W->st_ctl), 0u, 12, st);   // the arrival counters return to zero
+    }
+    ws[k] = W;
   }
-  hipEvent_t start = nullptr;
-  HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-  HIP_TRY(hipEventRecord(start, caller));
-  for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(ctx->campaign_streams[k], start, 0));
-  (void)hipEventDestroy(start);
-
   const sg_site* d_sites = P<sg_site>(ctx->camp_sites);
   const sg_variant* d_vars = P<sg_variant>(ctx->camp_vars);
+  VariantState* c_vs = P<VariantState>(ctx->camp_vs);
+  Rec* c_ovr = P<Rec>(ctx->camp_ovr);
   const DevScene& s = prep->scene;
   const CompArgs ca0 = item_comp_args(ws[0], prep, nullptr);
-  const int nb = (n_variants + B - 1) / B;
-  auto worker = [&](int t) {
-    (void)hipSetDevice(ctx->device);
-    for (int b = 0; b < nb; ++b) {
-      const int k = b % NS;
-      if (k % NT != t) continue;
-      Workspace* W = ws[k];
-      hipStream_t st = ctx->campaign_streams[k];
-      const int v0 = b * B, nv = std::min(B, n_variants - v0);
-      BatchBuffers bb = batch_buffers(W, prep, d_sites, d_vars + v0, nv);
-      bb.prev_parts = P<Partial>(W->bparts);
-      bb.prev_out = W->pend_out;
-      bb.prev_B = W->pend_B;
-      {
-        PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
-        launch_variant_prep(s, box, prep->cam, prep->ras, P<float4>(prep->r0), P<float4>(prep->r1),
-                            P<float4>(prep->r2), P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
-      }
-      CompArgs ca = ca0;
-      ca.parts = P<Partial>(W->bparts);
-      {
-        PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st);
-        launch_composite_items(ca, item_args(ctx, W, prep, nv), st);
-      }
-      W->pend_out = metrics_out + v0;
-      W->pend_B = nv;
+  const ItemArgs it0 = item_args(ctx, ws[0], prep, B);
+  StepArgs base{};
+  base.tiles_x = ras.tiles_x;
+  base.tiles_y = ras.tiles_y;
+  base.n_tiles = ras.n_tiles;
+  base.stop_key = prep->ck_group ? P<uint64_t>(prep->stop_key) : nullptr;
+  base.tile_start = P<uint32_t>(prep->tile_start);
+  base.tile_cnt = P<uint32_t>(prep->tile_cnt);
+  base.n_pixels = (uint32_t)(prep->cam.W * prep->cam.H);
+
+  for (int c0 = 0; c0 < n_variants; c0 += chunk) {
+    const int cn = std::min(chunk, n_variants - c0);
+    {
+      PassScope ps(ctx, SG_PASS_VARIANT_PREP, caller);
+      launch_campaign_touch(s, box, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
+                            P<uint32_t>(prep->depth), P<uint2>(prep->rect), d_sites, d_vars + c0, cn, c_vs, c_ovr,
+                            caller);
     }
-  };
-  std::vector<std::thread> pool;
-  for (int t = 1; t < NT; ++t) pool.emplace_back(worker, t);
-  worker(0);
-  for (std::thread& th : pool) th.join();
-  const uint32_t n_pixels = (uint32_t)(prep->cam.W * prep->cam.H);
-  for (int k = 0; k < NS; ++k) {
-    Workspace* W = ws[k];
-    hipStream_t st = ctx->campaign_streams[k];
-    if (W->pend_B) {
-      PassScope ps(ctx, SG_PASS_REDUCE, st);
-      launch_reduce_metrics(P<Partial>(W->bparts), P<uint32_t>(W->item_off), P<uint32_t>(W->n_items_v), 0,
-                            P<VariantState>(W->vs), nullptr, nullptr, n_pixels, W->pend_out, W->pend_B, 0u, st);
-      W->pend_B = 0;
-      W->pend_out = nullptr;
+    hipEvent_t staged = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(staged, caller));
+    for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(ctx->campaign_streams[k], staged, 0));
+    (void)hipEventDestroy(staged);
+    const int nb = (cn + B - 1) / B;
+    const int per_stream = (nb + NS - 1) / NS;   // batches of the first stream (the most)
+    auto worker = [&](int t) {
+      (void)hipSetDevice(ctx->device);
+      // launch i of every owned stream, then launch i + 1 ...
+      for (int i = 0; i < per_stream + 2; ++i)
+        for (int k = t; k < NS; k += NT) {
+          const int m = nb > k ? (nb - k + NS - 1) / NS : 0;   // batches k, k + NS, ... of the chunk
+          if (i > m + 1) continue;
+          Workspace* W = ws[k];
+          hipStream_t st = ctx->campaign_streams[k];
+          auto lb = [&](int pos) { return (pos * NS + k) * B; };   // first variant (in the chunk) of batch `pos`
+          auto nvb = [&](int pos) { return std::min(B, cn - lb(pos)); };
+          StepArgs a = base;
+          if (i < m) {
+            const int q = i % 3;
+            a.tB = nvb(i);
+            a.t_vs = c_vs + lb(i);
+            a.t_items = P<uint4>(W->st_items[q]);
+            a.t_n_items = P<uint32_t>(W->st_n[q]);
+            a.t_item_off = P<uint32_t>(W->st_off[q]);
+            a.t_counter = P<uint32_t>(W->st_ctl) + 4 * q;
+            a.t_arrive = P<uint32_t>(W->st_ctl) + 4 * q + 1;
+          }
+          a.A = ca0;
+          a.I = it0;
+          a.I.B = 0;
+          if (i >= 1 && i <= m) {
+            const int q = (i - 1) % 3;
+            a.A.parts = P<Partial>(W->st_parts[q]);
+            a.I.vs = c_vs + lb(i - 1);
+            a.I.ovr = c_ovr + (int64_t)lb(i - 1) * kMaxTouch;
+            a.I.items = P<uint4>(W->st_items[q]);
+            a.I.item_off = P<uint32_t>(W->st_off[q]);
+            a.I.counter = P<uint32_t>(W->st_ctl) + 4 * q;
+            a.I.B = nvb(i - 1);
+          }
+          if (i >= 2) {
+            const int q = (i - 2) % 3;
+            a.rB = nvb(i - 2);
+            a.r_parts = P<Partial>(W->st_parts[q]);
+            a.r_item_off = P<uint32_t>(W->st_off[q]);
+            a.r_n_items = P<uint32_t>(W->st_n[q]);
+            a.r_vs = c_vs + lb(i - 2);
+            a.r_out = metrics_out + c0 + lb(i - 2);
+          }
+          PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st);
+          launch_campaign_step(a, st);
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < NT; ++t) pool.emplace_back(worker, t);
+    worker(0);
+    for (std::thread& th : pool) th.join();
+    for (int k = 0; k < NS; ++k) {
+      hipEvent_t e = nullptr;
+      HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      HIP_TRY(hipEventRecord(e, ctx->campaign_streams[k]));
+      HIP_TRY(hipStreamWaitEvent(caller, e, 0));
+      (void)hipEventDestroy(e);
     }
-    hipEvent_t e = nullptr;
-    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(e, st));
-    HIP_TRY(hipStreamWaitEvent(caller, e, 0));
-    (void)hipEventDestroy(e);
   }
   HIP_TRY(hipEventRecord(ctx->camp_done, caller));
   return check_last("sg_campaign");

@@ -167,9 +167,6 @@ struct BatchBuffers {
   int B;
   VariantState* vs;
   Rec* ovr;                 // B * kMaxTouch override records
-  uint64_t* bitmap;         // B * bm_words dirty-tile bitmaps
-  int bm_words;             // words per variant bitmap
-  int row_words;            // words per tile row
   uint32_t* item_off;       // B + 1: first item of each variant, then the total
   uint32_t* n_items_v;      // B: work items (dirty tiles that can change) per variant
   // B x n_tiles work items: variant v's at [v * n_tiles, ...), each
@@ -181,18 +178,16 @@ struct BatchBuffers {
   const uint64_t* stop_key; // per tile of the prepared view (nullable): see CompArgs
   const uint32_t* tile_start;
   const uint32_t* tile_cnt;
-  // The previous batch of this workspace, whose metrics are still to be
-  // reduced (prev_B = 0: none): its item partials, per-variant item ranges
-  // (item_off, n_items_v) and states (vs) are read before this batch
-  // overwrites them.
-  const Partial* prev_parts;
-  sg_metrics_t* prev_out;
-  int prev_B;
-  uint32_t n_pixels;
 };
 void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                          const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
                          const uint2* rect, const BatchBuffers& bb, hipStream_t st);
+// Campaign pre-pass over n variants: states (touches, clamps, non-finite
+// flag) and override records (kMaxTouch per variant).
+void launch_campaign_touch(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
+                           const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
+                           const uint2* rect, const sg_site* sites, const sg_variant* variants, int n,
+                           VariantState* vs, Rec* ovr, hipStream_t st);
 
 // k_bin.hip
 struct BinBuffers {
@@ -262,5 +257,37 @@ struct ItemArgs {
   int B;
 };
 void launch_composite_items(const CompArgs& a, const ItemArgs& it, hipStream_t st);
+
+// One step of a pipelined campaign stream: the work items of batch j + 1,
+// the compositing of batch j and the metric reduction of batch j - 1, each
+// in workgroups of their own and on buffers of their own, so that nothing
+// in the launch waits for anything else in it.  A role with no batch has
+// B = 0.
+struct StepArgs {
+  // work items of the next batch: one workgroup (its first wave) per variant
+  int tB;
+  VariantState* t_vs;       // the batch's variant states (touches in, n_dirty and regions out)
+  uint4* t_items;           // tB x n_tiles
+  uint32_t* t_n_items;
+  uint32_t* t_item_off;
+  uint32_t* t_counter;
+  uint32_t* t_arrive;
+  int tiles_x, tiles_y, n_tiles;
+  const uint64_t* stop_key;
+  const uint32_t* tile_start;
+  const uint32_t* tile_cnt;
+  // metrics of the previous batch: one wave per variant
+  int rB;
+  const Partial* r_parts;
+  const uint32_t* r_item_off;
+  const uint32_t* r_n_items;
+  const VariantState* r_vs;
+  sg_metrics_t* r_out;
+  uint32_t n_pixels;
+  // compositing of the current batch (I.B = 0: none)
+  CompArgs A;
+  ItemArgs I;
+};
+void launch_campaign_step(const StepArgs& a, hipStream_t st);
 
 }  // namespace sg

@@ -56,11 +56,14 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
   sg_raster base = raster ? *raster : sg_raster{16, 0.99f, 1.0f / 255.0f, 1e-4f, 9.0f, 0.3f, {1.f, 1.f, 1.f}};
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
 
-  // single-site variants over the sample, a whole number of the largest batch
-  std::vector<sg_variant> vars(n_sites);
-  for (int i = 0; i < n_sites; ++i) vars[i] = {(uint32_t)i, 1u, 0u, 0u};
+  // single-site variants cycling over the sample: a timed campaign has at
+  // least 8 batches per stream (each stream's pipeline fills and drains once
+  // per campaign) and at least the whole sample
+  constexpr int kMaxVars = 1 << 17;
+  std::vector<sg_variant> vars(std::max(n_sites, kMaxVars));
+  for (size_t i = 0; i < vars.size(); ++i) vars[i] = {(uint32_t)(i % (size_t)n_sites), 1u, 0u, 0u};
   sg_metrics_t* met = nullptr;
-  if (hipMalloc(&met, (size_t)n_sites * sizeof(sg_metrics_t)) != hipSuccess)
+  if (hipMalloc(&met, vars.size() * sizeof(sg_metrics_t)) != hipSuccess)
     return sg_fail(SG_E_NOMEM, "hipMalloc of the tuning records failed");
 
   std::map<std::pair<int, int>, sg_prep*> preps;   // (tile, resume) -> prepared scene
@@ -90,8 +93,8 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
     s.graphs = c.graphs;
     sg_settings_set(ctx, s);
     sg_campaign_cfg cc{c.batch, c.streams, c.threads, 0};
-    const int nv = std::max(c.batch, (n_sites / c.batch) * c.batch);
-    const int use = std::min(nv, n_sites);
+    const int want = std::min(kMaxVars, std::max(n_sites, 8 * c.streams * c.batch));
+    const int use = std::max(c.batch, (want / c.batch) * c.batch);
     // one untimed campaign warms the workspaces; then campaigns are
     // timed until at least 40 ms (and two campaigns) have elapsed
     double total = 0.0;
