@@ -42,25 +42,33 @@ sys.path.insert(0, ROOT)
 N_HI = 134_826
 FLOPS_PER_EVAL = 20            # q-form and alpha test of one pixel-primitive evaluation
 FP32_PEAK_TFLOPS = 157.3       # MI355X fp32 vector peak
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "composite_items_w2hi_f32_b32_hbm_traffic.txt")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "campaign_step_w2hi_f32_b32_hbm_traffic.txt")
+# the sources the campaign step kernel is compiled from
+STEP_SOURCES = ("k_composite.hip", "sg_batch.h", "sg_device.h", "sg_kernels.h", "sg_types.h")
 DIRTY_BINS = [0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
 PAPER_CONTEXT = {"inj_per_s": 2515, "hardware": "Blackwell-generation GPU (model not named), B=32, resolution not stated",
                  "l40s_inj_per_s": 1522}
 
 
-def _measured_traffic():
-    """HBM bytes per compositing launch from the committed counter summary,
-    valid only while the compositing source is the one that was measured."""
+def step_sources_sha():
+    """sha256 over the campaign step kernel's sources, in STEP_SOURCES order."""
     import hashlib
+    h = hashlib.sha256()
+    for name in STEP_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2606_21791_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def _measured_traffic():
+    """HBM bytes per campaign step launch from the committed counter summary,
+    valid only while the kernel's sources are the ones that were measured."""
     try:
         txt = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
     vals = dict(line.strip().split(": ", 1) for line in txt.splitlines()
-                if line.strip().startswith(("traffic_bytes_per_launch:", "k_composite.hip sha256 at measurement:")))
-    src = os.path.join(ROOT, "paper_2606_21791_amd", "csrc", "k_composite.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if vals.get("k_composite.hip sha256 at measurement") != sha:
+                if line.strip().startswith(("traffic_bytes_per_launch:", "sources sha256 at measurement:")))
+    if vals.get("sources sha256 at measurement") != step_sources_sha():
         return None
     return int(vals["traffic_bytes_per_launch"])
 
@@ -155,8 +163,8 @@ def main():
                     help="use --tile/--streams/--threads/--wgs-per-cu/--resume/--graphs as given instead of the "
                          "autotuner's choice at the fixed --batch")
     ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--streams", type=int, default=16, help="HIP streams the batches rotate over")
-    ap.add_argument("--threads", type=int, default=4,
+    ap.add_argument("--streams", type=int, default=64, help="HIP streams the batches rotate over")
+    ap.add_argument("--threads", type=int, default=2,
                     help="host threads of the native campaign call (0: a Python loop of sg_render_batch calls)")
     ap.add_argument("--wgs-per-cu", type=int, default=2, help="persistent compositing workgroups per CU (0: default)")
     ap.add_argument("--grid", type=int, default=0,
@@ -283,7 +291,8 @@ def main():
     # dominant kernel: the persistent compositing launch
     comp_ms, comp_n = passes["composite_items"]
     comp_avg_s = comp_ms / max(comp_n, 1) / 1e3
-    evals_per_launch = float(recs["evals"].sum()) / args.steps
+    # a stream's pipeline has two launches more than batches: per launch over all of them
+    evals_per_launch = float(recs["evals"].sum()) / max(comp_n, 1)
     achieved = evals_per_launch * FLOPS_PER_EVAL / comp_avg_s / 1e12 if comp_avg_s > 0 else 0.0
 
     # the other storage formats at the same launch configuration
@@ -416,8 +425,8 @@ def main():
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                      "traffic": (_measured_traffic()
                                  if (args.fmt == "f32" and B == 32 and args.tile == 16 and args.resume == 32) else None),
-                     "aggregate_achieved": round(evals_per_launch * args.steps * FLOPS_PER_EVAL / elapsed / 1e12, 3),
-                     "kernel": "k_composite_items", "avg_launch_ms": round(comp_avg_s * 1e3, 4),
+                     "aggregate_achieved": round(float(recs["evals"].sum()) * FLOPS_PER_EVAL / elapsed / 1e12, 3),
+                     "kernel": "k_campaign_step", "avg_launch_ms": round(comp_avg_s * 1e3, 4),
                      "evals_per_launch": round(evals_per_launch), "flops_per_eval": FLOPS_PER_EVAL},
         "paper_context": PAPER_CONTEXT,
     }

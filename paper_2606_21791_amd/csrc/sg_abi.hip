@@ -1139,6 +1139,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* prep, const sg_site* s
             a.r_vs = c_vs + lb(i - 2);
             a.r_out = metrics_out + c0 + lb(i - 2);
           }
+          if (a.tB == 0 && a.I.B == 0 && a.rB == 0) continue;
           PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st);
           launch_campaign_step(a, st);
         }
