@@ -18,6 +18,8 @@
 // not walked at all; the others restart from the clean render's checkpoint at
 // the largest multiple of the checkpoint spacing not above m0, which holds the
 // exact (C, T) state after that many entries.
+#include <hip/hip_ext.h>
+
 #include "sg_batch.h"
 #include "sg_device.h"
 #include "sg_kernels.h"
@@ -509,14 +511,14 @@ __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_campaign_st
   items_role<TILE>(S.A, S.I);
 }
 
-void launch_campaign_step(const StepArgs& a, hipStream_t st) {
+void launch_campaign_step(const StepArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int bs = a.A.ras.tile * a.A.ras.tile;
   const int grid = a.tB + (a.rB + bs / 64 - 1) / (bs / 64) + (a.I.B > 0 ? a.I.grid : 0);
   if (grid <= 0) return;
   switch (a.A.ras.tile) {
-    case 8: k_campaign_step<8><<<grid, 64, 0, st>>>(a); break;
-    case 32: k_campaign_step<32><<<grid, 1024, 0, st>>>(a); break;
-    default: k_campaign_step<16><<<grid, 256, 0, st>>>(a); break;
+    case 8: hipExtLaunchKernelGGL(k_campaign_step<8>, dim3(grid), dim3(64), 0, st, e0, e1, 0, a); break;
+    case 32: hipExtLaunchKernelGGL(k_campaign_step<32>, dim3(grid), dim3(1024), 0, st, e0, e1, 0, a); break;
+    default: hipExtLaunchKernelGGL(k_campaign_step<16>, dim3(grid), dim3(256), 0, st, e0, e1, 0, a); break;
   }
 }
 

@@ -255,10 +255,13 @@ sg_status stage_batch(Workspace* w, const sg_site* sites, int n_sites, size_t si
 }
 
 // Records HIP events around the launches of one pass while timing is on.
+// With `at_kernel`, the events are instead handed to a single kernel launch
+// (a, b), which records them at that kernel's own start and end.
 struct PassScope {
   sg_ctx* c;
   int pass;
   hipStream_t st;
+  bool at_kernel = false;
   hipEvent_t a = nullptr, b = nullptr;
   static hipEvent_t get(sg_ctx* c) {
     std::lock_guard<std::mutex> g(c->mu);
@@ -271,15 +274,16 @@ struct PassScope {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
   }
-  PassScope(sg_ctx* c_, int pass_, hipStream_t st_) : c(c_), pass(pass_), st(st_) {
+  PassScope(sg_ctx* c_, int pass_, hipStream_t st_, bool at_kernel_ = false)
+      : c(c_), pass(pass_), st(st_), at_kernel(at_kernel_) {
     if (!c->timing) return;
     a = get(c);
     b = get(c);
-    if (a && b) (void)hipEventRecord(a, st);
+    if (a && b && !at_kernel) (void)hipEventRecord(a, st);
   }
   ~PassScope() {
     if (a && b) {
-      (void)hipEventRecord(b, st);
+      if (!at_kernel) (void)hipEventRecord(b, st);
       std::lock_guard<std::mutex> g(c->mu);
       c->pending[pass].push_back({a, b});
     }
@@ -1140,8 +1144,8 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* prep, const sg_site* s
             a.r_out = metrics_out + c0 + lb(i - 2);
           }
           if (a.tB == 0 && a.I.B == 0 && a.rB == 0) continue;
-          PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st);
-          launch_campaign_step(a, st);
+          PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st, true);
+          launch_campaign_step(a, st, ps.a, ps.b);
         }
     };
     std::vector<std::thread> pool;

@@ -288,6 +288,7 @@ struct StepArgs {
   CompArgs A;
   ItemArgs I;
 };
-void launch_campaign_step(const StepArgs& a, hipStream_t st);
+// e0, e1 (nullable): events recorded at the launch's own start and end.
+void launch_campaign_step(const StepArgs& a, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 }  // namespace sg

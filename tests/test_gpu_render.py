@@ -287,6 +287,37 @@ def test_campaign_matches_batches(ctx):
         ctx.campaign(prep, sa, bad, b.metrics_tensor(len(va)), box=box, batch=B)
 
 
+def test_campaign_across_prepass_chunks(ctx):
+    """A campaign longer than one pre-pass chunk (131,072 variants) gives the
+    same records as the same variants in two campaigns that each fit in one
+    chunk: the chunk offsets of the states, the batches and the records are
+    consistent, with a ragged last batch."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(1500, seed=41)
+    cam = synth.make_camera(48, 40)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam)
+    s = synth.make_sites_stratified(sc.n, 0, 64, seed=42, width_bits=32, fields=(0, 1, 2, 3, 4))
+    sa = b.sites_array(s.field, s.comp, s.prim, s.bit)
+    n = (1 << 17) + 1000 + 5
+    va = b.variants_array(np.arange(n) % len(sa), np.ones(n, np.uint32))
+    whole = b.metrics_tensor(n)
+    ctx.campaign(prep, sa, va, whole, batch=32, streams=8, threads=2)
+    cut = 70_000
+    first, second = b.metrics_tensor(cut), b.metrics_tensor(n - cut)
+    ctx.campaign(prep, sa, va[:cut], first, batch=32, streams=8, threads=2)
+    ctx.campaign(prep, sa, va[cut:], second, batch=32, streams=8, threads=2)
+    torch.cuda.synchronize()
+    got = b.read_metrics(whole)
+    ref = np.concatenate([b.read_metrics(first), b.read_metrics(second)])
+    for key in ref.dtype.names:
+        assert np.array_equal(got[key], ref[key]), key
+    # a variant's record depends only on its site
+    same = va["site_off"] == va["site_off"][0]
+    assert np.all(got["sse"][same] == got["sse"][0]) and same.sum() > 100
+
+
 def test_autotune_and_cache(ctx, tmp_path):
     """The autotuner returns a valid configuration, caches it (a second call
     is a hit and measures nothing), leaves the context's settings alone, and
