@@ -289,12 +289,13 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
  * When every variant is incremental (at most 8 distinct primitives), the
  * campaign copies sites and variants to device memory once, stages and
  * projects the corrupted primitives of up to 131,072 variants in one
- * pre-pass launch, and then enqueues one launch per batch on its stream:
- * launch i lists the work items of the stream's batch i, composites batch
- * i - 1 and reduces the metrics of batch i - 2 (two more launches per
- * stream drain the pipeline).  Campaigns on one context run one at a time
- * (a second call waits until the first one's device buffers are no longer
- * read). */
+ * pre-pass launch per view, and then enqueues one launch per batch on its
+ * stream: launch i lists the work items of the stream's batch i, composites
+ * batch i - 1 and reduces the metrics of batch i - 2 (two more launches per
+ * stream drain the pipeline).  With K views, the views of a chunk run one
+ * after the other and their records are then pooled.  Campaigns on one
+ * context run one at a time (a second call waits until the first one's
+ * device buffers are no longer read). */
 typedef struct {
   int32_t batch;     /* variants per launch; 0 = 32; at most SG_MAX_BATCH */
   int32_t streams;   /* device streams; 0 = 8 (at most 64) */

@@ -105,7 +105,7 @@ struct sg_ctx {
   // states and override records of a chunk of its variants; camp_done marks
   // the end of the campaign that last used them; camp_mu serialises
   // campaigns on one context
-  DevBuf camp_sites, camp_vars, camp_vs, camp_ovr;
+  DevBuf camp_sites, camp_vars, camp_vs, camp_ovr, camp_views;
   hipEvent_t camp_done = nullptr;
   std::mutex camp_mu;
   // guards ws, in_use and the timing state: sg_campaign enqueues from several
@@ -546,6 +546,7 @@ void sg_ctx_destroy(sg_ctx* c) {
   dev_free(c, c->camp_vars);
   dev_free(c, c->camp_vs);
   dev_free(c, c->camp_ovr);
+  dev_free(c, c->camp_views);
   if (c->camp_done) (void)hipEventDestroy(c->camp_done);
   for (int p = 0; p < SG_N_PASSES; ++p)
     for (auto& pr : c->pending[p]) c->ev_pool.insert(c->ev_pool.end(), {pr.first, pr.second});
@@ -1026,15 +1027,18 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
   return check_last("sg_render_batch_views");
 }
 
-// sg_campaign with one view and every variant incremental.  The campaign's
-// sites and variants are copied to the device once, and the corrupted
-// primitives of a chunk of variants are staged and projected by one
-// pre-pass launch.  Each stream then runs its batches as a pipeline of one
-// launch per batch: launch i lists the work items of the stream's batch i,
-// composites batch i - 1 and reduces the metrics of batch i - 2, on three
-// rotating buffer sets; two more launches drain it.  The records are those
-// of sg_render_batch on the same batches.
-static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites,
+// sg_campaign(_views) when every variant is incremental.  The campaign's
+// sites and variants are copied to the device once.  Per chunk of variants
+// and per view, the corrupted primitives are staged and projected by one
+// pre-pass launch, and each stream then runs its batches as a pipeline of
+// one launch per batch: launch i lists the work items of the stream's batch
+// i, composites batch i - 1 and reduces the metrics of batch i - 2, on three
+// rotating buffer sets; two more launches drain it.  With K > 1 views the
+// per-view records of the chunk are then pooled.  Views follow one another
+// on the device (the caller's stream joins every campaign stream before the
+// next pre-pass), with no host synchronisation.  The records are those of
+// sg_render_batch(_views) on the same batches.
+static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, const sg_site* sites, int32_t n_sites,
                                     const sg_variant* variants, int32_t n_variants, const DevBox& box, int B, int NS,
                                     int NT, sg_metrics_t* metrics_out, hipStream_t caller) {
   constexpr int kChunk = 1 << 17;   // variants staged per pre-pass
@@ -1042,11 +1046,13 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* prep, const sg_site* s
   if (ctx->camp_done) HIP_TRY(hipEventSynchronize(ctx->camp_done));   // the previous campaign's buffers are free
   else HIP_TRY(hipEventCreateWithFlags(&ctx->camp_done, hipEventDisableTiming));
   const int chunk = std::min(n_variants, (kChunk / B) * B);
-  const DevRaster& ras = prep->ras;
+  int max_tiles = 0;
+  for (int v = 0; v < K; ++v) max_tiles = std::max(max_tiles, preps[v]->ras.n_tiles);
   SG_TRY(dev_alloc(ctx, ctx->camp_sites, std::max<size_t>(1, (size_t)n_sites) * sizeof(sg_site)));
   SG_TRY(dev_alloc(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant)));
   SG_TRY(dev_alloc(ctx, ctx->camp_vs, (size_t)chunk * sizeof(VariantState)));
   SG_TRY(dev_alloc(ctx, ctx->camp_ovr, (size_t)chunk * kMaxTouch * sizeof(Rec)));
+  if (K > 1) SG_TRY(dev_alloc(ctx, ctx->camp_views, (size_t)K * chunk * sizeof(sg_metrics_t)));
   if (n_sites)
     HIP_TRY(hipMemcpyAsync(ctx->camp_sites.p, sites, (size_t)n_sites * sizeof(sg_site), hipMemcpyHostToDevice, caller));
   HIP_TRY(hipMemcpyAsync(ctx->camp_vars.p, variants, (size_t)n_variants * sizeof(sg_variant), hipMemcpyHostToDevice,
@@ -1057,8 +1063,8 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* prep, const sg_site* s
     Workspace* W = workspace(ctx, st);
     if (!W) return fail(SG_E_NOMEM, "pinned allocation for a workspace failed");
     for (int q = 0; q < 3; ++q) {
-      SG_TRY(dev_alloc(ctx, W->st_items[q], (size_t)B * ras.n_tiles * sizeof(uint4)));
-      SG_TRY(dev_alloc(ctx, W->st_parts[q], (size_t)B * ras.n_tiles * sizeof(Partial)));
+      SG_TRY(dev_alloc(ctx, W->st_items[q], (size_t)B * max_tiles * sizeof(uint4)));
+      SG_TRY(dev_alloc(ctx, W->st_parts[q], (size_t)B * max_tiles * sizeof(Partial)));
       SG_TRY(dev_alloc(ctx, W->st_off[q], (size_t)(B + 1) * sizeof(uint32_t)));
       SG_TRY(dev_alloc(ctx, W->st_n[q], (size_t)B * sizeof(uint32_t)));
     }
@@ -1072,93 +1078,100 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* prep, const sg_site* s
   const sg_variant* d_vars = P<sg_variant>(ctx->camp_vars);
   VariantState* c_vs = P<VariantState>(ctx->camp_vs);
   Rec* c_ovr = P<Rec>(ctx->camp_ovr);
-  const DevScene& s = prep->scene;
-  const CompArgs ca0 = item_comp_args(ws[0], prep, nullptr);
-  const ItemArgs it0 = item_args(ctx, ws[0], prep, B);
-  StepArgs base{};
-  base.tiles_x = ras.tiles_x;
-  base.tiles_y = ras.tiles_y;
-  base.n_tiles = ras.n_tiles;
-  base.stop_key = prep->ck_group ? P<uint64_t>(prep->stop_key) : nullptr;
-  base.tile_start = P<uint32_t>(prep->tile_start);
-  base.tile_cnt = P<uint32_t>(prep->tile_cnt);
-  base.n_pixels = (uint32_t)(prep->cam.W * prep->cam.H);
+  sg_metrics_t* per_view = P<sg_metrics_t>(ctx->camp_views);
 
   for (int c0 = 0; c0 < n_variants; c0 += chunk) {
     const int cn = std::min(chunk, n_variants - c0);
-    {
-      PassScope ps(ctx, SG_PASS_VARIANT_PREP, caller);
-      launch_campaign_touch(s, box, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
-                            P<uint32_t>(prep->depth), P<uint2>(prep->rect), d_sites, d_vars + c0, cn, c_vs, c_ovr,
-                            caller);
+    for (int view = 0; view < K; ++view) {
+      const sg_prep* prep = preps[view];
+      const DevRaster& ras = prep->ras;
+      const DevScene& s = prep->scene;
+      sg_metrics_t* out = K == 1 ? metrics_out + c0 : per_view + (int64_t)view * cn;
+      const CompArgs ca0 = item_comp_args(ws[0], prep, nullptr);
+      const ItemArgs it0 = item_args(ctx, ws[0], prep, B);
+      StepArgs base{};
+      base.tiles_x = ras.tiles_x;
+      base.tiles_y = ras.tiles_y;
+      base.n_tiles = ras.n_tiles;
+      base.stop_key = prep->ck_group ? P<uint64_t>(prep->stop_key) : nullptr;
+      base.tile_start = P<uint32_t>(prep->tile_start);
+      base.tile_cnt = P<uint32_t>(prep->tile_cnt);
+      base.n_pixels = (uint32_t)(prep->cam.W * prep->cam.H);
+      {
+        PassScope ps(ctx, SG_PASS_VARIANT_PREP, caller);
+        launch_campaign_touch(s, box, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
+                              P<uint32_t>(prep->depth), P<uint2>(prep->rect), d_sites, d_vars + c0, cn, c_vs, c_ovr,
+                              caller);
+      }
+      hipEvent_t staged = nullptr;
+      HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
+      HIP_TRY(hipEventRecord(staged, caller));
+      for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(ctx->campaign_streams[k], staged, 0));
+      (void)hipEventDestroy(staged);
+      const int nb = (cn + B - 1) / B;
+      const int per_stream = (nb + NS - 1) / NS;   // batches of the first stream (the most)
+      auto worker = [&](int t) {
+        (void)hipSetDevice(ctx->device);
+        // launch i of every owned stream, then launch i + 1 ...
+        for (int i = 0; i < per_stream + 2; ++i)
+          for (int k = t; k < NS; k += NT) {
+            const int m = nb > k ? (nb - k + NS - 1) / NS : 0;   // batches k, k + NS, ... of the chunk
+            if (i > m + 1) continue;
+            Workspace* W = ws[k];
+            hipStream_t st = ctx->campaign_streams[k];
+            auto lb = [&](int pos) { return (pos * NS + k) * B; };   // first variant (in the chunk) of batch `pos`
+            auto nvb = [&](int pos) { return std::min(B, cn - lb(pos)); };
+            StepArgs a = base;
+            if (i < m) {
+              const int q = i % 3;
+              a.tB = nvb(i);
+              a.t_vs = c_vs + lb(i);
+              a.t_items = P<uint4>(W->st_items[q]);
+              a.t_n_items = P<uint32_t>(W->st_n[q]);
+              a.t_item_off = P<uint32_t>(W->st_off[q]);
+              a.t_counter = P<uint32_t>(W->st_ctl) + 4 * q;
+              a.t_arrive = P<uint32_t>(W->st_ctl) + 4 * q + 1;
+            }
+            a.A = ca0;
+            a.I = it0;
+            a.I.B = 0;
+            if (i >= 1 && i <= m) {
+              const int q = (i - 1) % 3;
+              a.A.parts = P<Partial>(W->st_parts[q]);
+              a.I.vs = c_vs + lb(i - 1);
+              a.I.ovr = c_ovr + (int64_t)lb(i - 1) * kMaxTouch;
+              a.I.items = P<uint4>(W->st_items[q]);
+              a.I.item_off = P<uint32_t>(W->st_off[q]);
+              a.I.counter = P<uint32_t>(W->st_ctl) + 4 * q;
+              a.I.B = nvb(i - 1);
+            }
+            if (i >= 2) {
+              const int q = (i - 2) % 3;
+              a.rB = nvb(i - 2);
+              a.r_parts = P<Partial>(W->st_parts[q]);
+              a.r_item_off = P<uint32_t>(W->st_off[q]);
+              a.r_n_items = P<uint32_t>(W->st_n[q]);
+              a.r_vs = c_vs + lb(i - 2);
+              a.r_out = out + lb(i - 2);
+            }
+            if (a.tB == 0 && a.I.B == 0 && a.rB == 0) continue;
+            PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st, true);
+            launch_campaign_step(a, st, ps.a, ps.b);
+          }
+      };
+      std::vector<std::thread> pool;
+      for (int t = 1; t < NT; ++t) pool.emplace_back(worker, t);
+      worker(0);
+      for (std::thread& th : pool) th.join();
+      for (int k = 0; k < NS; ++k) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(e, ctx->campaign_streams[k]));
+        HIP_TRY(hipStreamWaitEvent(caller, e, 0));
+        (void)hipEventDestroy(e);
+      }
     }
-    hipEvent_t staged = nullptr;
-    HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(staged, caller));
-    for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(ctx->campaign_streams[k], staged, 0));
-    (void)hipEventDestroy(staged);
-    const int nb = (cn + B - 1) / B;
-    const int per_stream = (nb + NS - 1) / NS;   // batches of the first stream (the most)
-    auto worker = [&](int t) {
-      (void)hipSetDevice(ctx->device);
-      // launch i of every owned stream, then launch i + 1 ...
-      for (int i = 0; i < per_stream + 2; ++i)
-        for (int k = t; k < NS; k += NT) {
-          const int m = nb > k ? (nb - k + NS - 1) / NS : 0;   // batches k, k + NS, ... of the chunk
-          if (i > m + 1) continue;
-          Workspace* W = ws[k];
-          hipStream_t st = ctx->campaign_streams[k];
-          auto lb = [&](int pos) { return (pos * NS + k) * B; };   // first variant (in the chunk) of batch `pos`
-          auto nvb = [&](int pos) { return std::min(B, cn - lb(pos)); };
-          StepArgs a = base;
-          if (i < m) {
-            const int q = i % 3;
-            a.tB = nvb(i);
-            a.t_vs = c_vs + lb(i);
-            a.t_items = P<uint4>(W->st_items[q]);
-            a.t_n_items = P<uint32_t>(W->st_n[q]);
-            a.t_item_off = P<uint32_t>(W->st_off[q]);
-            a.t_counter = P<uint32_t>(W->st_ctl) + 4 * q;
-            a.t_arrive = P<uint32_t>(W->st_ctl) + 4 * q + 1;
-          }
-          a.A = ca0;
-          a.I = it0;
-          a.I.B = 0;
-          if (i >= 1 && i <= m) {
-            const int q = (i - 1) % 3;
-            a.A.parts = P<Partial>(W->st_parts[q]);
-            a.I.vs = c_vs + lb(i - 1);
-            a.I.ovr = c_ovr + (int64_t)lb(i - 1) * kMaxTouch;
-            a.I.items = P<uint4>(W->st_items[q]);
-            a.I.item_off = P<uint32_t>(W->st_off[q]);
-            a.I.counter = P<uint32_t>(W->st_ctl) + 4 * q;
-            a.I.B = nvb(i - 1);
-          }
-          if (i >= 2) {
-            const int q = (i - 2) % 3;
-            a.rB = nvb(i - 2);
-            a.r_parts = P<Partial>(W->st_parts[q]);
-            a.r_item_off = P<uint32_t>(W->st_off[q]);
-            a.r_n_items = P<uint32_t>(W->st_n[q]);
-            a.r_vs = c_vs + lb(i - 2);
-            a.r_out = metrics_out + c0 + lb(i - 2);
-          }
-          if (a.tB == 0 && a.I.B == 0 && a.rB == 0) continue;
-          PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st, true);
-          launch_campaign_step(a, st, ps.a, ps.b);
-        }
-    };
-    std::vector<std::thread> pool;
-    for (int t = 1; t < NT; ++t) pool.emplace_back(worker, t);
-    worker(0);
-    for (std::thread& th : pool) th.join();
-    for (int k = 0; k < NS; ++k) {
-      hipEvent_t e = nullptr;
-      HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      HIP_TRY(hipEventRecord(e, ctx->campaign_streams[k]));
-      HIP_TRY(hipStreamWaitEvent(caller, e, 0));
-      (void)hipEventDestroy(e);
-    }
+    if (K > 1) launch_pool_views(per_view, K, cn, metrics_out + c0, caller);
   }
   HIP_TRY(hipEventRecord(ctx->camp_done, caller));
   return check_last("sg_campaign");
@@ -1171,6 +1184,16 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
   if (K < 1 || K > kMaxViews) return fail(SG_E_INVAL, "K must be in [1, 64]");
   sg_prep* prep = preps[0];
   if (!prep) return fail(SG_E_INVAL, "preps[0] is NULL");
+  for (int k = 0; k < K; ++k) {
+    if (!preps[k]) return fail(SG_E_INVAL, "preps[" + std::to_string(k) + "] is NULL");
+    if (preps[k]->ctx != ctx && preps[k]->ctx->device != ctx->device)
+      return fail(SG_E_INVAL, "preps[" + std::to_string(k) + "] is on another device");
+    const sg_scene& a = prep->host_scene;
+    const sg_scene& c = preps[k]->host_scene;
+    bool same = a.n == c.n && a.sh_degree == c.sh_degree && a.dtype == c.dtype;
+    for (int f = 0; f < 6 && same; ++f) same = a.ptr[f] == c.ptr[f];
+    if (!same) return fail(SG_E_INVAL, "the views are not prepared from one scene");
+  }
   if (n_variants < 0 || (n_variants > 0 && !variants)) return fail(SG_E_INVAL, "bad variants");
   const int B = cfg && cfg->batch > 0 ? cfg->batch : 32;
   const int NS = cfg && cfg->streams > 0 ? cfg->streams : 8;
@@ -1193,7 +1216,7 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
   // the campaign's launches follow the caller's earlier work on `stream` and
   // the caller's later work follows all of them
   hipStream_t caller = S(stream);
-  if (K == 1) {
+  {
     // the pipelined path takes campaigns whose variants all stay incremental
     DevBox b;
     SG_TRY(to_dev_box(box, box_field_mask, prep->scene, &b));
@@ -1213,7 +1236,7 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
       }
     }
     if (incremental)
-      return campaign_pipelined(ctx, prep, sites, n_sites, variants, n_variants, b, B, NS, NT, metrics_out, caller);
+      return campaign_pipelined(ctx, preps, K, sites, n_sites, variants, n_variants, b, B, NS, NT, metrics_out, caller);
   }
   hipEvent_t start = nullptr;
   HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
