@@ -774,7 +774,7 @@ def run_views(args):
     for K in (1, 2, 4, 8, 16):
         cams = synth.make_orbit_cameras(K, 800, 800)
         preps = [ctx.prepare(ds, c, sgb.raster_struct(tile=args.tile)) for c in cams]
-        n = max(B, (n_inj // K) // B * B)
+        n = n_inj   # the same injections in every K (each stream's pipeline stays full)
         mt = sgb.metrics_tensor(n)
         kw = dict(batch=B, streams=args.streams, threads=max(1, args.threads))
         ctx.campaign(preps, sa, va[:4 * B], mt, **kw)
