@@ -287,6 +287,40 @@ def test_campaign_matches_batches(ctx):
         ctx.campaign(prep, sa, bad, b.metrics_tensor(len(va)), box=box, batch=B)
 
 
+@pytest.mark.parametrize("tile", [8, 32])
+def test_campaign_other_tile_sizes(ctx, tile):
+    """The pipelined campaign at 8 x 8 and 32 x 32 tiles (one and sixteen
+    waves per workgroup) gives the records of sg_render_batch at that tile
+    size, guarded variants and a ragged last batch included."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(3000, seed=44, sh_degree=1)
+    cam = synth.make_camera(150, 110)
+    lo32, hi32 = synth.make_box_jitter(sc, seed=5)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    box = b.Box.per_prim(ctx, lo32, hi32, "f32")
+    prep = ctx.prepare(ds, cam, b.raster_struct(tile=tile))
+    s = synth.make_sites_stratified(sc.n, 1, 12, seed=45, width_bits=32)
+    sa = b.sites_array(s.field, s.comp, s.prim, s.bit)
+    n = len(sa)
+    va = b.variants_array(np.arange(n), np.ones(n, np.uint32))
+    va["guard"] = np.arange(n) % 2
+    B = 10   # 72 variants: a last batch of 2
+    ref = []
+    for v0 in range(0, n, B):
+        mt = b.metrics_tensor(len(va[v0:v0 + B]))
+        ctx.render_batch(prep, sa, va[v0:v0 + B], box=box, metrics=mt)
+        ref.append(b.read_metrics(mt))
+    ref = np.concatenate(ref)
+    got = b.metrics_tensor(n)
+    ctx.campaign(prep, sa, va, got, box=box, batch=B, streams=3, threads=2)
+    torch.cuda.synchronize()
+    G = b.read_metrics(got)
+    for key in ref.dtype.names:
+        assert np.array_equal(G[key], ref[key]), (tile, key)
+    assert G["dirty_tiles"].max() > 1 and np.all(G["path"] == 0)
+
+
 def test_campaign_across_prepass_chunks(ctx):
     """A campaign longer than one pre-pass chunk (131,072 variants) gives the
     same records as the same variants in two campaigns that each fit in one
