@@ -86,8 +86,17 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
   }
   uint32_t evals = done ? 0u : mlen - start;   // list entries this pixel evaluates
   uint32_t next_ck = A.ck_group;               // kFullWrite: next checkpoint index
+  __shared__ uint32_t s_all[NW];         // per wave: every pixel of the wave has stopped
   for (uint32_t base = start; base < mlen; base += BS) {
-    if (__syncthreads_and(done)) break;
+    // leave once every pixel has stopped (the slots are rewritten only after
+    // the two barriers of the compaction below)
+    const bool wave_done = __all(done);   // a vote of all 64 lanes, taken outside the lane-0 branch
+    if (lane == 0) s_all[wave] = wave_done ? 1u : 0u;
+    __syncthreads();
+    bool all_done = true;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) all_done &= s_all[w] != 0u;
+    if (all_done) break;
     const uint32_t m = base + tid;
     uint32_t mask = 0;                   // target waves whose block this entry may reach
     if (m < mlen) {
@@ -311,27 +320,43 @@ __device__ __forceinline__ void items_role(const CompArgs& A, const ItemArgs& I)
       v = (uint32_t)__builtin_amdgcn_readfirstlane(lo);
     }
     const uint32_t first = __builtin_amdgcn_readfirstlane(off[v]);
+    // The prologue's loads are all issued before any of them is waited for:
+    // branch-free, from clamped addresses, with a lane that has nothing to
+    // read reading the variant's state instead and dropping the value.  First
+    // the variant state and the item record, then the pixel's stop index and
+    // clean colour and the clean list.
+    constexpr int VPT = (VSW + BS - 1) / BS;   // variant-state words per thread
+    const uint32_t* vsrc = reinterpret_cast<const uint32_t*>(I.vs + v);
+    uint32_t vw[VPT];
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) vw[k] = vsrc[min(tid + k * BS, VSW - 1)];
     const uint4 ent = I.items[(int64_t)v * A.ras.n_tiles + (item - first)];
-    for (int k = tid; k < VSW; k += BS) s_vs[k] = reinterpret_cast<const uint32_t*>(I.vs + v)[k];
     const int tile = (int)ent.x;
     const uint32_t raw_start = ent.y, L = ent.z;
     const int tx = tile % A.ras.tiles_x, ty = tile / A.ras.tiles_x;
     const int x = tx * TILE + pxo, y = ty * TILE + pyo;
-    uint32_t sp = 0;
-    float cl0 = 0.f, cl1 = 0.f, cl2 = 0.f;
-    if (x < A.W && y < A.H) {
-      const int64_t p = (int64_t)y * A.W + x;
-      if (A.stop) sp = A.stop[p];
-      if (A.clean) { cl0 = A.clean[3 * p]; cl1 = A.clean[3 * p + 1]; cl2 = A.clean[3 * p + 2]; }
-    }
+    const bool inside = x < A.W && y < A.H;
+    const int64_t p = (int64_t)min(y, A.H - 1) * A.W + min(x, A.W - 1);
+    const uint32_t sp_w = *(A.stop ? A.stop + p : vsrc);
+    const float* csrc = A.clean ? A.clean + 3 * p : reinterpret_cast<const float*>(vsrc);
+    const float cw0 = csrc[0], cw1 = csrc[1], cw2 = csrc[2];
     const bool staged = L <= (uint32_t)KCAP;
     const uint64_t* keys = A.keys + raw_start;
     uint64_t kr[KPT];
 #pragma unroll
     for (int k = 0; k < KPT; ++k) {
       const uint32_t m = (uint32_t)(tid + k * BS);
-      kr[k] = staged && m < L ? keys[m] : ~0ull;   // padding compares above every key
+      const bool have = staged && m < L;
+      const uint64_t kv = *(have ? keys + m : reinterpret_cast<const uint64_t*>(vsrc));
+      kr[k] = have ? kv : ~0ull;   // padding compares above every key
     }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k)
+      if (tid + k * BS < VSW) s_vs[tid + k * BS] = vw[k];
+    const bool use_px = inside && A.stop;
+    const uint32_t sp = use_px ? sp_w : 0u;
+    const bool use_cl = inside && A.clean;
+    const float cl0 = use_cl ? cw0 : 0.f, cl1 = use_cl ? cw1 : 0.f, cl2 = use_cl ? cw2 : 0.f;
     if (tid < NT) { s_cnt[tid] = 0; s_fnd[tid] = 0; s_bkt[tid] = 0; }
     __syncthreads();
     if (tid == 0) {

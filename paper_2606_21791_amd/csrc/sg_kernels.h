@@ -11,7 +11,9 @@ namespace sg {
 // Block-wide reduction of a metric partial in a fixed order (wave butterflies,
 // then waves in index order), so the result does not depend on scheduling.
 // Every thread of the block must call it; thread 0 writes *out and gets the
-// changed-pixel total as the return value (0 elsewhere).
+// changed-pixel total as the return value (0 elsewhere).  It holds one
+// barrier: two calls by one workgroup must be separated by another barrier
+// (the per-wave slots are reused), which every caller's control flow has.
 __device__ __forceinline__ uint32_t block_reduce_partial(double sse, uint32_t changed, float mx, uint32_t nonfin,
                                                          unsigned long long evals, Partial* out) {
   for (int o = 32; o > 0; o >>= 1) {
@@ -26,22 +28,18 @@ __device__ __forceinline__ uint32_t block_reduce_partial(double sse, uint32_t ch
   __shared__ uint32_t s_ch[16], s_nf[16];
   __shared__ float s_mx[16];
   const int w = threadIdx.x >> 6;
-  __syncthreads();
   if ((threadIdx.x & 63) == 0) { s_sse[w] = sse; s_ch[w] = changed; s_mx[w] = mx; s_nf[w] = nonfin; s_ev[w] = evals; }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    Partial p;
-    p.sse = 0.0; p.evals = 0; p.changed = 0; p.max_abs = 0.f; p.nonfinite = 0; p._pad = 0;
-    for (int i = 0; i < nw; ++i) {
-      p.sse += s_sse[i]; p.changed += s_ch[i]; p.max_abs = fmaxf(p.max_abs, s_mx[i]); p.nonfinite |= s_nf[i];
-      p.evals += s_ev[i];
-    }
-    *out = p;
-    changed = p.changed;
+  if (threadIdx.x != 0) return 0u;
+  const int nw = (blockDim.x + 63) >> 6;
+  Partial p;
+  p.sse = 0.0; p.evals = 0; p.changed = 0; p.max_abs = 0.f; p.nonfinite = 0; p._pad = 0;
+  for (int i = 0; i < nw; ++i) {
+    p.sse += s_sse[i]; p.changed += s_ch[i]; p.max_abs = fmaxf(p.max_abs, s_mx[i]); p.nonfinite |= s_nf[i];
+    p.evals += s_ev[i];
   }
-  __syncthreads();
-  return threadIdx.x == 0 ? changed : 0u;
+  *out = p;
+  return p.changed;
 }
 
 // One wave's sum of the partials parts[off .. off + n) in a fixed order (lane
