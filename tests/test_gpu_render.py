@@ -272,7 +272,12 @@ def test_campaign_matches_batches(ctx):
         return np.concatenate(ref)
 
     ref = batches(va)
-    for vs, r in ((va, ref), (va[:-1], ref[:-1]), (va[:5], ref[:5])):
+    # a variant without sites renders the clean frame
+    empty = b.variants_array(np.array([0]), np.array([0]), 0)
+    va_e = np.concatenate([va[:-1], empty])
+    ref_e = batches(va_e)
+    assert ref_e["sse"][-1] == 0 and ref_e["dirty_tiles"][-1] == 0
+    for vs, r in ((va, ref), (va[:-1], ref[:-1]), (va[:5], ref[:5]), (va_e, ref_e)):
         for streams, threads in ((1, 1), (4, 2), (5, 3)):
             mt = b.metrics_tensor(len(vs))
             ctx.campaign(prep, sa, vs, mt, box=box, batch=B, streams=streams, threads=threads)
