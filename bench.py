@@ -260,22 +260,24 @@ def main():
 
     run_steps(0, args.warmup)
     torch.cuda.synchronize()
-    # the K timed steps as REPS equal campaigns, each bracketed by a
-    # synchronisation (the spread of their rates is reported beside the total)
-    REPS = 5
-    bounds = [args.warmup + (args.steps * r) // REPS for r in range(REPS + 1)]
-    rep_dt = []
+    # the K timed steps: one campaign, bracketed by synchronisations
     with _no_gc():
         t_start = time.perf_counter()
-        for r in range(REPS):
-            t0 = time.perf_counter()
-            run_steps(bounds[r], bounds[r + 1])
-            torch.cuda.synchronize()
-            rep_dt.append(time.perf_counter() - t0)
+        run_steps(args.warmup, steps_total)
+        torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
     recs = sgb.read_metrics(mt_all)[w_end:]
     inj_per_s = args.steps * B / elapsed
-    rep_rates = np.array([(bounds[r + 1] - bounds[r]) * B / rep_dt[r] for r in range(REPS)])
+    # the same campaign REPS more times, for the spread of the rate
+    REPS = 3
+    rep_rates = []
+    for r in range(REPS):
+        with _no_gc():
+            t0 = time.perf_counter()
+            run_steps(args.warmup, steps_total)
+            torch.cuda.synchronize()
+            rep_rates.append(args.steps * B / (time.perf_counter() - t0))
+    rep_rates = np.array(rep_rates)
 
     # the same steps again with per-pass HIP events (graphs are not used while
     # timing), for the per-pass breakdown and the compositing launch duration

@@ -209,20 +209,101 @@ __global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, Dev
 }
 
 // Campaign pre-pass: the staged corrupted primitives of every variant of a
-// campaign chunk at once (one 64-thread workgroup per variant), written to
-// the campaign's per-variant states and override records.
+// campaign chunk at once, one thread per variant, written to the campaign's
+// per-variant states and override records.  The steps are those of
+// stage_touches, in its order: the first kMaxTouch distinct primitives of
+// the variant's sites (more: st.full and none staged), each primitive's
+// stored words with the variant's sites XORed in and the guard clamp
+// applied, its projection, and the comparison with its clean record.
 template <int DEG>
 __global__ void __launch_bounds__(64) k_campaign_touch(DevScene s, DevBox box, DevCam cam, DevRaster ras,
                                                        const float4* __restrict__ r0, const float4* __restrict__ r1,
                                                        const float4* __restrict__ r2,
                                                        const uint32_t* __restrict__ depth,
                                                        const uint2* __restrict__ rect, const sg_site* sites,
-                                                       const sg_variant* variants, VariantState* vs, Rec* ovr) {
-  const int64_t g = blockIdx.x;
-  __shared__ VariantState st;
+                                                       const sg_variant* variants, int n, VariantState* vs, Rec* ovr) {
+  using L = Layout<DEG>;
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= n) return;
   const sg_variant var = variants[g];
-  stage_touches<DEG>(s, box, cam, ras, r0, r1, r2, depth, rect, var, sites, st, ovr + g * kMaxTouch);
-  if (threadIdx.x == 0) vs[g] = st;
+  const sg_site* vsites = sites + var.site_off;
+  const bool guard = var.guard != 0 && box.mask != 0;
+  uint32_t prims[kMaxTouch];
+  uint32_t n_touch = 0, full = 0;
+  for (uint32_t k = 0; k < var.n_sites; ++k) {
+    const uint32_t p = vsites[k].prim;
+    bool seen = false;
+    for (uint32_t j = 0; j < n_touch; ++j) seen |= prims[j] == p;
+    if (!seen) {
+      if (n_touch == kMaxTouch) { full = 1; break; }
+      prims[n_touch++] = p;
+    }
+  }
+  if (full) n_touch = 0;
+  VariantState* out = vs + g;
+  unsigned long long clamps = 0;
+  uint32_t nonfinite = 0;
+  for (uint32_t j = 0; j < n_touch; ++j) {
+    const uint32_t p = prims[j];
+    uint32_t w[L::kWords];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int C = f < 5 ? (f == 2 ? 4 : (f == 3 ? 1 : 3)) : L::kRest;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        uint32_t x = load_word(s, f, p, c);
+        for (uint32_t k = 0; k < var.n_sites; ++k) {
+          const sg_site t = vsites[k];
+          if (t.prim == p && t.field == f && t.comp == c && !site_corrected(var.protect, t.bit, s.dtype))
+            x ^= 1u << t.bit;
+        }
+        if (guard && ((box.mask >> f) & 1u)) {
+          uint32_t lo, hi;
+          bool cl;
+          box_words(box, f, p, c, s.n, &lo, &hi);
+          x = clamp_word(x, lo, hi, s.dtype, &cl);
+          clamps += cl ? 1ull : 0ull;
+        }
+        w[L::off(f) + c] = x;
+      }
+    }
+    auto get = [&](int f, int c) -> uint32_t { return w[L::off(f) + c]; };
+    const ProjOut o = project_prim<DEG>(get, s.dtype, cam, ras);
+    nonfinite |= o.nonfinite ? 1u : 0u;
+    const uint2 orc = rect[p];
+    const bool old_vis = orc.x != 0xffffffffu;
+    Touch t;
+    t.prim = p;
+    t.old_depth = depth[p];
+    t.old_rect0 = orc.x;
+    t.old_rect1 = orc.y;
+    t.new_depth = o.depth;
+    t.new_rect0 = o.rect0;
+    t.new_rect1 = o.rect1;
+    bool same = old_vis == o.visible;
+    if (same && old_vis) {
+      const float4 a0 = r0[p], a1 = r1[p], a2 = r2[p];
+      same = t.old_depth == t.new_depth && orc.x == o.rect0 && orc.y == o.rect1 &&
+             __float_as_uint(a0.x) == __float_as_uint(o.rec.r0.x) && __float_as_uint(a0.y) == __float_as_uint(o.rec.r0.y) &&
+             __float_as_uint(a0.z) == __float_as_uint(o.rec.r0.z) && __float_as_uint(a0.w) == __float_as_uint(o.rec.r0.w) &&
+             __float_as_uint(a1.x) == __float_as_uint(o.rec.r1.x) && __float_as_uint(a1.y) == __float_as_uint(o.rec.r1.y) &&
+             __float_as_uint(a1.z) == __float_as_uint(o.rec.r1.z) && __float_as_uint(a1.w) == __float_as_uint(o.rec.r1.w) &&
+             __float_as_uint(a2.x) == __float_as_uint(o.rec.r2.x) && __float_as_uint(a2.y) == __float_as_uint(o.rec.r2.y) &&
+             __float_as_uint(a2.z) == __float_as_uint(o.rec.r2.z) && __float_as_uint(a2.w) == __float_as_uint(o.rec.r2.w);
+    }
+    t.flags = (old_vis ? 1u : 0u) | (o.visible ? 2u : 0u) | (same ? 4u : 0u);
+    out->touch[j] = t;
+    ovr[g * kMaxTouch + j] = o.rec;
+  }
+  out->n_touch = n_touch;
+  out->full = full;
+  out->nonfinite = nonfinite;
+  out->n_dirty = 0;
+  out->clamps = clamps;
+  out->_pad0 = 0;
+  out->_pad = 0;
+  out->pred_regions = 0;
+  out->rend_regions = 0;
 }
 
 void launch_project(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
@@ -262,11 +343,12 @@ void launch_campaign_touch(const DevScene& s, const DevBox& box, const DevCam& c
                            const uint2* rect, const sg_site* sites, const sg_variant* variants, int n,
                            VariantState* vs, Rec* ovr, hipStream_t st) {
   if (n <= 0) return;
+  const int grid = (n + 63) / 64;
   switch (s.sh_degree) {
-    case 0: k_campaign_touch<0><<<n, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, vs, ovr); break;
-    case 1: k_campaign_touch<1><<<n, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, vs, ovr); break;
-    case 2: k_campaign_touch<2><<<n, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, vs, ovr); break;
-    default: k_campaign_touch<3><<<n, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, vs, ovr); break;
+    case 0: k_campaign_touch<0><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr); break;
+    case 1: k_campaign_touch<1><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr); break;
+    case 2: k_campaign_touch<2><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr); break;
+    default: k_campaign_touch<3><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr); break;
   }
 }
 
