@@ -621,6 +621,37 @@ def test_w2_hi_sampled_pixels(ctx, fmt):
         assert np.mean(err <= PIXEL_TOL) >= 0.98, (k, np.sort(err)[-5:])
 
 
+def test_w2_hi_campaign_matches_batches(ctx):
+    """Full W2 size (N = 134,826, SH degree 3, fp32, 800 x 800) in the launch
+    configuration of the headline (B = 32, 64 streams, 2 host threads, the
+    campaign pipeline): every record equals sg_render_batch's on the same
+    batches, whose frames the sampled-pixel test above checks against the
+    oracle."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(134_826, seed=3, sh_degree=3)
+    cam = synth.make_camera(800, 800)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam)
+    s = synth.make_sites_stratified(sc.n, 3, 64, seed=46, width_bits=32)
+    sa = b.sites_array(s.field, s.comp, s.prim, s.bit)
+    n = len(sa)
+    va = b.variants_array(np.arange(n), np.ones(n, np.uint32))
+    ref = []
+    for v0 in range(0, n, 32):
+        mt = b.metrics_tensor(len(va[v0:v0 + 32]))
+        ctx.render_batch(prep, sa, va[v0:v0 + 32], metrics=mt)
+        ref.append(b.read_metrics(mt))
+    ref = np.concatenate(ref)
+    got = b.metrics_tensor(n)
+    ctx.campaign(prep, sa, va, got, batch=32, streams=64, threads=2)
+    torch.cuda.synchronize()
+    G = b.read_metrics(got)
+    for key in ref.dtype.names:
+        assert np.array_equal(G[key], ref[key]), key
+    assert np.any(G["dirty_tiles"] > 0) and np.any(G["changed_px"] > 0)
+
+
 def test_graph_replay_matches_eager(ctx):
     """The captured incremental batch, replayed several times with eager work
     and synchronisations in between, gives exactly the eager records."""
