@@ -18,6 +18,11 @@
 // not walked at all; the others restart from the clean render's checkpoint at
 // the largest multiple of the checkpoint spacing not above m0, which holds the
 // exact (C, T) state after that many entries.
+//
+// k_campaign_step holds, in one launch, the three stages of a campaign
+// stream's pipeline on separate buffers: the work items of its next batch,
+// the persistent compositing of its current batch and the metric reduction
+// of its previous batch.
 #include <hip/hip_ext.h>
 
 #include "sg_batch.h"
