@@ -222,18 +222,23 @@ __device__ __forceinline__ ProjOut project_prim(Get get, int dtype, const DevCam
   for (int k = 0; k < 3; ++k) { s[k] = exp(ls[k]); if (!in_range(s[k])) return o; }
   const double qa = fmax(fmax(fabs(qv[0]), fabs(qv[1])), fmax(fabs(qv[2]), fabs(qv[3])));
   if (!(qa > 0.0)) return o;
-  double qw = qv[0] / qa, qx = qv[1] / qa, qy = qv[2] / qa, qz = qv[3] / qa;
+  // reciprocals are taken once and multiplied (fp64 keeps the products within
+  // a few units of the last place, far below the fp32 record's rounding)
+  const double iqa = 1.0 / qa;
+  double qw = qv[0] * iqa, qx = qv[1] * iqa, qy = qv[2] * iqa, qz = qv[3] * iqa;
   const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-  qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+  const double iqn = 1.0 / qn;
+  qw *= iqn; qx *= iqn; qy *= iqn; qz *= iqn;
   const double Rq[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy),
                         2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
                         2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
 
   // EWA: Jacobian with the tangent clamp
-  const double tx = fmin(cam.limx, fmax(-cam.limx, px / pz)) * pz;
-  const double ty = fmin(cam.limy, fmax(-cam.limy, py / pz)) * pz;
-  const double J00 = cam.fx / pz, J02 = -cam.fx * tx / (pz * pz);
-  const double J11 = cam.fy / pz, J12 = -cam.fy * ty / (pz * pz);
+  const double ipz = 1.0 / pz;
+  const double tx = fmin(cam.limx, fmax(-cam.limx, px * ipz)) * pz;
+  const double ty = fmin(cam.limy, fmax(-cam.limy, py * ipz)) * pz;
+  const double J00 = cam.fx * ipz, J02 = -cam.fx * tx * ipz * ipz;
+  const double J11 = cam.fy * ipz, J12 = -cam.fy * ty * ipz * ipz;
   // U = R * Rq (world-to-camera rotation of the principal axes)
   double U[9];
 #pragma unroll
@@ -258,7 +263,9 @@ __device__ __forceinline__ ProjOut project_prim(Get get, int dtype, const DevCam
   a += ras.dil; c += ras.dil;
   if (!in_range(a) || !in_range(b) || !in_range(c)) return o;
   const double hd = 0.5 * (a - c);
-  const double h = hypot(hd, b);
+  // a, b and c are within the fp32 range here, so the squares cannot leave
+  // the fp64 range and no scaled hypot is needed
+  const double h = sqrt(hd * hd + b * b);
   const double lam1 = 0.5 * a + 0.5 * c + h;
   if (!in_range(lam1)) return o;
   // det(Sigma') = det A + dil tr A + dil^2 with det A by Cauchy-Binet: the 2x2
@@ -273,17 +280,17 @@ __device__ __forceinline__ ProjOut project_prim(Get get, int dtype, const DevCam
   // unit major axis without cancellation
   double e0, e1;
   if (hd >= 0.0) { e0 = hd + h; e1 = b; } else { e0 = b; e1 = -hd + h; }
-  const double en = hypot(e0, e1);
-  if (en > 0.0) { e0 /= en; e1 /= en; } else { e0 = 1.0; e1 = 0.0; }
+  const double en = sqrt(e0 * e0 + e1 * e1);
+  if (en > 0.0) { const double ien = 1.0 / en; e0 *= ien; e1 *= ien; } else { e0 = 1.0; e1 = 0.0; }
 
-  const double u = cam.fx * px / pz + cam.cx;
-  const double v = cam.fy * py / pz + cam.cy;
+  const double u = cam.fx * px * ipz + cam.cx;
+  const double v = cam.fy * py * ipz + cam.cy;
   if (!in_range(u) || !in_range(v)) return o;
 
   // colour along the viewing direction
   double dx = mu[0] - cam.campos[0], dy = mu[1] - cam.campos[1], dz = mu[2] - cam.campos[2];
   const double dn = sqrt(dx * dx + dy * dy + dz * dz);
-  if (dn > 0.0) { dx /= dn; dy /= dn; dz /= dn; }
+  if (dn > 0.0) { const double idn = 1.0 / dn; dx *= idn; dy *= idn; dz *= idn; }
   double Y[16];
   sh_basis(dx, dy, dz, sh_degree, Y);
   double col[3] = {Y[0] * dc[0], Y[0] * dc[1], Y[0] * dc[2]};
@@ -311,8 +318,9 @@ __device__ __forceinline__ ProjOut project_prim(Get get, int dtype, const DevCam
   const double xlo = floor(u - hx - 0.5), xhi = ceil(u + hx - 0.5);
   const double ylo = floor(v - hy - 0.5), yhi = ceil(v + hy - 0.5);
   if (xhi < 0.0 || yhi < 0.0 || xlo > (double)(cam.W - 1) || ylo > (double)(cam.H - 1)) return o;
-  const int tx0 = (int)fmax(0.0, floor(xlo / ras.tile)), tx1 = (int)fmin((double)(ras.tiles_x - 1), floor(xhi / ras.tile));
-  const int ty0 = (int)fmax(0.0, floor(ylo / ras.tile)), ty1 = (int)fmin((double)(ras.tiles_y - 1), floor(yhi / ras.tile));
+  const double itile = 1.0 / (double)ras.tile;   // exact: the tile size is a power of two
+  const int tx0 = (int)fmax(0.0, floor(xlo * itile)), tx1 = (int)fmin((double)(ras.tiles_x - 1), floor(xhi * itile));
+  const int ty0 = (int)fmax(0.0, floor(ylo * itile)), ty1 = (int)fmin((double)(ras.tiles_y - 1), floor(yhi * itile));
   if (tx1 < tx0 || ty1 < ty0) return o;
 
   const float cf = (float)e0, sf = (float)e1;
