@@ -499,18 +499,18 @@ __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_composite_i
   items_role<TILE>(A, I);
 }
 
-// The work items of variant v of a campaign's next batch (first wave only).
-__device__ __forceinline__ void tiles_role(const StepArgs& S, int v) {
+// The work items of variant v of a campaign's next batch, by the calling
+// wave alone (slot: its LDS copy of the variant's state).
+__device__ __forceinline__ void tiles_role(const StepArgs& S, int v, VariantState& slot) {
   constexpr int VSW = (int)(sizeof(VariantState) / sizeof(uint32_t));
-  __shared__ VariantState s_tv;
   const int lane = threadIdx.x & 63;
   const uint32_t* src = reinterpret_cast<const uint32_t*>(S.t_vs + v);
-  uint32_t* dst = reinterpret_cast<uint32_t*>(&s_tv);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&slot);
   for (int k = lane; k < VSW; k += 64) dst[k] = src[k];
   wave_sync();
   uint32_t nd, ni;
   uint64_t pred;
-  enumerate_items(s_tv.touch, s_tv.n_touch, S.tiles_x, S.tiles_y, S.stop_key, S.tile_start, S.tile_cnt,
+  enumerate_items(slot.touch, slot.n_touch, S.tiles_x, S.tiles_y, S.stop_key, S.tile_start, S.tile_cnt,
                   S.t_items + (int64_t)v * S.n_tiles, &nd, &ni, &pred);
   if (lane == 0) {
     S.t_vs[v].n_dirty = nd;
@@ -520,21 +520,23 @@ __device__ __forceinline__ void tiles_role(const StepArgs& S, int v) {
   finish_batch(S.t_arrive, (uint32_t)S.tB, S.t_n_items, S.t_item_off, S.tB, S.t_counter);
 }
 
-// Workgroups [0, tB): work items of the next batch, one variant each (its
-// other waves leave at once); then ceil(rB / waves) workgroups reducing the
-// previous batch's metrics, a variant per wave; then the persistent
-// compositing of the current batch.
+// Workgroups [0, ceil(tB / waves)): work items of the next batch, a variant
+// per wave; then ceil(rB / waves) workgroups reducing the previous batch's
+// metrics, a variant per wave; then the persistent compositing of the
+// current batch.  The waves of the first two roles work alone (no barrier).
 template <int TILE>
 __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_campaign_step(StepArgs S) {
   constexpr int NW = TILE * TILE / 64;
-  const int nt = S.tB, nr = (S.rB + NW - 1) / NW;
-  const int b = blockIdx.x;
+  const int nt = (S.tB + NW - 1) / NW, nr = (S.rB + NW - 1) / NW;
+  const int b = blockIdx.x, wave = (int)(threadIdx.x >> 6);
   if (b < nt) {
-    if (threadIdx.x < 64) tiles_role(S, b);
+    __shared__ VariantState s_tv[NW];
+    const int v = b * NW + wave;
+    if (v < S.tB) tiles_role(S, v, s_tv[wave]);
     return;
   }
   if (b < nt + nr) {
-    const int v = (b - nt) * NW + (int)(threadIdx.x >> 6);
+    const int v = (b - nt) * NW + wave;
     if (v < S.rB) reduce_batch_variant(S.r_parts, S.r_item_off, S.r_n_items, S.r_vs, S.n_pixels, v, S.r_out);
     return;
   }
@@ -542,8 +544,8 @@ __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_campaign_st
 }
 
 void launch_campaign_step(const StepArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  const int bs = a.A.ras.tile * a.A.ras.tile;
-  const int grid = a.tB + (a.rB + bs / 64 - 1) / (bs / 64) + (a.I.B > 0 ? a.I.grid : 0);
+  const int nw = a.A.ras.tile * a.A.ras.tile / 64;
+  const int grid = (a.tB + nw - 1) / nw + (a.rB + nw - 1) / nw + (a.I.B > 0 ? a.I.grid : 0);
   if (grid <= 0) return;
   switch (a.A.ras.tile) {
     case 8: hipExtLaunchKernelGGL(k_campaign_step<8>, dim3(grid), dim3(64), 0, st, e0, e1, 0, a); break;
