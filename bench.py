@@ -305,7 +305,7 @@ def main():
         sc_f, _, sites_f = _workload(fmt)
         ds_f = sgb.DeviceScene.upload(ctx, sc_f, fmt)
         prep_fm = ctx.prepare(ds_f, cam, sgb.raster_struct(tile=args.tile))
-        n_f = min(args.steps, 1000) * B
+        n_f = args.steps * B   # the headline campaign length
         idx_f = np.arange(n_f) % len(sites_f)
         sa_f = sgb.sites_array(sites_f.field[idx_f], sites_f.comp[idx_f], sites_f.prim[idx_f], sites_f.bit[idx_f])
         va_f = sgb.variants_array(np.arange(n_f), np.ones(n_f, np.uint32))
