@@ -326,6 +326,35 @@ def test_campaign_other_tile_sizes(ctx, tile):
     assert G["dirty_tiles"].max() > 1 and np.all(G["path"] == 0)
 
 
+def test_campaign_largest_batch(ctx):
+    """Batches of SG_MAX_BATCH (2,048) variants, in a campaign and in
+    sg_render_batch, give the same records (a full batch and a ragged one)."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(2500, seed=47)
+    cam = synth.make_camera(64, 48)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam)
+    s = synth.make_sites_stratified(sc.n, 0, 64, seed=48, width_bits=32, fields=(0, 1, 2, 3, 4))
+    sa = b.sites_array(s.field, s.comp, s.prim, s.bit)
+    n = 2048 + 52
+    va = b.variants_array(np.arange(n) % len(sa), np.ones(n, np.uint32))
+    ref = []
+    for v0 in range(0, n, 2048):
+        mt = b.metrics_tensor(len(va[v0:v0 + 2048]))
+        ctx.render_batch(prep, sa, va[v0:v0 + 2048], metrics=mt)
+        ref.append(b.read_metrics(mt))
+    ref = np.concatenate(ref)
+    got = b.metrics_tensor(n)
+    ctx.campaign(prep, sa, va, got, batch=2048, streams=2, threads=1)
+    torch.cuda.synchronize()
+    G = b.read_metrics(got)
+    for key in ref.dtype.names:
+        assert np.array_equal(G[key], ref[key]), key
+    with pytest.raises(b.SgError):
+        ctx.campaign(prep, sa, va, got, batch=2049)
+
+
 def test_campaign_across_prepass_chunks(ctx):
     """A campaign longer than one pre-pass chunk (131,072 variants) gives the
     same records as the same variants in two campaigns that each fit in one
