@@ -173,6 +173,7 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
       int e = idx[0];
       int en = idx[min(1u, len - 1)];
       float4 a = s_r0[e], b = s_r1[e], c = s_r2[e];
+#pragma unroll 2
       for (uint32_t j = 0; j < len; ++j) {
         if (MODE == kFullWrite) {
           // the state before this entry is the state after every entry below it
@@ -190,19 +191,20 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
         const float vv = fmaf(ey, a.z, fmaf(-ex, a.w, -b.y));
         const float q = fmaf(vv, vv * b.w, uu * (uu * b.z));
         const float alpha = fminf(amax, c.x * __builtin_amdgcn_exp2f(-q));
-        if (q <= qc && alpha >= amin && !done) {
-          const float Tn = T * (1.f - alpha);
-          if (Tn < tmin) {
-            done = true;
-            evals = base + (uint32_t)e + 1u - start;
-          } else {
-            const float w = alpha * T;
-            C0 = fmaf(c.y, w, C0);
-            C1 = fmaf(c.z, w, C1);
-            C2 = fmaf(c.w, w, C2);
-            T = Tn;
-          }
-        }
+        // branch-free: every lane computes the update, and selects keep it
+        // only where the entry contributes (the same values the branches
+        // would compute)
+        const bool take = q <= qc && alpha >= amin && !done;
+        const float Tn = T * (1.f - alpha);
+        const bool stop = take && Tn < tmin;
+        const bool blend = take && !(Tn < tmin);
+        const float w = alpha * T;
+        C0 = blend ? fmaf(c.y, w, C0) : C0;
+        C1 = blend ? fmaf(c.z, w, C1) : C1;
+        C2 = blend ? fmaf(c.w, w, C2) : C2;
+        T = blend ? Tn : T;
+        evals = stop ? base + (uint32_t)e + 1u - start : evals;
+        done = done || stop;
         e = en;
         en = enn;
         a = an;
