@@ -334,9 +334,19 @@ __global__ void __launch_bounds__(256) k_big_partition(BinBuffers bb, uint32_t w
   const uint32_t nblk = (uint32_t)bb.total[5];
   for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nblk; g += gridDim.x * blockDim.x) {
     const MergeBlock m = merge_block(bb, nbig, g, w);
+    if (m.n <= w) continue;   // the tile is already one sorted run (k_big_merge skips it)
     const uint64_t* src = src_all + bb.tile_start[m.t];
     bb.big_split[g] = m.nb ? merge_split(src + m.a0, m.na, src + m.b0, m.nb, m.o0 - m.a0) : m.o0 - m.a0;
   }
+}
+
+// Merge passes a big tile takes: one per width kSortCap, 2 kSortCap, ...
+// below its length.  Its sorted keys end in keys after an even number and in
+// keys_tmp after an odd one.
+__device__ __forceinline__ uint32_t merge_passes(uint32_t n) {
+  uint32_t p = 0;
+  for (uint64_t w = kSortCap; w < n; w <<= 1) ++p;
+  return p;
 }
 
 __global__ void __launch_bounds__(256) k_big_merge(BinBuffers bb, uint32_t w, const uint64_t* __restrict__ src_all,
@@ -345,7 +355,9 @@ __global__ void __launch_bounds__(256) k_big_merge(BinBuffers bb, uint32_t w, co
   const int nbig = (int)bb.total[2];
   const uint32_t nblk = (uint32_t)bb.total[5];
   for (uint32_t g = blockIdx.x; g < nblk; g += gridDim.x) {
-    const MergeBlock m = merge_block(bb, nbig, g, w);
+    // w = 0: the final copy of the tiles whose keys ended in keys_tmp
+    const MergeBlock m = merge_block(bb, nbig, g, w ? w : 0xffffffffu);
+    if (w ? m.n <= w : (merge_passes(m.n) & 1u) == 0u) continue;   // nothing to move for this tile
     const uint64_t* src = src_all + bb.tile_start[m.t];
     uint64_t* dst = dst_all + bb.tile_start[m.t];
     const uint32_t cnt = m.o1 - m.o0;
@@ -398,6 +410,9 @@ void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, const unsigned
   k_big_chunks<<<(unsigned)std::min<unsigned long long>(nch, (unsigned long long)n_cu * 2), 1024, 0, st>>>(bb);
   const unsigned pgrid = (unsigned)std::max<unsigned long long>(1, (nblk + 255) / 256);
   const unsigned mgrid = (unsigned)std::min<unsigned long long>(nblk, (unsigned long long)n_cu * 8);
+  // Pass k merges runs of width kSortCap << k into runs of twice that width,
+  // from one buffer into the other, for the tiles still longer than one run;
+  // a tile that is already one sorted run is left where its last pass put it.
   uint64_t* src = bb.keys;
   uint64_t* dst = bb.keys_tmp;
   int passes = 0;
@@ -406,7 +421,8 @@ void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, const unsigned
     k_big_merge<<<mgrid, 256, 0, st>>>(bb, (uint32_t)w, src, dst);
     std::swap(src, dst);
   }
-  if (passes & 1) k_big_merge<<<mgrid, 256, 0, st>>>(bb, 0xffffffffu, src, dst);   // back into keys
+  // the tiles that took an odd number of passes, back into keys
+  if (passes) k_big_merge<<<mgrid, 256, 0, st>>>(bb, 0u, bb.keys_tmp, bb.keys);
 }
 
 }  // namespace sg
