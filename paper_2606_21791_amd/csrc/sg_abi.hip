@@ -1226,6 +1226,7 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
       const sg_variant& x = variants[v];
       if (x.guard && !b.mask) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": guard requested without a box");
       if (x.protect > SG_PROTECT_VOTE) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": unknown protect mode");
+      if (x.n_sites <= (uint32_t)kMaxTouch) continue;   // at most kMaxTouch sites: incremental
       prims.clear();
       for (uint32_t k = 0; k < x.n_sites && incremental; ++k) {
         const uint32_t pr = sites[x.site_off + k].prim;
