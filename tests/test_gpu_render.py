@@ -345,6 +345,14 @@ def test_campaign_largest_batch(ctx):
         ctx.render_batch(prep, sa, va[v0:v0 + 2048], metrics=mt)
         ref.append(b.read_metrics(mt))
     ref = np.concatenate(ref)
+    # the full batch's variants walk items found by a search of the offsets
+    # in global memory: the full-render path gives the same records
+    mf = b.metrics_tensor(2048)
+    ctx.render_batch(prep, sa, va[:2048], metrics=mf, mode=b.SG_FULL)
+    F = b.read_metrics(mf)
+    for key in ("changed_px", "max_abs", "nonfinite"):
+        assert np.array_equal(F[key], ref[key][:2048]), key
+    assert np.allclose(F["sse"], ref["sse"][:2048], rtol=1e-12, atol=0.0)
     got = b.metrics_tensor(n)
     ctx.campaign(prep, sa, va, got, batch=2048, streams=2, threads=1)
     torch.cuda.synchronize()
