@@ -106,6 +106,77 @@ def test_w1_variants_parity(ctx):
         _check_variant(imgs[j], ms[j], ref, clean_ref, clean_gpu)
 
 
+@pytest.mark.parametrize("case", ["hidden", "single"])
+def test_degenerate_scenes(ctx, case):
+    """Degenerate scenes: every primitive behind the camera (no tile
+    instances, a background frame) and a one-primitive scene.  Variants that
+    bring hidden primitives into view, and flips of every component of the
+    single primitive, match the oracle; the incremental and full paths give
+    the same images and the campaign the same records."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    cam = synth.make_camera(96, 64)
+    if case == "hidden":
+        sc = synth.make_scene(400, seed=61)
+        # z in [-4.25, -3.75]: behind the camera, which sits at z = -3
+        sc.fields[0][2, :] = np.float32(-4.0) + np.float32(0.25) * sc.fields[0][2, :]
+        sh = 0
+        # the sign bit of z puts a primitive in front of the camera; the top
+        # exponent bit of z (value 4 = 2^2) sends it towards z = 0
+        rng = np.random.default_rng(63)
+        prims = rng.choice(sc.n, 16, replace=False)
+        sites = synth._mk_sites(np.zeros(32), np.full(32, 2), np.concatenate([prims, prims]),
+                                np.concatenate([np.full(16, 31), np.full(16, 30)]))
+        extra = synth.make_sites_uniform(sc.n, 0, 24, seed=64)
+        sites = synth._mk_sites(np.concatenate([sites.field, extra.field]), np.concatenate([sites.comp, extra.comp]),
+                                np.concatenate([sites.prim, extra.prim]), np.concatenate([sites.bit, extra.bit]))
+    else:
+        sc = synth.make_scene(1, seed=62, sh_degree=1)
+        sc.fields[0][:, 0] = [0.1, -0.05, 0.0]
+        sc.fields[1][:, 0] = [-1.2, -1.6, -1.4]
+        sc.fields[3][:, 0] = [2.0]
+        sh = 1
+        comps = synth.field_components(1)
+        f, c, bits = [], [], []
+        for fld in range(6):
+            for comp in range(comps[fld]):
+                for bit in (31, 30, 26, 23, 20, 10):
+                    f.append(fld); c.append(comp); bits.append(bit)
+        sites = synth._mk_sites(f, c, np.zeros(len(f)), bits)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam)
+    clean_gpu = prep.frame().cpu().numpy()
+    words = stored(sc, "f32")
+    clean_ref = oracle_render(words, "f32", sh, cam)
+    if case == "hidden":
+        assert prep.instances() == 0
+        assert np.all(clean_gpu == 1.0) and np.all(clean_ref["image"] == 1.0)
+    else:
+        assert prep.instances() > 0 and np.any(clean_gpu < 1.0)
+        worst, _ = compare_image(clean_gpu, clean_ref)
+        assert worst <= PIXEL_TOL, worst
+    groups = [np.array([k]) for k in range(len(sites))]
+    inc, mi = _batch(ctx, prep, sites, groups, mode=0)
+    full, mf = _batch(ctx, prep, sites, groups, mode=1)
+    assert np.array_equal(inc, full)
+    for key in ("changed_px", "max_abs", "nonfinite"):
+        assert np.array_equal(mi[key], mf[key]), key
+    visible = 0
+    for k in range(len(sites)):
+        ref = oracle_render(apply_sites(words, sites, k), "f32", sh, cam)
+        _check_variant(inc[k], mi[k], ref, clean_ref, clean_gpu)
+        visible += int(mi[k]["changed_px"] > 0)
+    assert visible >= 8, visible
+    sa = b.sites_array(sites.field, sites.comp, sites.prim, sites.bit)
+    va = b.variants_array(np.arange(len(sites)), np.ones(len(sites), np.uint32))
+    got = b.metrics_tensor(len(sites))
+    ctx.campaign(prep, sa, va, got, batch=8, streams=3, threads=2)
+    torch.cuda.synchronize()
+    G = b.read_metrics(got)
+    for key in mi.dtype.names:
+        assert np.array_equal(G[key], mi[key]), key
+
+
 @pytest.mark.parametrize("fmt", ["f32", "f16", "bf16"])
 def test_incremental_equals_full_render(ctx, fmt):
     from paper_2606_21791_amd import binding as b
