@@ -106,17 +106,26 @@ def test_w1_variants_parity(ctx):
         _check_variant(imgs[j], ms[j], ref, clean_ref, clean_gpu)
 
 
-@pytest.mark.parametrize("case", ["hidden", "single"])
+@pytest.mark.parametrize("case", ["hidden", "single", "frame13x7", "frame1x1"])
 def test_degenerate_scenes(ctx, case):
     """Degenerate scenes: every primitive behind the camera (no tile
-    instances, a background frame) and a one-primitive scene.  Variants that
-    bring hidden primitives into view, and flips of every component of the
-    single primitive, match the oracle; the incremental and full paths give
-    the same images and the campaign the same records."""
+    instances, a background frame), a one-primitive scene, and frames smaller
+    than one tile (13 x 7 and 1 x 1 pixels).  Variants that bring hidden
+    primitives into view, flips of every component of the single primitive
+    and stratified sites of the small frames match the oracle; the
+    incremental and full paths give the same images and the campaign the
+    same records."""
     import torch
     from paper_2606_21791_amd import binding as b
     cam = synth.make_camera(96, 64)
-    if case == "hidden":
+    if case.startswith("frame"):
+        w, h = (13, 7) if case == "frame13x7" else (1, 1)
+        cam = synth.make_camera(w, h)
+        sc = synth.make_scene(60, seed=65)
+        sc.fields[1][:] += np.float32(2.0)   # splats larger than the small frame's pixels
+        sh = 0
+        sites = synth.make_sites_stratified(sc.n, 0, 32, seed=66, width_bits=32, fields=(0, 1, 2, 3, 4))
+    elif case == "hidden":
         sc = synth.make_scene(400, seed=61)
         # z in [-4.25, -3.75]: behind the camera, which sits at z = -3
         sc.fields[0][2, :] = np.float32(-4.0) + np.float32(0.25) * sc.fields[0][2, :]
@@ -151,6 +160,9 @@ def test_degenerate_scenes(ctx, case):
     if case == "hidden":
         assert prep.instances() == 0
         assert np.all(clean_gpu == 1.0) and np.all(clean_ref["image"] == 1.0)
+    elif case.startswith("frame"):
+        worst, _ = compare_image(clean_gpu, clean_ref)
+        assert worst <= PIXEL_TOL, worst
     else:
         assert prep.instances() > 0 and np.any(clean_gpu < 1.0)
         worst, _ = compare_image(clean_gpu, clean_ref)
@@ -166,7 +178,7 @@ def test_degenerate_scenes(ctx, case):
         ref = oracle_render(apply_sites(words, sites, k), "f32", sh, cam)
         _check_variant(inc[k], mi[k], ref, clean_ref, clean_gpu)
         visible += int(mi[k]["changed_px"] > 0)
-    assert visible >= 8, visible
+    assert visible >= (1 if case == "frame1x1" else 8), visible
     sa = b.sites_array(sites.field, sites.comp, sites.prim, sites.bit)
     va = b.variants_array(np.arange(len(sites)), np.ones(len(sites), np.uint32))
     got = b.metrics_tensor(len(sites))
