@@ -8,8 +8,10 @@ the method themselves.
 Scenes stand in for the trained 3DGS models of the paper (Sec. 3, "Scenes and
 models", Table 1), which are not available: the primitive counts follow the
 paper (134,826 for the chair model, a 5% subsample of 6,741, the 2,056,645
-primitives of the real scene in Sec. 5.8) and the value distributions follow
-the workload recipes stated in the design doc.
+primitives of the real scene in Sec. 5.8).  The value distributions are the
+ones `make_scene` states: uniform or clustered means, log-scales around -4,
+uniform quaternion directions, opacity logits around 0, uniform base colours
+and small higher-order coefficients.
 
 Layout: every field is a C-contiguous float32 array of shape (C_f, N)
 (component-major, "SoA"), which is what the device kernels read coalesced.
