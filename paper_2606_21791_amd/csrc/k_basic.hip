@@ -252,7 +252,8 @@ __global__ void __launch_bounds__(64) k_reduce_metrics(const Partial* __restrict
 // delta and the non-finite flag are kept, the footprint is the mean of the
 // per-view footprints (Def. 1), PSNR follows from the pooled MSE, and the
 // catastrophe rule (Def. 2) is applied to the pooled footprint.
-__global__ void k_pool_views(const sg_metrics_t* __restrict__ views, int K, int B, sg_metrics_t* __restrict__ out) {
+__global__ void k_pool_views(const sg_metrics_t* __restrict__ views, int K, int B, int64_t view_stride,
+                             int64_t var_stride, sg_metrics_t* __restrict__ out) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= B) return;
   Partial r;
@@ -261,7 +262,7 @@ __global__ void k_pool_views(const sg_metrics_t* __restrict__ views, int K, int 
   double foot = 0.0;
   uint64_t pr = 0, rr = 0;
   for (int k = 0; k < K; ++k) {
-    const sg_metrics_t& m = views[(int64_t)k * B + v];
+    const sg_metrics_t& m = views[(int64_t)k * view_stride + (int64_t)v * var_stride];
     pr |= m.predicted_regions;
     rr |= m.rendered_regions;
     r.sse += m.sse;
@@ -273,7 +274,8 @@ __global__ void k_pool_views(const sg_metrics_t* __restrict__ views, int K, int 
     px += m.n_pixels;
     foot += (double)m.changed_px / (double)m.n_pixels;
   }
-  sg_metrics_t o = make_metrics(r, 0u, dirty, views[v].clamps, px, views[v].path, pr, rr);
+  const sg_metrics_t& m0 = views[(int64_t)v * var_stride];
+  sg_metrics_t o = make_metrics(r, 0u, dirty, m0.clamps, px, m0.path, pr, rr);
   o.footprint = (float)(foot / K);
   o.catastrophic = (o.nonfinite || foot / K > 0.01) ? 1u : 0u;
   out[v] = o;
@@ -344,9 +346,10 @@ void launch_reduce_metrics(const Partial* parts, const uint32_t* item_off, const
                                      path, tiles_x, tiles_y);
 }
 
-void launch_pool_views(const sg_metrics_t* views, int K, int B, sg_metrics_t* out, hipStream_t st) {
+void launch_pool_views(const sg_metrics_t* views, int K, int B, int64_t view_stride, int64_t var_stride,
+                       sg_metrics_t* out, hipStream_t st) {
   if (B <= 0) return;
-  k_pool_views<<<(B + 255) / 256, 256, 0, st>>>(views, K, B, out);
+  k_pool_views<<<(B + 255) / 256, 256, 0, st>>>(views, K, B, view_stride, var_stride, out);
 }
 
 }  // namespace sg

@@ -22,7 +22,10 @@
 // k_campaign_step holds, in one launch, the three stages of a campaign
 // stream's pipeline on separate buffers: the work items of its next batch,
 // the persistent compositing of its current batch and the metric reduction
-// of its previous batch.
+// of its previous batch.  Its multi-view form (MV) renders every variant of
+// a batch in K views of one resolution within the same launch (Def. 1
+// averages the footprint over views): each stage then counts variant-views
+// and takes each view's clean state from a per-view table.
 #include <hip/hip_ext.h>
 
 #include "sg_batch.h"
@@ -287,8 +290,11 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_full(CompArgs A) {
 // stopped, in the clean render, before all of the tile's target keys.
 // 16 x 16 tiles: registers are held to five resident workgroups per CU, the
 // number their LDS allows.
-template <int TILE>
-__device__ __forceinline__ void items_role(const CompArgs& A, const ItemArgs& I) {
+// MV: the items are variant-views (index v * K + k for view k of variant v)
+// and each takes its view's clean state from views[k].
+template <int TILE, bool MV = false>
+__device__ __forceinline__ void items_role(const CompArgs& A0, const ItemArgs& I, int K = 1,
+                                           const ViewArgs* views = nullptr) {
   constexpr int BS = TILE * TILE;
   constexpr int NT = 2 * kMaxTouch;
   constexpr int KPT = TILE == 8 ? 8 : (TILE == 16 ? 4 : 2);   // staged list keys per thread
@@ -327,6 +333,15 @@ __device__ __forceinline__ void items_role(const CompArgs& A, const ItemArgs& I)
       v = (uint32_t)__builtin_amdgcn_readfirstlane(lo);
     }
     const uint32_t first = __builtin_amdgcn_readfirstlane(off[v]);
+    CompArgs Am;   // MV: A0 with the clean state of the item's view
+    if constexpr (MV) {
+      const ViewArgs& w = views[v % (uint32_t)K];
+      Am = A0;
+      Am.r0 = w.r0; Am.r1 = w.r1; Am.r2 = w.r2;
+      Am.tile_start = w.tile_start; Am.tile_cnt = w.tile_cnt; Am.keys = w.keys;
+      Am.clean = w.clean; Am.stop = w.stop; Am.ck = w.ck; Am.ck_off = w.ck_off; Am.stop_key = w.stop_key;
+    }
+    const CompArgs& A = MV ? Am : A0;
     // The prologue's loads are all issued before any of them is waited for:
     // branch-free, from clamped addresses, with a lane that has nothing to
     // read reading the variant's state instead and dropping the value.  First
@@ -501,8 +516,9 @@ __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_composite_i
   items_role<TILE>(A, I);
 }
 
-// The work items of variant v of a campaign's next batch, by the calling
-// wave alone (slot: its LDS copy of the variant's state).
+// The work items of variant v of a campaign's next batch (variant-view v
+// when MV), by the calling wave alone (slot: its LDS copy of the state).
+template <bool MV>
 __device__ __forceinline__ void tiles_role(const StepArgs& S, int v, VariantState& slot) {
   constexpr int VSW = (int)(sizeof(VariantState) / sizeof(uint32_t));
   const int lane = threadIdx.x & 63;
@@ -512,7 +528,16 @@ __device__ __forceinline__ void tiles_role(const StepArgs& S, int v, VariantStat
   wave_sync();
   uint32_t nd, ni;
   uint64_t pred;
-  enumerate_items(slot.touch, slot.n_touch, S.tiles_x, S.tiles_y, S.stop_key, S.tile_start, S.tile_cnt,
+  const uint64_t* stop_key = S.stop_key;
+  const uint32_t* tile_start = S.tile_start;
+  const uint32_t* tile_cnt = S.tile_cnt;
+  if constexpr (MV) {
+    const ViewArgs& w = S.views[v % S.K];
+    stop_key = w.stop_key;
+    tile_start = w.tile_start;
+    tile_cnt = w.tile_cnt;
+  }
+  enumerate_items(slot.touch, slot.n_touch, S.tiles_x, S.tiles_y, stop_key, tile_start, tile_cnt,
                   S.t_items + (int64_t)v * S.n_tiles, &nd, &ni, &pred);
   if (lane == 0) {
     S.t_vs[v].n_dirty = nd;
@@ -523,10 +548,11 @@ __device__ __forceinline__ void tiles_role(const StepArgs& S, int v, VariantStat
 }
 
 // Workgroups [0, ceil(tB / waves)): work items of the next batch, a variant
-// per wave; then ceil(rB / waves) workgroups reducing the previous batch's
-// metrics, a variant per wave; then the persistent compositing of the
-// current batch.  The waves of the first two roles work alone (no barrier).
-template <int TILE>
+// (variant-view when MV) per wave; then ceil(rB / waves) workgroups reducing
+// the previous batch's metrics, one per wave; then the persistent
+// compositing of the current batch.  The waves of the first two roles work
+// alone (no barrier).
+template <int TILE, bool MV>
 __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_campaign_step(StepArgs S) {
   constexpr int NW = TILE * TILE / 64;
   const int nt = (S.tB + NW - 1) / NW, nr = (S.rB + NW - 1) / NW;
@@ -534,7 +560,7 @@ __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_campaign_st
   if (b < nt) {
     __shared__ VariantState s_tv[NW];
     const int v = b * NW + wave;
-    if (v < S.tB) tiles_role(S, v, s_tv[wave]);
+    if (v < S.tB) tiles_role<MV>(S, v, s_tv[wave]);
     return;
   }
   if (b < nt + nr) {
@@ -542,17 +568,25 @@ __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_campaign_st
     if (v < S.rB) reduce_batch_variant(S.r_parts, S.r_item_off, S.r_n_items, S.r_vs, S.n_pixels, v, S.r_out);
     return;
   }
-  items_role<TILE>(S.A, S.I);
+  items_role<TILE, MV>(S.A, S.I, S.K, S.views);
 }
 
 void launch_campaign_step(const StepArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int nw = a.A.ras.tile * a.A.ras.tile / 64;
   const int grid = (a.tB + nw - 1) / nw + (a.rB + nw - 1) / nw + (a.I.B > 0 ? a.I.grid : 0);
   if (grid <= 0) return;
+  if (a.K > 1) {
+    switch (a.A.ras.tile) {
+      case 8: hipExtLaunchKernelGGL(k_campaign_step<8, true>, dim3(grid), dim3(64), 0, st, e0, e1, 0, a); break;
+      case 32: hipExtLaunchKernelGGL(k_campaign_step<32, true>, dim3(grid), dim3(1024), 0, st, e0, e1, 0, a); break;
+      default: hipExtLaunchKernelGGL(k_campaign_step<16, true>, dim3(grid), dim3(256), 0, st, e0, e1, 0, a); break;
+    }
+    return;
+  }
   switch (a.A.ras.tile) {
-    case 8: hipExtLaunchKernelGGL(k_campaign_step<8>, dim3(grid), dim3(64), 0, st, e0, e1, 0, a); break;
-    case 32: hipExtLaunchKernelGGL(k_campaign_step<32>, dim3(grid), dim3(1024), 0, st, e0, e1, 0, a); break;
-    default: hipExtLaunchKernelGGL(k_campaign_step<16>, dim3(grid), dim3(256), 0, st, e0, e1, 0, a); break;
+    case 8: hipExtLaunchKernelGGL(k_campaign_step<8, false>, dim3(grid), dim3(64), 0, st, e0, e1, 0, a); break;
+    case 32: hipExtLaunchKernelGGL(k_campaign_step<32, false>, dim3(grid), dim3(1024), 0, st, e0, e1, 0, a); break;
+    default: hipExtLaunchKernelGGL(k_campaign_step<16, false>, dim3(grid), dim3(256), 0, st, e0, e1, 0, a); break;
   }
 }
 

@@ -221,7 +221,8 @@ __global__ void __launch_bounds__(64) k_campaign_touch(DevScene s, DevBox box, D
                                                        const float4* __restrict__ r2,
                                                        const uint32_t* __restrict__ depth,
                                                        const uint2* __restrict__ rect, const sg_site* sites,
-                                                       const sg_variant* variants, int n, VariantState* vs, Rec* ovr) {
+                                                       const sg_variant* variants, int n, VariantState* vs, Rec* ovr,
+                                                       int stride, int offset) {
   using L = Layout<DEG>;
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= n) return;
@@ -240,7 +241,8 @@ __global__ void __launch_bounds__(64) k_campaign_touch(DevScene s, DevBox box, D
     }
   }
   if (full) n_touch = 0;
-  VariantState* out = vs + g;
+  const int64_t slot = g * stride + offset;   // this variant's state and records
+  VariantState* out = vs + slot;
   unsigned long long clamps = 0;
   uint32_t nonfinite = 0;
   for (uint32_t j = 0; j < n_touch; ++j) {
@@ -293,7 +295,7 @@ __global__ void __launch_bounds__(64) k_campaign_touch(DevScene s, DevBox box, D
     }
     t.flags = (old_vis ? 1u : 0u) | (o.visible ? 2u : 0u) | (same ? 4u : 0u);
     out->touch[j] = t;
-    ovr[g * kMaxTouch + j] = o.rec;
+    ovr[slot * kMaxTouch + j] = o.rec;
   }
   out->n_touch = n_touch;
   out->full = full;
@@ -341,14 +343,14 @@ void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam
 void launch_campaign_touch(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                            const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
                            const uint2* rect, const sg_site* sites, const sg_variant* variants, int n,
-                           VariantState* vs, Rec* ovr, hipStream_t st) {
+                           VariantState* vs, Rec* ovr, int stride, int offset, hipStream_t st) {
   if (n <= 0) return;
   const int grid = (n + 63) / 64;
   switch (s.sh_degree) {
-    case 0: k_campaign_touch<0><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr); break;
-    case 1: k_campaign_touch<1><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr); break;
-    case 2: k_campaign_touch<2><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr); break;
-    default: k_campaign_touch<3><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr); break;
+    case 0: k_campaign_touch<0><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset); break;
+    case 1: k_campaign_touch<1><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset); break;
+    case 2: k_campaign_touch<2><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset); break;
+    default: k_campaign_touch<3><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset); break;
   }
 }
 

@@ -104,8 +104,10 @@ struct sg_ctx {
   // device copies of a pipelined campaign's sites and variants, and the
   // states and override records of a chunk of its variants; camp_done marks
   // the end of the campaign that last used them; camp_mu serialises
-  // campaigns on one context
-  DevBuf camp_sites, camp_vars, camp_vs, camp_ovr, camp_views;
+  // campaigns on one context; camp_vargs holds the per-view clean state of a
+  // multi-view campaign (its host copy stays alive for the upload)
+  DevBuf camp_sites, camp_vars, camp_vs, camp_ovr, camp_views, camp_vargs;
+  std::vector<ViewArgs> camp_vargs_host;
   hipEvent_t camp_done = nullptr;
   std::mutex camp_mu;
   // guards ws, in_use and the timing state: sg_campaign enqueues from several
@@ -547,6 +549,7 @@ void sg_ctx_destroy(sg_ctx* c) {
   dev_free(c, c->camp_vs);
   dev_free(c, c->camp_ovr);
   dev_free(c, c->camp_views);
+  dev_free(c, c->camp_vargs);
   if (c->camp_done) (void)hipEventDestroy(c->camp_done);
   for (int p = 0; p < SG_N_PASSES; ++p)
     for (auto& pr : c->pending[p]) c->ev_pool.insert(c->ev_pool.end(), {pr.first, pr.second});
@@ -1023,7 +1026,7 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
   for (int k = 0; k < K; ++k)
     SG_TRY(sg_render_batch(ctx, preps[k], sites, n_sites, variants, B, box, box_field_mask, nullptr,
                            pv + (int64_t)k * B, mode, stream));
-  launch_pool_views(pv, K, B, metrics_out, st);
+  launch_pool_views(pv, K, B, B, 1, metrics_out, st);
   return check_last("sg_render_batch_views");
 }
 
@@ -1041,18 +1044,48 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
 static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, const sg_site* sites, int32_t n_sites,
                                     const sg_variant* variants, int32_t n_variants, const DevBox& box, int B, int NS,
                                     int NT, sg_metrics_t* metrics_out, hipStream_t caller) {
-  constexpr int kChunk = 1 << 17;   // variants staged per pre-pass
+  constexpr int kChunk = 1 << 17;   // variants staged per pre-pass (one view)
   std::lock_guard<std::mutex> cg(ctx->camp_mu);
   if (ctx->camp_done) HIP_TRY(hipEventSynchronize(ctx->camp_done));   // the previous campaign's buffers are free
   else HIP_TRY(hipEventCreateWithFlags(&ctx->camp_done, hipEventDisableTiming));
-  const int chunk = std::min(n_variants, (kChunk / B) * B);
+  // K views of one resolution, raster and checkpoint spacing, with B * K
+  // variant-views within a launch's limit, share each launch: its roles then
+  // count variant-views (view k of variant v at v * K + k).  Other view sets
+  // run view after view.
+  bool mv = K > 1 && (int64_t)B * K <= kMaxBatch;
+  for (int k = 1; k < K && mv; ++k) {
+    const sg_prep* a = preps[0];
+    const sg_prep* c = preps[k];
+    mv = a->cam.W == c->cam.W && a->cam.H == c->cam.H && a->ck_group == c->ck_group &&
+         std::memcmp(&a->ras, &c->ras, sizeof(DevRaster)) == 0;
+  }
+  const int per = mv ? K : 1;                                  // variant-views per variant in a launch
+  const int64_t cap = mv ? (int64_t)1 << 21 : (int64_t)kChunk;  // variant-views staged per pre-pass
+  const int chunk = (int)std::min<int64_t>(n_variants, std::max<int64_t>(B, (cap / per / B) * B));
   int max_tiles = 0;
   for (int v = 0; v < K; ++v) max_tiles = std::max(max_tiles, preps[v]->ras.n_tiles);
   SG_TRY(dev_alloc(ctx, ctx->camp_sites, std::max<size_t>(1, (size_t)n_sites) * sizeof(sg_site)));
   SG_TRY(dev_alloc(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant)));
-  SG_TRY(dev_alloc(ctx, ctx->camp_vs, (size_t)chunk * sizeof(VariantState)));
-  SG_TRY(dev_alloc(ctx, ctx->camp_ovr, (size_t)chunk * kMaxTouch * sizeof(Rec)));
+  SG_TRY(dev_alloc(ctx, ctx->camp_vs, (size_t)chunk * per * sizeof(VariantState)));
+  SG_TRY(dev_alloc(ctx, ctx->camp_ovr, (size_t)chunk * per * kMaxTouch * sizeof(Rec)));
   if (K > 1) SG_TRY(dev_alloc(ctx, ctx->camp_views, (size_t)K * chunk * sizeof(sg_metrics_t)));
+  const ViewArgs* d_views = nullptr;
+  if (mv) {
+    ctx->camp_vargs_host.resize(K);
+    for (int k = 0; k < K; ++k) {
+      const sg_prep* p = preps[k];
+      const bool rs = p->ck_group != 0;
+      ctx->camp_vargs_host[k] = ViewArgs{P<float4>(p->r0), P<float4>(p->r1), P<float4>(p->r2),
+                                         P<uint32_t>(p->tile_start), P<uint32_t>(p->tile_cnt), P<uint64_t>(p->keys),
+                                         P<float>(p->frame), rs ? P<uint32_t>(p->stop) : nullptr,
+                                         rs ? P<float4>(p->ck) : nullptr, rs ? P<uint32_t>(p->ck_off) : nullptr,
+                                         rs ? P<uint64_t>(p->stop_key) : nullptr};
+    }
+    SG_TRY(dev_alloc(ctx, ctx->camp_vargs, (size_t)K * sizeof(ViewArgs)));
+    HIP_TRY(hipMemcpyAsync(ctx->camp_vargs.p, ctx->camp_vargs_host.data(), (size_t)K * sizeof(ViewArgs),
+                           hipMemcpyHostToDevice, caller));
+    d_views = P<ViewArgs>(ctx->camp_vargs);
+  }
   if (n_sites)
     HIP_TRY(hipMemcpyAsync(ctx->camp_sites.p, sites, (size_t)n_sites * sizeof(sg_site), hipMemcpyHostToDevice, caller));
   HIP_TRY(hipMemcpyAsync(ctx->camp_vars.p, variants, (size_t)n_variants * sizeof(sg_variant), hipMemcpyHostToDevice,
@@ -1063,10 +1096,10 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
     Workspace* W = workspace(ctx, st);
     if (!W) return fail(SG_E_NOMEM, "pinned allocation for a workspace failed");
     for (int q = 0; q < 3; ++q) {
-      SG_TRY(dev_alloc(ctx, W->st_items[q], (size_t)B * max_tiles * sizeof(uint4)));
-      SG_TRY(dev_alloc(ctx, W->st_parts[q], (size_t)B * max_tiles * sizeof(Partial)));
-      SG_TRY(dev_alloc(ctx, W->st_off[q], (size_t)(B + 1) * sizeof(uint32_t)));
-      SG_TRY(dev_alloc(ctx, W->st_n[q], (size_t)B * sizeof(uint32_t)));
+      SG_TRY(dev_alloc(ctx, W->st_items[q], (size_t)B * per * max_tiles * sizeof(uint4)));
+      SG_TRY(dev_alloc(ctx, W->st_parts[q], (size_t)B * per * max_tiles * sizeof(Partial)));
+      SG_TRY(dev_alloc(ctx, W->st_off[q], (size_t)(B * per + 1) * sizeof(uint32_t)));
+      SG_TRY(dev_alloc(ctx, W->st_n[q], (size_t)B * per * sizeof(uint32_t)));
     }
     if (!W->st_ctl.p) {
       SG_TRY(dev_alloc(ctx, W->st_ctl, 3 * 4 * sizeof(uint32_t)));
@@ -1082,11 +1115,11 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
 
   for (int c0 = 0; c0 < n_variants; c0 += chunk) {
     const int cn = std::min(chunk, n_variants - c0);
-    for (int view = 0; view < K; ++view) {
+    for (int view = 0; view < (mv ? 1 : K); ++view) {
       const sg_prep* prep = preps[view];
       const DevRaster& ras = prep->ras;
-      const DevScene& s = prep->scene;
-      sg_metrics_t* out = K == 1 ? metrics_out + c0 : per_view + (int64_t)view * cn;
+      // per-view records: view-major (cn per view) view after view, variant-major (K per variant) when shared
+      sg_metrics_t* out = K == 1 ? metrics_out + c0 : per_view + (mv ? 0 : (int64_t)view * cn);
       const CompArgs ca0 = item_comp_args(ws[0], prep, nullptr);
       const ItemArgs it0 = item_args(ctx, ws[0], prep, B);
       StepArgs base{};
@@ -1097,11 +1130,14 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
       base.tile_start = P<uint32_t>(prep->tile_start);
       base.tile_cnt = P<uint32_t>(prep->tile_cnt);
       base.n_pixels = (uint32_t)(prep->cam.W * prep->cam.H);
-      {
+      base.K = per;
+      base.views = d_views;
+      for (int k = mv ? 0 : view; k < (mv ? K : view + 1); ++k) {
+        const sg_prep* pk = preps[k];
         PassScope ps(ctx, SG_PASS_VARIANT_PREP, caller);
-        launch_campaign_touch(s, box, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
-                              P<uint32_t>(prep->depth), P<uint2>(prep->rect), d_sites, d_vars + c0, cn, c_vs, c_ovr,
-                              caller);
+        launch_campaign_touch(pk->scene, box, pk->cam, pk->ras, P<float4>(pk->r0), P<float4>(pk->r1),
+                              P<float4>(pk->r2), P<uint32_t>(pk->depth), P<uint2>(pk->rect), d_sites, d_vars + c0, cn,
+                              c_vs, c_ovr, per, mv ? k : 0, caller);
       }
       hipEvent_t staged = nullptr;
       HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
@@ -1124,8 +1160,8 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
             StepArgs a = base;
             if (i < m) {
               const int q = i % 3;
-              a.tB = nvb(i);
-              a.t_vs = c_vs + lb(i);
+              a.tB = nvb(i) * per;
+              a.t_vs = c_vs + (int64_t)lb(i) * per;
               a.t_items = P<uint4>(W->st_items[q]);
               a.t_n_items = P<uint32_t>(W->st_n[q]);
               a.t_item_off = P<uint32_t>(W->st_off[q]);
@@ -1138,21 +1174,21 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
             if (i >= 1 && i <= m) {
               const int q = (i - 1) % 3;
               a.A.parts = P<Partial>(W->st_parts[q]);
-              a.I.vs = c_vs + lb(i - 1);
-              a.I.ovr = c_ovr + (int64_t)lb(i - 1) * kMaxTouch;
+              a.I.vs = c_vs + (int64_t)lb(i - 1) * per;
+              a.I.ovr = c_ovr + (int64_t)lb(i - 1) * per * kMaxTouch;
               a.I.items = P<uint4>(W->st_items[q]);
               a.I.item_off = P<uint32_t>(W->st_off[q]);
               a.I.counter = P<uint32_t>(W->st_ctl) + 4 * q;
-              a.I.B = nvb(i - 1);
+              a.I.B = nvb(i - 1) * per;
             }
             if (i >= 2) {
               const int q = (i - 2) % 3;
-              a.rB = nvb(i - 2);
+              a.rB = nvb(i - 2) * per;
               a.r_parts = P<Partial>(W->st_parts[q]);
               a.r_item_off = P<uint32_t>(W->st_off[q]);
               a.r_n_items = P<uint32_t>(W->st_n[q]);
-              a.r_vs = c_vs + lb(i - 2);
-              a.r_out = out + lb(i - 2);
+              a.r_vs = c_vs + (int64_t)lb(i - 2) * per;
+              a.r_out = out + (int64_t)lb(i - 2) * per;
             }
             if (a.tB == 0 && a.I.B == 0 && a.rB == 0) continue;
             PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st, true);
@@ -1171,7 +1207,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
         (void)hipEventDestroy(e);
       }
     }
-    if (K > 1) launch_pool_views(per_view, K, cn, metrics_out + c0, caller);
+    if (K > 1) launch_pool_views(per_view, K, cn, mv ? 1 : cn, mv ? K : 1, metrics_out + c0, caller);
   }
   HIP_TRY(hipEventRecord(ctx->camp_done, caller));
   return check_last("sg_campaign");

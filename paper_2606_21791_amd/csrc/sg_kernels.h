@@ -137,7 +137,10 @@ void launch_guard_rows(const DevScene& s, const DevBox& b, const GuardRows& gr, 
 void launch_health(const unsigned long long* count, unsigned long long thr, uint32_t* alert, hipStream_t st);
 void launch_metrics_partials(const float* img, const float* clean, int64_t px_per_var, int nchunks, int B,
                              Partial* out, hipStream_t st);
-void launch_pool_views(const sg_metrics_t* views, int K, int B, sg_metrics_t* out, hipStream_t st);
+// Pools the K view records of each of B variants; view k of variant v is
+// views[k * view_stride + v * var_stride].
+void launch_pool_views(const sg_metrics_t* views, int K, int B, int64_t view_stride, int64_t var_stride,
+                       sg_metrics_t* out, hipStream_t st);
 // tiles_x > 0 marks per-tile partials of a full render (uniform_items tiles):
 // their rendered regions are derived from the tiles with a changed pixel.
 void launch_reduce_metrics(const Partial* parts, const uint32_t* item_off, const uint32_t* n_items,
@@ -181,11 +184,13 @@ void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam
                          const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
                          const uint2* rect, const BatchBuffers& bb, hipStream_t st);
 // Campaign pre-pass over n variants: states (touches, clamps, non-finite
-// flag) and override records (kMaxTouch per variant).
+// flag) and override records (kMaxTouch per variant).  Variant g's state is
+// vs[g * stride + offset] and its records start at ovr[(g * stride + offset)
+// * kMaxTouch] (stride K, offset the view: the views of a variant side by side).
 void launch_campaign_touch(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                            const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
                            const uint2* rect, const sg_site* sites, const sg_variant* variants, int n,
-                           VariantState* vs, Rec* ovr, hipStream_t st);
+                           VariantState* vs, Rec* ovr, int stride, int offset, hipStream_t st);
 
 // k_bin.hip
 struct BinBuffers {
@@ -261,6 +266,21 @@ void launch_composite_items(const CompArgs& a, const ItemArgs& it, hipStream_t s
 // in workgroups of their own and on buffers of their own, so that nothing
 // in the launch waits for anything else in it.  A role with no batch has
 // B = 0.
+// The clean state of one view of a multi-view campaign step.
+struct ViewArgs {
+  const float4* r0;
+  const float4* r1;
+  const float4* r2;
+  const uint32_t* tile_start;
+  const uint32_t* tile_cnt;
+  const uint64_t* keys;
+  const float* clean;
+  const uint32_t* stop;
+  const float4* ck;
+  const uint32_t* ck_off;
+  const uint64_t* stop_key;
+};
+
 struct StepArgs {
   // work items of the next batch: one workgroup (its first wave) per variant
   int tB;
@@ -285,6 +305,12 @@ struct StepArgs {
   // compositing of the current batch (I.B = 0: none)
   CompArgs A;
   ItemArgs I;
+  // K > 1: each variant in K views of one resolution in the same launch.  The
+  // roles then count variant-views, view k of variant v at index v * K + k,
+  // and take each view's clean state from views[k] in place of the fields of
+  // A (and of stop_key, tile_start, tile_cnt above) that differ by view.
+  int K = 1;
+  const ViewArgs* views = nullptr;
 };
 // e0, e1 (nullable): events recorded at the launch's own start and end.
 void launch_campaign_step(const StepArgs& a, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

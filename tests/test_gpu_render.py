@@ -565,21 +565,25 @@ def test_k_views_pooling(ctx):
     assert np.allclose(P["mse"], sse / (3.0 * V["n_pixels"].sum(axis=0)), rtol=1e-15, atol=0)
     assert np.array_equal(P["catastrophic"], ((P["nonfinite"] > 0) | (foot > 0.01)).astype(np.uint32))
     assert P["path"][-1] == 1 and V["n_pixels"][0][0] == 96 * 80
-    # with the full-path variant the campaign renders batch by batch; without
-    # it, every view goes through the pipelined campaign and is then pooled
-    for vs in (va, va[:-1]):
+    # With the full-path variant the campaign renders batch by batch.
+    # Without it, the pipelined campaign renders the K views of a batch in
+    # the same launches; views of different sizes, and batches whose
+    # variant-views exceed one launch (B * K > 2,048), run view after view.
+    cams2 = synth.make_orbit_cameras(2, 96, 80) + [synth.make_camera(64, 48)]
+    preps2 = [ctx.prepare(ds, c) for c in cams2]
+    for pp, vs, bsz in ((preps, va, 7), (preps, va[:-1], 7), (preps2, va[:-1], 7), (preps, va[:-1], 700)):
         got = b.metrics_tensor(len(vs))
-        ctx.campaign(preps, sa, vs, got, box=box, batch=7, streams=4, threads=2)
+        ctx.campaign(pp, sa, vs, got, box=box, batch=bsz, streams=4, threads=2)
         torch.cuda.synchronize()
         G = b.read_metrics(got)
         ref = []
-        for v0 in range(0, len(vs), 7):
-            mt = b.metrics_tensor(len(vs[v0:v0 + 7]))
-            ctx.render_batch_views(preps, sa, vs[v0:v0 + 7], mt, box=box)
+        for v0 in range(0, len(vs), bsz):
+            mt = b.metrics_tensor(len(vs[v0:v0 + bsz]))
+            ctx.render_batch_views(pp, sa, vs[v0:v0 + bsz], mt, box=box)
             ref.append(b.read_metrics(mt))
         ref = np.concatenate(ref)
         for key in ref.dtype.names:
-            assert np.array_equal(G[key], ref[key]), (len(vs), key)
+            assert np.array_equal(G[key], ref[key]), (len(vs), len(pp), bsz, key)
     with pytest.raises(b.SgError):   # views of different scenes
         other = b.DeviceScene.upload(ctx, sc, "f32")
         ctx.render_batch_views([preps[0], ctx.prepare(other, cams[1])], sa, va, pooled)
