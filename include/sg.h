@@ -292,8 +292,10 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
  * pre-pass launch per view, and then enqueues one launch per batch on its
  * stream: launch i lists the work items of the stream's batch i, composites
  * batch i - 1 and reduces the metrics of batch i - 2 (two more launches per
- * stream drain the pipeline).  With K views, the views of a chunk run one
- * after the other and their records are then pooled.  Campaigns on one
+ * stream drain the pipeline).  With K views of one resolution, raster and
+ * checkpoint spacing (and B * K <= SG_MAX_BATCH), each launch renders its
+ * batch in all K views; other view sets run view after view.  The per-view
+ * records are then pooled.  Campaigns on one
  * context run one at a time (a second call waits until the first one's
  * device buffers are no longer read).
  *

@@ -1037,9 +1037,11 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
 // one launch per batch: launch i lists the work items of the stream's batch
 // i, composites batch i - 1 and reduces the metrics of batch i - 2, on three
 // rotating buffer sets; two more launches drain it.  With K > 1 views the
-// per-view records of the chunk are then pooled.  Views follow one another
-// on the device (the caller's stream joins every campaign stream before the
-// next pre-pass), with no host synchronisation.  The records are those of
+// per-view records of the chunk are then pooled.  Views of one resolution,
+// raster and checkpoint spacing share each launch (its stages count
+// variant-views); other view sets follow one another on the device (the
+// caller's stream joins every campaign stream before the next pre-pass),
+// with no host synchronisation.  The records are those of
 // sg_render_batch(_views) on the same batches.
 static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, const sg_site* sites, int32_t n_sites,
                                     const sg_variant* variants, int32_t n_variants, const DevBox& box, int B, int NS,
