@@ -293,9 +293,11 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
  * stream: launch i lists the work items of the stream's batch i, composites
  * batch i - 1 and reduces the metrics of batch i - 2 (two more launches per
  * stream drain the pipeline).  With K views of one resolution, raster and
- * checkpoint spacing (and B * K <= SG_MAX_BATCH), each launch renders its
- * batch in all K views; other view sets run view after view.  The per-view
- * records are then pooled.  Campaigns on one
+ * checkpoint spacing, each launch renders its batch in all K views when
+ * B * K <= SG_MAX_BATCH and the streams' work-item buffers (room for every
+ * tile of every variant-view: 3 * streams * B * K * tiles * 40 bytes) stay
+ * within 16 GiB; other view sets run view after view.  The per-view records
+ * are then pooled.  Campaigns on one
  * context run one at a time (a second call waits until the first one's
  * device buffers are no longer read).
  *

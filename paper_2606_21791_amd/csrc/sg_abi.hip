@@ -1054,7 +1054,14 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
   // variant-views within a launch's limit, share each launch: its roles then
   // count variant-views (view k of variant v at v * K + k).  Other view sets
   // run view after view.
-  bool mv = K > 1 && (int64_t)B * K <= kMaxBatch;
+  // The per-stream work-item buffers hold every tile of every variant-view
+  // (3 sets per stream); views share launches only while those stay within
+  // kSharedBytes in all.
+  constexpr int64_t kSharedBytes = (int64_t)16 << 30;
+  int max_tiles = 0;
+  for (int v = 0; v < K; ++v) max_tiles = std::max(max_tiles, preps[v]->ras.n_tiles);
+  bool mv = K > 1 && (int64_t)B * K <= kMaxBatch &&
+            (int64_t)B * K * max_tiles * (int64_t)(sizeof(uint4) + sizeof(Partial)) * 3 * NS <= kSharedBytes;
   for (int k = 1; k < K && mv; ++k) {
     const sg_prep* a = preps[0];
     const sg_prep* c = preps[k];
@@ -1064,8 +1071,6 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
   const int per = mv ? K : 1;                                  // variant-views per variant in a launch
   const int64_t cap = mv ? (int64_t)1 << 21 : (int64_t)kChunk;  // variant-views staged per pre-pass
   const int chunk = (int)std::min<int64_t>(n_variants, std::max<int64_t>(B, (cap / per / B) * B));
-  int max_tiles = 0;
-  for (int v = 0; v < K; ++v) max_tiles = std::max(max_tiles, preps[v]->ras.n_tiles);
   SG_TRY(dev_alloc(ctx, ctx->camp_sites, std::max<size_t>(1, (size_t)n_sites) * sizeof(sg_site)));
   SG_TRY(dev_alloc(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant)));
   SG_TRY(dev_alloc(ctx, ctx->camp_vs, (size_t)chunk * per * sizeof(VariantState)));
