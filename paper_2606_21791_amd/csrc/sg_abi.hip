@@ -1120,6 +1120,8 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
   Rec* c_ovr = P<Rec>(ctx->camp_ovr);
   sg_metrics_t* per_view = P<sg_metrics_t>(ctx->camp_views);
 
+  std::mutex launch_mu;
+  hipError_t launch_err = hipSuccess;
   for (int c0 = 0; c0 < n_variants; c0 += chunk) {
     const int cn = std::min(chunk, n_variants - c0);
     for (int view = 0; view < (mv ? 1 : K); ++view) {
@@ -1201,11 +1203,19 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
             PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st, true);
             launch_campaign_step(a, st, ps.a, ps.b);
           }
+        // launch errors are per host thread: each worker reports its own
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+          std::lock_guard<std::mutex> g(launch_mu);
+          if (launch_err == hipSuccess) launch_err = e;
+        }
       };
       std::vector<std::thread> pool;
       for (int t = 1; t < NT; ++t) pool.emplace_back(worker, t);
       worker(0);
       for (std::thread& th : pool) th.join();
+      if (launch_err != hipSuccess)
+        return fail(SG_E_DEVICE, std::string("campaign step launch: ") + hipGetErrorString(launch_err));
       for (int k = 0; k < NS; ++k) {
         hipEvent_t e = nullptr;
         HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
