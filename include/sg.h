@@ -321,6 +321,23 @@ sg_status sg_campaign(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t 
 sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const sg_site* sites, int32_t n_sites,
                             const sg_variant* variants, int32_t n_variants, const sg_box* box, uint32_t box_field_mask,
                             const sg_campaign_cfg* cfg, sg_metrics_t* metrics_out, void* stream);
+/* A campaign over several prepared scenes of uneven size (Sec. 5.12: many
+ * independently corrupted variants per launch): variant v is a variant of
+ * preps[scene_of[v]] and is rendered there only; the batches mix the scenes,
+ * and each launch composites the (variant, tile) work items of all of them.
+ * preps: n_preps (1..64) prepared scenes or views on this device, any sizes
+ * and formats, one tile size.  scene_of: HOST array of n_variants indices
+ * into preps.  sites, variants: host arrays as in sg_campaign; a variant's
+ * sites address its own scene and are validated against it.  boxes
+ * (nullable; entries nullable): the guard box of each scene, used by
+ * variants with guard != 0.  Every variant must touch at most 8 distinct
+ * primitives (SG_E_UNSUPPORTED otherwise).  metrics_out (device, n_variants
+ * records) receives what sg_render_batch gives on each variant's own scene.
+ * Ordering, streams and threads as in sg_campaign. */
+sg_status sg_campaign_scenes(sg_ctx* ctx, sg_prep* const* preps, int32_t n_preps, const sg_site* sites, int32_t n_sites,
+                             const sg_variant* variants, const uint16_t* scene_of, int32_t n_variants,
+                             const sg_box* const* boxes, uint32_t box_field_mask, const sg_campaign_cfg* cfg,
+                             sg_metrics_t* metrics_out, void* stream);
 
 /* Autotuner.  Picks the launch configuration of injection campaigns on one
  * scene and camera by measurement: tile size, variants per launch B,

@@ -126,6 +126,7 @@ def _load():
         "sg_render_batch": (i32, [vp, vp, vp, i32, vp, i32, P(SgBox), u32, vp, vp, i32, vp]),
         "sg_campaign": (i32, [vp, vp, vp, i32, vp, i32, P(SgBox), u32, P(SgCampaignCfg), vp, vp]),
         "sg_campaign_views": (i32, [vp, vp, i32, vp, i32, vp, i32, P(SgBox), u32, P(SgCampaignCfg), vp, vp]),
+        "sg_campaign_scenes": (i32, [vp, vp, i32, vp, i32, vp, vp, i32, vp, u32, P(SgCampaignCfg), vp, vp]),
         "sg_render_batch_views": (i32, [vp, vp, i32, vp, i32, vp, i32, P(SgBox), u32, vp, vp, i32, vp]),
         "sg_metrics": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
         "sg_ssim": (i32, [vp, vp, vp, i32, i32, i32, vp, vp]),
@@ -157,7 +158,7 @@ LIB = _load()
 EXPORTED = ("sg_ctx_create", "sg_ctx_destroy", "sg_last_error", "sg_ctx_bytes", "sg_cast", "sg_inject",
             "sg_restore", "sg_guard_box", "sg_guard", "sg_render", "sg_prepare", "sg_prep_destroy",
             "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_render_batch_views", "sg_campaign",
-            "sg_campaign_views", "sg_autotune", "sg_metrics", "sg_ssim",
+            "sg_campaign_views", "sg_campaign_scenes", "sg_autotune", "sg_metrics", "sg_ssim",
             "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_persistent_grid", "sg_ctx_set_resume", "sg_ctx_set_graphs",
             "sg_serve_create",
             "sg_serve_add_scene", "sg_serve_add_view", "sg_serve_submit", "sg_serve_poll", "sg_serve_wait",
@@ -326,6 +327,24 @@ class Context:
         else:
             check(LIB.sg_campaign(self.h, prep.h, s.ctypes.data_as(C.c_void_p), len(s), v.ctypes.data_as(C.c_void_p),
                                   len(v), bx, mask, C.byref(cfg), _ptr(metrics), _stream()))
+
+    def campaign_scenes(self, preps, sites: np.ndarray, variants: np.ndarray, scene_of, metrics, boxes=None,
+                        box_mask: int = SG_FIELD_MASK_GUARD, batch: int = 32, streams: int = 8, threads: int = 2):
+        """Variants of several prepared scenes in one campaign: variant j belongs
+        to preps[scene_of[j]]; boxes (optional) lists each scene's box or None."""
+        s = np.ascontiguousarray(sites, SITE_DTYPE)
+        v = np.ascontiguousarray(variants, VARIANT_DTYPE)
+        sc = np.ascontiguousarray(scene_of, np.uint16)
+        assert sc.shape == (len(v),)
+        cfg = SgCampaignCfg(int(batch), int(streams), int(threads), 0)
+        hs = (C.c_void_p * len(preps))(*[p.h for p in preps])
+        bxs = None
+        if boxes is not None:
+            bxs = (C.c_void_p * len(preps))(*[C.cast(C.pointer(b.st), C.c_void_p) if b is not None else None
+                                              for b in boxes])
+        check(LIB.sg_campaign_scenes(self.h, hs, len(preps), s.ctypes.data_as(C.c_void_p), len(s),
+                                     v.ctypes.data_as(C.c_void_p), sc.ctypes.data_as(C.c_void_p), len(v), bxs,
+                                     box_mask if boxes is not None else 0, C.byref(cfg), _ptr(metrics), _stream()))
 
     def render_batch_views(self, preps, sites: np.ndarray, variants: np.ndarray, metrics, per_view=None, box=None,
                            box_mask: int = SG_FIELD_MASK_GUARD, mode: int = SG_INCREMENTAL):

@@ -290,11 +290,12 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_full(CompArgs A) {
 // stopped, in the clean render, before all of the tile's target keys.
 // 16 x 16 tiles: registers are held to five resident workgroups per CU, the
 // number their LDS allows.
-// MV: the items are variant-views (index v * K + k for view k of variant v)
-// and each takes its view's clean state from views[k].
+// MV: the items are variant-views and each takes its view's clean state
+// from views[]: view v % K of variant-view v, or view_of[v] when given.
+// Their work items sit A0.ras.n_tiles apart per variant-view.
 template <int TILE, bool MV = false>
 __device__ __forceinline__ void items_role(const CompArgs& A0, const ItemArgs& I, int K = 1,
-                                           const ViewArgs* views = nullptr) {
+                                           const ViewArgs* views = nullptr, const uint16_t* view_of = nullptr) {
   constexpr int BS = TILE * TILE;
   constexpr int NT = 2 * kMaxTouch;
   constexpr int KPT = TILE == 8 ? 8 : (TILE == 16 ? 4 : 2);   // staged list keys per thread
@@ -335,11 +336,13 @@ __device__ __forceinline__ void items_role(const CompArgs& A0, const ItemArgs& I
     const uint32_t first = __builtin_amdgcn_readfirstlane(off[v]);
     CompArgs Am;   // MV: A0 with the clean state of the item's view
     if constexpr (MV) {
-      const ViewArgs& w = views[v % (uint32_t)K];
+      const uint32_t view = view_of ? (uint32_t)view_of[v] : v % (uint32_t)K;
+      const ViewArgs& w = views[view];
       Am = A0;
       Am.r0 = w.r0; Am.r1 = w.r1; Am.r2 = w.r2;
       Am.tile_start = w.tile_start; Am.tile_cnt = w.tile_cnt; Am.keys = w.keys;
       Am.clean = w.clean; Am.stop = w.stop; Am.ck = w.ck; Am.ck_off = w.ck_off; Am.stop_key = w.stop_key;
+      Am.ras = w.ras; Am.W = w.W; Am.H = w.H; Am.ck_group = w.ck_group;
     }
     const CompArgs& A = MV ? Am : A0;
     // The prologue's loads are all issued before any of them is waited for:
@@ -352,7 +355,7 @@ __device__ __forceinline__ void items_role(const CompArgs& A0, const ItemArgs& I
     uint32_t vw[VPT];
 #pragma unroll
     for (int k = 0; k < VPT; ++k) vw[k] = vsrc[min(tid + k * BS, VSW - 1)];
-    const uint4 ent = I.items[(int64_t)v * A.ras.n_tiles + (item - first)];
+    const uint4 ent = I.items[(int64_t)v * A0.ras.n_tiles + (item - first)];
     const int tile = (int)ent.x;
     const uint32_t raw_start = ent.y, L = ent.z;
     const int tx = tile % A.ras.tiles_x, ty = tile / A.ras.tiles_x;
@@ -531,13 +534,16 @@ __device__ __forceinline__ void tiles_role(const StepArgs& S, int v, VariantStat
   const uint64_t* stop_key = S.stop_key;
   const uint32_t* tile_start = S.tile_start;
   const uint32_t* tile_cnt = S.tile_cnt;
+  int tiles_x = S.tiles_x, tiles_y = S.tiles_y;
   if constexpr (MV) {
-    const ViewArgs& w = S.views[v % S.K];
+    const ViewArgs& w = S.views[S.t_view_of ? (int)S.t_view_of[v] : v % S.K];
     stop_key = w.stop_key;
     tile_start = w.tile_start;
     tile_cnt = w.tile_cnt;
+    tiles_x = w.ras.tiles_x;
+    tiles_y = w.ras.tiles_y;
   }
-  enumerate_items(slot.touch, slot.n_touch, S.tiles_x, S.tiles_y, stop_key, tile_start, tile_cnt,
+  enumerate_items(slot.touch, slot.n_touch, tiles_x, tiles_y, stop_key, tile_start, tile_cnt,
                   S.t_items + (int64_t)v * S.n_tiles, &nd, &ni, &pred);
   if (lane == 0) {
     S.t_vs[v].n_dirty = nd;
@@ -565,17 +571,24 @@ __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_campaign_st
   }
   if (b < nt + nr) {
     const int v = (b - nt) * NW + wave;
-    if (v < S.rB) reduce_batch_variant(S.r_parts, S.r_item_off, S.r_n_items, S.r_vs, S.n_pixels, v, S.r_out);
+    if (v < S.rB) {
+      uint32_t n_pixels = S.n_pixels;
+      if constexpr (MV) {
+        const ViewArgs& w = S.views[S.r_view_of ? (int)S.r_view_of[v] : v % S.K];
+        n_pixels = (uint32_t)(w.W * w.H);
+      }
+      reduce_batch_variant(S.r_parts, S.r_item_off, S.r_n_items, S.r_vs, n_pixels, v, S.r_out);
+    }
     return;
   }
-  items_role<TILE, MV>(S.A, S.I, S.K, S.views);
+  items_role<TILE, MV>(S.A, S.I, S.K, S.views, S.i_view_of);
 }
 
 void launch_campaign_step(const StepArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int nw = a.A.ras.tile * a.A.ras.tile / 64;
   const int grid = (a.tB + nw - 1) / nw + (a.rB + nw - 1) / nw + (a.I.B > 0 ? a.I.grid : 0);
   if (grid <= 0) return;
-  if (a.K > 1) {
+  if (a.views) {
     switch (a.A.ras.tile) {
       case 8: hipExtLaunchKernelGGL(k_campaign_step<8, true>, dim3(grid), dim3(64), 0, st, e0, e1, 0, a); break;
       case 32: hipExtLaunchKernelGGL(k_campaign_step<32, true>, dim3(grid), dim3(1024), 0, st, e0, e1, 0, a); break;

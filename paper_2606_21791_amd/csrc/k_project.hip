@@ -222,10 +222,11 @@ __global__ void __launch_bounds__(64) k_campaign_touch(DevScene s, DevBox box, D
                                                        const uint32_t* __restrict__ depth,
                                                        const uint2* __restrict__ rect, const sg_site* sites,
                                                        const sg_variant* variants, int n, VariantState* vs, Rec* ovr,
-                                                       int stride, int offset) {
+                                                       int stride, int offset, const uint16_t* view_of, int view) {
   using L = Layout<DEG>;
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= n) return;
+  if (view_of && view_of[g] != view) return;   // a variant of another scene
   const sg_variant var = variants[g];
   const sg_site* vsites = sites + var.site_off;
   const bool guard = var.guard != 0 && box.mask != 0;
@@ -343,14 +344,15 @@ void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam
 void launch_campaign_touch(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                            const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
                            const uint2* rect, const sg_site* sites, const sg_variant* variants, int n,
-                           VariantState* vs, Rec* ovr, int stride, int offset, hipStream_t st) {
+                           VariantState* vs, Rec* ovr, int stride, int offset, const uint16_t* view_of, int view,
+                           hipStream_t st) {
   if (n <= 0) return;
   const int grid = (n + 63) / 64;
   switch (s.sh_degree) {
-    case 0: k_campaign_touch<0><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset); break;
-    case 1: k_campaign_touch<1><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset); break;
-    case 2: k_campaign_touch<2><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset); break;
-    default: k_campaign_touch<3><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset); break;
+    case 0: k_campaign_touch<0><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
+    case 1: k_campaign_touch<1><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
+    case 2: k_campaign_touch<2><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
+    default: k_campaign_touch<3><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
   }
 }
 

@@ -106,8 +106,9 @@ struct sg_ctx {
   // the end of the campaign that last used them; camp_mu serialises
   // campaigns on one context; camp_vargs holds the per-view clean state of a
   // multi-view campaign (its host copy stays alive for the upload)
-  DevBuf camp_sites, camp_vars, camp_vs, camp_ovr, camp_views, camp_vargs;
+  DevBuf camp_sites, camp_vars, camp_vs, camp_ovr, camp_views, camp_vargs, camp_scene_of;
   std::vector<ViewArgs> camp_vargs_host;
+  std::vector<uint16_t> camp_scene_of_host;
   hipEvent_t camp_done = nullptr;
   std::mutex camp_mu;
   // guards ws, in_use and the timing state: sg_campaign enqueues from several
@@ -550,6 +551,7 @@ void sg_ctx_destroy(sg_ctx* c) {
   dev_free(c, c->camp_ovr);
   dev_free(c, c->camp_views);
   dev_free(c, c->camp_vargs);
+  dev_free(c, c->camp_scene_of);
   if (c->camp_done) (void)hipEventDestroy(c->camp_done);
   for (int p = 0; p < SG_N_PASSES; ++p)
     for (auto& pr : c->pending[p]) c->ev_pool.insert(c->ev_pool.end(), {pr.first, pr.second});
@@ -1045,7 +1047,8 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
 // sg_render_batch(_views) on the same batches.
 static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, const sg_site* sites, int32_t n_sites,
                                     const sg_variant* variants, int32_t n_variants, const DevBox& box, int B, int NS,
-                                    int NT, sg_metrics_t* metrics_out, hipStream_t caller) {
+                                    int NT, sg_metrics_t* metrics_out, hipStream_t caller,
+                                    const uint16_t* scene_of = nullptr, const DevBox* scene_boxes = nullptr) {
   constexpr int kChunk = 1 << 17;   // variants staged per pre-pass (one view)
   std::lock_guard<std::mutex> cg(ctx->camp_mu);
   if (ctx->camp_done) HIP_TRY(hipEventSynchronize(ctx->camp_done));   // the previous campaign's buffers are free
@@ -1060,15 +1063,19 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
   constexpr int64_t kSharedBytes = (int64_t)16 << 30;
   int max_tiles = 0;
   for (int v = 0; v < K; ++v) max_tiles = std::max(max_tiles, preps[v]->ras.n_tiles);
-  bool mv = K > 1 && (int64_t)B * K <= kMaxBatch &&
-            (int64_t)B * K * max_tiles * (int64_t)(sizeof(uint4) + sizeof(Partial)) * 3 * NS <= kSharedBytes;
-  for (int k = 1; k < K && mv; ++k) {
+  // scene_of (host, n_variants entries): the K preps are scenes (or views)
+  // of their own and each variant is rendered in preps[scene_of[v]] only; all
+  // of them share the launches through the per-view table.
+  const bool sc = scene_of != nullptr;
+  bool mv = sc || (K > 1 && (int64_t)B * K <= kMaxBatch &&
+                   (int64_t)B * K * max_tiles * (int64_t)(sizeof(uint4) + sizeof(Partial)) * 3 * NS <= kSharedBytes);
+  for (int k = 1; k < K && mv && !sc; ++k) {
     const sg_prep* a = preps[0];
     const sg_prep* c = preps[k];
     mv = a->cam.W == c->cam.W && a->cam.H == c->cam.H && a->ck_group == c->ck_group &&
          std::memcmp(&a->ras, &c->ras, sizeof(DevRaster)) == 0;
   }
-  const int per = mv ? K : 1;                                  // variant-views per variant in a launch
+  const int per = mv && !sc ? K : 1;                           // variant-views per variant in a launch
   const int64_t cap = mv ? (int64_t)1 << 21 : (int64_t)kChunk;  // variant-views staged per pre-pass
   const int chunk = (int)std::min<int64_t>(n_variants, std::max<int64_t>(B, (cap / per / B) * B));
   SG_TRY(dev_alloc(ctx, ctx->camp_sites, std::max<size_t>(1, (size_t)n_sites) * sizeof(sg_site)));
@@ -1086,12 +1093,21 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
                                          P<uint32_t>(p->tile_start), P<uint32_t>(p->tile_cnt), P<uint64_t>(p->keys),
                                          P<float>(p->frame), rs ? P<uint32_t>(p->stop) : nullptr,
                                          rs ? P<float4>(p->ck) : nullptr, rs ? P<uint32_t>(p->ck_off) : nullptr,
-                                         rs ? P<uint64_t>(p->stop_key) : nullptr};
+                                         rs ? P<uint64_t>(p->stop_key) : nullptr, p->ras, p->cam.W, p->cam.H,
+                                         p->ck_group};
     }
     SG_TRY(dev_alloc(ctx, ctx->camp_vargs, (size_t)K * sizeof(ViewArgs)));
     HIP_TRY(hipMemcpyAsync(ctx->camp_vargs.p, ctx->camp_vargs_host.data(), (size_t)K * sizeof(ViewArgs),
                            hipMemcpyHostToDevice, caller));
     d_views = P<ViewArgs>(ctx->camp_vargs);
+  }
+  const uint16_t* d_scene_of = nullptr;
+  if (sc) {
+    ctx->camp_scene_of_host.assign(scene_of, scene_of + n_variants);
+    SG_TRY(dev_alloc(ctx, ctx->camp_scene_of, std::max<size_t>(1, (size_t)n_variants) * sizeof(uint16_t)));
+    HIP_TRY(hipMemcpyAsync(ctx->camp_scene_of.p, ctx->camp_scene_of_host.data(), (size_t)n_variants * sizeof(uint16_t),
+                           hipMemcpyHostToDevice, caller));
+    d_scene_of = P<uint16_t>(ctx->camp_scene_of);
   }
   if (n_sites)
     HIP_TRY(hipMemcpyAsync(ctx->camp_sites.p, sites, (size_t)n_sites * sizeof(sg_site), hipMemcpyHostToDevice, caller));
@@ -1128,13 +1144,14 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
       const sg_prep* prep = preps[view];
       const DevRaster& ras = prep->ras;
       // per-view records: view-major (cn per view) view after view, variant-major (K per variant) when shared
-      sg_metrics_t* out = K == 1 ? metrics_out + c0 : per_view + (mv ? 0 : (int64_t)view * cn);
-      const CompArgs ca0 = item_comp_args(ws[0], prep, nullptr);
+      sg_metrics_t* out = K == 1 || sc ? metrics_out + c0 : per_view + (mv ? 0 : (int64_t)view * cn);
+      CompArgs ca0 = item_comp_args(ws[0], prep, nullptr);
+      if (mv) ca0.ras.n_tiles = max_tiles;   // work items sit max_tiles apart per variant-view
       const ItemArgs it0 = item_args(ctx, ws[0], prep, B);
       StepArgs base{};
       base.tiles_x = ras.tiles_x;
       base.tiles_y = ras.tiles_y;
-      base.n_tiles = ras.n_tiles;
+      base.n_tiles = mv ? max_tiles : ras.n_tiles;
       base.stop_key = prep->ck_group ? P<uint64_t>(prep->stop_key) : nullptr;
       base.tile_start = P<uint32_t>(prep->tile_start);
       base.tile_cnt = P<uint32_t>(prep->tile_cnt);
@@ -1144,9 +1161,10 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
       for (int k = mv ? 0 : view; k < (mv ? K : view + 1); ++k) {
         const sg_prep* pk = preps[k];
         PassScope ps(ctx, SG_PASS_VARIANT_PREP, caller);
-        launch_campaign_touch(pk->scene, box, pk->cam, pk->ras, P<float4>(pk->r0), P<float4>(pk->r1),
-                              P<float4>(pk->r2), P<uint32_t>(pk->depth), P<uint2>(pk->rect), d_sites, d_vars + c0, cn,
-                              c_vs, c_ovr, per, mv ? k : 0, caller);
+        launch_campaign_touch(pk->scene, sc ? scene_boxes[k] : box, pk->cam, pk->ras, P<float4>(pk->r0),
+                              P<float4>(pk->r1), P<float4>(pk->r2), P<uint32_t>(pk->depth), P<uint2>(pk->rect),
+                              d_sites, d_vars + c0, cn, c_vs, c_ovr, per, mv && !sc ? k : 0,
+                              sc ? d_scene_of + c0 : nullptr, k, caller);
       }
       hipEvent_t staged = nullptr;
       HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
@@ -1171,6 +1189,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
               const int q = i % 3;
               a.tB = nvb(i) * per;
               a.t_vs = c_vs + (int64_t)lb(i) * per;
+              if (sc) a.t_view_of = d_scene_of + c0 + lb(i);
               a.t_items = P<uint4>(W->st_items[q]);
               a.t_n_items = P<uint32_t>(W->st_n[q]);
               a.t_item_off = P<uint32_t>(W->st_off[q]);
@@ -1189,6 +1208,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
               a.I.item_off = P<uint32_t>(W->st_off[q]);
               a.I.counter = P<uint32_t>(W->st_ctl) + 4 * q;
               a.I.B = nvb(i - 1) * per;
+              if (sc) a.i_view_of = d_scene_of + c0 + lb(i - 1);
             }
             if (i >= 2) {
               const int q = (i - 2) % 3;
@@ -1198,6 +1218,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
               a.r_n_items = P<uint32_t>(W->st_n[q]);
               a.r_vs = c_vs + (int64_t)lb(i - 2) * per;
               a.r_out = out + (int64_t)lb(i - 2) * per;
+              if (sc) a.r_view_of = d_scene_of + c0 + lb(i - 2);
             }
             if (a.tB == 0 && a.I.B == 0 && a.rB == 0) continue;
             PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st, true);
@@ -1224,7 +1245,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
         (void)hipEventDestroy(e);
       }
     }
-    if (K > 1) launch_pool_views(per_view, K, cn, mv ? 1 : cn, mv ? K : 1, metrics_out + c0, caller);
+    if (K > 1 && !sc) launch_pool_views(per_view, K, cn, mv ? 1 : cn, mv ? K : 1, metrics_out + c0, caller);
   }
   HIP_TRY(hipEventRecord(ctx->camp_done, caller));
   return check_last("sg_campaign");
@@ -1358,6 +1379,62 @@ sg_status sg_campaign(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t 
                       sg_metrics_t* metrics_out, void* stream) {
   return sg_campaign_views(ctx, &prep, 1, sites, n_sites, variants, n_variants, box, box_field_mask, cfg, metrics_out,
                            stream);
+}
+
+sg_status sg_campaign_scenes(sg_ctx* ctx, sg_prep* const* preps, int32_t n_preps, const sg_site* sites, int32_t n_sites,
+                             const sg_variant* variants, const uint16_t* scene_of, int32_t n_variants,
+                             const sg_box* const* boxes, uint32_t box_field_mask, const sg_campaign_cfg* cfg,
+                             sg_metrics_t* metrics_out, void* stream) {
+  if (!ctx || !preps || !metrics_out) return fail(SG_E_INVAL, "ctx/preps/metrics_out is NULL");
+  if (n_preps < 1 || n_preps > kMaxViews) return fail(SG_E_INVAL, "n_preps must be in [1, 64]");
+  for (int k = 0; k < n_preps; ++k) {
+    if (!preps[k]) return fail(SG_E_INVAL, "preps[" + std::to_string(k) + "] is NULL");
+    if (preps[k]->ctx != ctx && preps[k]->ctx->device != ctx->device)
+      return fail(SG_E_INVAL, "preps[" + std::to_string(k) + "] is on another device");
+    if (preps[k]->ras.tile != preps[0]->ras.tile)
+      return fail(SG_E_INVAL, "the prepared scenes must share one tile size");
+  }
+  if (n_variants < 0 || (n_variants > 0 && (!variants || !scene_of))) return fail(SG_E_INVAL, "bad variants");
+  if (n_sites < 0 || (n_sites > 0 && !sites)) return fail(SG_E_INVAL, "bad sites");
+  const int B = cfg && cfg->batch > 0 ? cfg->batch : 32;
+  const int NS = cfg && cfg->streams > 0 ? cfg->streams : 8;
+  const int NT = std::min(cfg && cfg->threads > 0 ? cfg->threads : 2, NS);
+  if (B > kMaxBatch || NS > 64 || NT > 64) return fail(SG_E_INVAL, "campaign batch/streams/threads out of range");
+  std::vector<DevBox> db(n_preps);
+  for (int k = 0; k < n_preps; ++k)
+    SG_TRY(to_dev_box(boxes ? boxes[k] : nullptr, box_field_mask, preps[k]->scene, &db[k]));
+  // every variant against its own scene: sites in range and valid for that
+  // scene, guard only with a box, at most kMaxTouch distinct primitives
+  std::vector<uint32_t> prims;
+  for (int v = 0; v < n_variants; ++v) {
+    const sg_variant& x = variants[v];
+    const int sc = scene_of[v];
+    if (sc >= n_preps) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": scene index out of range");
+    if ((uint64_t)x.site_off + x.n_sites > (uint64_t)n_sites)
+      return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": sites out of range");
+    if (x.guard && !db[sc].mask) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": guard requested without a box");
+    if (x.protect > SG_PROTECT_VOTE) return fail(SG_E_INVAL, "variant " + std::to_string(v) + ": unknown protect mode");
+    SG_TRY(validate_sites(preps[sc]->scene, sites + x.site_off, (int32_t)x.n_sites));
+    prims.clear();
+    for (uint32_t k = 0; k < x.n_sites; ++k) {
+      const uint32_t pr = sites[x.site_off + k].prim;
+      if (std::find(prims.begin(), prims.end(), pr) == prims.end()) prims.push_back(pr);
+    }
+    if ((int)prims.size() > kMaxTouch)
+      return fail(SG_E_UNSUPPORTED, "variant " + std::to_string(v) + ": more than 8 corrupted primitives");
+  }
+  if (n_variants == 0) return SG_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    while ((int)ctx->campaign_streams.size() < NS) {
+      hipStream_t st = nullptr;
+      HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      ctx->campaign_streams.push_back(st);
+    }
+  }
+  return campaign_pipelined(ctx, preps, n_preps, sites, n_sites, variants, n_variants, db[0], B, NS, NT, metrics_out,
+                            S(stream), scene_of, db.data());
 }
 
 sg_status sg_ssim(sg_ctx* ctx, const float* images, const float* clean, int32_t B, int32_t H, int32_t W, double* out,

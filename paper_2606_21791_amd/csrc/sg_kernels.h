@@ -187,10 +187,13 @@ void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam
 // flag) and override records (kMaxTouch per variant).  Variant g's state is
 // vs[g * stride + offset] and its records start at ovr[(g * stride + offset)
 // * kMaxTouch] (stride K, offset the view: the views of a variant side by side).
+// view_of (nullable): only the variants g with view_of[g] == view are staged
+// (a campaign over several scenes stages each scene's variants in its launch).
 void launch_campaign_touch(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                            const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
                            const uint2* rect, const sg_site* sites, const sg_variant* variants, int n,
-                           VariantState* vs, Rec* ovr, int stride, int offset, hipStream_t st);
+                           VariantState* vs, Rec* ovr, int stride, int offset, const uint16_t* view_of, int view,
+                           hipStream_t st);
 
 // k_bin.hip
 struct BinBuffers {
@@ -266,7 +269,8 @@ void launch_composite_items(const CompArgs& a, const ItemArgs& it, hipStream_t s
 // in workgroups of their own and on buffers of their own, so that nothing
 // in the launch waits for anything else in it.  A role with no batch has
 // B = 0.
-// The clean state of one view of a multi-view campaign step.
+// The clean state of one prepared view of a multi-view step: a camera view
+// of the batch's scene, or one of several scenes of uneven size.
 struct ViewArgs {
   const float4* r0;
   const float4* r1;
@@ -279,6 +283,9 @@ struct ViewArgs {
   const float4* ck;
   const uint32_t* ck_off;
   const uint64_t* stop_key;
+  DevRaster ras;        // its tile grid and compositing constants
+  int32_t W, H;
+  uint32_t ck_group;    // checkpoint spacing of its resume state (0: none)
 };
 
 struct StepArgs {
@@ -305,12 +312,18 @@ struct StepArgs {
   // compositing of the current batch (I.B = 0: none)
   CompArgs A;
   ItemArgs I;
-  // K > 1: each variant in K views of one resolution in the same launch.  The
-  // roles then count variant-views, view k of variant v at index v * K + k,
-  // and take each view's clean state from views[k] in place of the fields of
-  // A (and of stop_key, tile_start, tile_cnt above) that differ by view.
+  // Multi-view steps (views != null): each variant-view takes its view's
+  // clean state from views[] in place of the fields of A (and of stop_key,
+  // tile_start, tile_cnt, tiles_x, tiles_y and n_pixels above) that differ by
+  // view.  Either every variant in K views (K > 1, view k of variant v at
+  // index v * K + k), or every variant in one view of its own (*_view_of:
+  // the view of each variant of the role's batch).  Work items then sit
+  // n_tiles (the largest view's tile count) apart per variant-view.
   int K = 1;
   const ViewArgs* views = nullptr;
+  const uint16_t* t_view_of = nullptr;
+  const uint16_t* i_view_of = nullptr;
+  const uint16_t* r_view_of = nullptr;
 };
 // e0, e1 (nullable): events recorded at the launch's own start and end.
 void launch_campaign_step(const StepArgs& a, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

@@ -375,6 +375,66 @@ def test_campaign_matches_batches(ctx):
         ctx.campaign(prep, sa, bad, b.metrics_tensor(len(va)), box=box, batch=B)
 
 
+def test_campaign_scenes_of_uneven_size(ctx):
+    """Variants of three scenes of uneven size (primitive counts, frame sizes,
+    formats, SH degrees) mixed in one campaign share its launches: every
+    record equals sg_render_batch's on the variant's own scene, guarded
+    variants included; invalid scene indices and sites are rejected."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    specs = [(6741, 1, "f32", 200, 160), (2500, 0, "bf16", 96, 64), (12000, 3, "f16", 256, 144)]
+    preps, boxes, site_sets = [], [], []
+    for j, (n, sh, fmt, w, h) in enumerate(specs):
+        sc = synth.make_scene(n, seed=70 + j, sh_degree=sh)
+        ds = b.DeviceScene.upload(ctx, sc, fmt)
+        preps.append(ctx.prepare(ds, synth.make_camera(w, h)))
+        preps[-1]._ds = ds   # keeps the scene's device arrays alive with its prepared state
+        W = formats.width(fmt)
+        if j == 0:
+            lo, hi = synth.make_box_jitter(sc, seed=75)
+            boxes.append(b.Box.per_prim(ctx, lo, hi, fmt))
+        else:
+            boxes.append(None)
+        site_sets.append(synth.make_sites_stratified(n, sh, 2 * W, seed=80 + j, width_bits=W,
+                                                     fields=(0, 1, 2, 3, 4)))
+    # one shared site array; each variant one site of its own scene, interleaved
+    cat = lambda key: np.concatenate([getattr(t, key) for t in site_sets])
+    sa = b.sites_array(cat("field"), cat("comp"), cat("prim"), cat("bit"))
+    base = np.cumsum([0] + [len(t.prim) for t in site_sets])
+    rng = np.random.default_rng(77)
+    scene_of = rng.integers(0, 3, size=150).astype(np.uint16)
+    off = np.array([base[k] + rng.integers(0, len(site_sets[k].prim)) for k in scene_of])
+    va = b.variants_array(off, np.ones(len(off), np.uint32))
+    va["guard"] = (scene_of == 0) & (np.arange(len(off)) % 2 == 1)
+    got = b.metrics_tensor(len(va))
+    ctx.campaign_scenes(preps, sa, va, scene_of, got, boxes=boxes, batch=8, streams=5, threads=2)
+    torch.cuda.synchronize()
+    G = b.read_metrics(got)
+    for k in range(3):
+        # the reference: sg_render_batch on the scene's own sites (it checks every site it is given)
+        idx = np.nonzero(scene_of == k)[0]
+        t = site_sets[k]
+        vk = va[idx].copy()
+        vk["site_off"] -= np.uint32(base[k])
+        mt = b.metrics_tensor(len(idx))
+        ctx.render_batch(preps[k], b.sites_array(t.field, t.comp, t.prim, t.bit), vk, box=boxes[k], metrics=mt)
+        ref = b.read_metrics(mt)
+        assert np.all(ref["path"] == 0)
+        for key in ref.dtype.names:
+            assert np.array_equal(G[key][idx], ref[key]), (k, key)
+    assert np.any(G["changed_px"] > 0) and np.any(G["clamps"] > 0)
+    assert len(set(G["n_pixels"].tolist())) == 3
+    with pytest.raises(b.SgError):
+        bad = scene_of.copy()
+        bad[4] = 3
+        ctx.campaign_scenes(preps, sa, va, bad, b.metrics_tensor(len(va)), boxes=boxes)
+    with pytest.raises(b.SgError):
+        # a scene-2 site (component of SH degree 3) given to a variant of the SH0 scene
+        wrong = scene_of.copy()
+        wrong[:] = 1
+        ctx.campaign_scenes(preps, sa, va, wrong, b.metrics_tensor(len(va)), boxes=boxes)
+
+
 @pytest.mark.parametrize("tile", [8, 32])
 def test_campaign_other_tile_sizes(ctx, tile):
     """The pipelined campaign at 8 x 8 and 32 x 32 tiles (one and sixteen
