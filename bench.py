@@ -188,7 +188,8 @@ def main():
                     help="oracle processes run at once for the all-core baseline (0: the host's cores, at most 16)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="seconds of Poisson arrivals for the serving measurement (0: skip)")
-    ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve", "copy", "views", "storm"],
+    ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve", "copy", "views", "storm",
+                                                         "scenes"],
                     help="w2: the headline; guard: support guard and accumulated dose on the N=134,826 scene; "
                          "large: the 2,056,645-primitive bf16 scene at 1600x900; stress: one guarded render at "
                          "65,812,640 primitives")
@@ -198,7 +199,7 @@ def main():
         sys.exit(2)
     if args.workload != "w2":
         {"guard": run_guard, "large": run_large, "stress": run_stress, "serve": run_serve,
-         "copy": run_copy, "views": run_views, "storm": run_storm}[args.workload](args)
+         "copy": run_copy, "views": run_views, "storm": run_storm, "scenes": run_scenes}[args.workload](args)
         return
 
     sc, cam, sites = _workload(args.fmt)
@@ -803,6 +804,78 @@ def run_views(args):
            "curve": curve,
            "paper_context": {"view_mpix_per_s": 837, "saturation_views": 16, "hardware": "Blackwell-generation GPU, "
                              "full renders of K views per injection"}}
+    print(json.dumps(out), flush=True)
+
+
+def run_scenes(args):
+    """Scenes of uneven size in one campaign: single-bit variants of three
+    resident scenes (6,741 Gaussians fp32 at 512x512, 134,826 fp32 at
+    800x800, 500,000 clustered bf16 at 1600x900, all SH degree 3) mixed in
+    random order, B variants per launch.  The same variants as one
+    sg_campaign_scenes call, and as one sg_campaign per scene back to back."""
+    import torch
+    from paper_2606_21791_amd import binding as sgb, synth
+    specs = [(6741, "f32", 512, 512, "uniform"), (N_HI, "f32", 800, 800, "uniform"),
+             (500_000, "bf16", 1600, 900, "clusters")]
+    ctx = sgb.Context(0)
+    ctx.set_persistent(args.wgs_per_cu)
+    ctx.set_resume(args.resume)
+    preps, keep, site_sets = [], [], []
+    for j, (n, fmt, w, h, means) in enumerate(specs):
+        sc = synth.make_scene(n, seed=90 + j, sh_degree=3, means=means)
+        ds = sgb.DeviceScene.upload(ctx, sc, fmt)
+        cam = synth.make_camera(w, h) if means == "uniform" else synth.make_camera(w, h, distance=25.0)
+        preps.append(ctx.prepare(ds, cam, sgb.raster_struct(tile=args.tile)))
+        keep.append(ds)
+        W = 32 if fmt == "f32" else 16
+        site_sets.append(synth.make_sites_stratified(n, 3, 1000, seed=95 + j, width_bits=W))
+    torch.cuda.synchronize()
+    cat = lambda key: np.concatenate([getattr(t, key) for t in site_sets])
+    sa = sgb.sites_array(cat("field"), cat("comp"), cat("prim"), cat("bit"))
+    base = np.cumsum([0] + [len(t.prim) for t in site_sets])
+    B = args.batch
+    n_inj = min(args.steps, 1000) * B
+    rng = np.random.default_rng(97)
+    scene_of = rng.integers(0, len(specs), size=n_inj).astype(np.uint16)
+    off = np.array([base[k] + rng.integers(0, len(site_sets[k].prim)) for k in scene_of])
+    va = sgb.variants_array(off, np.ones(n_inj, np.uint32))
+    kw = dict(batch=B, streams=args.streams, threads=max(1, args.threads))
+    mt = sgb.metrics_tensor(n_inj)
+    ctx.campaign_scenes(preps, sa, va[:4 * B], scene_of[:4 * B], mt, **kw)
+    torch.cuda.synchronize()
+    with _no_gc():
+        t0 = time.perf_counter()
+        ctx.campaign_scenes(preps, sa, va, scene_of, mt, **kw)
+        torch.cuda.synchronize()
+        dt_mixed = time.perf_counter() - t0
+    mixed = sgb.read_metrics(mt)
+    # one campaign per scene, on that scene's own sites
+    per_scene = []
+    for k in range(len(specs)):
+        idx = np.nonzero(scene_of == k)[0]
+        t = site_sets[k]
+        vk = va[idx].copy()
+        vk["site_off"] -= np.uint32(base[k])
+        per_scene.append((idx, sgb.sites_array(t.field, t.comp, t.prim, t.bit), vk, sgb.metrics_tensor(len(idx))))
+    for k, (idx, sak, vk, mk) in enumerate(per_scene):
+        ctx.campaign(preps[k], sak, vk[:4 * B], mk, **kw)
+    torch.cuda.synchronize()
+    with _no_gc():
+        t0 = time.perf_counter()
+        for k, (idx, sak, vk, mk) in enumerate(per_scene):
+            ctx.campaign(preps[k], sak, vk, mk, **kw)
+        torch.cuda.synchronize()
+        dt_split = time.perf_counter() - t0
+    same = all(np.array_equal(sgb.read_metrics(mk)[key], mixed[key][idx])
+               for idx, _, _, mk in per_scene for key in ("sse", "changed_px", "dirty_tiles", "evals"))
+    out = {"metric": "scenes of uneven size: injections/s of one mixed campaign vs one campaign per scene",
+           "config": {"workload": "3 scenes (6,741 fp32 512x512; 134,826 fp32 800x800; 500,000 clustered bf16 "
+                                  f"1600x900; SH degree 3), single-bit variants in random scene order, B={B}",
+                      "injections": n_inj, "streams": args.streams, "host_threads": args.threads,
+                      "wgs_per_cu": args.wgs_per_cu, "resume_spacing": args.resume},
+           "mixed_inj_per_s": round(n_inj / dt_mixed, 1), "per_scene_inj_per_s": round(n_inj / dt_split, 1),
+           "records_identical": bool(same),
+           "per_scene_injections": [int(len(idx)) for idx, _, _, _ in per_scene]}
     print(json.dumps(out), flush=True)
 
 
