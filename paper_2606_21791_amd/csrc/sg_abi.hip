@@ -1043,8 +1043,11 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
 // raster and checkpoint spacing share each launch (its stages count
 // variant-views); other view sets follow one another on the device (the
 // caller's stream joins every campaign stream before the next pre-pass),
-// with no host synchronisation.  The records are those of
-// sg_render_batch(_views) on the same batches.
+// with no host synchronisation.  With scene_of, the K preps are scenes of
+// their own: each scene's pre-pass stages its variants, and every launch
+// takes each variant's clean state from the per-scene table.  The records
+// are those of sg_render_batch(_views) on the same batches (on each
+// variant's own scene).
 static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, const sg_site* sites, int32_t n_sites,
                                     const sg_variant* variants, int32_t n_variants, const DevBox& box, int B, int NS,
                                     int NT, sg_metrics_t* metrics_out, hipStream_t caller,
