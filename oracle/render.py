@@ -187,37 +187,55 @@ def _order(proj):
     return idx[np.lexsort((idx, keys))]
 
 
-def render(proj, cam, raster: Raster = Raster(), bands: Bands = Bands()) -> dict:
+def render(proj, cam, raster: Raster = Raster(), bands: Bands = Bands(), window=None) -> dict:
     """Full frame, primitive-major: contributors are visited in (depth, id)
     order and each pixel applies the per-contributor rule above, which is the
-    same sequence of operations per pixel as a pixel-major loop."""
+    same sequence of operations per pixel as a pixel-major loop.
+
+    window=(x0, y0, x1, y1) evaluates only the pixels x0 <= i < x1,
+    y0 <= j < y1 (clipped to the frame) and returns arrays of the window's
+    shape.  The rule of a pixel involves no other pixel, so each of them gets
+    exactly the value it has in the full frame; primitives whose support
+    misses the window are not visited."""
     H, W = cam.height, cam.width
-    Tr = np.ones((H, W))
-    C = np.zeros((H, W, 3))
-    done = np.zeros((H, W), bool)
-    amb = np.zeros((H, W), bool)
-    terr = np.zeros((H, W))
-    ovf = np.zeros((H, W, 3), bool)
+    if window is None:
+        x0, y0, x1, y1 = 0, 0, W, H
+    else:
+        x0, y0 = max(0, int(window[0])), max(0, int(window[1]))
+        x1, y1 = min(W, int(window[2])), min(H, int(window[3]))
+        x1, y1 = max(x1, x0), max(y1, y0)
+    h, w = y1 - y0, x1 - x0
+    Tr = np.ones((h, w))
+    C = np.zeros((h, w, 3))
+    done = np.zeros((h, w), bool)
+    amb = np.zeros((h, w), bool)
+    terr = np.zeros((h, w))
+    ovf = np.zeros((h, w, 3), bool)
     cut = raster.cut_q
     # a primitive culled by a range test taken inside its band may be drawn by
     # an fp32 implementation, anywhere on the frame
     if np.any(proj["amb"] & ~proj["valid"] & ~proj["nonfinite_param"]):
         amb[:] = True
-    for i in _order(proj):
+    order = _order(proj)
+    # pixels whose centre can satisfy q <= cut (plus a margin for the band),
+    # as the pixel-index range [i0, i1] x [j0, j1] of each primitive, clipped
+    # to the window
+    u_all, v_all = proj["u"][order], proj["v"][order]
+    rx = np.sqrt(cut * proj["a"][order]) * 1.001 + 1e-3
+    ry = np.sqrt(cut * proj["c"][order]) * 1.001 + 1e-3
+    I0 = np.clip(np.ceil(u_all - rx - 0.5), x0, x1).astype(np.int64)
+    I1 = np.clip(np.floor(u_all + rx - 0.5), x0 - 1, x1 - 1).astype(np.int64)
+    J0 = np.clip(np.ceil(v_all - ry - 0.5), y0, y1).astype(np.int64)
+    J1 = np.clip(np.floor(v_all + ry - 0.5), y0 - 1, y1 - 1).astype(np.int64)
+    meets = (I1 >= I0) & (J1 >= J0)
+    for k in np.nonzero(meets)[0]:
+        i = order[k]
         a, b, c, det = proj["a"][i], proj["b"][i], proj["c"][i], proj["det"][i]
         u, v = proj["u"][i], proj["v"][i]
-        # pixels whose centre can satisfy q <= cut (plus a margin for the band)
-        rx = np.sqrt(cut * a) * 1.001 + 1e-3
-        ry = np.sqrt(cut * c) * 1.001 + 1e-3
-        i0 = int(np.clip(np.ceil(u - rx - 0.5), 0, W))
-        i1 = int(np.clip(np.floor(u + rx - 0.5), -1, W - 1))
-        j0 = int(np.clip(np.ceil(v - ry - 0.5), 0, H))
-        j1 = int(np.clip(np.floor(v + ry - 0.5), -1, H - 1))
+        i0, i1, j0, j1 = int(I0[k]), int(I1[k]), int(J0[k]), int(J1[k])
+        win = (slice(j0 - y0, j1 - y0 + 1), slice(i0 - x0, i1 - x0 + 1))
         if proj["amb"][i]:
-            amb[max(j0, 0):j1 + 1, max(i0, 0):i1 + 1] = True
-        if i1 < i0 or j1 < j0:
-            continue
-        win = (slice(j0, j1 + 1), slice(i0, i1 + 1))
+            amb[win] = True
         dx = (np.arange(i0, i1 + 1) + 0.5)[None, :] - u
         dy = (np.arange(j0, j1 + 1) + 0.5)[:, None] - v
         q = (c * dx * dx - 2.0 * b * dx * dy + a * dy * dy) / det
@@ -253,7 +271,7 @@ def render(proj, cam, raster: Raster = Raster(), bands: Bands = Bands()) -> dict
     pre[ovf] = np.inf
     image = np.minimum(pre, 1.0)
     nonfinite = bool(np.any(proj["nonfinite_param"]) or np.any(ovf))
-    return dict(image=image, pre=pre, amb=amb, nonfinite=nonfinite, T=Tr)
+    return dict(image=image, pre=pre, amb=amb, nonfinite=nonfinite, T=Tr, window=(x0, y0, x1, y1))
 
 
 def render_pixels(proj, cam, xs, ys, raster: Raster = Raster()) -> np.ndarray:

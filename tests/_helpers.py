@@ -56,3 +56,53 @@ def compare_metrics(m, ref_img, clean_img, amb, nonfinite):
 
 def ref_metrics(ref_img, clean_img, nonfinite, mask=None):
     return ometrics.frame_metrics(ref_img, clean_img, nonfinite, mask)
+
+
+def support_window(proj, i, cam, pad=2.0):
+    """Pixel window (x0, y0, x1, y1) holding every pixel centre that primitive
+    i can reach (q <= 9 on the projection's conic), widened by `pad` pixels;
+    None if the primitive is culled or its support misses the frame."""
+    import math
+    if not proj["valid"][i]:
+        return None
+    rx = math.sqrt(9.0 * proj["a"][i]) * 1.01 + pad
+    ry = math.sqrt(9.0 * proj["c"][i]) * 1.01 + pad
+    u, v = proj["u"][i], proj["v"][i]
+    x0, x1 = max(0, math.floor(u - rx)), min(cam.width, math.ceil(u + rx) + 1)
+    y0, y1 = max(0, math.floor(v - ry)), min(cam.height, math.ceil(v + ry) + 1)
+    if x1 <= x0 or y1 <= y0:
+        return None
+    return (int(x0), int(y0), int(x1), int(y1))
+
+
+def union_window(*wins):
+    wins = [w for w in wins if w is not None]
+    if not wins:
+        return None
+    return (min(w[0] for w in wins), min(w[1] for w in wins), max(w[2] for w in wins), max(w[3] for w in wins))
+
+
+def splice_projection(proj, words, prims, fmt, sh_degree, cam):
+    """The projection of a scene that differs from the projected one only in
+    the primitives `prims`: those are projected alone and written into a copy
+    of `proj`.  Projection treats every primitive on its own, so this equals
+    projecting the whole corrupted scene (up to the rounding order of the
+    library products)."""
+    prims = np.unique(np.atleast_1d(prims).astype(np.int64))
+    one = [w[:, prims] for w in words]
+    q = orender.project(orender.decode_scene(one, fmt), sh_degree, cam)
+    out = dict(proj)
+    for k, v in proj.items():
+        if isinstance(v, np.ndarray) and v.shape[:1] == (proj["n"],):
+            v = v.copy()
+            v[prims] = q[k]
+            out[k] = v
+    return out
+
+
+def changed_window(clean_proj, var_proj, prims, cam):
+    """Window outside which a variant whose corrupted primitives are `prims`
+    equals the clean frame exactly: no pixel outside the old and new supports
+    of those primitives has a different contributor list."""
+    return union_window(*[support_window(p, int(i), cam) for i in np.atleast_1d(prims)
+                          for p in (clean_proj, var_proj)])
