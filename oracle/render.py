@@ -62,20 +62,27 @@ class Bands:
     threshold decision differently from float64.
 
     q: the fp32 quadratic form differs from the exact one by at most
-       q_abs + q_dir * |d| / sqrt(lambda2): a few ulps of q plus the rounding
-       of the fp32 principal direction (about 2^-22 per unit length of d,
-       amplified by 2 * 3 / sqrt(lambda2) at the cut).
+       q_abs + q_rel * q + q_dir * (|d| + 1) * sqrt(q / 9) / sqrt(lambda2): a
+       few ulps of q, plus the rounding of the pixel's eigenframe coordinates
+       (products of the offset d from the centre with the fp32 principal
+       direction, about 2^-23 per unit length of d, which moves q by
+       2 sqrt(q) / sqrt(lambda2) per unit of coordinate error); at the cut the
+       last term is 1.5e-6 |d| / sqrt(lambda2), twice the rounding bound.
     alpha: relative error of o * exp(-q/2) in fp32 (exp, product, rounding of o)
        plus half the q error.
     transmittance: each factor (1 - alpha) carries relative error
-       2^-23 + alpha / (1 - alpha) * alpha_err; the running sum is tracked per pixel.
+       2^-23 + alpha / (1 - alpha) * alpha_err (amax_rel instead for a
+       contributor clamped at alpha_max: 1 - 0.99 and 1 - fp32(0.99) differ by
+       9.5e-7 relative); the running sum is tracked per pixel.
     fp32 range: relative band around FLT_MAX for overflow tests.
     """
-    q_abs: float = 1e-5
+    q_abs: float = 2e-6
+    q_rel: float = 1e-6
     q_dir: float = 1.5e-6
     alpha_rel: float = 4e-7
     t_base: float = 1e-6
     t_step: float = 2.4e-7
+    amax_rel: float = 1.2e-6
     range_rel: float = 1e-5
 
 
@@ -242,7 +249,8 @@ def render(proj, cam, raster: Raster = Raster(), bands: Bands = Bands(), window=
         live = ~done[win]
         araw = proj["o"][i] * np.exp(-0.5 * q)
         alpha = np.minimum(raster.alpha_max, araw)
-        qband = bands.q_abs + bands.q_dir * np.sqrt(dx * dx + dy * dy) / np.sqrt(proj["lam2"][i])
+        qband = bands.q_abs + bands.q_rel * np.abs(q) + bands.q_dir * (np.sqrt(dx * dx + dy * dy) + 1.0) * \
+            np.sqrt(np.abs(q) / cut) / np.sqrt(proj["lam2"][i])
         aband = bands.alpha_rel + 0.5 * qband
         inq = q <= cut
         ina = alpha >= raster.alpha_min
@@ -251,7 +259,11 @@ def render(proj, cam, raster: Raster = Raster(), bands: Bands = Bands(), window=
         amb_a = live & (q <= cut + qband) & (np.abs(alpha / raster.alpha_min - 1.0) <= aband)
         Tw = Tr[win]
         Tn = Tw * (1.0 - alpha)
-        step_err = bands.t_step + (alpha / (1.0 - alpha)) * aband
+        # relative error of the factor (1 - alpha): the alpha error amplified by
+        # alpha / (1 - alpha), or, for a contributor clamped at alpha_max, the
+        # difference between alpha_max and its fp32 value
+        clamped = araw >= raster.alpha_max * (1.0 + aband)
+        step_err = bands.t_step + np.where(clamped, bands.amax_rel, (alpha / (1.0 - alpha)) * aband)
         terr_n = terr[win] + step_err
         stop = contrib & (Tn < raster.t_min)
         amb_t = contrib & (np.abs(Tn / raster.t_min - 1.0) <= bands.t_base + 2.0 * terr_n)
