@@ -8,7 +8,7 @@ the method themselves.
 Scenes stand in for the trained 3DGS models of the paper (Sec. 3, "Scenes and
 models", Table 1), which are not available: the primitive counts follow the
 paper (134,826 for the chair model, a 5% subsample of 6,741, the 2,056,645
-primitives of the real scene in Sec. 5.8).  The value distributions are the
+primitives of the real scene in Sec. 5.6).  The value distributions are the
 ones `make_scene` states: uniform or clustered means, log-scales around -4,
 uniform quaternion directions, opacity logits around 0, uniform base colours
 and small higher-order coefficients.
@@ -48,7 +48,7 @@ class Scene:
         return int(self.fields[0].shape[1])
 
     def subset(self, n: int) -> "Scene":
-        """The first n primitives (the paper subsamples trained models, Sec. 5.5)."""
+        """The first n primitives (the paper subsamples trained models, Sec. 5.6)."""
         return Scene([np.ascontiguousarray(f[:, :n]) for f in self.fields], self.sh_degree, self.seed)
 
 
