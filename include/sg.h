@@ -301,17 +301,31 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
  * context run one at a time (a second call waits until the first one's
  * device buffers are no longer read).
  *
- * Throughput comes from many streams' launches running at once.  The HIP
+ * SG_ENGINE_PERSISTENT renders the campaign in chunks of `batch` variants
+ * (0: as many as fit: a chunk bounds its variant-views so that each may
+ * dirty every tile of its view, within 2^25 work items and 2^18
+ * variant-views) with four launches per chunk on one of two internal
+ * streams: the pre-pass (one per view or scene), one listing every
+ * variant's work items compactly, one persistent launch compositing all of
+ * them and one reducing the records (plus the pooling of K views).  It
+ * needs neither many streams nor many hardware queues; its buffers take up
+ * to 3.3 GB.  Its records equal the pipelined engine's.
+ *
+ * Throughput of the pipelined engine comes from many streams' launches
+ * running at once.  The HIP
  * runtime maps streams onto GPU_MAX_HW_QUEUES hardware queues (4 unless the
  * environment sets it before the runtime starts), and each queue runs its
  * launches one after another: on the MI355X the campaign rate rises with the
  * queue count up to 23 queues and collapses at 24.  Eighteen queues with 64
- * streams is the measured configuration. */
+ * streams is the measured configuration; the pipelined engine returns
+ * SG_E_UNSUPPORTED when GPU_MAX_HW_QUEUES is above 23. */
+typedef enum { SG_ENGINE_PIPELINED = 0, SG_ENGINE_PERSISTENT = 1 } sg_engine;
 typedef struct {
-  int32_t batch;     /* variants per launch; 0 = 32; at most SG_MAX_BATCH */
-  int32_t streams;   /* device streams; 0 = 8 (at most 64) */
-  int32_t threads;   /* host threads; 0 = 2 (at most streams) */
-  int32_t _pad;
+  int32_t batch;     /* variants per launch.  Pipelined: 0 = 32, at most SG_MAX_BATCH.
+                        Persistent: 0 = as many as the work-item buffers hold */
+  int32_t streams;   /* pipelined: device streams; 0 = 8 (at most 64) */
+  int32_t threads;   /* pipelined: host threads; 0 = 2 (at most streams) */
+  int32_t engine;    /* SG_ENGINE_PIPELINED (0) or SG_ENGINE_PERSISTENT */
 } sg_campaign_cfg;
 sg_status sg_campaign(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int32_t n_sites, const sg_variant* variants,
                       int32_t n_variants, const sg_box* box, uint32_t box_field_mask, const sg_campaign_cfg* cfg,
@@ -408,9 +422,11 @@ sg_status sg_ctx_set_graphs(sg_ctx* ctx, int32_t enable);
 enum {
   SG_PASS_VARIANT_PREP = 0,     /* corrupted-primitive projection and dirty-tile planning
                                    (a campaign: its pre-pass over all variants) */
-  SG_PASS_COMPOSITE_ITEMS = 1,  /* persistent incremental compositing (a campaign: its fused
-                                   per-batch step, which also plans and reduces) */
-  SG_PASS_REDUCE = 2,           /* per-variant metric reduction */
+  SG_PASS_COMPOSITE_ITEMS = 1,  /* persistent incremental compositing (a campaign: each fused
+                                   per-batch step launch with a compositing role, which also
+                                   plans the next batch and reduces the previous one) */
+  SG_PASS_REDUCE = 2,           /* per-variant metric reduction (a campaign: the pipeline's fill
+                                   and drain step launches, which have no compositing role) */
   SG_PASS_PROJECT = 3,          /* full projection */
   SG_PASS_BIN = 4,              /* tile counts, offsets and instance scatter */
   SG_PASS_SORT = 5,             /* per-tile depth sort */

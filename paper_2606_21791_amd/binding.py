@@ -21,6 +21,7 @@ SG_F32, SG_F16, SG_BF16 = 0, 1, 2
 SG_RNE, SG_RD, SG_RU = 0, 1, 2
 SG_BOX_GLOBAL, SG_BOX_PER_PRIM = 0, 1
 SG_INCREMENTAL, SG_FULL = 0, 1
+SG_ENGINE_PIPELINED, SG_ENGINE_PERSISTENT = 0, 1
 SG_FIELD_MASK_GUARD = 0x1F
 DTYPES = {"f32": SG_F32, "f16": SG_F16, "bf16": SG_BF16}
 
@@ -57,7 +58,7 @@ class SgBox(C.Structure):
 
 
 class SgCampaignCfg(C.Structure):
-    _fields_ = [("batch", C.c_int32), ("streams", C.c_int32), ("threads", C.c_int32), ("_pad", C.c_int32)]
+    _fields_ = [("batch", C.c_int32), ("streams", C.c_int32), ("threads", C.c_int32), ("engine", C.c_int32)]
 
 
 class SgTune(C.Structure):
@@ -310,13 +311,18 @@ class Context:
                                   box_mask if box is not None else 0, _ptr(images), _ptr(metrics), mode, _stream()))
 
     def campaign(self, prep, sites: np.ndarray, variants: np.ndarray, metrics, box=None,
-                 box_mask: int = SG_FIELD_MASK_GUARD, batch: int = 32, streams: int = 8, threads: int = 2):
-        """All variants of a campaign in batches of `batch`, over `streams` device
-        streams enqueued by `threads` host threads; records into `metrics`.
-        `prep` may be a list of views of one scene (pooled records)."""
+                 box_mask: int = SG_FIELD_MASK_GUARD, batch: int | None = None, streams: int = 8, threads: int = 2,
+                 engine: int = SG_ENGINE_PIPELINED):
+        """All variants of a campaign in batches of `batch` (default 32), over
+        `streams` device streams enqueued by `threads` host threads (pipelined
+        engine), or in persistent chunks of `batch` variants (default: as many
+        as fit); records into `metrics`.  `prep` may be a list of views of one
+        scene (pooled records)."""
         s = np.ascontiguousarray(sites, SITE_DTYPE)
         v = np.ascontiguousarray(variants, VARIANT_DTYPE)
-        cfg = SgCampaignCfg(int(batch), int(streams), int(threads), 0)
+        if batch is None:
+            batch = 0 if engine == SG_ENGINE_PERSISTENT else 32
+        cfg = SgCampaignCfg(int(batch), int(streams), int(threads), int(engine))
         bx = C.byref(box.st) if box is not None else None
         mask = box_mask if box is not None else 0
         if isinstance(prep, (list, tuple)):
@@ -329,14 +335,17 @@ class Context:
                                   len(v), bx, mask, C.byref(cfg), _ptr(metrics), _stream()))
 
     def campaign_scenes(self, preps, sites: np.ndarray, variants: np.ndarray, scene_of, metrics, boxes=None,
-                        box_mask: int = SG_FIELD_MASK_GUARD, batch: int = 32, streams: int = 8, threads: int = 2):
+                        box_mask: int = SG_FIELD_MASK_GUARD, batch: int | None = None, streams: int = 8,
+                        threads: int = 2, engine: int = SG_ENGINE_PIPELINED):
         """Variants of several prepared scenes in one campaign: variant j belongs
         to preps[scene_of[j]]; boxes (optional) lists each scene's box or None."""
         s = np.ascontiguousarray(sites, SITE_DTYPE)
         v = np.ascontiguousarray(variants, VARIANT_DTYPE)
         sc = np.ascontiguousarray(scene_of, np.uint16)
         assert sc.shape == (len(v),)
-        cfg = SgCampaignCfg(int(batch), int(streams), int(threads), 0)
+        if batch is None:
+            batch = 0 if engine == SG_ENGINE_PERSISTENT else 32
+        cfg = SgCampaignCfg(int(batch), int(streams), int(threads), int(engine))
         hs = (C.c_void_p * len(preps))(*[p.h for p in preps])
         bxs = None
         if boxes is not None:

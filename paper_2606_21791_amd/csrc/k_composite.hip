@@ -293,9 +293,22 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_full(CompArgs A) {
 // MV: the items are variant-views and each takes its view's clean state
 // from views[]: view v % K of variant-view v, or view_of[v] when given.
 // Their work items sit A0.ras.n_tiles apart per variant-view.
-template <int TILE, bool MV = false>
-__device__ __forceinline__ void items_role(const CompArgs& A0, const ItemArgs& I, int K = 1,
-                                           const ViewArgs* views = nullptr, const uint16_t* view_of = nullptr) {
+// One (variant, tile) work item, run by the whole workgroup: the positions
+// of the corrupted primitives' old keys and new keys in the tile's sorted
+// clean list (each target's lower bound) are counted over the whole list,
+// which a list of at most KCAP entries brings into registers in one round of
+// loads (its ids then stay in LDS for the compositing); a longer list is
+// searched in two rounds: the last keys of TILE*TILE equal buckets locate each
+// target's bucket, and one pass over that bucket counts the keys below the
+// target.  ent is the item record {tile, first entry of its clean list, its
+// length, -}, v its variant (variant-view when MV) and `item` its partial's
+// slot.  The caller separates two calls by a barrier.
+// MV: the item takes its view's clean state from views[]: view v % K of
+// variant-view v, or view_of[v] when given.
+template <int TILE, bool MV>
+__device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __restrict__ vs_all, const Rec* ovr,
+                                          int64_t image_stride, int K, const ViewArgs* views,
+                                          const uint16_t* view_of, uint32_t v, uint4 ent, uint32_t item) {
   constexpr int BS = TILE * TILE;
   constexpr int NT = 2 * kMaxTouch;
   constexpr int KPT = TILE == 8 ? 8 : (TILE == 16 ? 4 : 2);   // staged list keys per thread
@@ -304,16 +317,205 @@ __device__ __forceinline__ void items_role(const CompArgs& A0, const ItemArgs& I
   constexpr int BPR = TILE / 8;
   __shared__ float4 s_r0[BS], s_r1[BS], s_r2[BS];
   __shared__ MergeSpec ms;
-  __shared__ uint32_t s_item;
   __shared__ __align__(8) uint32_t s_vs[VSW];   // the item's VariantState
   __shared__ uint32_t s_ids[KCAP];      // ids of a staged clean list
   __shared__ uint64_t s_tgt[NT];        // removal keys, then insertion keys (sorted)
   __shared__ uint32_t s_cnt[NT], s_fnd[NT], s_bkt[NT];
   __shared__ int s_nr, s_ni;
-  // the variants' first items (B + 1 offsets; B <= kMaxBatch)
-  __shared__ uint32_t off[kMaxBatch + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int pxo = (wave % BPR) * 8 + (lane & 7), pyo = (wave / BPR) * 8 + (lane >> 3);   // as in composite_tile
+  CompArgs Am;   // MV: A0 with the clean state of the item's view
+  if constexpr (MV) {
+    const uint32_t view = view_of ? (uint32_t)view_of[v] : v % (uint32_t)K;
+    const ViewArgs& w = views[view];
+    Am = A0;
+    Am.r0 = w.r0; Am.r1 = w.r1; Am.r2 = w.r2;
+    Am.tile_start = w.tile_start; Am.tile_cnt = w.tile_cnt; Am.keys = w.keys;
+    Am.clean = w.clean; Am.stop = w.stop; Am.ck = w.ck; Am.ck_off = w.ck_off; Am.stop_key = w.stop_key;
+    Am.ras = w.ras; Am.W = w.W; Am.H = w.H; Am.ck_group = w.ck_group;
+  }
+  const CompArgs& A = MV ? Am : A0;
+  // The prologue's loads are all issued before any of them is waited for:
+  // branch-free, from clamped addresses, with a lane that has nothing to
+  // read reading the variant's state instead and dropping the value: the
+  // variant state, the pixel's stop index and clean colour and the clean
+  // list (all of them follow from the item record).
+  constexpr int VPT = (VSW + BS - 1) / BS;   // variant-state words per thread
+  const uint32_t* vsrc = reinterpret_cast<const uint32_t*>(vs_all + v);
+  uint32_t vw[VPT];
+#pragma unroll
+  for (int k = 0; k < VPT; ++k) vw[k] = vsrc[min(tid + k * BS, VSW - 1)];
+  const int tile = (int)ent.x;
+  const uint32_t raw_start = ent.y, L = ent.z;
+  const int tx = tile % A.ras.tiles_x, ty = tile / A.ras.tiles_x;
+  const int x = tx * TILE + pxo, y = ty * TILE + pyo;
+  const bool inside = x < A.W && y < A.H;
+  const int64_t p = (int64_t)min(y, A.H - 1) * A.W + min(x, A.W - 1);
+  const uint32_t sp_w = *(A.stop ? A.stop + p : vsrc);
+  const float* csrc = A.clean ? A.clean + 3 * p : reinterpret_cast<const float*>(vsrc);
+  const float cw0 = csrc[0], cw1 = csrc[1], cw2 = csrc[2];
+  const bool staged = L <= (uint32_t)KCAP;
+  const uint64_t* keys = A.keys + raw_start;
+  uint64_t kr[KPT];
+#pragma unroll
+  for (int k = 0; k < KPT; ++k) {
+    const uint32_t m = (uint32_t)(tid + k * BS);
+    const bool have = staged && m < L;
+    const uint64_t kv = *(have ? keys + m : reinterpret_cast<const uint64_t*>(vsrc));
+    kr[k] = have ? kv : ~0ull;   // padding compares above every key
+  }
+#pragma unroll
+  for (int k = 0; k < VPT; ++k)
+    if (tid + k * BS < VSW) s_vs[tid + k * BS] = vw[k];
+  const bool use_px = inside && A.stop;
+  const uint32_t sp = use_px ? sp_w : 0u;
+  const bool use_cl = inside && A.clean;
+  const float cl0 = use_cl ? cw0 : 0.f, cl1 = use_cl ? cw1 : 0.f, cl2 = use_cl ? cw2 : 0.f;
+  if (tid < NT) { s_cnt[tid] = 0; s_fnd[tid] = 0; s_bkt[tid] = 0; }
+  __syncthreads();
+  if (tid == 0) {
+    const VariantState& vs = *reinterpret_cast<const VariantState*>(s_vs);
+    int nr = 0, ni = 0;
+    // removal keys fill s_tgt from the front, insertion keys from the back
+    for (uint32_t j = 0; j < vs.n_touch; ++j) {
+      const Touch t = vs.touch[j];
+      if (t.flags & 4u) continue;   // unchanged primitive
+      if ((t.flags & 1u) && rect_has(t.old_rect0, t.old_rect1, tx, ty)) s_tgt[nr++] = ((uint64_t)t.old_depth << 32) | t.prim;
+      if ((t.flags & 2u) && rect_has(t.new_rect0, t.new_rect1, tx, ty)) {
+        s_tgt[NT - 1 - ni] = ((uint64_t)t.new_depth << 32) | t.prim;
+        ms.ins_src[ni] = v * kMaxTouch + j;
+        ++ni;
+      }
+    }
+    // move the insertion keys behind the removals, sorted by key
+    for (int j = 0; j < ni; ++j) s_tgt[nr + j] = s_tgt[NT - 1 - j];
+    for (int a = 1; a < ni; ++a)
+      for (int b = a; b > 0 && s_tgt[nr + b - 1] > s_tgt[nr + b]; --b) {
+        const uint64_t k = s_tgt[nr + b]; s_tgt[nr + b] = s_tgt[nr + b - 1]; s_tgt[nr + b - 1] = k;
+        const uint32_t z = ms.ins_src[b]; ms.ins_src[b] = ms.ins_src[b - 1]; ms.ins_src[b - 1] = z;
+      }
+    s_nr = nr;
+    s_ni = ni;
+  }
+  __syncthreads();
+  const int nr = __builtin_amdgcn_readfirstlane(s_nr), nt = nr + __builtin_amdgcn_readfirstlane(s_ni);
+  if (nt == 0) {   // the variant changes nothing in this tile
+    if (tid == 0) {
+      Partial z;
+      z.sse = 0.0; z.evals = 0; z.changed = 0; z.max_abs = 0.f; z.nonfinite = 0; z._pad = 0;
+      A.parts[item] = z;
+    }
+    return;
+  }
+  const uint32_t G = (L + BS - 1) / BS;   // bucket width of a long list
+  if (staged) {
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+      const uint32_t m = (uint32_t)(tid + k * BS);
+      if (m < L) s_ids[m] = (uint32_t)kr[k];
+    }
+    for (int j = 0; j < nt; ++j) {
+      const uint64_t tgt = s_tgt[j];
+      uint32_t c = 0;
+      bool eq = false;
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        c += kr[k] < tgt ? 1u : 0u;
+        eq |= kr[k] == tgt;
+      }
+      for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o);
+      const unsigned long long me = __ballot(eq);
+      if (lane == 0) {
+        if (c) atomicAdd(&s_cnt[j], c);
+        if (me) atomicOr(&s_fnd[j], 1u);
+      }
+    }
+  } else {
+    // round 1: a target's bucket is the number of buckets whose last key is below it
+    uint64_t last = ~0ull;
+    if (tid * G < L) last = keys[min(L, (tid + 1) * G) - 1];
+    for (int j = 0; j < nt; ++j) {
+      const unsigned long long m = __ballot(last < s_tgt[j]);
+      if (lane == 0 && m) atomicAdd(&s_bkt[j], (uint32_t)__popcll(m));
+    }
+    __syncthreads();
+    // round 2: keys below the target inside its bucket, and whether it is present
+    for (int j = 0; j < nt; ++j) {
+      const uint64_t tgt = s_tgt[j];
+      const uint32_t b0 = s_bkt[j] * G, b1 = min(L, b0 + G);
+      uint32_t c = 0;
+      bool eq = false;
+      for (uint32_t m = b0 + tid; m < b1; m += BS) {
+        const uint64_t key = keys[m];
+        c += key < tgt ? 1u : 0u;
+        eq |= key == tgt;
+      }
+      for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o);
+      const unsigned long long me = __ballot(eq);
+      if (lane == 0) {
+        if (c) atomicAdd(&s_cnt[j], c);
+        if (me) atomicOr(&s_fnd[j], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // lower bound of target j: the keys below it in its bucket plus the
+    // buckets before it (no buckets for a staged list)
+    int n_rm = 0;
+    for (int j = 0; j < nr; ++j)
+      if (s_fnd[j]) ms.rm_pos[n_rm++] = s_cnt[j] + min(s_bkt[j] * G, L);
+    for (int a = 1; a < n_rm; ++a)
+      for (int b = a; b > 0 && ms.rm_pos[b - 1] > ms.rm_pos[b]; --b) {
+        const uint32_t z = ms.rm_pos[b]; ms.rm_pos[b] = ms.rm_pos[b - 1]; ms.rm_pos[b - 1] = z;
+      }
+    const int ni = nt - nr;
+    for (int j = 0; j < ni; ++j) {
+      const uint32_t praw = s_cnt[nr + j] + min(s_bkt[nr + j] * G, L);
+      uint32_t rm_before = 0;
+      for (int k = 0; k < n_rm; ++k) rm_before += ms.rm_pos[k] < praw ? 1u : 0u;
+      ms.ins_mpos[j] = praw - rm_before + (uint32_t)j;
+    }
+    ms.raw_start = raw_start;
+    ms.raw_len = L;
+    ms.n_rm = n_rm;
+    ms.n_ins = ni;
+    ms.mlen = L - (uint32_t)n_rm + (uint32_t)ni;
+    uint32_t m0 = L;
+    if (n_rm) m0 = min(m0, ms.rm_pos[0]);
+    if (ni) m0 = min(m0, ms.ins_mpos[0]);
+    ms.m0 = m0;
+    ms.start = A.ck_group ? (m0 / A.ck_group) * A.ck_group : 0u;
+  }
+  __syncthreads();
+  float* img = A.image ? A.image + (int64_t)v * image_stride : nullptr;
+  const uint32_t changed = composite_tile<TILE, kItem>(A, tile, &ms, ovr, img, A.parts + item, s_r0, s_r1, s_r2,
+                                                       staged ? s_ids : nullptr, sp, cl0, cl1, cl2);
+  if (tid == 0 && changed)
+    atomicOr((unsigned long long*)&vs_all[v].rend_regions,
+             (unsigned long long)region_bit(tx, ty, A.ras.tiles_x, A.ras.tiles_y));
+}
+
+// Persistent incremental compositing of one batch: a fixed grid of
+// workgroups pops (variant, tile) work items from a device counter until the
+// batch's item count (known only on the device) is exhausted.  Variant v's
+// items sit at [v * n_tiles, ...) and its first item index is item_off[v].
+// The next item is popped while the current one runs.
+//
+// The variant prep has already dropped every dirty tile whose last pixel
+// stopped, in the clean render, before all of the tile's target keys.
+// 16 x 16 tiles: registers are held to five resident workgroups per CU, the
+// number their LDS allows.
+// MV: the items are variant-views (see item_work); their work items sit
+// A0.ras.n_tiles apart per variant-view.
+template <int TILE, bool MV = false>
+__device__ __forceinline__ void items_role(const CompArgs& A0, const ItemArgs& I, int K = 1,
+                                           const ViewArgs* views = nullptr, const uint16_t* view_of = nullptr) {
+  constexpr int BS = TILE * TILE;
+  __shared__ uint32_t s_item;
+  // the variants' first items (B + 1 offsets; B <= kMaxBatch)
+  __shared__ uint32_t off[kMaxBatch + 1];
+  const int tid = threadIdx.x;
   for (int k = tid; k <= I.B; k += BS) off[k] = I.item_off[k];
   if (tid == 0) s_item = atomicAdd(I.counter, 1u);
   __syncthreads();
@@ -334,181 +536,50 @@ __device__ __forceinline__ void items_role(const CompArgs& A0, const ItemArgs& I
       v = (uint32_t)__builtin_amdgcn_readfirstlane(lo);
     }
     const uint32_t first = __builtin_amdgcn_readfirstlane(off[v]);
-    CompArgs Am;   // MV: A0 with the clean state of the item's view
-    if constexpr (MV) {
-      const uint32_t view = view_of ? (uint32_t)view_of[v] : v % (uint32_t)K;
-      const ViewArgs& w = views[view];
-      Am = A0;
-      Am.r0 = w.r0; Am.r1 = w.r1; Am.r2 = w.r2;
-      Am.tile_start = w.tile_start; Am.tile_cnt = w.tile_cnt; Am.keys = w.keys;
-      Am.clean = w.clean; Am.stop = w.stop; Am.ck = w.ck; Am.ck_off = w.ck_off; Am.stop_key = w.stop_key;
-      Am.ras = w.ras; Am.W = w.W; Am.H = w.H; Am.ck_group = w.ck_group;
-    }
-    const CompArgs& A = MV ? Am : A0;
-    // The prologue's loads are all issued before any of them is waited for:
-    // branch-free, from clamped addresses, with a lane that has nothing to
-    // read reading the variant's state instead and dropping the value.  First
-    // the variant state and the item record, then the pixel's stop index and
-    // clean colour and the clean list.
-    constexpr int VPT = (VSW + BS - 1) / BS;   // variant-state words per thread
-    const uint32_t* vsrc = reinterpret_cast<const uint32_t*>(I.vs + v);
-    uint32_t vw[VPT];
-#pragma unroll
-    for (int k = 0; k < VPT; ++k) vw[k] = vsrc[min(tid + k * BS, VSW - 1)];
     const uint4 ent = I.items[(int64_t)v * A0.ras.n_tiles + (item - first)];
-    const int tile = (int)ent.x;
-    const uint32_t raw_start = ent.y, L = ent.z;
-    const int tx = tile % A.ras.tiles_x, ty = tile / A.ras.tiles_x;
-    const int x = tx * TILE + pxo, y = ty * TILE + pyo;
-    const bool inside = x < A.W && y < A.H;
-    const int64_t p = (int64_t)min(y, A.H - 1) * A.W + min(x, A.W - 1);
-    const uint32_t sp_w = *(A.stop ? A.stop + p : vsrc);
-    const float* csrc = A.clean ? A.clean + 3 * p : reinterpret_cast<const float*>(vsrc);
-    const float cw0 = csrc[0], cw1 = csrc[1], cw2 = csrc[2];
-    const bool staged = L <= (uint32_t)KCAP;
-    const uint64_t* keys = A.keys + raw_start;
-    uint64_t kr[KPT];
-#pragma unroll
-    for (int k = 0; k < KPT; ++k) {
-      const uint32_t m = (uint32_t)(tid + k * BS);
-      const bool have = staged && m < L;
-      const uint64_t kv = *(have ? keys + m : reinterpret_cast<const uint64_t*>(vsrc));
-      kr[k] = have ? kv : ~0ull;   // padding compares above every key
-    }
-#pragma unroll
-    for (int k = 0; k < VPT; ++k)
-      if (tid + k * BS < VSW) s_vs[tid + k * BS] = vw[k];
-    const bool use_px = inside && A.stop;
-    const uint32_t sp = use_px ? sp_w : 0u;
-    const bool use_cl = inside && A.clean;
-    const float cl0 = use_cl ? cw0 : 0.f, cl1 = use_cl ? cw1 : 0.f, cl2 = use_cl ? cw2 : 0.f;
-    if (tid < NT) { s_cnt[tid] = 0; s_fnd[tid] = 0; s_bkt[tid] = 0; }
+    item_work<TILE, MV>(A0, I.vs, I.ovr, I.image_stride, K, views, view_of, v, ent, item);
+    if (tid == 0) s_item = next;
     __syncthreads();
+  }
+}
+
+// Campaign-wide persistent compositing: the work items of a whole campaign
+// chunk (every variant's dirty tiles, compact, each record tagged with its
+// variant) in one launch.  ctl[0] holds the item count, ctl[1] the work
+// counter.  Each workgroup keeps two items ahead: while item i runs, the
+// record of item i + 1 (popped during item i - 1) is loaded and item i + 2
+// is popped, so an item starts with its record, and therefore its variant,
+// tile and list range, already in hand.
+template <int TILE, bool MV>
+__device__ __forceinline__ void persistent_role(const PersistArgs& P) {
+  __shared__ uint32_t s_cur, s_nxt;
+  __shared__ uint4 s_rec;
+  const int tid = threadIdx.x;
+  const uint32_t total = P.ctl[0];
+  if (tid == 0) {
+    const uint32_t a = atomicAdd(P.ctl + 1, 1u);
+    s_cur = a;
+    s_rec = a < total ? P.items[a] : make_uint4(0u, 0u, 0u, 0u);
+    s_nxt = atomicAdd(P.ctl + 1, 1u);
+  }
+  __syncthreads();
+  for (;;) {
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_cur);
+    if (item >= total) break;
+    const uint32_t nxt = __builtin_amdgcn_readfirstlane(s_nxt);
+    const uint4 ent = make_uint4(__builtin_amdgcn_readfirstlane(s_rec.x), __builtin_amdgcn_readfirstlane(s_rec.y),
+                                 __builtin_amdgcn_readfirstlane(s_rec.z), __builtin_amdgcn_readfirstlane(s_rec.w));
+    uint4 rec_n = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t nxt2 = 0;
     if (tid == 0) {
-      const VariantState& vs = *reinterpret_cast<const VariantState*>(s_vs);
-      int nr = 0, ni = 0;
-      // removal keys fill s_tgt from the front, insertion keys from the back
-      for (uint32_t j = 0; j < vs.n_touch; ++j) {
-        const Touch t = vs.touch[j];
-        if (t.flags & 4u) continue;   // unchanged primitive
-        if ((t.flags & 1u) && rect_has(t.old_rect0, t.old_rect1, tx, ty)) s_tgt[nr++] = ((uint64_t)t.old_depth << 32) | t.prim;
-        if ((t.flags & 2u) && rect_has(t.new_rect0, t.new_rect1, tx, ty)) {
-          s_tgt[NT - 1 - ni] = ((uint64_t)t.new_depth << 32) | t.prim;
-          ms.ins_src[ni] = v * kMaxTouch + j;
-          ++ni;
-        }
-      }
-      // move the insertion keys behind the removals, sorted by key
-      for (int j = 0; j < ni; ++j) s_tgt[nr + j] = s_tgt[NT - 1 - j];
-      for (int a = 1; a < ni; ++a)
-        for (int b = a; b > 0 && s_tgt[nr + b - 1] > s_tgt[nr + b]; --b) {
-          const uint64_t k = s_tgt[nr + b]; s_tgt[nr + b] = s_tgt[nr + b - 1]; s_tgt[nr + b - 1] = k;
-          const uint32_t z = ms.ins_src[b]; ms.ins_src[b] = ms.ins_src[b - 1]; ms.ins_src[b - 1] = z;
-        }
-      s_nr = nr;
-      s_ni = ni;
+      if (nxt < total) rec_n = P.items[nxt];
+      nxt2 = atomicAdd(P.ctl + 1, 1u);
     }
-    __syncthreads();
-    const int nr = __builtin_amdgcn_readfirstlane(s_nr), nt = nr + __builtin_amdgcn_readfirstlane(s_ni);
-    if (nt == 0) {   // the variant changes nothing in this tile
-      if (tid == 0) {
-        Partial z;
-        z.sse = 0.0; z.evals = 0; z.changed = 0; z.max_abs = 0.f; z.nonfinite = 0; z._pad = 0;
-        A.parts[item] = z;
-        s_item = next;
-      }
-      __syncthreads();
-      continue;
-    }
-    const uint32_t G = (L + BS - 1) / BS;   // bucket width of a long list
-    if (staged) {
-#pragma unroll
-      for (int k = 0; k < KPT; ++k) {
-        const uint32_t m = (uint32_t)(tid + k * BS);
-        if (m < L) s_ids[m] = (uint32_t)kr[k];
-      }
-      for (int j = 0; j < nt; ++j) {
-        const uint64_t tgt = s_tgt[j];
-        uint32_t c = 0;
-        bool eq = false;
-#pragma unroll
-        for (int k = 0; k < KPT; ++k) {
-          c += kr[k] < tgt ? 1u : 0u;
-          eq |= kr[k] == tgt;
-        }
-        for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o);
-        const unsigned long long me = __ballot(eq);
-        if (lane == 0) {
-          if (c) atomicAdd(&s_cnt[j], c);
-          if (me) atomicOr(&s_fnd[j], 1u);
-        }
-      }
-    } else {
-      // round 1: a target's bucket is the number of buckets whose last key is below it
-      uint64_t last = ~0ull;
-      if (tid * G < L) last = keys[min(L, (tid + 1) * G) - 1];
-      for (int j = 0; j < nt; ++j) {
-        const unsigned long long m = __ballot(last < s_tgt[j]);
-        if (lane == 0 && m) atomicAdd(&s_bkt[j], (uint32_t)__popcll(m));
-      }
-      __syncthreads();
-      // round 2: keys below the target inside its bucket, and whether it is present
-      for (int j = 0; j < nt; ++j) {
-        const uint64_t tgt = s_tgt[j];
-        const uint32_t b0 = s_bkt[j] * G, b1 = min(L, b0 + G);
-        uint32_t c = 0;
-        bool eq = false;
-        for (uint32_t m = b0 + tid; m < b1; m += BS) {
-          const uint64_t key = keys[m];
-          c += key < tgt ? 1u : 0u;
-          eq |= key == tgt;
-        }
-        for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o);
-        const unsigned long long me = __ballot(eq);
-        if (lane == 0) {
-          if (c) atomicAdd(&s_cnt[j], c);
-          if (me) atomicOr(&s_fnd[j], 1u);
-        }
-      }
-    }
-    __syncthreads();
+    item_work<TILE, MV>(P.A, P.vs, P.ovr, 0, P.K, P.views, P.view_of, ent.w, ent, item);
     if (tid == 0) {
-      // lower bound of target j: the keys below it in its bucket plus the
-      // buckets before it (no buckets for a staged list)
-      int n_rm = 0;
-      for (int j = 0; j < nr; ++j)
-        if (s_fnd[j]) ms.rm_pos[n_rm++] = s_cnt[j] + min(s_bkt[j] * G, L);
-      for (int a = 1; a < n_rm; ++a)
-        for (int b = a; b > 0 && ms.rm_pos[b - 1] > ms.rm_pos[b]; --b) {
-          const uint32_t z = ms.rm_pos[b]; ms.rm_pos[b] = ms.rm_pos[b - 1]; ms.rm_pos[b - 1] = z;
-        }
-      const int ni = nt - nr;
-      for (int j = 0; j < ni; ++j) {
-        const uint32_t praw = s_cnt[nr + j] + min(s_bkt[nr + j] * G, L);
-        uint32_t rm_before = 0;
-        for (int k = 0; k < n_rm; ++k) rm_before += ms.rm_pos[k] < praw ? 1u : 0u;
-        ms.ins_mpos[j] = praw - rm_before + (uint32_t)j;
-      }
-      ms.raw_start = raw_start;
-      ms.raw_len = L;
-      ms.n_rm = n_rm;
-      ms.n_ins = ni;
-      ms.mlen = L - (uint32_t)n_rm + (uint32_t)ni;
-      uint32_t m0 = L;
-      if (n_rm) m0 = min(m0, ms.rm_pos[0]);
-      if (ni) m0 = min(m0, ms.ins_mpos[0]);
-      ms.m0 = m0;
-      ms.start = A.ck_group ? (m0 / A.ck_group) * A.ck_group : 0u;
-    }
-    __syncthreads();
-    float* img = A.image ? A.image + (int64_t)v * I.image_stride : nullptr;
-    const uint32_t changed = composite_tile<TILE, kItem>(A, tile, &ms, I.ovr, img, A.parts + item, s_r0, s_r1, s_r2,
-                                                         staged ? s_ids : nullptr, sp, cl0, cl1, cl2);
-    if (tid == 0) {
-      if (changed)
-        atomicOr((unsigned long long*)&I.vs[v].rend_regions,
-                 (unsigned long long)region_bit(tx, ty, A.ras.tiles_x, A.ras.tiles_y));
-      s_item = next;
+      s_cur = nxt;
+      s_rec = rec_n;
+      s_nxt = nxt2;
     }
     __syncthreads();
   }
@@ -600,6 +671,117 @@ void launch_campaign_step(const StepArgs& a, hipStream_t st, hipEvent_t e0, hipE
     case 8: hipExtLaunchKernelGGL(k_campaign_step<8, false>, dim3(grid), dim3(64), 0, st, e0, e1, 0, a); break;
     case 32: hipExtLaunchKernelGGL(k_campaign_step<32, false>, dim3(grid), dim3(1024), 0, st, e0, e1, 0, a); break;
     default: hipExtLaunchKernelGGL(k_campaign_step<16, false>, dim3(grid), dim3(256), 0, st, e0, e1, 0, a); break;
+  }
+}
+
+// The work items of a campaign chunk, one wave per variant (variant-view
+// when MV): it counts its items, takes a contiguous range of the chunk's item
+// array with one atomic add on the list's cursor, and lists them there in the
+// order of enumerate_items, each tagged with the variant.  The order of a
+// variant's items, and so its reduction, is that of the batched path.
+template <bool MV>
+__global__ void __launch_bounds__(256) k_persist_list(PersistArgs P) {
+  constexpr int VSW = (int)(sizeof(VariantState) / sizeof(uint32_t));
+  __shared__ VariantState s_v[4];
+  const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int v = (int)blockIdx.x * 4 + wave;
+  if (v >= P.nv) return;
+  VariantState& slot = s_v[wave];
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(P.vs + v);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&slot);
+  for (int k = lane; k < VSW; k += 64) dst[k] = src[k];
+  wave_sync();
+  const uint64_t* stop_key = P.A.stop_key;
+  const uint32_t* tile_start = P.A.tile_start;
+  const uint32_t* tile_cnt = P.A.tile_cnt;
+  int tiles_x = P.A.ras.tiles_x, tiles_y = P.A.ras.tiles_y;
+  if constexpr (MV) {
+    const ViewArgs& w = P.views[P.view_of ? (int)P.view_of[v] : v % P.K];
+    stop_key = w.stop_key;
+    tile_start = w.tile_start;
+    tile_cnt = w.tile_cnt;
+    tiles_x = w.ras.tiles_x;
+    tiles_y = w.ras.tiles_y;
+  }
+  uint32_t nd, ni;
+  uint64_t pred;
+  enumerate_items(slot.touch, slot.n_touch, tiles_x, tiles_y, stop_key, tile_start, tile_cnt, nullptr, &nd, &ni, &pred);
+  uint32_t base = 0;
+  if (lane == 0 && ni) base = atomicAdd(P.ctl, ni);
+  base = (uint32_t)__shfl((int)base, 0);
+  if (ni)
+    enumerate_items(slot.touch, slot.n_touch, tiles_x, tiles_y, stop_key, tile_start, tile_cnt, P.items + base, &nd,
+                    &ni, &pred, (uint32_t)v);
+  if (lane == 0) {
+    P.item_off[v] = base;
+    P.n_items[v] = ni;
+    P.vs[v].n_dirty = nd;
+    P.vs[v].pred_regions = pred;
+  }
+}
+
+template <int TILE, bool MV>
+__global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 5 : 1) k_persist_composite(PersistArgs P) {
+  persistent_role<TILE, MV>(P);
+}
+
+// Each variant's record from its items' partials, one wave per variant.
+template <bool MV>
+__global__ void __launch_bounds__(256) k_persist_reduce(PersistArgs P) {
+  const int v = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (v >= P.nv) return;
+  uint32_t n_pixels = P.n_pixels;
+  if constexpr (MV) {
+    const ViewArgs& w = P.views[P.view_of ? (int)P.view_of[v] : v % P.K];
+    n_pixels = (uint32_t)(w.W * w.H);
+  }
+  reduce_batch_variant(P.A.parts, P.item_off, P.n_items, P.vs, n_pixels, v, P.out);
+}
+
+void launch_persist_list(const PersistArgs& a, hipStream_t st) {
+  const int grid = (a.nv + 3) / 4;
+  if (grid <= 0) return;
+  if (a.views) k_persist_list<true><<<grid, 256, 0, st>>>(a);
+  else k_persist_list<false><<<grid, 256, 0, st>>>(a);
+}
+
+void launch_persist_reduce(const PersistArgs& a, hipStream_t st) {
+  const int grid = (a.nv + 3) / 4;
+  if (grid <= 0) return;
+  if (a.views) k_persist_reduce<true><<<grid, 256, 0, st>>>(a);
+  else k_persist_reduce<false><<<grid, 256, 0, st>>>(a);
+}
+
+template <int TILE, bool MV>
+static int occupancy_of() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist_composite<TILE, MV>, TILE * TILE, 0) != hipSuccess)
+    nb = 1;
+  return nb > 0 ? nb : 1;
+}
+
+int persist_occupancy(int tile, bool mv) {
+  static const int occ[3][2] = {{occupancy_of<8, false>(), occupancy_of<8, true>()},
+                                {occupancy_of<16, false>(), occupancy_of<16, true>()},
+                                {occupancy_of<32, false>(), occupancy_of<32, true>()}};
+  return occ[tile == 8 ? 0 : (tile == 32 ? 2 : 1)][mv ? 1 : 0];
+}
+
+void launch_persist_composite(const PersistArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (a.grid <= 0 || a.nv <= 0) return;
+  const dim3 g(a.grid);
+  if (a.views) {
+    switch (a.A.ras.tile) {
+      case 8: hipExtLaunchKernelGGL(k_persist_composite<8, true>, g, dim3(64), 0, st, e0, e1, 0, a); break;
+      case 32: hipExtLaunchKernelGGL(k_persist_composite<32, true>, g, dim3(1024), 0, st, e0, e1, 0, a); break;
+      default: hipExtLaunchKernelGGL(k_persist_composite<16, true>, g, dim3(256), 0, st, e0, e1, 0, a); break;
+    }
+    return;
+  }
+  switch (a.A.ras.tile) {
+    case 8: hipExtLaunchKernelGGL(k_persist_composite<8, false>, g, dim3(64), 0, st, e0, e1, 0, a); break;
+    case 32: hipExtLaunchKernelGGL(k_persist_composite<32, false>, g, dim3(1024), 0, st, e0, e1, 0, a); break;
+    default: hipExtLaunchKernelGGL(k_persist_composite<16, false>, g, dim3(256), 0, st, e0, e1, 0, a); break;
   }
 }
 

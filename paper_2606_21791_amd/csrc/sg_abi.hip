@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <atomic>
 #include <mutex>
@@ -109,6 +110,10 @@ struct sg_ctx {
   DevBuf camp_sites, camp_vars, camp_vs, camp_ovr, camp_views, camp_vargs, camp_scene_of;
   std::vector<ViewArgs> camp_vargs_host;
   std::vector<uint16_t> camp_scene_of_host;
+  // the persistent campaign path's two buffer sets (its chunks alternate
+  // between them and between two streams): states, override records, work
+  // items, partials, per-variant item ranges, control words, per-view records
+  DevBuf pst_vs[2], pst_ovr[2], pst_items[2], pst_parts[2], pst_off[2], pst_n[2], pst_ctl[2], pst_views[2];
   hipEvent_t camp_done = nullptr;
   std::mutex camp_mu;
   // guards ws, in_use and the timing state: sg_campaign enqueues from several
@@ -552,6 +557,10 @@ void sg_ctx_destroy(sg_ctx* c) {
   dev_free(c, c->camp_views);
   dev_free(c, c->camp_vargs);
   dev_free(c, c->camp_scene_of);
+  for (int k = 0; k < 2; ++k)
+    for (DevBuf* b : {&c->pst_vs[k], &c->pst_ovr[k], &c->pst_items[k], &c->pst_parts[k], &c->pst_off[k], &c->pst_n[k],
+                      &c->pst_ctl[k], &c->pst_views[k]})
+      dev_free(c, *b);
   if (c->camp_done) (void)hipEventDestroy(c->camp_done);
   for (int p = 0; p < SG_N_PASSES; ++p)
     for (auto& pr : c->pending[p]) c->ev_pool.insert(c->ev_pool.end(), {pr.first, pr.second});
@@ -1048,11 +1057,33 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
 // takes each variant's clean state from the per-scene table.  The records
 // are those of sg_render_batch(_views) on the same batches (on each
 // variant's own scene).
+// The pipelined campaign spreads its streams over the HIP runtime's hardware
+// queues (GPU_MAX_HW_QUEUES, read by the runtime when it starts).  On the
+// MI355X its rate rises with the queue count up to 23 and collapses at 24;
+// at 26 a campaign made no progress for minutes.  The likely cause is that
+// the process then holds more user-mode compute queues than the device's
+// scheduler keeps mapped at once, so the queues are time-sliced while the
+// campaign's streams wait on one another's events.  Larger settings are
+// refused rather than risked.
+constexpr int kMaxCampaignHwQueues = 23;
+
+static sg_status check_hw_queues() {
+  const char* e = std::getenv("GPU_MAX_HW_QUEUES");
+  if (!e || !*e) return SG_OK;
+  char* end = nullptr;
+  const long q = std::strtol(e, &end, 10);
+  if (end == e || q <= kMaxCampaignHwQueues) return SG_OK;
+  return fail(SG_E_UNSUPPORTED, "GPU_MAX_HW_QUEUES=" + std::string(e) +
+                                    ": the pipelined campaign supports at most 23 hardware queues (at 24 its rate "
+                                    "collapses and at 26 it stalled)");
+}
+
 static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, const sg_site* sites, int32_t n_sites,
                                     const sg_variant* variants, int32_t n_variants, const DevBox& box, int B, int NS,
                                     int NT, sg_metrics_t* metrics_out, hipStream_t caller,
                                     const uint16_t* scene_of = nullptr, const DevBox* scene_boxes = nullptr) {
   constexpr int kChunk = 1 << 17;   // variants staged per pre-pass (one view)
+  SG_TRY(check_hw_queues());
   std::lock_guard<std::mutex> cg(ctx->camp_mu);
   if (ctx->camp_done) HIP_TRY(hipEventSynchronize(ctx->camp_done));   // the previous campaign's buffers are free
   else HIP_TRY(hipEventCreateWithFlags(&ctx->camp_done, hipEventDisableTiming));
@@ -1224,7 +1255,10 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
               if (sc) a.r_view_of = d_scene_of + c0 + lb(i - 2);
             }
             if (a.tB == 0 && a.I.B == 0 && a.rB == 0) continue;
-            PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st, true);
+            // launches with a compositing role are timed as compositing; the
+            // pipeline's fill and drain launches (work items or metrics only)
+            // as the reduction pass
+            PassScope ps(ctx, a.I.B > 0 ? SG_PASS_COMPOSITE_ITEMS : SG_PASS_REDUCE, st, true);
             launch_campaign_step(a, st, ps.a, ps.b);
           }
         // launch errors are per host thread: each worker reports its own
@@ -1254,6 +1288,165 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
   return check_last("sg_campaign");
 }
 
+// Work items one persistent launch can hold per buffer set (16 B record and
+// 32 B partial each: 1.6 GB per set).  A chunk's variants are bounded so that
+// every one of them may dirty every tile of its view.
+constexpr int64_t kPersistItems = (int64_t)1 << 25;
+constexpr int64_t kPersistVariants = (int64_t)1 << 18;   // variant-views per chunk
+
+// The persistent campaign: chunks of variants, each rendered by its pre-pass
+// (per view or scene), one launch listing every variant's work items
+// compactly, one persistent compositing launch over all of them and one
+// reduction launch; chunks alternate between two streams and two buffer sets
+// so that a chunk's listing overlaps the previous chunk's last items.  With
+// K > 1 views (scene_of null) every variant is rendered in every view, the
+// views of a variant side by side, and the per-view records are pooled; with
+// scene_of, variant v is rendered in preps[scene_of[v]] only.  B > 0 caps the
+// variants per chunk.  The records are those of sg_render_batch(_views).
+static sg_status campaign_persistent(sg_ctx* ctx, sg_prep* const* preps, int K, const sg_site* sites, int32_t n_sites,
+                                     const sg_variant* variants, int32_t n_variants, const DevBox& box, int B,
+                                     sg_metrics_t* metrics_out, hipStream_t caller, const uint16_t* scene_of = nullptr,
+                                     const DevBox* scene_boxes = nullptr) {
+  std::lock_guard<std::mutex> cg(ctx->camp_mu);
+  if (ctx->camp_done) HIP_TRY(hipEventSynchronize(ctx->camp_done));   // the previous campaign's buffers are free
+  else HIP_TRY(hipEventCreateWithFlags(&ctx->camp_done, hipEventDisableTiming));
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    while ((int)ctx->campaign_streams.size() < 2) {
+      hipStream_t st = nullptr;
+      HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      ctx->campaign_streams.push_back(st);
+    }
+  }
+  const bool sc = scene_of != nullptr;
+  const bool mv = sc || K > 1;
+  const int per = mv && !sc ? K : 1;   // variant-views per variant
+  int max_tiles = 1;
+  for (int k = 0; k < K; ++k) max_tiles = std::max(max_tiles, preps[k]->ras.n_tiles);
+  int64_t chunk = std::min<int64_t>(kPersistVariants / per, kPersistItems / ((int64_t)per * max_tiles));
+  if (B > 0) chunk = std::min<int64_t>(chunk, B);
+  chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, n_variants));
+  const int64_t nvv = chunk * per;   // variant-views per chunk
+  SG_TRY(dev_alloc(ctx, ctx->camp_sites, std::max<size_t>(1, (size_t)n_sites) * sizeof(sg_site)));
+  SG_TRY(dev_alloc(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant)));
+  for (int k = 0; k < 2; ++k) {
+    SG_TRY(dev_alloc(ctx, ctx->pst_vs[k], (size_t)nvv * sizeof(VariantState)));
+    SG_TRY(dev_alloc(ctx, ctx->pst_ovr[k], (size_t)nvv * kMaxTouch * sizeof(Rec)));
+    SG_TRY(dev_alloc(ctx, ctx->pst_items[k], (size_t)nvv * max_tiles * sizeof(uint4)));
+    SG_TRY(dev_alloc(ctx, ctx->pst_parts[k], (size_t)nvv * max_tiles * sizeof(Partial)));
+    SG_TRY(dev_alloc(ctx, ctx->pst_off[k], (size_t)nvv * sizeof(uint32_t)));
+    SG_TRY(dev_alloc(ctx, ctx->pst_n[k], (size_t)nvv * sizeof(uint32_t)));
+    SG_TRY(dev_alloc(ctx, ctx->pst_ctl[k], 2 * sizeof(uint32_t)));
+    if (per > 1) SG_TRY(dev_alloc(ctx, ctx->pst_views[k], (size_t)nvv * sizeof(sg_metrics_t)));
+  }
+  const ViewArgs* d_views = nullptr;
+  if (mv) {
+    ctx->camp_vargs_host.resize(K);
+    for (int k = 0; k < K; ++k) {
+      const sg_prep* p = preps[k];
+      const bool rs = p->ck_group != 0;
+      ctx->camp_vargs_host[k] = ViewArgs{P<float4>(p->r0), P<float4>(p->r1), P<float4>(p->r2),
+                                         P<uint32_t>(p->tile_start), P<uint32_t>(p->tile_cnt), P<uint64_t>(p->keys),
+                                         P<float>(p->frame), rs ? P<uint32_t>(p->stop) : nullptr,
+                                         rs ? P<float4>(p->ck) : nullptr, rs ? P<uint32_t>(p->ck_off) : nullptr,
+                                         rs ? P<uint64_t>(p->stop_key) : nullptr, p->ras, p->cam.W, p->cam.H,
+                                         p->ck_group};
+    }
+    SG_TRY(dev_alloc(ctx, ctx->camp_vargs, (size_t)K * sizeof(ViewArgs)));
+    HIP_TRY(hipMemcpyAsync(ctx->camp_vargs.p, ctx->camp_vargs_host.data(), (size_t)K * sizeof(ViewArgs),
+                           hipMemcpyHostToDevice, caller));
+    d_views = P<ViewArgs>(ctx->camp_vargs);
+  }
+  const uint16_t* d_scene_of = nullptr;
+  if (sc) {
+    ctx->camp_scene_of_host.assign(scene_of, scene_of + n_variants);
+    SG_TRY(dev_alloc(ctx, ctx->camp_scene_of, std::max<size_t>(1, (size_t)n_variants) * sizeof(uint16_t)));
+    HIP_TRY(hipMemcpyAsync(ctx->camp_scene_of.p, ctx->camp_scene_of_host.data(), (size_t)n_variants * sizeof(uint16_t),
+                           hipMemcpyHostToDevice, caller));
+    d_scene_of = P<uint16_t>(ctx->camp_scene_of);
+  }
+  if (n_sites)
+    HIP_TRY(hipMemcpyAsync(ctx->camp_sites.p, sites, (size_t)n_sites * sizeof(sg_site), hipMemcpyHostToDevice, caller));
+  HIP_TRY(hipMemcpyAsync(ctx->camp_vars.p, variants, (size_t)n_variants * sizeof(sg_variant), hipMemcpyHostToDevice,
+                         caller));
+  hipStream_t streams[2] = {ctx->campaign_streams[0], ctx->campaign_streams[1]};
+  {
+    hipEvent_t staged = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(staged, caller));
+    for (hipStream_t st : streams) HIP_TRY(hipStreamWaitEvent(st, staged, 0));
+    (void)hipEventDestroy(staged);
+  }
+  const sg_site* d_sites = P<sg_site>(ctx->camp_sites);
+  const sg_variant* d_vars = P<sg_variant>(ctx->camp_vars);
+  const sg_prep* p0 = preps[0];
+  const int tile = p0->ras.tile;
+  const int occ = persist_occupancy(tile, mv);
+  const int grid = ctx->persistent_grid > 0 ? ctx->persistent_grid : ctx->n_cu * occ;
+  int set = 0;
+  for (int64_t c0 = 0; c0 < n_variants; c0 += chunk, set ^= 1) {
+    const int cn = (int)std::min<int64_t>(chunk, n_variants - c0);
+    hipStream_t st = streams[set];
+    VariantState* vs = P<VariantState>(ctx->pst_vs[set]);
+    Rec* ovr = P<Rec>(ctx->pst_ovr[set]);
+    uint32_t* ctl = P<uint32_t>(ctx->pst_ctl[set]);
+    launch_fill_u32(ctl, 0u, 2, st);   // the list's cursor and the work counter start at zero
+    for (int k = 0; k < K; ++k) {
+      const sg_prep* pk = preps[k];
+      PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
+      launch_campaign_touch(pk->scene, sc ? scene_boxes[k] : box, pk->cam, pk->ras, P<float4>(pk->r0),
+                            P<float4>(pk->r1), P<float4>(pk->r2), P<uint32_t>(pk->depth), P<uint2>(pk->rect), d_sites,
+                            d_vars + c0, cn, vs, ovr, per, sc ? 0 : k, sc ? d_scene_of + c0 : nullptr, k, st);
+    }
+    PersistArgs a{};
+    a.A = CompArgs{P<float4>(p0->r0), P<float4>(p0->r1), P<float4>(p0->r2), P<uint32_t>(p0->tile_start),
+                   P<uint32_t>(p0->tile_cnt), P<uint64_t>(p0->keys), P<float>(p0->frame), nullptr,
+                   P<Partial>(ctx->pst_parts[set]), p0->ras, p0->cam.W, p0->cam.H};
+    if (p0->ck_group) {
+      a.A.stop = P<uint32_t>(p0->stop);
+      a.A.ck = P<float4>(p0->ck);
+      a.A.ck_off = P<uint32_t>(p0->ck_off);
+      a.A.stop_key = P<uint64_t>(p0->stop_key);
+      a.A.ck_group = p0->ck_group;
+    }
+    a.vs = vs;
+    a.ovr = ovr;
+    a.items = P<uint4>(ctx->pst_items[set]);
+    a.item_off = P<uint32_t>(ctx->pst_off[set]);
+    a.n_items = P<uint32_t>(ctx->pst_n[set]);
+    a.ctl = ctl;
+    a.nv = cn * per;
+    a.grid = grid;
+    a.out = per > 1 ? P<sg_metrics_t>(ctx->pst_views[set]) : metrics_out + c0;
+    a.n_pixels = (uint32_t)(p0->cam.W * p0->cam.H);
+    a.K = per;
+    a.views = d_views;
+    a.view_of = sc ? d_scene_of + c0 : nullptr;
+    {
+      PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
+      launch_persist_list(a, st);
+    }
+    {
+      PassScope ps(ctx, SG_PASS_COMPOSITE_ITEMS, st, true);
+      launch_persist_composite(a, st, ps.a, ps.b);
+    }
+    {
+      PassScope ps(ctx, SG_PASS_REDUCE, st);
+      launch_persist_reduce(a, st);
+      if (per > 1) launch_pool_views(a.out, K, cn, 1, K, metrics_out + c0, st);
+    }
+  }
+  for (hipStream_t st : streams) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(e, st));
+    HIP_TRY(hipStreamWaitEvent(caller, e, 0));
+    (void)hipEventDestroy(e);
+  }
+  HIP_TRY(hipEventRecord(ctx->camp_done, caller));
+  return check_last("sg_campaign (persistent)");
+}
+
 sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const sg_site* sites, int32_t n_sites,
                             const sg_variant* variants, int32_t n_variants, const sg_box* box, uint32_t box_field_mask,
                             const sg_campaign_cfg* cfg, sg_metrics_t* metrics_out, void* stream) {
@@ -1272,10 +1465,14 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
     if (!same) return fail(SG_E_INVAL, "the views are not prepared from one scene");
   }
   if (n_variants < 0 || (n_variants > 0 && !variants)) return fail(SG_E_INVAL, "bad variants");
-  const int B = cfg && cfg->batch > 0 ? cfg->batch : 32;
+  const int engine = cfg ? cfg->engine : SG_ENGINE_PIPELINED;
+  if (engine != SG_ENGINE_PIPELINED && engine != SG_ENGINE_PERSISTENT) return fail(SG_E_INVAL, "unknown campaign engine");
+  const bool persistent = engine == SG_ENGINE_PERSISTENT;
+  const int B = cfg && cfg->batch > 0 ? cfg->batch : (persistent ? 0 : 32);
   const int NS = cfg && cfg->streams > 0 ? cfg->streams : 8;
   const int NT = std::min(cfg && cfg->threads > 0 ? cfg->threads : 2, NS);
-  if (B > kMaxBatch || NS > 64 || NT > 64) return fail(SG_E_INVAL, "campaign batch/streams/threads out of range");
+  if ((!persistent && B > kMaxBatch) || B < 0 || NS > 64 || NT > 64)
+    return fail(SG_E_INVAL, "campaign batch/streams/threads out of range");
   SG_TRY(validate_sites(prep->scene, sites, n_sites));
   for (int v = 0; v < n_variants; ++v)
     if ((uint64_t)variants[v].site_off + variants[v].n_sites > (uint64_t)n_sites)
@@ -1314,7 +1511,9 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
       }
     }
     if (incremental)
-      return campaign_pipelined(ctx, preps, K, sites, n_sites, variants, n_variants, b, B, NS, NT, metrics_out, caller);
+      return persistent ? campaign_persistent(ctx, preps, K, sites, n_sites, variants, n_variants, b, B, metrics_out, caller)
+                        : campaign_pipelined(ctx, preps, K, sites, n_sites, variants, n_variants, b, B, NS, NT,
+                                             metrics_out, caller);
   }
   hipEvent_t start = nullptr;
   HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
@@ -1322,7 +1521,8 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
   for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(ctx->campaign_streams[k], start, 0));
   (void)hipEventDestroy(start);
 
-  const int nb = (n_variants + B - 1) / B;
+  const int BB = B > 0 && B <= kMaxBatch ? B : 32;   // batches of sg_render_batch
+  const int nb = (n_variants + BB - 1) / BB;
   std::mutex err_mu;
   sg_status first_rc = SG_OK;
   std::string first_msg;
@@ -1336,7 +1536,7 @@ sg_status sg_campaign_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, const
         std::lock_guard<std::mutex> g(err_mu);
         if (first_rc != SG_OK) return;
       }
-      const int v0 = b * B, nv = std::min(B, n_variants - v0);
+      const int v0 = b * BB, nv = std::min(BB, n_variants - v0);
       // the sites this batch refers to, with its variants' offsets rebased
       uint32_t lo = UINT32_MAX, hi = 0;
       for (int v = v0; v < v0 + nv; ++v) {
@@ -1399,10 +1599,14 @@ sg_status sg_campaign_scenes(sg_ctx* ctx, sg_prep* const* preps, int32_t n_preps
   }
   if (n_variants < 0 || (n_variants > 0 && (!variants || !scene_of))) return fail(SG_E_INVAL, "bad variants");
   if (n_sites < 0 || (n_sites > 0 && !sites)) return fail(SG_E_INVAL, "bad sites");
-  const int B = cfg && cfg->batch > 0 ? cfg->batch : 32;
+  const int engine = cfg ? cfg->engine : SG_ENGINE_PIPELINED;
+  if (engine != SG_ENGINE_PIPELINED && engine != SG_ENGINE_PERSISTENT) return fail(SG_E_INVAL, "unknown campaign engine");
+  const bool persistent = engine == SG_ENGINE_PERSISTENT;
+  const int B = cfg && cfg->batch > 0 ? cfg->batch : (persistent ? 0 : 32);
   const int NS = cfg && cfg->streams > 0 ? cfg->streams : 8;
   const int NT = std::min(cfg && cfg->threads > 0 ? cfg->threads : 2, NS);
-  if (B > kMaxBatch || NS > 64 || NT > 64) return fail(SG_E_INVAL, "campaign batch/streams/threads out of range");
+  if ((!persistent && B > kMaxBatch) || B < 0 || NS > 64 || NT > 64)
+    return fail(SG_E_INVAL, "campaign batch/streams/threads out of range");
   std::vector<DevBox> db(n_preps);
   for (int k = 0; k < n_preps; ++k)
     SG_TRY(to_dev_box(boxes ? boxes[k] : nullptr, box_field_mask, preps[k]->scene, &db[k]));
@@ -1436,6 +1640,9 @@ sg_status sg_campaign_scenes(sg_ctx* ctx, sg_prep* const* preps, int32_t n_preps
       ctx->campaign_streams.push_back(st);
     }
   }
+  if (persistent)
+    return campaign_persistent(ctx, preps, n_preps, sites, n_sites, variants, n_variants, db[0], B, metrics_out,
+                               S(stream), scene_of, db.data());
   return campaign_pipelined(ctx, preps, n_preps, sites, n_sites, variants, n_variants, db[0], B, NS, NT, metrics_out,
                             S(stream), scene_of, db.data());
 }

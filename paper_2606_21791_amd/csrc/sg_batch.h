@@ -20,14 +20,14 @@ __device__ __forceinline__ void wave_sync() {
 // rectangles of its changed primitives (its predicted regions).  One wave
 // walks the rectangles' bounding box 64 tiles at a time in row order and
 // writes a work item {tile, first entry of its clean list, clean list
-// length, 0} for each dirty tile that can change: a tile is dropped when its
-// last pixel stopped, in the clean render, before every key the variant
+// length, tag} for each dirty tile that can change: a tile is dropped when
+// its last pixel stopped, in the clean render, before every key the variant
 // removes from or inserts into its list (stop_key nullable: none dropped).
-// The results are the same in every lane.
+// With items null it only counts.  The results are the same in every lane.
 __device__ __forceinline__ void enumerate_items(const Touch* touch, uint32_t n_touch, int tiles_x, int tiles_y,
                                                 const uint64_t* stop_key, const uint32_t* tile_start,
                                                 const uint32_t* tile_cnt, uint4* items, uint32_t* n_dirty,
-                                                uint32_t* n_items, uint64_t* pred) {
+                                                uint32_t* n_items, uint64_t* pred, uint32_t tag = 0u) {
   const int lane = threadIdx.x & 63;
   int x0 = tiles_x, y0 = tiles_y, x1 = -1, y1 = -1;
   for (uint32_t j = 0; j < n_touch; ++j) {
@@ -60,13 +60,13 @@ __device__ __forceinline__ void enumerate_items(const Touch* touch, uint32_t n_t
           const int t = ty * tiles_x + tx;
           pr |= region_bit(tx, ty, tiles_x, tiles_y);
           const unsigned long long sk = stop_key ? stop_key[t] : ~0ull;
-          ent = make_uint4((uint32_t)t, tile_start[t], tile_cnt[t], 0u);
+          if (items) ent = make_uint4((uint32_t)t, tile_start[t], tile_cnt[t], tag);
           keep = mk <= sk;
         }
       }
       nd += (uint32_t)__popcll(__ballot(dirty));
       const unsigned long long kb = __ballot(keep);
-      if (keep) items[ni + (uint32_t)__popcll(kb & lt)] = ent;
+      if (keep && items) items[ni + (uint32_t)__popcll(kb & lt)] = ent;
       ni += (uint32_t)__popcll(kb);
     }
   }

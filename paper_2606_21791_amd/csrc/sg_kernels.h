@@ -328,4 +328,34 @@ struct StepArgs {
 // e0, e1 (nullable): events recorded at the launch's own start and end.
 void launch_campaign_step(const StepArgs& a, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
+// Campaign-wide persistent path.  A chunk of a campaign's variants (or
+// variant-views) is rendered by three launches on one stream: one lists the
+// work items of every variant compactly, one persistent launch composites all
+// of them, one reduces each variant's record.
+struct PersistArgs {
+  CompArgs A;               // clean state of the single view and the per-item partials A.parts (no images)
+  VariantState* vs;         // the chunk's variant states (from the campaign pre-pass)
+  const Rec* ovr;           // their override records, kMaxTouch per variant
+  uint4* items;             // work items {tile, first entry of its clean list, its length, variant}
+  uint32_t* item_off;       // per variant: index of its first item
+  uint32_t* n_items;        // per variant: its item count
+  uint32_t* ctl;            // [0] items listed so far (the list's cursor), [1] compositing work counter
+  int nv;                   // variants (variant-views) of the chunk
+  int grid;                 // workgroups of the persistent compositing launch
+  sg_metrics_t* out;        // per variant (variant-view): its record
+  uint32_t n_pixels;        // single view: pixels of the frame
+  // Several views or scenes (views != null), as in StepArgs: each
+  // variant-view takes its view's clean state, tile grid and size from
+  // views[view_of ? view_of[v] : v % K].
+  int K = 1;
+  const ViewArgs* views = nullptr;
+  const uint16_t* view_of = nullptr;
+};
+void launch_persist_list(const PersistArgs& a, hipStream_t st);
+// e0, e1 (nullable): events recorded at the launch's own start and end.
+void launch_persist_composite(const PersistArgs& a, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_persist_reduce(const PersistArgs& a, hipStream_t st);
+// Resident workgroups per CU of the persistent compositing kernel at a tile size.
+int persist_occupancy(int tile, bool mv);
+
 }  // namespace sg
