@@ -17,84 +17,110 @@ constexpr int kSortCap = 4096;       // keys sorted in LDS by one block
 constexpr int kMergeTile = 2048;     // outputs of one block in a merge pass
 constexpr int kEmitSmall = 32;       // rectangles up to this many tiles are emitted by one thread
 
+constexpr int kPrefixLds = 12288;   // difference-grid entries prefix-summed in LDS (48 KB)
+
+// Inclusive scans of up to three values per thread over the block (1,024
+// threads: wave scans by shuffles, then the wave totals), with two barriers.
+// tot receives the block totals.
+template <int NV>
+__device__ __forceinline__ void block_scan(uint32_t (&v)[NV], uint32_t (&tot)[NV], uint32_t (*s_w)[16]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)v[q], o);
+      if (lane >= o) v[q] += y;
+    }
+    if (lane == 63) s_w[q][wave] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    uint32_t off = 0, t = 0;
+    for (int w = 0; w < nw; ++w) {
+      const uint32_t x = s_w[q][w];
+      off += w < wave ? x : 0u;
+      t += x;
+    }
+    v[q] += off;
+    tot[q] = t;
+  }
+  __syncthreads();
+}
+
+// Tile counts and list offsets from the difference grid, in one workgroup of
+// 1,024 threads: the grid's row and column prefix sums (in LDS when it fits),
+// then a scan of the tile counts, then the tiles whose lists exceed one LDS
+// sort with the prefix counts of their LDS chunks and merge blocks.
 __global__ void __launch_bounds__(1024) k_tile_prefix(DevRaster ras, BinBuffers bb) {
   const int X = ras.tiles_x + 1, Y = ras.tiles_y + 1;
+  __shared__ int s_grid[kPrefixLds];
+  __shared__ uint32_t s_w[3][16];
+  const bool in_lds = X * Y <= kPrefixLds;
+  int* grid = in_lds ? s_grid : bb.diff;
+  if (in_lds) {
+    for (int i = threadIdx.x; i < X * Y; i += blockDim.x) s_grid[i] = bb.diff[i];
+    __syncthreads();
+  }
   for (int r = threadIdx.x; r < Y; r += blockDim.x) {
     int acc = 0;
-    for (int x = 0; x < X; ++x) { acc += bb.diff[r * X + x]; bb.diff[r * X + x] = acc; }
+    for (int x = 0; x < X; ++x) { acc += grid[r * X + x]; grid[r * X + x] = acc; }
   }
   __syncthreads();
   for (int x = threadIdx.x; x < X; x += blockDim.x) {
     int acc = 0;
-    for (int r = 0; r < Y; ++r) { acc += bb.diff[r * X + x]; bb.diff[r * X + x] = acc; }
+    for (int r = 0; r < Y; ++r) { acc += grid[r * X + x]; grid[r * X + x] = acc; }
   }
   __syncthreads();
-  __shared__ uint32_t s[1024];
   unsigned long long carry = 0;
   for (int base = 0; base < ras.n_tiles; base += 1024) {
     const int t = base + threadIdx.x;
     uint32_t c = 0;
     if (t < ras.n_tiles) {
       const int tx = t % ras.tiles_x, ty = t / ras.tiles_x;
-      c = (uint32_t)bb.diff[ty * X + tx];
+      c = (uint32_t)grid[ty * X + tx];
       bb.tile_cnt[t] = c;
       bb.cursor[t] = 0;
     }
-    s[threadIdx.x] = c;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const uint32_t y = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
-      __syncthreads();
-      s[threadIdx.x] += y;
-      __syncthreads();
-    }
-    if (t < ras.n_tiles) bb.tile_start[t] = (uint32_t)(carry + s[threadIdx.x] - c);
-    carry += s[1023];
-    __syncthreads();
+    uint32_t v[1] = {c}, tot[1];
+    block_scan<1>(v, tot, s_w);
+    if (t < ras.n_tiles) bb.tile_start[t] = (uint32_t)(carry + v[0] - c);
+    carry += tot[0];
   }
   // tiles whose lists exceed one LDS sort, in tile order, with the prefix
   // counts of their LDS chunks and of their merge blocks
-  __shared__ unsigned long long s_acc[3];
-  __shared__ uint32_t s_max;
-  if (threadIdx.x == 0) { s_acc[0] = s_acc[1] = s_acc[2] = 0; s_max = 0; }
-  __syncthreads();
+  unsigned long long acc0 = 0, acc1 = 0, acc2 = 0;
+  uint32_t mx = 0;
   for (int base = 0; base < ras.n_tiles; base += 1024) {
     const int t = base + threadIdx.x;
     const uint32_t c = t < ras.n_tiles ? bb.tile_cnt[t] : 0u;
     const bool big = c > (uint32_t)kSortCap;
     const uint32_t nch = big ? (c + kSortCap - 1) / kSortCap : 0u, ngr = big ? (c + kMergeTile - 1) / kMergeTile : 0u;
-    // three inclusive scans over the 1024 tiles of this round, in one LDS pass each
-    uint32_t v[3] = {big ? 1u : 0u, nch, ngr}, excl[3];
-    for (int q = 0; q < 3; ++q) {
-      s[threadIdx.x] = v[q];
-      __syncthreads();
-      for (int o = 1; o < 1024; o <<= 1) {
-        const uint32_t y = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
-        __syncthreads();
-        s[threadIdx.x] += y;
-        __syncthreads();
-      }
-      excl[q] = s[threadIdx.x] - v[q];
-      v[q] = s[1023];
-      __syncthreads();
-    }
+    uint32_t v[3] = {big ? 1u : 0u, nch, ngr}, tot[3];
+    block_scan<3>(v, tot, s_w);
     if (big) {
-      const uint32_t k = (uint32_t)(s_acc[0] + excl[0]);
+      const uint32_t k = (uint32_t)(acc0 + v[0] - 1u);
       bb.big_tiles[k] = (uint32_t)t;
-      bb.big_choff[k] = (uint32_t)(s_acc[1] + excl[1]);
-      bb.big_goff[k] = (uint32_t)(s_acc[2] + excl[2]);
-      atomicMax(&s_max, c);
+      bb.big_choff[k] = (uint32_t)(acc1 + v[1] - nch);
+      bb.big_goff[k] = (uint32_t)(acc2 + v[2] - ngr);
+      mx = max(mx, c);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) { s_acc[0] += v[0]; s_acc[1] += v[1]; s_acc[2] += v[2]; }
-    __syncthreads();
+    acc0 += tot[0];
+    acc1 += tot[1];
+    acc2 += tot[2];
   }
+  // the longest big list: a block maximum
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o));
+  if ((threadIdx.x & 63) == 0) s_w[0][threadIdx.x >> 6] = mx;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t nb = (uint32_t)s_acc[0];
-    bb.big_choff[nb] = (uint32_t)s_acc[1];
-    bb.big_goff[nb] = (uint32_t)s_acc[2];
-    bb.total[0] = carry; bb.total[1] = 0; bb.total[2] = nb; bb.total[3] = s_max;
-    bb.total[4] = s_acc[1]; bb.total[5] = s_acc[2];
+    uint32_t m = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = max(m, s_w[0][w]);
+    const uint32_t nb = (uint32_t)acc0;
+    bb.big_choff[nb] = (uint32_t)acc1;
+    bb.big_goff[nb] = (uint32_t)acc2;
+    bb.total[0] = carry; bb.total[1] = 0; bb.total[2] = nb; bb.total[3] = m;
+    bb.total[4] = acc1; bb.total[5] = acc2;
   }
 }
 
