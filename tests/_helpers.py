@@ -54,6 +54,44 @@ def compare_metrics(m, ref_img, clean_img, amb, nonfinite):
     return dict(ref_changed=ref_changed, n_amb=int(np.count_nonzero(amb | near)), nonfinite=bool(nonfinite))
 
 
+AMB_CAP = 1e-3           # largest fraction of ambiguous pixels a parity test accepts
+
+
+def check_variant(img, m, ref, clean_ref, clean_gpu, amb_cap=AMB_CAP):
+    """Pixel, PSNR and footprint parity of one variant (GPU image and record
+    against the oracle's full frames of the variant and the clean scene);
+    returns the ambiguous fraction."""
+    amb = ref["amb"] | clean_ref["amb"]
+    worst, amb_frac = compare_image(img, ref, clean_ref["amb"])
+    assert worst <= PIXEL_TOL, worst
+    assert amb_frac <= amb_cap, amb_frac
+    assert bool(m["nonfinite"]) == ref["nonfinite"]
+    ok = ~amb
+    d_gpu = np.abs(img.astype(np.float64) - clean_gpu.astype(np.float64))
+    d_ref = np.abs(ref["image"] - clean_ref["image"])
+    # the record is what the image says (exact recount on the GPU image)
+    dmax_gpu = d_gpu.max(axis=2)
+    assert int(m["changed_px"]) == int(np.count_nonzero(dmax_gpu > LEVEL))
+    assert abs(float(m["sse"]) - float(np.sum(d_gpu ** 2))) <= 1e-9 * max(1.0, float(np.sum(d_gpu ** 2)))
+    # footprint: exact on pixels not within LEVEL_BAND of the level and not ambiguous
+    dmax_ref = d_ref.max(axis=2)
+    cmp = ok & (np.abs(dmax_ref - LEVEL) > LEVEL_BAND)
+    assert np.array_equal((dmax_gpu > LEVEL)[cmp], (dmax_ref > LEVEL)[cmp])
+    # PSNR over the non-ambiguous pixels of both frames
+    mse_g = float(np.mean(d_gpu[ok] ** 2))
+    mse_r = float(np.mean(d_ref[ok] ** 2))
+    if mse_r == 0.0:
+        assert mse_g == 0.0 or 10 * np.log10(1 / mse_g) > 69.95
+    else:
+        pr = 10 * np.log10(1 / mse_r)
+        pg = 10 * np.log10(1 / mse_g) if mse_g > 0 else np.inf
+        if pr <= 70.0:
+            assert abs(pg - pr) <= PSNR_TOL_DB, (pg, pr)
+        else:
+            assert pg > 69.95
+    return amb_frac
+
+
 def ref_metrics(ref_img, clean_img, nonfinite, mask=None):
     return ometrics.frame_metrics(ref_img, clean_img, nonfinite, mask)
 

@@ -8,7 +8,8 @@ import pytest
 from oracle import formats, guard as oguard, metrics as om, render as orender
 from paper_2606_21791_amd import synth
 
-from ._helpers import PIXEL_TOL, PSNR_TOL_DB, LEVEL, LEVEL_BAND, apply_sites, compare_image, oracle_render, stored
+from ._helpers import PIXEL_TOL, LEVEL, apply_sites, check_variant as _check_variant, compare_image, \
+    oracle_render, stored
 
 pytestmark = pytest.mark.gpu
 
@@ -38,38 +39,6 @@ def _batch(ctx, prep, sites, idx_groups, guard=0, box=None, mode=0, want_images=
     return (imgs.cpu().numpy() if want_images else None), b.read_metrics(mt)
 
 
-def _check_variant(img, m, ref, clean_ref, clean_gpu):
-    """Pixel, PSNR and footprint parity of one variant."""
-    amb = ref["amb"] | clean_ref["amb"]
-    worst, amb_frac = compare_image(img, ref, clean_ref["amb"])
-    assert worst <= PIXEL_TOL, worst
-    assert amb_frac <= 5e-3, amb_frac
-    assert bool(m["nonfinite"]) == ref["nonfinite"]
-    ok = ~amb
-    d_gpu = np.abs(img.astype(np.float64) - clean_gpu.astype(np.float64))
-    d_ref = np.abs(ref["image"] - clean_ref["image"])
-    # the record is what the image says (exact recount on the GPU image)
-    dmax_gpu = d_gpu.max(axis=2)
-    assert int(m["changed_px"]) == int(np.count_nonzero(dmax_gpu > LEVEL))
-    assert abs(float(m["sse"]) - float(np.sum(d_gpu ** 2))) <= 1e-9 * max(1.0, float(np.sum(d_gpu ** 2)))
-    # footprint: exact on pixels not within LEVEL_BAND of the level and not ambiguous
-    dmax_ref = d_ref.max(axis=2)
-    cmp = ok & (np.abs(dmax_ref - LEVEL) > LEVEL_BAND)
-    assert np.array_equal((dmax_gpu > LEVEL)[cmp], (dmax_ref > LEVEL)[cmp])
-    # PSNR over the non-ambiguous pixels of both frames
-    mse_g = float(np.mean(d_gpu[ok] ** 2))
-    mse_r = float(np.mean(d_ref[ok] ** 2))
-    if mse_r == 0.0:
-        assert mse_g == 0.0 or 10 * np.log10(1 / mse_g) > 69.95
-    else:
-        pr = 10 * np.log10(1 / mse_r)
-        pg = 10 * np.log10(1 / mse_g) if mse_g > 0 else np.inf
-        if pr <= 70.0:
-            assert abs(pg - pr) <= PSNR_TOL_DB, (pg, pr)
-        else:
-            assert pg > 69.95
-
-
 def test_clean_frame_parity_w1_and_full_render_equal(ctx):
     import torch
     from paper_2606_21791_amd import binding as b
@@ -81,7 +50,7 @@ def test_clean_frame_parity_w1_and_full_render_equal(ctx):
     ref = oracle_render(stored(sc, "f32"), "f32", 0, cam)
     worst, amb = compare_image(frame, ref)
     print(f"W1 clean: max err {worst:.3g}, ambiguous {amb:.2e}, instances {prep.instances()}")
-    assert worst <= PIXEL_TOL and amb <= 2e-3
+    assert worst <= PIXEL_TOL and amb <= 2e-4
     img = torch.zeros((256, 256, 3), dtype=torch.float32, device="cuda")
     ctx.render(ds, cam, image=img)
     torch.cuda.synchronize()
@@ -250,7 +219,7 @@ def test_long_tile_lists(ctx, n):
     """Lists longer than one LDS sort (thousands of entries per 32x32 tile, so
     the grid-wide chunk sort and two or three merge passes run) give the same
     frame as 8x8 tiles (lists within one LDS sort at n=14,000; two merge
-    passes at n=40,000) and agree with the oracle on sampled pixels."""
+    passes at n=40,000) and agree with the oracle on every decided pixel."""
     from paper_2606_21791_amd import binding as b
     sc = synth.make_scene(n, seed=29)
     sc.fields[1][:] += 1.5                    # larger primitives: each covers several tiles
@@ -265,12 +234,10 @@ def test_long_tile_lists(ctx, n):
     # central tiles hold about 2.5 times the mean
     assert inst[32] / 9 > 3000
     assert np.array_equal(frames[8], frames[32])
-    rng = np.random.default_rng(5)
-    ys, xs = rng.integers(0, 96, 64), rng.integers(0, 96, 64)
-    pr = orender.project(orender.decode_scene(stored(sc, "f32"), "f32"), 0, cam)
-    ref = orender.render_pixels(pr, cam, xs, ys)
-    err = np.abs(frames[32][ys, xs] - ref).max(axis=1)
-    assert np.mean(err <= PIXEL_TOL) >= 0.98, np.sort(err)[-5:]
+    ref = oracle_render(stored(sc, "f32"), "f32", 0, cam)
+    worst, amb = compare_image(frames[32], ref)
+    print(f"long lists n={n}: max err {worst:.3g}, ambiguous {amb:.2e}", flush=True)
+    assert worst <= PIXEL_TOL and amb <= 2e-3, (worst, amb)
 
 
 def test_tile_size_invariance(ctx):
@@ -778,39 +745,12 @@ def test_sg_metrics_matches_definition(ctx):
     assert m["nonfinite"][2] == 1 and m["catastrophic"][2] == 1
 
 
-@pytest.mark.parametrize("fmt", ["f32", "bf16"])
-def test_w2_hi_sampled_pixels(ctx, fmt):
-    """Full W2 size (N = 134,826, SH degree 3, 800 x 800): the clean frame and
-    a few variants, checked on sampled pixels the oracle evaluates one by one."""
-    from paper_2606_21791_amd import binding as b
-    sc = synth.make_scene(134_826, seed=3, sh_degree=3)
-    cam = synth.make_camera(800, 800)
-    ds = b.DeviceScene.upload(ctx, sc, fmt)
-    prep = ctx.prepare(ds, cam)
-    words = stored(sc, fmt)
-    rng = np.random.default_rng(5)
-    xs, ys = rng.integers(0, 800, 150), rng.integers(0, 800, 150)
-    W = formats.width(fmt)
-    sites = synth.make_sites_stratified(sc.n, 3, W, seed=12, width_bits=W, fields=(1, 0, 4))
-    pick = [W - 1, W - 2, 3, W + W - 1, 2 * W + W - 2]
-    imgs, ms = _batch(ctx, prep, sites, [np.array([k]) for k in pick])
-    frame = prep.frame().cpu().numpy()
-    pr = orender.project(orender.decode_scene(words, fmt), 3, cam)
-    ref = orender.render_pixels(pr, cam, xs, ys)
-    assert np.max(np.abs(frame[ys, xs] - ref)) <= PIXEL_TOL
-    for j, k in enumerate(pick):
-        prv = orender.project(orender.decode_scene(apply_sites(words, sites, k), fmt), 3, cam)
-        refv = orender.render_pixels(prv, cam, xs, ys)
-        err = np.abs(imgs[j][ys, xs] - refv).max(axis=1)
-        assert np.mean(err <= PIXEL_TOL) >= 0.98, (k, np.sort(err)[-5:])
-
-
 def test_w2_hi_campaign_matches_batches(ctx):
     """Full W2 size (N = 134,826, SH degree 3, fp32, 800 x 800) in the launch
     configuration of the headline (B = 32, 64 streams, 2 host threads, the
     campaign pipeline): every record equals sg_render_batch's on the same
-    batches, whose frames the sampled-pixel test above checks against the
-    oracle."""
+    batches, whose frames test_gpu_parity_full checks against the oracle over
+    the whole frame."""
     import torch
     from paper_2606_21791_amd import binding as b
     sc = synth.make_scene(134_826, seed=3, sh_degree=3)
@@ -867,3 +807,133 @@ def test_graph_replay_matches_eager(ctx):
         for key in ("sse", "changed_px", "max_abs", "nonfinite", "dirty_tiles", "evals"):
             assert np.array_equal(e[key], g[key]), key
     assert not all(np.array_equal(eager[0]["sse"], e["sse"]) for e in eager[1:])   # the batches differ
+
+
+def test_persistent_campaign_matches_batches(ctx):
+    """The persistent campaign engine (chunks of variants, each listed,
+    composited in one persistent launch and reduced) gives exactly the
+    records of sg_render_batch on the same variants: guarded and multi-site
+    variants, an empty variant, chunks of one size and of several (the two
+    buffer sets alternating, a ragged last chunk), and, with a variant of
+    more than eight primitives, the batch-by-batch fallback."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(4000, seed=14, sh_degree=1)
+    cam = synth.make_camera(160, 128)
+    lo32, hi32 = synth.make_box_jitter(sc, seed=4)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    box = b.Box.per_prim(ctx, lo32, hi32, "f32")
+    prep = ctx.prepare(ds, cam)
+    single = synth.make_sites_stratified(sc.n, 1, 40, seed=19, width_bits=32)
+    dose = synth.make_sites_dose(sc.n, 1, 12, seed=20, width_bits=32)      # 12 primitives: full path
+    sites = synth.Sites(*(np.concatenate([a, c]) for a, c in zip(
+        (single.field, single.comp, single.prim, single.bit), (dose.field, dose.comp, dose.prim, dose.bit))))
+    ns = len(single.prim)
+    sa = b.sites_array(sites.field, sites.comp, sites.prim, sites.bit)
+    offs = list(range(ns)) + [0, 0, ns]
+    cnts = [1] * ns + [3, 0, len(dose.prim)]
+    va = b.variants_array(np.array(offs), np.array(cnts), 0)
+    va["guard"] = np.arange(len(offs)) % 3 == 0
+    ref = []
+    for v0 in range(0, len(va), 7):
+        mt = b.metrics_tensor(len(va[v0:v0 + 7]))
+        ctx.render_batch(prep, sa, va[v0:v0 + 7], box=box, metrics=mt)
+        ref.append(b.read_metrics(mt))
+    ref = np.concatenate(ref)
+    for vs, r in ((va[:-1], ref[:-1]), (va, ref)):
+        for batch in (0, 5, 64):
+            mt = b.metrics_tensor(len(vs))
+            ctx.campaign(prep, sa, vs, mt, box=box, batch=batch, engine=b.SG_ENGINE_PERSISTENT)
+            torch.cuda.synchronize()
+            got = b.read_metrics(mt)
+            for key in ref.dtype.names:
+                assert np.array_equal(got[key], r[key]), (len(vs), batch, key)
+    assert ref["path"][-1] == 1 and np.all(ref["path"][:-1] == 0) and ref["sse"][-2] == 0
+
+
+def test_persistent_campaign_views_and_scenes(ctx):
+    """The persistent engine over K views (the views of a variant side by
+    side in every launch, views of different sizes included) and over scenes
+    of uneven size: records equal sg_render_batch_views per batch and
+    sg_render_batch on each variant's own scene."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(4000, seed=14, sh_degree=1)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    lo32, hi32 = synth.make_box_jitter(sc, seed=4)
+    box = b.Box.per_prim(ctx, lo32, hi32, "f32")
+    s = synth.make_sites_stratified(sc.n, 1, 12, seed=31, width_bits=32)
+    sa = b.sites_array(s.field, s.comp, s.prim, s.bit)
+    va = b.variants_array(np.arange(len(sa)), np.ones(len(sa), np.uint32))
+    va["guard"] = np.arange(len(va)) % 2
+    for cams in (synth.make_orbit_cameras(3, 96, 80), synth.make_orbit_cameras(2, 96, 80) + [synth.make_camera(64, 48)]):
+        preps = [ctx.prepare(ds, c) for c in cams]
+        ref = []
+        for v0 in range(0, len(va), 9):
+            mt = b.metrics_tensor(len(va[v0:v0 + 9]))
+            ctx.render_batch_views(preps, sa, va[v0:v0 + 9], mt, box=box)
+            ref.append(b.read_metrics(mt))
+        ref = np.concatenate(ref)
+        for batch in (0, 10):
+            got = b.metrics_tensor(len(va))
+            ctx.campaign(preps, sa, va, got, box=box, batch=batch, engine=b.SG_ENGINE_PERSISTENT)
+            torch.cuda.synchronize()
+            G = b.read_metrics(got)
+            for key in ref.dtype.names:
+                assert np.array_equal(G[key], ref[key]), (len(cams), batch, key)
+    # scenes of uneven size
+    specs = [(6741, 1, "f32", 200, 160), (2500, 0, "bf16", 96, 64), (12000, 3, "f16", 256, 144)]
+    preps, site_sets = [], []
+    for j, (n, sh, fmt, w, h) in enumerate(specs):
+        scj = synth.make_scene(n, seed=70 + j, sh_degree=sh)
+        dsj = b.DeviceScene.upload(ctx, scj, fmt)
+        preps.append(ctx.prepare(dsj, synth.make_camera(w, h)))
+        preps[-1]._ds = dsj
+        W = formats.width(fmt)
+        site_sets.append(synth.make_sites_stratified(n, sh, 2 * W, seed=80 + j, width_bits=W, fields=(0, 1, 2, 3, 4)))
+    cat = lambda key: np.concatenate([getattr(t, key) for t in site_sets])
+    sa = b.sites_array(cat("field"), cat("comp"), cat("prim"), cat("bit"))
+    base = np.cumsum([0] + [len(t.prim) for t in site_sets])
+    rng = np.random.default_rng(77)
+    scene_of = rng.integers(0, 3, size=150).astype(np.uint16)
+    off = np.array([base[k] + rng.integers(0, len(site_sets[k].prim)) for k in scene_of])
+    va = b.variants_array(off, np.ones(len(off), np.uint32))
+    for batch in (0, 16):
+        got = b.metrics_tensor(len(va))
+        ctx.campaign_scenes(preps, sa, va, scene_of, got, batch=batch, engine=b.SG_ENGINE_PERSISTENT)
+        torch.cuda.synchronize()
+        G = b.read_metrics(got)
+        for k in range(3):
+            idx = np.nonzero(scene_of == k)[0]
+            t = site_sets[k]
+            vk = va[idx].copy()
+            vk["site_off"] -= np.uint32(base[k])
+            mt = b.metrics_tensor(len(idx))
+            ctx.render_batch(preps[k], b.sites_array(t.field, t.comp, t.prim, t.bit), vk, metrics=mt)
+            ref = b.read_metrics(mt)
+            for key in ref.dtype.names:
+                assert np.array_equal(G[key][idx], ref[key]), (batch, k, key)
+
+
+def test_persistent_campaign_w2_hi_matches_pipelined(ctx):
+    """Full W2 size (N = 134,826, SH degree 3, fp32, 800 x 800): the persistent
+    engine's records over 2,000 stratified single-bit variants equal the
+    pipelined engine's in the headline configuration (B = 32, 64 streams)."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(134_826, seed=3, sh_degree=3)
+    cam = synth.make_camera(800, 800)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam)
+    s = synth.make_sites_stratified(sc.n, 3, 400, seed=46, width_bits=32)
+    sa = b.sites_array(s.field, s.comp, s.prim, s.bit)
+    n = len(sa)
+    va = b.variants_array(np.arange(n), np.ones(n, np.uint32))
+    ref, got = b.metrics_tensor(n), b.metrics_tensor(n)
+    ctx.campaign(prep, sa, va, ref, batch=32, streams=64, threads=2)
+    ctx.campaign(prep, sa, va, got, engine=b.SG_ENGINE_PERSISTENT)
+    torch.cuda.synchronize()
+    R, G = b.read_metrics(ref), b.read_metrics(got)
+    for key in R.dtype.names:
+        assert np.array_equal(G[key], R[key]), key
+    assert np.any(G["dirty_tiles"] > 1000) and np.any(G["changed_px"] > 0)
