@@ -5,15 +5,17 @@ one-render-per-injection path, on one GPU.
 Workload: the scaling-sweep scene at its large size (N = 134,826 Gaussians,
 SH degree 3, 800 x 800, 16 x 16 tiles), parameters stored as fp32 (or
 --fmt f16/bf16), 5,000 single-bit sites per field (bit j mod width, every
-field), B = 32 variants per launch.  A step is one sg_render_batch call:
-build the 32 corrupted variants, project their corrupted primitives, plan
-and re-composite their dirty tiles in one persistent launch, reduce their
-PSNR/footprint records.  The clean scene, its tile lists and its clean frame
-are resident (prepared once, outside the timed region).
+field), B = 32 variants per launch.  A step is one B-variant batch on every
+campaign stream (global_batch = B x streams injections): each batch stages
+its corrupted variants, projects their corrupted primitives, lists and
+re-composites their dirty tiles and reduces their PSNR/footprint records.
+The K timed steps run as one sg_campaign call.  The clean scene, its tile
+lists and its clean frame are resident (prepared once, outside the timed
+region).
 
 Prints one JSON line.  `value` is batched injections/s; `plain` holds the
 plain path (sg_inject + sg_render + sg_restore + metric readback per
-injection) on the same GPU; `roofline` is the compositing kernel's fp32
+injection) on the same GPU; `roofline` is the compositing launches' fp32
 arithmetic rate (20 flops per pixel-primitive evaluation) against the fp32
 vector peak; `cpu_baseline` is the FP64 oracle's plain path on the host.
 """
@@ -158,8 +160,9 @@ def cpu_baseline(sc, cam, sites, fmt, n_inj, procs):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=60,
+                    help="timed steps; a step is one --batch batch on every stream")
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-tune", action="store_true",
@@ -178,6 +181,8 @@ def main():
     ap.add_argument("--free-batch", type=int, default=512,
                     help="also tune B up to this bound and time that configuration (0: skip)")
     ap.add_argument("--plain", type=int, default=100, help="injections timed on the plain path")
+    ap.add_argument("--no-persistent", dest="persistent", action="store_false",
+                    help="skip the persistent campaign engine's rate on the same injections")
     ap.add_argument("--storm-n", type=int, default=32 * 2_056_645, help="primitives of the fault-storm scene")
     ap.add_argument("--storm-k", type=int, default=1000, help="upsets written per storm frame")
     ap.add_argument("--storm-frames", type=int, default=300, help="frames of the fault storm")
@@ -186,7 +191,7 @@ def main():
     ap.add_argument("--cpu-inj", type=int, default=1, help="oracle injections timed on one host thread (0: skip)")
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="oracle processes run at once for the all-core baseline (0: the host's cores, at most 16)")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="seconds of Poisson arrivals for the serving measurement (0: skip)")
     ap.add_argument("--workload", default="w2", choices=["w2", "guard", "large", "stress", "serve", "copy", "views", "storm",
                                                          "scenes"],
@@ -226,41 +231,38 @@ def main():
     ctx.set_persistent_grid(args.grid)
     ctx.set_resume(args.resume)
     ctx.set_graphs(args.graphs)
-    streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
+    NS = max(1, args.streams)
+    streams = [torch.cuda.Stream() for _ in range(NS)]
     prep = ctx.prepare(ds, cam, sgb.raster_struct(tile=args.tile))
     torch.cuda.synchronize()
     B = args.batch
+    # A step is one B-variant batch on every stream: GB injections, each of
+    # them the whole hot path (staging, projection of the corrupted
+    # primitives, dirty tiles, compositing, metrics).
+    GB = B * NS
     n_sites = len(sites)
     steps_total = args.warmup + args.steps
-    batches = []
-    for i in range(steps_total):
-        idx = (np.arange(B) + i * B) % n_sites
-        sa = sgb.sites_array(sites.field[idx], sites.comp[idx], sites.prim[idx], sites.bit[idx])
-        batches.append(sa)
-    va = sgb.variants_array(np.arange(B), np.ones(B, np.uint32))
-    rec_bytes = B * sgb.METRICS_DTYPE.itemsize
-    mt_all = sgb.metrics_tensor(B * steps_total)
-    mts = [mt_all[i * rec_bytes:(i + 1) * rec_bytes] for i in range(steps_total)]
-
-    def run(i):
-        with torch.cuda.stream(streams[i % len(streams)]):
-            ctx.render_batch(prep, batches[i], va, metrics=mts[i])
-
-    # native campaign: every step's batch in one sg_campaign call (batches of
-    # B round-robin over the streams, enqueued by `threads` host threads)
-    all_idx = np.arange(steps_total * B) % n_sites
+    n_all = steps_total * GB
+    all_idx = np.arange(n_all) % n_sites
     sa_all = sgb.sites_array(sites.field[all_idx], sites.comp[all_idx], sites.prim[all_idx], sites.bit[all_idx])
-    va_all = sgb.variants_array(np.arange(steps_total * B), np.ones(steps_total * B, np.uint32))
-    w_end = args.warmup * B
+    va_all = sgb.variants_array(np.arange(n_all), np.ones(n_all, np.uint32))
+    va_b = sgb.variants_array(np.arange(B), np.ones(B, np.uint32))
+    rec_bytes = sgb.METRICS_DTYPE.itemsize
+    mt_all = sgb.metrics_tensor(n_all)
+    w_end = args.warmup * GB
 
     def run_steps(first, last):
-        """Steps [first, last): a campaign call, or a Python loop of batches."""
+        """Steps [first, last): one campaign call (batches round-robin over the
+        streams, enqueued by `threads` host threads), or a Python loop of
+        sg_render_batch calls."""
         if args.threads > 0:
-            ctx.campaign(prep, sa_all, va_all[first * B:last * B], mt_all[first * rec_bytes:last * rec_bytes],
-                         batch=B, streams=len(streams), threads=args.threads)
+            ctx.campaign(prep, sa_all, va_all[first * GB:last * GB], mt_all[first * GB * rec_bytes:last * GB * rec_bytes],
+                         batch=B, streams=NS, threads=args.threads)
         else:
-            for i in range(first, last):
-                run(i)
+            for j in range(first * NS, last * NS):
+                with torch.cuda.stream(streams[j % NS]):
+                    ctx.render_batch(prep, sa_all[j * B:(j + 1) * B], va_b,
+                                     metrics=mt_all[j * B * rec_bytes:(j + 1) * B * rec_bytes])
 
     run_steps(0, args.warmup)
     torch.cuda.synchronize()
@@ -271,7 +273,7 @@ def main():
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
     recs = sgb.read_metrics(mt_all)[w_end:]
-    inj_per_s = args.steps * B / elapsed
+    inj_per_s = args.steps * GB / elapsed
     # the same campaign REPS more times, for the spread of the rate
     REPS = 3
     rep_rates = []
@@ -280,11 +282,12 @@ def main():
             t0 = time.perf_counter()
             run_steps(args.warmup, steps_total)
             torch.cuda.synchronize()
-            rep_rates.append(args.steps * B / (time.perf_counter() - t0))
+            rep_rates.append(args.steps * GB / (time.perf_counter() - t0))
     rep_rates = np.array(rep_rates)
 
-    # the same steps again with per-pass HIP events (graphs are not used while
-    # timing), for the per-pass breakdown and the compositing launch duration
+    # the same steps again with per-launch HIP events (recorded by each step
+    # launch at its own start and end), for the per-pass breakdown and the
+    # duration of the compositing launches
     ctx.timing(True)
     ctx.pass_times()
     with _no_gc():
@@ -294,14 +297,29 @@ def main():
     ctx.timing(False)
     recs_timed = sgb.read_metrics(mt_all)[w_end:]
 
-    # dominant kernel: the persistent compositing launch
+    # dominant kernel: the campaign step launches that composite a batch (the
+    # pipeline's fill and drain launches are timed apart, under "reduce")
     comp_ms, comp_n = passes["composite_items"]
     comp_avg_s = comp_ms / max(comp_n, 1) / 1e3
-    # a stream's pipeline has two launches more than batches: per launch over all of them
     evals_per_launch = float(recs["evals"].sum()) / max(comp_n, 1)
     achieved = evals_per_launch * FLOPS_PER_EVAL / comp_avg_s / 1e12 if comp_avg_s > 0 else 0.0
 
-    # the other storage formats at the same launch configuration
+    def campaign_rate(c, pr, sa, n_inj, batch, nstreams, threads):
+        """Injections/s of one campaign over the first n_inj variants of sa
+        (after a warm-up campaign of a few steps), and its records."""
+        va = sgb.variants_array(np.arange(n_inj), np.ones(n_inj, np.uint32))
+        mt = sgb.metrics_tensor(n_inj)
+        kw = dict(batch=batch, streams=nstreams, threads=threads)
+        c.campaign(pr, sa, va[:min(n_inj, max(1, args.warmup) * batch * nstreams)], mt, **kw)
+        torch.cuda.synchronize()
+        with _no_gc():
+            t0 = time.perf_counter()
+            c.campaign(pr, sa, va, mt, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        return n_inj / dt, sgb.read_metrics(mt)
+
+    # the other storage formats at the same launch configuration and step count
     per_format = {}
     for fmt in ("f32", "f16", "bf16"):
         if fmt == args.fmt or not args.formats:
@@ -309,21 +327,11 @@ def main():
         sc_f, _, sites_f = _workload(fmt)
         ds_f = sgb.DeviceScene.upload(ctx, sc_f, fmt)
         prep_fm = ctx.prepare(ds_f, cam, sgb.raster_struct(tile=args.tile))
-        n_f = args.steps * B   # the headline campaign length
+        n_f = args.steps * GB
         idx_f = np.arange(n_f) % len(sites_f)
         sa_f = sgb.sites_array(sites_f.field[idx_f], sites_f.comp[idx_f], sites_f.prim[idx_f], sites_f.bit[idx_f])
-        va_f = sgb.variants_array(np.arange(n_f), np.ones(n_f, np.uint32))
-        mt_fm = sgb.metrics_tensor(n_f)
-        kw = dict(batch=B, streams=len(streams), threads=max(1, args.threads))
-        ctx.campaign(prep_fm, sa_f, va_f[:8 * B], mt_fm, **kw)
-        torch.cuda.synchronize()
-        with _no_gc():
-            t0 = time.perf_counter()
-            ctx.campaign(prep_fm, sa_f, va_f, mt_fm, **kw)
-            torch.cuda.synchronize()
-            dt_fm = time.perf_counter() - t0
-        r_f = sgb.read_metrics(mt_fm)
-        per_format[fmt] = {"value": round(n_f / dt_fm, 1), "injections": n_f,
+        rate_f, r_f = campaign_rate(ctx, prep_fm, sa_f, n_f, B, NS, max(1, args.threads))
+        per_format[fmt] = {"value": round(rate_f, 1), "injections": n_f, "steps": args.steps,
                            "dirty_tiles_per_injection": round(float(r_f["dirty_tiles"].mean()), 2),
                            "catastrophic_fraction": round(float(r_f["catastrophic"].mean()), 4)}
         del prep_fm, ds_f
@@ -337,31 +345,61 @@ def main():
         ctx_f = sgb.Context(0)
         ctx_f.apply_tune(tf)
         prep_f = ctx_f.prepare(ds, cam, sgb.raster_struct(tile=tf["tile"]))
-        n_inj = args.steps * B
-        mt_f = sgb.metrics_tensor(n_inj)
-        kw = dict(batch=tf["batch"], streams=tf["streams"], threads=tf["threads"])
-        ctx_f.campaign(prep_f, sa_all, va_all[w_end:w_end + min(n_inj, 4 * tf["batch"])], mt_f, **kw)
-        torch.cuda.synchronize()
-        with _no_gc():
-            t0 = time.perf_counter()
-            ctx_f.campaign(prep_f, sa_all, va_all[w_end:w_end + n_inj], mt_f, **kw)
-            torch.cuda.synchronize()
-            dt_f = time.perf_counter() - t0
-        rf = sgb.read_metrics(mt_f)
+        n_inj = args.steps * GB
+        rate_tf, rf = campaign_rate(ctx_f, prep_f, sa_all[w_end:], n_inj, tf["batch"], tf["streams"], tf["threads"])
         same = all(np.array_equal(rf[k], recs[k]) for k in ("changed_px", "max_abs", "nonfinite")) and \
             bool(np.allclose(rf["sse"], recs["sse"], rtol=1e-12, atol=0.0))
-        free = {"value": round(n_inj / dt_f, 1), "unit": "injections/s", "injections": n_inj,
+        free = {"value": round(rate_tf, 1), "unit": "injections/s", "injections": n_inj,
                 "config": {k: tf[k] for k in ("tile", "batch", "streams", "threads", "wgs_per_cu", "grid", "resume",
                                               "graphs")},
                 "tune_seconds": tf["seconds"], "records_identical_to_headline": same}
         del prep_f, ctx_f
+
+    # the same injections through the persistent engine: chunks of as many
+    # variants as its buffers hold, each listed, composited by one persistent
+    # launch and reduced (no per-batch launches, two streams)
+    persist = None
+    if args.persistent:
+        n_inj = args.steps * GB
+        va_p = sgb.variants_array(np.arange(n_inj), np.ones(n_inj, np.uint32))
+        mt_p = sgb.metrics_tensor(n_inj)
+        sa_p = sa_all[w_end:]
+        ctx.campaign(prep, sa_p, va_p[:min(n_inj, 8192)], mt_p, engine=sgb.SG_ENGINE_PERSISTENT)
+        torch.cuda.synchronize()
+        p_rates = []
+        for r in range(1 + REPS):
+            with _no_gc():
+                t0 = time.perf_counter()
+                ctx.campaign(prep, sa_p, va_p, mt_p, engine=sgb.SG_ENGINE_PERSISTENT)
+                torch.cuda.synchronize()
+                p_rates.append(n_inj / (time.perf_counter() - t0))
+        rp = sgb.read_metrics(mt_p)
+        ctx.timing(True)
+        ctx.pass_times()
+        ctx.campaign(prep, sa_p, va_p, mt_p, engine=sgb.SG_ENGINE_PERSISTENT)
+        torch.cuda.synchronize()
+        pp = ctx.pass_times()
+        ctx.timing(False)
+        pc_ms, pc_n = pp["composite_items"]
+        pc_avg_s = pc_ms / max(pc_n, 1) / 1e3
+        p_evals = float(rp["evals"].sum()) / max(pc_n, 1)
+        p_ach = p_evals * FLOPS_PER_EVAL / pc_avg_s / 1e12 if pc_avg_s > 0 else 0.0
+        persist = {"value": round(p_rates[0], 1), "unit": "injections/s", "injections": n_inj,
+                   "repetitions": {"n": REPS, "median": round(float(np.median(p_rates[1:])), 1)},
+                   "variants_per_launch": int(-(-n_inj // max(pc_n, 1))),
+                   "records_identical_to_headline": bool(all(np.array_equal(rp[k], recs[k]) for k in rp.dtype.names)),
+                   "pass_ms": {k: round(v[0], 3) for k, v in pp.items() if v[1]},
+                   "roofline": {"bound": "alu", "kernel": "k_persist_composite", "achieved": round(p_ach, 3),
+                                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(p_ach / FP32_PEAK_TFLOPS, 4),
+                                "avg_launch_ms": round(pc_avg_s * 1e3, 4), "launches": pc_n,
+                                "evals_per_launch": round(p_evals), "flops_per_eval": FLOPS_PER_EVAL}}
 
     # plain path: inject, full render with metrics against the clean frame, restore, read back
     frame = prep.frame()
     mt1 = sgb.metrics_tensor(1)
     P = args.plain
     for k in range(min(5, P)):
-        sa = batches[k][:1]
+        sa = sa_all[k:k + 1]
         ctx.inject(ds, sa)
         ctx.render(ds, cam, sgb.raster_struct(tile=args.tile), clean=frame, metrics=mt1)
         ctx.restore(ds, sa)
@@ -372,8 +410,7 @@ def main():
     t0 = time.perf_counter()
     plain_recs = []
     for k in range(P):
-        i = args.warmup + k // B
-        sa = batches[i][k % B:k % B + 1]
+        sa = sa_all[w_end + k:w_end + k + 1]
         ctx.inject(ds, sa)
         ctx.render(ds, cam, sgb.raster_struct(tile=args.tile), clean=frame, metrics=mt1)
         ctx.restore(ds, sa)
@@ -403,9 +440,10 @@ def main():
         "data": "synthetic (seeded scene and sites standing in for the paper's trained scenes)",
         "config": {"workload": f"scaling-sweep large scene: N=134,826 Gaussians, SH degree 3, {args.fmt} storage, "
                                f"800x800, {args.tile}x{args.tile} tiles, B={B} single-bit variants per launch, "
-                               "incremental dirty-tile re-composite",
-                   "global_batch": B, "n_sites": n_sites, "instances_clean": prep.instances(),
-                   "streams": len(streams), "host_threads": args.threads, "wgs_per_cu": args.wgs_per_cu,
+                               "incremental dirty-tile re-composite; a step is one batch on each of the "
+                               f"{NS} streams",
+                   "global_batch": GB, "batch_per_launch": B, "n_sites": n_sites,
+                   "instances_clean": prep.instances(), "streams": NS, "host_threads": args.threads, "wgs_per_cu": args.wgs_per_cu,
                    "grid": args.grid,
                    "graphs": args.graphs, "resume_spacing": args.resume,
                    "tuned": tuned is not None, "gpu_max_hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"])},
@@ -418,6 +456,7 @@ def main():
                   "records_agree_with_batched": agree},
         "speedup_vs_plain": round(inj_per_s / (P / plain_dt), 2),
         "tuned_any_batch": free,
+        "persistent": persist,
         "pass_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in passes.items() if v[1]},
         "repetitions": {"n": REPS, "median": round(float(np.median(rep_rates)), 1),
                         "p10": round(float(np.percentile(rep_rates, 10)), 1),
@@ -880,7 +919,7 @@ def run_scenes(args):
 
 
 def run_storm(args):
-    """Fault storm on the largest model (Sec. 5.9): k random upsets over every
+    """Fault storm on the largest model (Sec. 5.12): k random upsets over every
     stored bit are written into the resident scene every frame, for F frames;
     each frame is rendered from the corrupted scene, unguarded, guarded every
     frame, or scrubbed every M frames (Cor. 2's periodic scrub).  Reports
