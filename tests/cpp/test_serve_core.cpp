@@ -1,8 +1,11 @@
 // Host unit test of the server's scheduling core: batching policy, admission
 // by budget, rejection, and nearest-rank percentiles.  Built with g++ by
 // tests/test_serve_core_cpu.py; exits nonzero on the first failed check.
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
+#include <thread>
+#include <vector>
 
 #include "../../paper_2606_21791_amd/csrc/serve_core.h"
 
@@ -95,6 +98,49 @@ int main() {
     std::vector<double> v;
     for (int i = 1; i <= 100; ++i) v.push_back((double)i);
     CHECK(percentile(v, 0.5) == 50.0 && percentile(v, 0.99) == 99.0 && percentile(v, 1.0) == 100.0);
+  }
+  // concurrent use, as by the server: producer threads submit while worker
+  // threads take launches and finish them; every accepted request completes
+  // exactly once and the memory held by running work returns to zero
+  {
+    constexpr int kProducers = 4, kWorkers = 4, kPerProducer = 3000;
+    Scheduler s(1 << 20, 1 << 18, 64, 1 << 20);
+    std::atomic<int> accepted{0}, refused{0}, done_reqs{0}, producers_left{kProducers};
+    std::vector<std::thread> th;
+    for (int p = 0; p < kProducers; ++p)
+      th.emplace_back([&, p] {
+        for (int i = 0; i < kPerProducer; ++i) {
+          const uint64_t t = (uint64_t)p * kPerProducer + (uint64_t)i + 1;
+          const size_t bytes = (t % 7 == 0) ? (size_t)1 << 20 : (size_t)(t % 5 + 1) << 12;   // 1 in 7 never fits
+          const int rc = s.submit(req(t, (int)(t % 3 == 0), (int)(t % 4), 1 + (int)(t % 16), (int64_t)t, bytes));
+          (rc == 0 ? accepted : refused).fetch_add(1);
+        }
+        producers_left.fetch_sub(1);
+      });
+    for (int w = 0; w < kWorkers; ++w)
+      th.emplace_back([&] {
+        for (;;) {
+          Batch b;
+          if (s.next(&b)) {
+            if (!b.rejected) {
+              CHECK(b.n_variants <= 64 || b.reqs.size() == 1);
+              done_reqs.fetch_add((int)b.reqs.size());
+            }
+            s.finish(b, (int64_t)1 << 40);
+          } else if (producers_left.load() == 0 && s.pending() == 0) {
+            return;
+          } else {
+            std::this_thread::yield();
+          }
+        }
+      });
+    for (std::thread& t : th) t.join();
+    Scheduler::Counters k = s.counters();
+    CHECK(accepted.load() + refused.load() == kProducers * kPerProducer);
+    CHECK((int)k.submitted == accepted.load() && (int)k.completed == done_reqs.load());
+    CHECK(k.completed + (k.rejected - (uint64_t)refused.load()) == k.submitted);
+    CHECK(s.running_bytes() == 0 && s.pending() == 0);
+    CHECK(s.latency(kCampaign).n + s.latency(kGuardedRender).n == k.completed);
   }
   std::printf("serve core ok\n");
   return 0;
