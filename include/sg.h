@@ -454,6 +454,20 @@ sg_status sg_ssim(sg_ctx* ctx, const float* images, const float* clean, int32_t 
 sg_status sg_metrics(sg_ctx* ctx, const float* images, const float* clean, int32_t B, int32_t K, int32_t H,
                      int32_t W, sg_metrics_t* out, void* stream);
 
+/* sg_metrics without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and records as sg_metrics.  Its
+ * partials live in a fixed 4 MiB scratch array in device memory, one per
+ * device, held until the process ends: B * min(256, ceil(K*H*W / 1024))
+ * partials of 32 bytes must fit (131,072 of them), otherwise SG_E_INVAL with
+ * the limit in sg_last_error() and nothing is launched.  The scratch address
+ * of a device is recorded by sg_ctx_create.  Every call on one device shares
+ * that device's scratch and overwrites it entirely before reading it, so
+ * calls that overlap on one device (different streams or threads without
+ * ordering between them) race; calls ordered on one stream do not. */
+sg_status sg_metrics_noalloc(sg_ctx* ctx, const float* images, const float* clean, int32_t B, int32_t K, int32_t H,
+                             int32_t W, sg_metrics_t* out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Serving: a request loop over resident scenes.  Scenes (and their guard
  * boxes) are copied to the device once; each (scene, camera) view is

@@ -130,6 +130,7 @@ def _load():
         "sg_campaign_scenes": (i32, [vp, vp, i32, vp, i32, vp, vp, i32, vp, u32, P(SgCampaignCfg), vp, vp]),
         "sg_render_batch_views": (i32, [vp, vp, i32, vp, i32, vp, i32, P(SgBox), u32, vp, vp, i32, vp]),
         "sg_metrics": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
+        "sg_metrics_noalloc": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
         "sg_ssim": (i32, [vp, vp, vp, i32, i32, i32, vp, vp]),
         "sg_autotune": (i32, [vp, P(SgScene), P(SgCamera), P(SgRaster), vp, i32, i32, i32, C.c_char_p, P(SgTune), vp]),
         "sg_ctx_timing": (i32, [vp, i32]),
@@ -159,7 +160,7 @@ LIB = _load()
 EXPORTED = ("sg_ctx_create", "sg_ctx_destroy", "sg_last_error", "sg_ctx_bytes", "sg_cast", "sg_inject",
             "sg_restore", "sg_guard_box", "sg_guard", "sg_render", "sg_prepare", "sg_prep_destroy",
             "sg_prep_frame", "sg_prep_instances", "sg_prep_copy_frame", "sg_render_batch", "sg_render_batch_views", "sg_campaign",
-            "sg_campaign_views", "sg_campaign_scenes", "sg_autotune", "sg_metrics", "sg_ssim",
+            "sg_campaign_views", "sg_campaign_scenes", "sg_autotune", "sg_metrics", "sg_metrics_noalloc", "sg_ssim",
             "sg_ctx_timing", "sg_ctx_pass_times", "sg_ctx_set_persistent", "sg_ctx_set_persistent_grid", "sg_ctx_set_resume", "sg_ctx_set_graphs",
             "sg_serve_create",
             "sg_serve_add_scene", "sg_serve_add_view", "sg_serve_submit", "sg_serve_poll", "sg_serve_wait",
@@ -399,6 +400,10 @@ class Context:
 
     def metrics(self, images, clean, B, K, H, W, out):
         check(LIB.sg_metrics(self.h, _ptr(images), _ptr(clean), B, K, H, W, _ptr(out), _stream()))
+
+    def metrics_noalloc(self, images, clean, B, K, H, W, out):
+        """sg_metrics_noalloc: the same records with no device allocation."""
+        check(LIB.sg_metrics_noalloc(self.h, _ptr(images), _ptr(clean), B, K, H, W, _ptr(out), _stream()))
 
 
 class DeviceScene:

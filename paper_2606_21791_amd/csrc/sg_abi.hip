@@ -523,6 +523,24 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
 
 }  // namespace
 
+// Scratch memory of the allocation-free metrics call (sg_metrics_noalloc):
+// the per-chunk metric partials of up to kScratchBytes / sizeof(Partial)
+// (variant, chunk) pairs.  Each device that the library runs on holds its own
+// copy until the process ends.  Host code never passes `scratch` itself (its
+// host-side name is not a device address): sg_ctx_create records, once per
+// device and with that device current, the address hipGetSymbolAddress gives
+// for it, and the call uses that address.
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kScratchDevices] = {};
+
+static void* scratch_of(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return device >= 0 && device < kScratchDevices ? g_scratch_dev[device] : nullptr;
+}
+
 extern "C" {
 
 const char* sg_last_error(void) { return g_err.c_str(); }
@@ -534,6 +552,16 @@ sg_status sg_ctx_create(int32_t device, size_t hbm_budget_bytes, sg_ctx** out) {
   if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return fail(SG_E_DEVICE, "no HIP device");
   if (device < 0 || device >= count) return fail(SG_E_INVAL, "device index out of range");
   HIP_TRY(hipSetDevice(device));
+  if (device < kScratchDevices) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fail(SG_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      g_scratch_dev[device] = p;
+    }
+  }
   sg_ctx* c = new sg_ctx();
   c->device = device;
   c->budget = hbm_budget_bytes;
@@ -1680,6 +1708,28 @@ sg_status sg_metrics(sg_ctx* ctx, const float* images, const float* clean, int32
   launch_reduce_metrics(P<Partial>(WS->metrics_tmp), nullptr, nullptr, (uint32_t)nchunks, nullptr, nullptr, nullptr,
                         (uint32_t)px, out, B, 1u, st);
   return check_last("sg_metrics");
+}
+
+sg_status sg_metrics_noalloc(sg_ctx* ctx, const float* images, const float* clean, int32_t B, int32_t K, int32_t H,
+                             int32_t W, sg_metrics_t* out, void* stream) {
+  if (!ctx || !images || !clean || !out) return fail(SG_E_INVAL, "NULL argument");
+  if (B < 1 || K < 1 || H < 1 || W < 1) return fail(SG_E_INVAL, "sizes must be >= 1");
+  const int64_t px = (int64_t)K * H * W;
+  const int nchunks = (int)std::min<int64_t>(256, (px + 1023) / 1024);
+  const size_t need = (size_t)B * (size_t)nchunks * sizeof(Partial);
+  if (need > kScratchBytes)
+    return fail(SG_E_INVAL, "sg_metrics_noalloc: " + std::to_string(B) + " variants of " + std::to_string(px) +
+                                " pixels need " + std::to_string(need) + " bytes of scratch; the limit is " +
+                                std::to_string(kScratchBytes) + " (" + std::to_string(kScratchBytes / sizeof(Partial)) +
+                                " variant-chunk partials, one chunk per 1,024 pixels up to 256 chunks)");
+  Partial* parts = static_cast<Partial*>(scratch_of(ctx->device));
+  if (!parts) return fail(SG_E_DEVICE, "no scratch address recorded for this device");
+  // every partial is written before the reduction reads it: nothing to clear
+  hipStream_t st = S(stream);
+  launch_metrics_partials(images, clean, px, nchunks, B, parts, st);
+  launch_reduce_metrics(parts, nullptr, nullptr, (uint32_t)nchunks, nullptr, nullptr, nullptr, (uint32_t)px, out, B, 1u,
+                        st);
+  return check_last("sg_metrics_noalloc");
 }
 
 }  // extern "C"
