@@ -115,7 +115,7 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
   Cfg cur;
   cur.batch = fixed_batch > 0 ? fixed_batch : std::min(32, max_batch);
   double cur_rate = measure(cur);
-  const std::vector<int> tiles = {8, 16, 32}, resumes = {32, 64, 128, 256}, wgss = {1, 2, 4, 8}, grids = {0, 64, 128},
+  const std::vector<int> tiles = {8, 16, 32}, resumes = {16, 32, 64, 128, 256}, wgss = {1, 2, 4, 8}, grids = {0, 64, 128},
                          streams = {4, 8, 16, 32, 64}, threads = {1, 2, 4};
   std::vector<int> batches;
   if (fixed_batch > 0) batches = {fixed_batch};
