@@ -5,9 +5,9 @@ one-render-per-injection path, on one GPU.
 Workload: the scaling-sweep scene at its large size (N = 134,826 Gaussians,
 SH degree 3, 800 x 800, 16 x 16 tiles), parameters stored as fp32 (or
 --fmt f16/bf16), 5,000 single-bit sites per field (bit j mod width, every
-field), B = 32 variants per launch.  A step is one B-variant batch on every
-campaign stream (global_batch = B x streams injections): each batch stages
-its corrupted variants, projects their corrupted primitives, lists and
+field), B = 32 variants per launch.  A step is four B-variant batches on
+every campaign stream (global_batch = 4 x B x streams injections): each batch
+stages its corrupted variants, projects their corrupted primitives, lists and
 re-composites their dirty tiles and reduces their PSNR/footprint records.
 The K timed steps run as one sg_campaign call.  The clean scene, its tile
 lists and its clean frame are resident (prepared once, outside the timed
@@ -65,18 +65,28 @@ def step_sources_sha():
     return h.hexdigest()
 
 
-def _measured_traffic():
+def _measured_traffic(resume=None):
     """HBM bytes per campaign step launch from the committed counter summary,
-    valid only while the kernel's sources are the ones that were measured."""
+    valid only while the kernel's sources are the ones that were measured.
+    The summary holds one figure per checkpoint spacing it was measured at
+    (lines "traffic_bytes_per_launch[resume=G]: bytes"); resume=None returns
+    all of them as {G: bytes}, an int returns that spacing's figure or None."""
     try:
         txt = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
-    vals = dict(line.strip().split(": ", 1) for line in txt.splitlines()
-                if line.strip().startswith(("traffic_bytes_per_launch:", "sources sha256 at measurement:")))
-    if vals.get("sources sha256 at measurement") != step_sources_sha():
+    sha = None
+    figs = {}
+    for line in txt.splitlines():
+        line = line.strip()
+        if line.startswith("sources sha256 at measurement:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes_per_launch[resume="):
+            key, val = line.split(":", 1)
+            figs[int(key[len("traffic_bytes_per_launch[resume="):-1])] = int(val)
+    if sha != step_sources_sha() or not figs:
         return None
-    return int(vals["traffic_bytes_per_launch"])
+    return figs if resume is None else figs.get(int(resume))
 
 
 def _workload(fmt):
@@ -93,9 +103,10 @@ _CPU = {}   # inputs of the oracle baseline, shared with forked workers
 
 
 def _cpu_one(k):
-    """One oracle injection on the bounded sample: FP64 projection of every
-    primitive, then compositing and metrics of the 400 x 400 quadrant.
-    Returns (projection seconds, quadrant seconds)."""
+    """One oracle injection of the plain path on the whole frame: FP64
+    projection of every primitive, compositing of all 800 x 800 pixels and
+    the metrics against the clean frame.  Returns (projection seconds,
+    compositing and metrics seconds)."""
     from threadpoolctl import threadpool_limits
     from oracle import formats, metrics as om, render as orender
     d = _CPU
@@ -105,55 +116,45 @@ def _cpu_one(k):
         f, c, p, b = int(st.field[k]), int(st.comp[k]), int(st.prim[k]), int(st.bit[k])
         w[f][c, p] = formats.flip(w[f][c, p:p + 1], b)[0]
         t0 = time.perf_counter()
-        pr = orender.project(orender.decode_scene(w, d["fmt"]), 3, d["quad"])
+        pr = orender.project(orender.decode_scene(w, d["fmt"]), 3, d["cam"])
         t1 = time.perf_counter()
-        out = orender.render(pr, d["quad"])
+        out = orender.render(pr, d["cam"])
         om.frame_metrics(out["image"], d["clean"], out["nonfinite"])
         t2 = time.perf_counter()
     return t1 - t0, t2 - t1
 
 
-def cpu_baseline(sc, cam, sites, fmt, n_inj, procs):
-    """The oracle's plain path timed on the host on a bounded sample: each
-    injection projects all primitives and composites the 400 x 400 top-left
-    quadrant of the frame (same intrinsics); its time is extrapolated as
-    projection + 4 x quadrant.  First n_inj injections on one thread, then
-    `procs` injections at once in forked worker processes (one thread each);
-    the reported value is the all-process rate.  Runs before the GPU is
-    touched, so the workers fork from a process without a device context."""
+def cpu_baseline(sc, cam, sites, fmt, procs):
+    """The oracle's plain path timed on the host on a bounded sample: `procs`
+    single-bit injections of the headline workload, each a full-frame FP64
+    render of the corrupted scene with its metrics, run at once in forked
+    worker processes of one thread each (the clean frame is rendered once
+    beforehand).  The value is the all-process rate; the single-thread rate
+    is the mean time of one injection.  Runs before the GPU is touched, so the
+    workers fork from a process without a device context."""
     import multiprocessing as mp
     from threadpoolctl import threadpool_limits
     from oracle import formats, render as orender
-    from paper_2606_21791_amd import synth
-    quad = synth.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx, cam.cy, cam.width // 2, cam.height // 2)
     with threadpool_limits(limits=1):
         words = [formats.store(f, fmt) for f in sc.fields]
-        clean = orender.render(orender.project(orender.decode_scene(words, fmt), 3, quad), quad)["image"]
-    _CPU.update(words=words, sites=sites, fmt=fmt, quad=quad, clean=clean)
-    one = [_cpu_one(k) for k in range(n_inj)]
-    t_proj = sum(a for a, _ in one) / n_inj
-    t_rend = sum(b for _, b in one) / n_inj
-    per_inj_1 = t_proj + 4.0 * t_rend
-    res = {"unit": "injections/s", "kind": "oracle", "single_thread_value": 1.0 / per_inj_1}
-    if procs > 1:
-        with mp.get_context("fork").Pool(procs) as pool:
-            t0 = time.perf_counter()
-            many = pool.map(_cpu_one, range(n_inj, n_inj + procs), chunksize=1)
-            wall = time.perf_counter() - t0
-        worst = max(a + 4.0 * b for a, b in many)
-        res.update(value=procs / worst, cores=procs,
-                   sample=f"{procs} single-bit injections of the same workload run at once in {procs} forked "
-                          f"processes of one thread each ({wall:.1f} s wall): FP64 projection of all {sc.n} "
-                          f"primitives plus compositing and metrics of the 400x400 top-left quadrant, each "
-                          f"extrapolated to the full frame as projection + 4 x quadrant (slowest process "
-                          f"{worst:.1f} s per injection); on one thread alone: projection {t_proj:.1f} s, "
-                          f"quadrant {t_rend:.1f} s, {per_inj_1:.1f} s per injection")
-    else:
-        res.update(value=1.0 / per_inj_1, cores=1,
-                   sample=f"{n_inj} single-bit injection(s) of the same workload on one thread: FP64 projection "
-                          f"of all {sc.n} primitives ({t_proj:.1f} s) plus compositing and metrics of the "
-                          f"400x400 top-left quadrant ({t_rend:.1f} s), extrapolated as projection + 4 x "
-                          f"quadrant = {per_inj_1:.1f} s per injection")
+        t0 = time.perf_counter()
+        clean = orender.render(orender.project(orender.decode_scene(words, fmt), 3, cam), cam)["image"]
+        t_clean = time.perf_counter() - t0
+    _CPU.update(words=words, sites=sites, fmt=fmt, cam=cam, clean=clean)
+    with mp.get_context("fork").Pool(procs) as pool:
+        t0 = time.perf_counter()
+        many = pool.map(_cpu_one, range(procs), chunksize=1)
+        wall = time.perf_counter() - t0
+    per = [a + b for a, b in many]
+    mean_one = float(np.mean(per))
+    res = {"unit": "injections/s", "kind": "oracle", "value": procs / wall, "cores": procs,
+           "single_thread_value": 1.0 / mean_one,
+           "sample": f"{procs} single-bit injections of the headline workload (sites 0..{procs - 1} of the "
+                     f"campaign), each an FP64 plain-path render of the whole {cam.width}x{cam.height} frame of "
+                     f"the {sc.n}-primitive scene (projection {np.mean([a for a, _ in many]):.1f} s, compositing "
+                     f"and metrics {np.mean([b for _, b in many]):.1f} s per injection), run at once in {procs} "
+                     f"forked processes of one thread each: {wall:.1f} s wall; the clean frame took "
+                     f"{t_clean:.1f} s beforehand and is not counted"}
     _CPU.clear()
     return res
 
@@ -162,7 +163,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60,
-                    help="timed steps; a step is one --batch batch on every stream")
+                    help="timed steps; a step is --batches-per-stream batches of --batch variants on every stream")
+    ap.add_argument("--batches-per-stream", type=int, default=4,
+                    help="batches of --batch variants each stream runs per step")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16"])
@@ -189,7 +192,7 @@ def main():
     ap.add_argument("--storm-frames", type=int, default=300, help="frames of the fault storm")
     ap.add_argument("--no-formats", dest="formats", action="store_false",
                     help="skip the fp16/bf16 (or fp32) rates at the headline configuration")
-    ap.add_argument("--cpu-inj", type=int, default=1, help="oracle injections timed on one host thread (0: skip)")
+    ap.add_argument("--cpu-inj", type=int, default=1, help="time the oracle baseline (0: skip)")
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="oracle processes run at once for the all-core baseline (0: the host's cores, at most 16)")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
@@ -212,7 +215,7 @@ def main():
     cpu = None
     if args.cpu_inj > 0:   # before the GPU is touched (the workers fork)
         procs = args.cpu_procs if args.cpu_procs > 0 else min(16, os.cpu_count() or 1)
-        cpu = cpu_baseline(sc, cam, sites, args.fmt, args.cpu_inj, procs)
+        cpu = cpu_baseline(sc, cam, sites, args.fmt, procs)
 
     import torch
     from paper_2606_21791_amd import binding as sgb
@@ -237,10 +240,10 @@ def main():
     prep = ctx.prepare(ds, cam, sgb.raster_struct(tile=args.tile))
     torch.cuda.synchronize()
     B = args.batch
-    # A step is one B-variant batch on every stream: GB injections, each of
-    # them the whole hot path (staging, projection of the corrupted
-    # primitives, dirty tiles, compositing, metrics).
-    GB = B * NS
+    # A step is --batches-per-stream B-variant batches on every stream: GB
+    # injections, each of them the whole hot path (staging, projection of the
+    # corrupted primitives, dirty tiles, compositing, metrics).
+    GB = B * NS * args.batches_per_stream
     n_sites = len(sites)
     steps_total = args.warmup + args.steps
     n_all = steps_total * GB
@@ -260,7 +263,7 @@ def main():
             ctx.campaign(prep, sa_all, va_all[first * GB:last * GB], mt_all[first * GB * rec_bytes:last * GB * rec_bytes],
                          batch=B, streams=NS, threads=args.threads)
         else:
-            for j in range(first * NS, last * NS):
+            for j in range(first * GB // B, last * GB // B):
                 with torch.cuda.stream(streams[j % NS]):
                     ctx.render_batch(prep, sa_all[j * B:(j + 1) * B], va_b,
                                      metrics=mt_all[j * B * rec_bytes:(j + 1) * B * rec_bytes])
@@ -394,7 +397,9 @@ def main():
         persist = {"value": round(p_rates[0], 1), "unit": "injections/s", "injections": n_inj,
                    "repetitions": {"n": REPS, "median": round(float(np.median(p_rates[1:])), 1)},
                    "variants_per_launch": int(-(-n_inj // max(pc_n, 1))), "resume_spacing": PERSIST_RESUME,
-                   "records_identical_to_headline": bool(all(np.array_equal(rp[k], recs[k]) for k in rp.dtype.names)),
+                   # every field but the evaluation count, which the checkpoint spacing changes
+                   "records_identical_to_headline": bool(all(np.array_equal(rp[k], recs[k]) for k in rp.dtype.names
+                                                             if k != "evals")),
                    "pass_ms": {k: round(v[0], 3) for k, v in pp.items() if v[1]},
                    "roofline": {"bound": "alu", "kernel": "k_persist_composite", "achieved": round(p_ach, 3),
                                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(p_ach / FP32_PEAK_TFLOPS, 4),
@@ -447,8 +452,8 @@ def main():
         "data": "synthetic (seeded scene and sites standing in for the paper's trained scenes)",
         "config": {"workload": f"scaling-sweep large scene: N=134,826 Gaussians, SH degree 3, {args.fmt} storage, "
                                f"800x800, {args.tile}x{args.tile} tiles, B={B} single-bit variants per launch, "
-                               "incremental dirty-tile re-composite; a step is one batch on each of the "
-                               f"{NS} streams",
+                               f"incremental dirty-tile re-composite; a step is {args.batches_per_stream} batches on "
+                               f"each of the {NS} streams",
                    "global_batch": GB, "batch_per_launch": B, "n_sites": n_sites,
                    "instances_clean": prep.instances(), "streams": NS, "host_threads": args.threads, "wgs_per_cu": args.wgs_per_cu,
                    "grid": args.grid,
@@ -475,8 +480,8 @@ def main():
         "catastrophic_fraction": round(float(recs["catastrophic"].mean()), 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                     "traffic": (_measured_traffic()
-                                 if (args.fmt == "f32" and B == 32 and args.tile == 16 and args.resume == 32) else None),
+                     "traffic": (_measured_traffic(args.resume)
+                                 if (args.fmt == "f32" and B == 32 and args.tile == 16) else None),
                      "aggregate_achieved": round(float(recs["evals"].sum()) * FLOPS_PER_EVAL / elapsed / 1e12, 3),
                      "kernel": "k_campaign_step", "avg_launch_ms": round(comp_avg_s * 1e3, 4),
                      "evals_per_launch": round(evals_per_launch), "flops_per_eval": FLOPS_PER_EVAL},
@@ -837,13 +842,18 @@ def run_views(args):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
         r = sgb.read_metrics(mt)
-        curve.append({"K": K, "inj_per_s": round(n / dt, 1), "view_mpix_per_s": round(n * K * 0.64 / dt, 1),
+        # dense equivalent: K full 800 x 800 frames per injection; the
+        # incremental path re-composites only the dirty tiles (an upper bound
+        # of the pixels it composites)
+        curve.append({"K": K, "inj_per_s": round(n / dt, 1),
+                      "dense_equiv_view_mpix_per_s": round(n * K * 0.64 / dt, 1),
+                      "dirty_tile_mpix_per_s": round(float(r["dirty_tiles"].sum()) * args.tile ** 2 / dt / 1e6, 1),
                       "mean_footprint": round(float(r["footprint"].mean()), 6),
                       "catastrophic_fraction": round(float(r["catastrophic"].mean()), 4),
                       "dirty_tiles_per_injection": round(float(r["dirty_tiles"].mean()), 2)})
         del preps
         torch.cuda.synchronize()
-    out = {"metric": "K-view injections: injections/s and view-Mpix/s vs K",
+    out = {"metric": "K-view injections: injections/s and (dense-equivalent) view-Mpix/s vs K",
            "config": {"workload": "N=134,826 Gaussians, SH degree 3, fp32, K orbit views at 800x800 "
                                   f"(elevation 15 deg), B={B}", "tile": args.tile, "streams": args.streams,
                       "host_threads": args.threads, "resume_spacing": args.resume, "tuned": tuned is not None},

@@ -288,7 +288,7 @@ sg_status sg_render_batch_views(sg_ctx* ctx, sg_prep* const* preps, int32_t K, c
  *
  * When every variant is incremental (at most 8 distinct primitives), the
  * campaign copies sites and variants to device memory once, stages and
- * projects the corrupted primitives of up to 131,072 variants in one
+ * projects the corrupted primitives of up to 524,288 variants in one
  * pre-pass launch per view, and then enqueues one launch per batch on its
  * stream: launch i lists the work items of the stream's batch i, composites
  * batch i - 1 and reduces the metrics of batch i - 2 (two more launches per

@@ -1110,7 +1110,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
                                     const sg_variant* variants, int32_t n_variants, const DevBox& box, int B, int NS,
                                     int NT, sg_metrics_t* metrics_out, hipStream_t caller,
                                     const uint16_t* scene_of = nullptr, const DevBox* scene_boxes = nullptr) {
-  constexpr int kChunk = 1 << 17;   // variants staged per pre-pass (one view)
+  constexpr int kChunk = 1 << 19;   // variants staged per pre-pass (one view; 360 MB of states and records)
   SG_TRY(check_hw_queues());
   std::lock_guard<std::mutex> cg(ctx->camp_mu);
   if (ctx->camp_done) HIP_TRY(hipEventSynchronize(ctx->camp_done));   // the previous campaign's buffers are free

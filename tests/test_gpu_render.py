@@ -474,7 +474,7 @@ def test_campaign_largest_batch(ctx):
 
 
 def test_campaign_across_prepass_chunks(ctx):
-    """A campaign longer than one pre-pass chunk (131,072 variants) gives the
+    """A campaign longer than one pre-pass chunk (524,288 variants) gives the
     same records as the same variants in two campaigns that each fit in one
     chunk: the chunk offsets of the states, the batches and the records are
     consistent, with a ragged last batch."""
@@ -486,11 +486,11 @@ def test_campaign_across_prepass_chunks(ctx):
     prep = ctx.prepare(ds, cam)
     s = synth.make_sites_stratified(sc.n, 0, 64, seed=42, width_bits=32, fields=(0, 1, 2, 3, 4))
     sa = b.sites_array(s.field, s.comp, s.prim, s.bit)
-    n = (1 << 17) + 1000 + 5
+    n = (1 << 19) + 1000 + 5
     va = b.variants_array(np.arange(n) % len(sa), np.ones(n, np.uint32))
     whole = b.metrics_tensor(n)
     ctx.campaign(prep, sa, va, whole, batch=32, streams=8, threads=2)
-    cut = 70_000
+    cut = 300_000
     first, second = b.metrics_tensor(cut), b.metrics_tensor(n - cut)
     ctx.campaign(prep, sa, va[:cut], first, batch=32, streams=8, threads=2)
     ctx.campaign(prep, sa, va[cut:], second, batch=32, streams=8, threads=2)
