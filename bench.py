@@ -551,6 +551,12 @@ def _batched_rate(ctx, prep, sites, B, streams, threads, steps, warmup, guard=0,
     return steps * B / dt, recs
 
 
+def _side_batches(args, cap):
+    """Batches timed by the workloads other than the headline: as many as the
+    headline's steps hold (steps x batches per stream x streams), at most cap."""
+    return max(1, min(cap, args.steps * args.batches_per_stream * max(1, args.streams)))
+
+
 def _tune_into(ctx, args, ds, cam, sites):
     """Autotune at the fixed --batch (unless --no-tune) and apply the result to
     ctx and args; returns the tuner's record or None."""
@@ -658,7 +664,7 @@ def run_guard(args):
                          "clamp_on_load_extra_us": round((proj["with"] - proj["without"]) * 1e3, 2),
                          "projection_us_without_guard": round(proj["without"] * 1e3, 2)}
     # single flips, unguarded and guarded
-    steps_g = min(args.steps, 2000)
+    steps_g = _side_batches(args, 2000)
     site_of = (np.arange(steps_g * args.batch) + args.warmup * args.batch) % len(sites)
     scale_sign = np.nonzero((sites.field[site_of] == 1) & (sites.bit[site_of] == 31))[0]
     for guard in (0, 1):
@@ -730,7 +736,7 @@ def run_large(args):
     torch.cuda.synchronize()
     prep_s = time.perf_counter() - t0
     rate, recs = _batched_rate(ctx, prep, sites, args.batch, args.streams, max(1, args.threads),
-                               min(args.steps, 2000), args.warmup)
+                               _side_batches(args, 2000), args.warmup)
     frame = prep.frame()
     mt1 = sgb.metrics_tensor(1)
     P = max(5, args.plain // 4)
@@ -747,6 +753,31 @@ def run_large(args):
     plain_dt = time.perf_counter() - t0
     pp = ctx.pass_times()
     ctx.timing(False)
+    # the same injections through the persistent engine (its own context,
+    # checkpoint spacing 16)
+    persist = None
+    if args.persistent:
+        ctx_p = sgb.Context(0)
+        ctx_p.set_resume(PERSIST_RESUME)
+        prep_p = ctx_p.prepare(ds, cam, sgb.raster_struct(tile=args.tile))
+        n_p = len(recs)
+        idx = (np.arange(n_p) + args.warmup * args.batch) % len(sites)
+        sa_p = sgb.sites_array(sites.field[idx], sites.comp[idx], sites.prim[idx], sites.bit[idx])
+        va_p = sgb.variants_array(np.arange(n_p), np.ones(n_p, np.uint32))
+        mt_p = sgb.metrics_tensor(n_p)
+        ctx_p.campaign(prep_p, sa_p, va_p, mt_p, engine=sgb.SG_ENGINE_PERSISTENT)
+        torch.cuda.synchronize()
+        with _no_gc():
+            t0 = time.perf_counter()
+            ctx_p.campaign(prep_p, sa_p, va_p, mt_p, engine=sgb.SG_ENGINE_PERSISTENT)
+            torch.cuda.synchronize()
+            dt_p = time.perf_counter() - t0
+        rp = sgb.read_metrics(mt_p)
+        persist = {"value": round(n_p / dt_p, 1), "unit": "injections/s", "injections": n_p,
+                   "resume_spacing": PERSIST_RESUME,
+                   "records_identical": bool(all(np.array_equal(rp[k], recs[k]) for k in rp.dtype.names
+                                                 if k != "evals"))}
+        del prep_p, ctx_p
     out = {"metric": "injections/s, 2,056,645-primitive scene, 1600x900, batched vs plain",
            "value": round(rate, 1), "unit": "injections/s",
            "config": {"workload": "N=2,056,645 Gaussians in 64 anisotropic clusters, SH degree 3, bf16 storage, "
@@ -758,6 +789,7 @@ def run_large(args):
            "plain": {"value": round(P / plain_dt, 1), "unit": "injections/s",
                      "pass_ms_per_injection": {k: round(v[0] / P, 4) for k, v in pp.items() if v[1]}},
            "speedup_vs_plain": round(rate / (P / plain_dt), 2),
+           "persistent": persist,
            "dirty_tiles_per_injection": round(float(recs["dirty_tiles"].mean()), 2), **_summ(recs)}
     print(json.dumps(out), flush=True)
 
@@ -823,7 +855,7 @@ def run_views(args):
     ds = sgb.DeviceScene.upload(ctx, sc, "f32")
     tuned = _tune_into(ctx, args, ds, cam, sites)
     B = args.batch
-    n_inj = min(args.steps, 1000) * B
+    n_inj = _side_batches(args, 1000) * B
     idx = np.arange(n_inj) % len(sites)
     sa = sgb.sites_array(sites.field[idx], sites.comp[idx], sites.prim[idx], sites.bit[idx])
     va = sgb.variants_array(np.arange(n_inj), np.ones(n_inj, np.uint32))
@@ -890,7 +922,7 @@ def run_scenes(args):
     sa = sgb.sites_array(cat("field"), cat("comp"), cat("prim"), cat("bit"))
     base = np.cumsum([0] + [len(t.prim) for t in site_sets])
     B = args.batch
-    n_inj = min(args.steps, 1000) * B
+    n_inj = _side_batches(args, 1000) * B
     rng = np.random.default_rng(97)
     scene_of = rng.integers(0, len(specs), size=n_inj).astype(np.uint16)
     off = np.array([base[k] + rng.integers(0, len(site_sets[k].prim)) for k in scene_of])
