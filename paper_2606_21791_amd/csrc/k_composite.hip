@@ -19,6 +19,13 @@
 // the largest multiple of the checkpoint spacing not above m0, which holds the
 // exact (C, T) state after that many entries.
 //
+// Only the entries a pixel takes (q within the cut and alpha at least
+// alpha_min) change its state or stop it, so removing or inserting an entry
+// the pixel does not take leaves its walk, its stop and its colour exactly as
+// they were.  A pixel is therefore unchanged, and not walked, when its clean
+// walk stopped before the first changed entry that it takes (none: never
+// reached).
+//
 // k_campaign_step holds, in one launch, the three stages of a campaign
 // stream's pipeline on separate buffers: the work items of its next batch,
 // the persistent compositing of its current batch and the metric reduction
@@ -42,7 +49,25 @@ struct MergeSpec {
   uint32_t ins_src[kMaxTouch];   // index into the override records
   uint32_t m0;                   // first index at which merged and clean lists differ
   uint32_t start;                // resume index (multiple of the checkpoint spacing, <= m0)
+  int n_chg;                     // changed entries of the tile: removals found in the list, then insertions
+  uint32_t chg_pos[2 * kMaxTouch];    // clean-list index of the entry removed, or of the first clean
+                                      // entry behind the insertion (the clean list's length if none)
+  uint32_t chg_slot[2 * kMaxTouch];   // staging slot of the change's record
 };
+
+// The loop's test of whether a pixel takes an entry (q within the cut and
+// alpha at least alpha_min), on the same fp32 operations, with both bounds
+// widened by 1e-4 relative: it may say yes where the loop says no, never the
+// reverse.
+__device__ __forceinline__ bool may_take(float px, float py, float4 a, float4 b, float4 c, float qc, float amin,
+                                         float amax) {
+  const float ex = px - a.x, ey = py - a.y;
+  const float uu = fmaf(ex, a.z, fmaf(ey, a.w, -b.x));
+  const float vv = fmaf(ey, a.z, fmaf(-ex, a.w, -b.y));
+  const float q = fmaf(vv, vv * b.w, uu * (uu * b.z));
+  const float alpha = fminf(amax, c.x * __builtin_amdgcn_exp2f(-q));
+  return q <= qc * 1.0001f && alpha >= amin * 0.9999f;
+}
 
 // MODE: 0 full render, 1 full render writing the resume state, 2 merged list
 // of a (variant, tile) item resumed from the clean state
@@ -61,7 +86,11 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
   constexpr int BS = TILE * TILE;
   constexpr int NW = BS / 64;            // waves per tile; wave w covers an 8 x 8 pixel block
   constexpr int BPR = TILE / 8;          // blocks per tile row
-  __shared__ uint16_t s_idx[NW][BS];     // per wave: batch entries whose box touches its block, in order
+  // per wave (row w at w * BS): byte offsets into the staged records of the
+  // batch entries whose box touches its block, in order.  Every value ever
+  // written is a valid offset, and two spare slots close the last row, so the
+  // walk may read two slots past its list.
+  __shared__ uint16_t s_idx[NW * BS + 2];
   __shared__ uint32_t s_cnt[NW][NW];     // [target wave][loading wave] entry counts
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -82,8 +111,21 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
   if (MODE == kItem && A.stop) {
     start = ms->start;
     if (inside) {
+      // sp: the clean walk's stop index (the list length if it never
+      // stopped, all ones if the clean pixel is not finite).  first: the
+      // clean index of the first changed entry this pixel may take; every
+      // change lies at or after m0.
       const uint32_t sp = sp_in;
-      if (sp < ms->m0) {
+      uint32_t first = ms->m0;
+      if (sp >= first) {
+        first = ~0u;
+        for (int k = 0; k < ms->n_chg; ++k) {
+          const uint32_t pos = ms->chg_pos[k];
+          const int slot = (int)ms->chg_slot[k];
+          if (pos < first && may_take(px, py, s_r0[slot], s_r1[slot], s_r2[slot], qc, amin, amax)) first = pos;
+        }
+      }
+      if (sp < first) {
         same = true;
         done = true;
       } else if (start) {
@@ -95,6 +137,7 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
   uint32_t evals = done ? 0u : mlen - start;   // list entries this pixel evaluates
   uint32_t next_ck = A.ck_group;               // kFullWrite: next checkpoint index
   __shared__ uint32_t s_all[NW];         // per wave: every pixel of the wave has stopped
+  for (int i = tid; i < NW * BS + 2; i += BS) s_idx[i] = 0;   // ordered before the walk by the loop's barriers
   for (uint32_t base = start; base < mlen; base += BS) {
     // leave once every pixel has stopped (the slots are rewritten only after
     // the two barriers of the compaction below)
@@ -111,7 +154,7 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
       float4 a, b, c;
       if (MODE != kItem) {
         const uint32_t id = (uint32_t)A.keys[raw_start + m];
-        a = A.r0[id]; b = A.r1[id]; c = A.r2[id];
+        a = A.rec[id].r0; b = A.rec[id].r1; c = A.rec[id].r2;
       } else {
         int before = 0, hit = -1;
         for (int j = 0; j < ms->n_ins; ++j) {
@@ -125,7 +168,7 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
           uint32_t raw = m - before;
           for (int k = 0; k < ms->n_rm; ++k) raw += ms->rm_pos[k] <= raw ? 1u : 0u;
           const uint32_t id = s_ids ? s_ids[raw] : (uint32_t)A.keys[raw_start + raw];
-          a = A.r0[id]; b = A.r1[id]; c = A.r2[id];
+          a = A.rec[id].r0; b = A.rec[id].r1; c = A.rec[id].r2;
         }
       }
       s_r0[tid] = a; s_r1[tid] = b; s_r2[tid] = c;
@@ -162,33 +205,33 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
       if ((mask >> w) & 1u) {
         uint32_t pos = (uint32_t)__popcll(bal[w] & lt);
         for (int v = 0; v < wave; ++v) pos += s_cnt[w][v];
-        s_idx[w][pos] = (uint16_t)tid;
+        s_idx[w * BS + pos] = (uint16_t)(tid * 16);
       }
     }
     uint32_t len = 0;
 #pragma unroll
     for (int v = 0; v < NW; ++v) len += s_cnt[wave][v];
+    len = __builtin_amdgcn_readfirstlane(len);   // the same in every lane: the walk's bounds stay scalar
     __syncthreads();
     if (!__all(done) && len) {
       // No divergent exits inside the batch: a stopped pixel is masked by
       // `done`; the wave leaves the batch once all of its lanes have stopped.
-      const uint16_t* idx = s_idx[wave];
-      int e = idx[0];
-      int en = idx[min(1u, len - 1)];
-      float4 a = s_r0[e], b = s_r1[e], c = s_r2[e];
-#pragma unroll 2
-      for (uint32_t j = 0; j < len; ++j) {
+      // Two entries per iteration; while one is evaluated, the next one's
+      // record and the offset of the one after it are read from LDS.
+      const uint16_t* idx = s_idx + wave * BS;
+      const char* r0b = reinterpret_cast<const char*>(s_r0);
+      const char* r1b = reinterpret_cast<const char*>(s_r1);
+      const char* r2b = reinterpret_cast<const char*>(s_r2);
+      const bool was_done = done;
+      uint32_t stop_off = 0;   // offset of the entry at which this pixel stopped in this batch
+      auto step = [&](const float4& a, const float4& b, const float4& c, uint32_t off) {
         if (MODE == kFullWrite) {
           // the state before this entry is the state after every entry below it
-          while (base + (uint32_t)e >= next_ck) {
+          while (base + (off >> 4) >= next_ck) {
             A.ck_out[((int64_t)A.ck_off[tile] + next_ck / A.ck_group - 1) * BS + tid] = make_float4(C0, C1, C2, T);
             next_ck += A.ck_group;
           }
         }
-        // while this entry is evaluated, the next entry's record and the
-        // index of the one after it are read from LDS
-        const int enn = idx[min(j + 2, len - 1)];
-        const float4 an = s_r0[en], bn = s_r1[en], cn = s_r2[en];
         const float ex = px - a.x, ey = py - a.y;
         const float uu = fmaf(ex, a.z, fmaf(ey, a.w, -b.x));
         const float vv = fmaf(ey, a.z, fmaf(-ex, a.w, -b.y));
@@ -206,15 +249,28 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
         C1 = blend ? fmaf(c.z, w, C1) : C1;
         C2 = blend ? fmaf(c.w, w, C2) : C2;
         T = blend ? Tn : T;
-        evals = stop ? base + (uint32_t)e + 1u - start : evals;
+        stop_off = stop ? off : stop_off;
         done = done || stop;
-        e = en;
-        en = enn;
-        a = an;
-        b = bn;
-        c = cn;
-        if ((j & 7) == 7 && __all(done)) break;
+      };
+      uint32_t o0 = idx[0], o1 = idx[1];
+      float4 a = *reinterpret_cast<const float4*>(r0b + o0), b = *reinterpret_cast<const float4*>(r1b + o0),
+             c = *reinterpret_cast<const float4*>(r2b + o0);
+      for (uint32_t j = 0; j < len; j += 2) {
+        const uint32_t o2 = idx[j + 2];
+        const float4 a1 = *reinterpret_cast<const float4*>(r0b + o1), b1 = *reinterpret_cast<const float4*>(r1b + o1),
+                     c1 = *reinterpret_cast<const float4*>(r2b + o1);
+        step(a, b, c, o0);
+        if (j + 1 >= len) break;
+        const uint32_t o3 = idx[j + 3];
+        a = *reinterpret_cast<const float4*>(r0b + o2);
+        b = *reinterpret_cast<const float4*>(r1b + o2);
+        c = *reinterpret_cast<const float4*>(r2b + o2);
+        step(a1, b1, c1, o1);
+        o0 = o2;
+        o1 = o3;
+        if ((j & 6) == 6 && __all(done)) break;
       }
+      if (done && !was_done) evals = base + (stop_off >> 4) + 1u - start;
     }
   }
 
@@ -321,6 +377,7 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
   __shared__ uint32_t s_ids[KCAP];      // ids of a staged clean list
   __shared__ uint64_t s_tgt[NT];        // removal keys, then insertion keys (sorted)
   __shared__ uint32_t s_cnt[NT], s_fnd[NT], s_bkt[NT];
+  __shared__ uint32_t s_tj[kMaxTouch];   // touch index of each removal target
   __shared__ int s_nr, s_ni;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int pxo = (wave % BPR) * 8 + (lane & 7), pyo = (wave / BPR) * 8 + (lane >> 3);   // as in composite_tile
@@ -329,7 +386,7 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
     const uint32_t view = view_of ? (uint32_t)view_of[v] : v % (uint32_t)K;
     const ViewArgs& w = views[view];
     Am = A0;
-    Am.r0 = w.r0; Am.r1 = w.r1; Am.r2 = w.r2;
+    Am.rec = w.rec;
     Am.tile_start = w.tile_start; Am.tile_cnt = w.tile_cnt; Am.keys = w.keys;
     Am.clean = w.clean; Am.stop = w.stop; Am.ck = w.ck; Am.ck_off = w.ck_off; Am.stop_key = w.stop_key;
     Am.ras = w.ras; Am.W = w.W; Am.H = w.H; Am.ck_group = w.ck_group;
@@ -373,6 +430,25 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
   const float cl0 = use_cl ? cw0 : 0.f, cl1 = use_cl ? cw1 : 0.f, cl2 = use_cl ? cw2 : 0.f;
   if (tid < NT) { s_cnt[tid] = 0; s_fnd[tid] = 0; s_bkt[tid] = 0; }
   __syncthreads();
+  {
+    // The records of the variant's changed primitives for composite_tile's
+    // per-pixel test, staged where its first list batch goes (slot j: the
+    // clean record of touch j, slot kMaxTouch + j: its new record).  Loaded
+    // by the second wave while thread 0 lists the targets.
+    const int ls = BS > 64 ? tid - 64 : tid;
+    const VariantState& vs = *reinterpret_cast<const VariantState*>(s_vs);
+    if (A.stop && ls >= 0 && ls < 2 * kMaxTouch && ls % kMaxTouch < (int)vs.n_touch) {
+      const int j = ls % kMaxTouch;
+      const Touch& t = vs.touch[j];
+      if (ls < kMaxTouch && (t.flags & 5u) == 1u) {
+        const Rec& r = A.rec[t.prim];
+        s_r0[ls] = r.r0; s_r1[ls] = r.r1; s_r2[ls] = r.r2;
+      } else if (ls >= kMaxTouch && (t.flags & 6u) == 2u) {
+        const Rec& r = ovr[v * kMaxTouch + (uint32_t)j];
+        s_r0[ls] = r.r0; s_r1[ls] = r.r1; s_r2[ls] = r.r2;
+      }
+    }
+  }
   if (tid == 0) {
     const VariantState& vs = *reinterpret_cast<const VariantState*>(s_vs);
     int nr = 0, ni = 0;
@@ -380,7 +456,10 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
     for (uint32_t j = 0; j < vs.n_touch; ++j) {
       const Touch t = vs.touch[j];
       if (t.flags & 4u) continue;   // unchanged primitive
-      if ((t.flags & 1u) && rect_has(t.old_rect0, t.old_rect1, tx, ty)) s_tgt[nr++] = ((uint64_t)t.old_depth << 32) | t.prim;
+      if ((t.flags & 1u) && rect_has(t.old_rect0, t.old_rect1, tx, ty)) {
+        s_tj[nr] = j;
+        s_tgt[nr++] = ((uint64_t)t.old_depth << 32) | t.prim;
+      }
       if ((t.flags & 2u) && rect_has(t.new_rect0, t.new_rect1, tx, ty)) {
         s_tgt[NT - 1 - ni] = ((uint64_t)t.new_depth << 32) | t.prim;
         ms.ins_src[ni] = v * kMaxTouch + j;
@@ -469,13 +548,22 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
       for (int b = a; b > 0 && ms.rm_pos[b - 1] > ms.rm_pos[b]; --b) {
         const uint32_t z = ms.rm_pos[b]; ms.rm_pos[b] = ms.rm_pos[b - 1]; ms.rm_pos[b - 1] = z;
       }
+    int nc = 0;
+    for (int j = 0; j < nr; ++j)
+      if (s_fnd[j]) {
+        ms.chg_pos[nc] = s_cnt[j] + min(s_bkt[j] * G, L);
+        ms.chg_slot[nc++] = s_tj[j];
+      }
     const int ni = nt - nr;
     for (int j = 0; j < ni; ++j) {
       const uint32_t praw = s_cnt[nr + j] + min(s_bkt[nr + j] * G, L);
       uint32_t rm_before = 0;
       for (int k = 0; k < n_rm; ++k) rm_before += ms.rm_pos[k] < praw ? 1u : 0u;
       ms.ins_mpos[j] = praw - rm_before + (uint32_t)j;
+      ms.chg_pos[nc] = praw;
+      ms.chg_slot[nc++] = (uint32_t)kMaxTouch + (ms.ins_src[j] - v * (uint32_t)kMaxTouch);
     }
+    ms.n_chg = nc;
     ms.raw_start = raw_start;
     ms.raw_len = L;
     ms.n_rm = n_rm;

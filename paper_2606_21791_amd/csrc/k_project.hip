@@ -54,9 +54,7 @@ __global__ void __launch_bounds__(256) k_project(DevScene s, DevBox box, DevCam 
     auto get = [&](int f, int c) -> uint32_t { return w[L::off(f) + c]; };
     const ProjOut o = project_prim<DEG>(get, s.dtype, cam, ras);
     nonfin |= o.nonfinite;
-    pb.r0[i] = o.rec.r0;
-    pb.r1[i] = o.rec.r1;
-    pb.r2[i] = o.rec.r2;
+    pb.rec[i] = o.rec;
     pb.depth[i] = o.depth;
     pb.rect[i] = o.visible ? make_uint2(o.rect0, o.rect1) : make_uint2(0xffffffffu, 0u);
     if (o.visible) {
@@ -98,8 +96,7 @@ __global__ void __launch_bounds__(256) k_project(DevScene s, DevBox box, DevCam 
 // corrupted record.  One 64-thread workgroup; every lane calls it.
 template <int DEG>
 __device__ void stage_touches(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
-                              const float4* __restrict__ r0, const float4* __restrict__ r1,
-                              const float4* __restrict__ r2, const uint32_t* __restrict__ depth,
+                              const Rec* __restrict__ rec, const uint32_t* __restrict__ depth,
                               const uint2* __restrict__ rect, const sg_variant& var, const sg_site* g_sites,
                               VariantState& st, Rec* ovr) {
   using L = Layout<DEG>;
@@ -166,7 +163,7 @@ __device__ void stage_touches(const DevScene& s, const DevBox& box, const DevCam
       t.new_rect1 = o.rect1;
       bool same = old_vis == o.visible;
       if (same && old_vis) {
-        const float4 a0 = r0[p], a1 = r1[p], a2 = r2[p];
+        const float4 a0 = rec[p].r0, a1 = rec[p].r1, a2 = rec[p].r2;
         same = t.old_depth == t.new_depth && orc.x == o.rect0 && orc.y == o.rect1 &&
                __float_as_uint(a0.x) == __float_as_uint(o.rec.r0.x) && __float_as_uint(a0.y) == __float_as_uint(o.rec.r0.y) &&
                __float_as_uint(a0.z) == __float_as_uint(o.rec.r0.z) && __float_as_uint(a0.w) == __float_as_uint(o.rec.r0.w) &&
@@ -187,14 +184,13 @@ __device__ void stage_touches(const DevScene& s, const DevBox& box, const DevCam
 // workgroup that finishes last, the batch's item offsets.
 template <int DEG>
 __global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, DevCam cam, DevRaster ras,
-                                                     const float4* __restrict__ r0, const float4* __restrict__ r1,
-                                                     const float4* __restrict__ r2,
+                                                     const Rec* __restrict__ rec,
                                                      const uint32_t* __restrict__ depth,
                                                      const uint2* __restrict__ rect, BatchBuffers bb) {
   const int v = blockIdx.x;
   __shared__ VariantState st;
   const sg_variant var = bb.variants[v];
-  stage_touches<DEG>(s, box, cam, ras, r0, r1, r2, depth, rect, var, bb.sites, st, bb.ovr + (int64_t)v * kMaxTouch);
+  stage_touches<DEG>(s, box, cam, ras, rec, depth, rect, var, bb.sites, st, bb.ovr + (int64_t)v * kMaxTouch);
   uint32_t nd, ni;
   uint64_t pred;
   enumerate_items(st.touch, st.n_touch, bb.tiles_x, bb.tiles_y, bb.stop_key, bb.tile_start, bb.tile_cnt,
@@ -217,8 +213,7 @@ __global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, Dev
 // applied, its projection, and the comparison with its clean record.
 template <int DEG>
 __global__ void __launch_bounds__(64) k_campaign_touch(DevScene s, DevBox box, DevCam cam, DevRaster ras,
-                                                       const float4* __restrict__ r0, const float4* __restrict__ r1,
-                                                       const float4* __restrict__ r2,
+                                                       const Rec* __restrict__ rec,
                                                        const uint32_t* __restrict__ depth,
                                                        const uint2* __restrict__ rect, const sg_site* sites,
                                                        const sg_variant* variants, int n, VariantState* vs, Rec* ovr,
@@ -285,7 +280,7 @@ __global__ void __launch_bounds__(64) k_campaign_touch(DevScene s, DevBox box, D
     t.new_rect1 = o.rect1;
     bool same = old_vis == o.visible;
     if (same && old_vis) {
-      const float4 a0 = r0[p], a1 = r1[p], a2 = r2[p];
+      const float4 a0 = rec[p].r0, a1 = rec[p].r1, a2 = rec[p].r2;
       same = t.old_depth == t.new_depth && orc.x == o.rect0 && orc.y == o.rect1 &&
              __float_as_uint(a0.x) == __float_as_uint(o.rec.r0.x) && __float_as_uint(a0.y) == __float_as_uint(o.rec.r0.y) &&
              __float_as_uint(a0.z) == __float_as_uint(o.rec.r0.z) && __float_as_uint(a0.w) == __float_as_uint(o.rec.r0.w) &&
@@ -329,30 +324,30 @@ void launch_project(const DevScene& s, const DevBox& box, const DevCam& cam, con
 }
 
 void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
-                         const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
-                         const uint2* rect, const BatchBuffers& bb, hipStream_t st) {
+                         const Rec* rec, const uint32_t* depth, const uint2* rect, const BatchBuffers& bb,
+                         hipStream_t st) {
   const int grid = bb.B;
   if (grid <= 0) return;
   switch (s.sh_degree) {
-    case 0: k_variant_prep<0><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, bb); break;
-    case 1: k_variant_prep<1><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, bb); break;
-    case 2: k_variant_prep<2><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, bb); break;
-    default: k_variant_prep<3><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, bb); break;
+    case 0: k_variant_prep<0><<<grid, 64, 0, st>>>(s, box, cam, ras, rec, depth, rect, bb); break;
+    case 1: k_variant_prep<1><<<grid, 64, 0, st>>>(s, box, cam, ras, rec, depth, rect, bb); break;
+    case 2: k_variant_prep<2><<<grid, 64, 0, st>>>(s, box, cam, ras, rec, depth, rect, bb); break;
+    default: k_variant_prep<3><<<grid, 64, 0, st>>>(s, box, cam, ras, rec, depth, rect, bb); break;
   }
 }
 
 void launch_campaign_touch(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
-                           const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
-                           const uint2* rect, const sg_site* sites, const sg_variant* variants, int n,
+                           const Rec* rec, const uint32_t* depth, const uint2* rect, const sg_site* sites,
+                           const sg_variant* variants, int n,
                            VariantState* vs, Rec* ovr, int stride, int offset, const uint16_t* view_of, int view,
                            hipStream_t st) {
   if (n <= 0) return;
   const int grid = (n + 63) / 64;
   switch (s.sh_degree) {
-    case 0: k_campaign_touch<0><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
-    case 1: k_campaign_touch<1><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
-    case 2: k_campaign_touch<2><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
-    default: k_campaign_touch<3><<<grid, 64, 0, st>>>(s, box, cam, ras, r0, r1, r2, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
+    case 0: k_campaign_touch<0><<<grid, 64, 0, st>>>(s, box, cam, ras, rec, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
+    case 1: k_campaign_touch<1><<<grid, 64, 0, st>>>(s, box, cam, ras, rec, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
+    case 2: k_campaign_touch<2><<<grid, 64, 0, st>>>(s, box, cam, ras, rec, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
+    default: k_campaign_touch<3><<<grid, 64, 0, st>>>(s, box, cam, ras, rec, depth, rect, sites, variants, n, vs, ovr, stride, offset, view_of, view); break;
   }
 }
 

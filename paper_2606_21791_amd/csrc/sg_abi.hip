@@ -63,7 +63,7 @@ struct DevBuf {
 struct Workspace {
   hipStream_t stream = nullptr;
   // full renders
-  DevBuf r0, r1, r2, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
+  DevBuf rec, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
       big_prims, big_tiles, big_choff, big_goff, big_split, parts, work_scene, sites_dev, box_keys, metrics_tmp;
   // batches of variants
   DevBuf vs, ovr, item_off, n_items_v, tiles, bparts, counter, arrive, gmetrics, views_tmp, ssim_tmp;
@@ -136,7 +136,7 @@ struct sg_prep {
   DevCam cam;
   DevRaster ras;
   int64_t n_inst = 0;
-  DevBuf r0, r1, r2, depth, rect, tile_cnt, tile_start, keys, frame;
+  DevBuf rec, depth, rect, tile_cnt, tile_start, keys, frame;
   DevBuf stop, ck, ck_off, stop_key;       // resume state of the clean render
   uint32_t ck_group = 0;
 };
@@ -197,7 +197,7 @@ Workspace* workspace(sg_ctx* ctx, hipStream_t st) {
 }
 
 void free_workspace(sg_ctx* ctx, Workspace* w) {
-  DevBuf* bufs[] = {&w->r0, &w->r1, &w->r2, &w->depth, &w->rect, &w->diff, &w->flags, &w->clamps, &w->tile_cnt,
+  DevBuf* bufs[] = {&w->rec, &w->depth, &w->rect, &w->diff, &w->flags, &w->clamps, &w->tile_cnt,
                     &w->tile_start, &w->cursor, &w->total, &w->keys, &w->keys_tmp, &w->big_prims, &w->big_tiles,
                     &w->big_choff, &w->big_goff, &w->big_split,
                     &w->parts, &w->work_scene, &w->sites_dev, &w->box_keys, &w->metrics_tmp, &w->vs, &w->ovr,
@@ -413,27 +413,15 @@ sg_status stage_sites(sg_ctx* ctx, const sg_site* sites, int n, DevBuf& dst, hip
   return SG_OK;
 }
 
-// Buffers of one full render, sized for n primitives and the raster's tiles.
-struct RenderBufs {
-  float4 *r0, *r1, *r2;
-  uint32_t* depth;
-  uint2* rect;
-  uint32_t *tile_cnt, *tile_start;
-  uint64_t* keys;
-  int64_t n_inst;
-};
-
 // Full render of a scene: project (with optional clamp-on-load), bin, sort,
 // composite (with metric partials against `clean` when given).  The record and
 // list buffers are either the context's workspaces or a prepared scene's.
 sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
-                      DevBuf& r0, DevBuf& r1, DevBuf& r2, DevBuf& depth, DevBuf& rect, DevBuf& tile_cnt,
+                      DevBuf& rec, DevBuf& depth, DevBuf& rect, DevBuf& tile_cnt,
                       DevBuf& tile_start, DevBuf& keys, float* image, const float* clean, Partial* parts,
                       hipStream_t st, int64_t* n_inst_out, sg_prep* resume = nullptr) {
   const int64_t n = s.n;
-  SG_TRY(dev_alloc(ctx, r0, n * sizeof(float4)));
-  SG_TRY(dev_alloc(ctx, r1, n * sizeof(float4)));
-  SG_TRY(dev_alloc(ctx, r2, n * sizeof(float4)));
+  SG_TRY(dev_alloc(ctx, rec, n * sizeof(Rec)));
   SG_TRY(dev_alloc(ctx, depth, n * sizeof(uint32_t)));
   SG_TRY(dev_alloc(ctx, rect, n * sizeof(uint2)));
   const int64_t diff_n = (int64_t)(ras.tiles_x + 1) * (ras.tiles_y + 1);
@@ -451,7 +439,7 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
   launch_fill_u32(P<uint32_t>(W->diff), 0u, diff_n, st);
   launch_fill_u32(P<uint32_t>(W->flags), 0u, 4, st);
   launch_fill_u32(P<uint32_t>(W->clamps), 0u, 4, st);
-  ProjBuffers pb{P<float4>(r0), P<float4>(r1), P<float4>(r2), P<uint32_t>(depth), P<uint2>(rect),
+  ProjBuffers pb{P<Rec>(rec), P<uint32_t>(depth), P<uint2>(rect),
                  P<int32_t>(W->diff), P<uint32_t>(W->flags), P<unsigned long long>(W->clamps)};
   {
     PassScope ps(ctx, SG_PASS_PROJECT, st);
@@ -485,7 +473,7 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
     bb.big_split = P<uint32_t>(W->big_split);
     launch_tile_sort(ras, bb, W->h_total, ctx->n_cu, st);
   }
-  CompArgs ca{P<float4>(r0), P<float4>(r1), P<float4>(r2), P<uint32_t>(tile_start), P<uint32_t>(tile_cnt),
+  CompArgs ca{P<Rec>(rec), P<uint32_t>(tile_start), P<uint32_t>(tile_cnt),
               P<uint64_t>(keys), clean, image, parts, ras, cam.W, cam.H};
   if (resume && resume->ck_group) {
     // checkpoint slots per tile: floor(count / spacing), laid out tile after tile
@@ -775,7 +763,7 @@ sg_status sg_render(sg_ctx* ctx, const sg_scene* scene, const sg_camera* cam, co
     SG_TRY(dev_alloc(ctx, W->parts, (size_t)r.n_tiles * sizeof(Partial)));
     parts = P<Partial>(W->parts);
   }
-  SG_TRY(full_render(ctx, W, s, b, c, r, W->r0, W->r1, W->r2, W->depth, W->rect, W->tile_cnt, W->tile_start,
+  SG_TRY(full_render(ctx, W, s, b, c, r, W->rec, W->depth, W->rect, W->tile_cnt, W->tile_start,
                      W->keys, image_out, clean_frame, parts, st, nullptr));
   if (metrics_out)
     launch_reduce_metrics(parts, nullptr, nullptr, (uint32_t)r.n_tiles, nullptr, P<uint32_t>(W->flags),
@@ -807,7 +795,7 @@ sg_status sg_prepare(sg_ctx* ctx, const sg_scene* clean, const sg_camera* cam, c
   Workspace* W = workspace(ctx, st);
   rc = W ? dev_alloc(ctx, p->frame, (size_t)p->cam.W * p->cam.H * 3 * sizeof(float)) : SG_E_NOMEM;
   if (rc == SG_OK)
-    rc = full_render(ctx, W, p->scene, nobox, p->cam, p->ras, p->r0, p->r1, p->r2, p->depth, p->rect, p->tile_cnt,
+    rc = full_render(ctx, W, p->scene, nobox, p->cam, p->ras, p->rec, p->depth, p->rect, p->tile_cnt,
                      p->tile_start, p->keys, P<float>(p->frame), nullptr, nullptr, st, &p->n_inst, p);
   if (rc != SG_OK) {
     sg_prep_destroy(p);
@@ -821,7 +809,7 @@ void sg_prep_destroy(sg_prep* p) {
   if (!p) return;
   sg_ctx* c = p->ctx;
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&p->r0,         &p->r1,   &p->r2,    &p->depth, &p->rect, &p->tile_cnt,
+  DevBuf* bufs[] = {&p->rec, &p->depth, &p->rect, &p->tile_cnt,
                     &p->tile_start, &p->keys, &p->frame, &p->stop,  &p->ck,   &p->ck_off, &p->stop_key};
   for (DevBuf* b : bufs) dev_free(c, *b);
   delete p;
@@ -866,7 +854,7 @@ static BatchBuffers batch_buffers(Workspace* W, const sg_prep* prep, const sg_si
 }
 
 static CompArgs item_comp_args(Workspace* W, const sg_prep* prep, float* images_out) {
-  CompArgs ca{P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2), P<uint32_t>(prep->tile_start),
+  CompArgs ca{P<Rec>(prep->rec), P<uint32_t>(prep->tile_start),
               P<uint32_t>(prep->tile_cnt), P<uint64_t>(prep->keys), P<float>(prep->frame), images_out,
               P<Partial>(W->bparts), prep->ras, prep->cam.W, prep->cam.H};
   if (prep->ck_group) {
@@ -944,7 +932,7 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
       const BatchBuffers bb = batch_buffers(W, prep, W->d_sites[slot], W->d_vars[slot], B);
       {
         PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
-        launch_variant_prep(s, b, prep->cam, ras, P<float4>(prep->r0), P<float4>(prep->r1), P<float4>(prep->r2),
+        launch_variant_prep(s, b, prep->cam, ras, P<Rec>(prep->rec),
                             P<uint32_t>(prep->depth), P<uint2>(prep->rect), bb, st);
       }
       const CompArgs ca = item_comp_args(W, prep, images_out);
@@ -1029,7 +1017,7 @@ sg_status sg_render_batch(sg_ctx* ctx, sg_prep* prep, const sg_site* sites, int3
       launch_inject(w, P<sg_site>(W->sites_dev), (int)applied.size(), nullptr, st);
       DevBox bx = b;
       if (!x.guard) bx.mask = 0;
-      SG_TRY(full_render(ctx, W, w, bx, prep->cam, ras, W->r0, W->r1, W->r2, W->depth, W->rect, W->tile_cnt,
+      SG_TRY(full_render(ctx, W, w, bx, prep->cam, ras, W->rec, W->depth, W->rect, W->tile_cnt,
                          W->tile_start, W->keys, images_out ? images_out + v * frame_floats : nullptr,
                          P<float>(prep->frame), P<Partial>(W->parts), st, nullptr));
       launch_reduce_metrics(P<Partial>(W->parts), nullptr, nullptr, (uint32_t)ras.n_tiles, nullptr,
@@ -1151,7 +1139,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
     for (int k = 0; k < K; ++k) {
       const sg_prep* p = preps[k];
       const bool rs = p->ck_group != 0;
-      ctx->camp_vargs_host[k] = ViewArgs{P<float4>(p->r0), P<float4>(p->r1), P<float4>(p->r2),
+      ctx->camp_vargs_host[k] = ViewArgs{P<Rec>(p->rec),
                                          P<uint32_t>(p->tile_start), P<uint32_t>(p->tile_cnt), P<uint64_t>(p->keys),
                                          P<float>(p->frame), rs ? P<uint32_t>(p->stop) : nullptr,
                                          rs ? P<float4>(p->ck) : nullptr, rs ? P<uint32_t>(p->ck_off) : nullptr,
@@ -1223,8 +1211,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
       for (int k = mv ? 0 : view; k < (mv ? K : view + 1); ++k) {
         const sg_prep* pk = preps[k];
         PassScope ps(ctx, SG_PASS_VARIANT_PREP, caller);
-        launch_campaign_touch(pk->scene, sc ? scene_boxes[k] : box, pk->cam, pk->ras, P<float4>(pk->r0),
-                              P<float4>(pk->r1), P<float4>(pk->r2), P<uint32_t>(pk->depth), P<uint2>(pk->rect),
+        launch_campaign_touch(pk->scene, sc ? scene_boxes[k] : box, pk->cam, pk->ras, P<Rec>(pk->rec), P<uint32_t>(pk->depth), P<uint2>(pk->rect),
                               d_sites, d_vars + c0, cn, c_vs, c_ovr, per, mv && !sc ? k : 0,
                               sc ? d_scene_of + c0 : nullptr, k, caller);
       }
@@ -1373,7 +1360,7 @@ static sg_status campaign_persistent(sg_ctx* ctx, sg_prep* const* preps, int K, 
     for (int k = 0; k < K; ++k) {
       const sg_prep* p = preps[k];
       const bool rs = p->ck_group != 0;
-      ctx->camp_vargs_host[k] = ViewArgs{P<float4>(p->r0), P<float4>(p->r1), P<float4>(p->r2),
+      ctx->camp_vargs_host[k] = ViewArgs{P<Rec>(p->rec),
                                          P<uint32_t>(p->tile_start), P<uint32_t>(p->tile_cnt), P<uint64_t>(p->keys),
                                          P<float>(p->frame), rs ? P<uint32_t>(p->stop) : nullptr,
                                          rs ? P<float4>(p->ck) : nullptr, rs ? P<uint32_t>(p->ck_off) : nullptr,
@@ -1422,12 +1409,11 @@ static sg_status campaign_persistent(sg_ctx* ctx, sg_prep* const* preps, int K, 
     for (int k = 0; k < K; ++k) {
       const sg_prep* pk = preps[k];
       PassScope ps(ctx, SG_PASS_VARIANT_PREP, st);
-      launch_campaign_touch(pk->scene, sc ? scene_boxes[k] : box, pk->cam, pk->ras, P<float4>(pk->r0),
-                            P<float4>(pk->r1), P<float4>(pk->r2), P<uint32_t>(pk->depth), P<uint2>(pk->rect), d_sites,
+      launch_campaign_touch(pk->scene, sc ? scene_boxes[k] : box, pk->cam, pk->ras, P<Rec>(pk->rec), P<uint32_t>(pk->depth), P<uint2>(pk->rect), d_sites,
                             d_vars + c0, cn, vs, ovr, per, sc ? 0 : k, sc ? d_scene_of + c0 : nullptr, k, st);
     }
     PersistArgs a{};
-    a.A = CompArgs{P<float4>(p0->r0), P<float4>(p0->r1), P<float4>(p0->r2), P<uint32_t>(p0->tile_start),
+    a.A = CompArgs{P<Rec>(p0->rec), P<uint32_t>(p0->tile_start),
                    P<uint32_t>(p0->tile_cnt), P<uint64_t>(p0->keys), P<float>(p0->frame), nullptr,
                    P<Partial>(ctx->pst_parts[set]), p0->ras, p0->cam.W, p0->cam.H};
     if (p0->ck_group) {

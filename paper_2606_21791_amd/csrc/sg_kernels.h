@@ -150,9 +150,7 @@ void launch_reduce_metrics(const Partial* parts, const uint32_t* item_off, const
 
 // k_project.hip
 struct ProjBuffers {
-  float4* r0;
-  float4* r1;
-  float4* r2;
+  Rec* rec;               // one 48-byte record per primitive: a list entry's gather touches one or two lines
   uint32_t* depth;
   uint2* rect;            // (tx0 | ty0 << 16, tx1 | ty1 << 16); x = 0xffffffff when culled
   int32_t* diff;          // (tiles_y + 1) x (tiles_x + 1) 2-D difference grid of tile counts
@@ -181,8 +179,8 @@ struct BatchBuffers {
   const uint32_t* tile_cnt;
 };
 void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
-                         const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
-                         const uint2* rect, const BatchBuffers& bb, hipStream_t st);
+                         const Rec* rec, const uint32_t* depth, const uint2* rect, const BatchBuffers& bb,
+                         hipStream_t st);
 // Campaign pre-pass over n variants: states (touches, clamps, non-finite
 // flag) and override records (kMaxTouch per variant).  Variant g's state is
 // vs[g * stride + offset] and its records start at ovr[(g * stride + offset)
@@ -190,8 +188,8 @@ void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam
 // view_of (nullable): only the variants g with view_of[g] == view are staged
 // (a campaign over several scenes stages each scene's variants in its launch).
 void launch_campaign_touch(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
-                           const float4* r0, const float4* r1, const float4* r2, const uint32_t* depth,
-                           const uint2* rect, const sg_site* sites, const sg_variant* variants, int n,
+                           const Rec* rec, const uint32_t* depth, const uint2* rect, const sg_site* sites,
+                           const sg_variant* variants, int n,
                            VariantState* vs, Rec* ovr, int stride, int offset, const uint16_t* view_of, int view,
                            hipStream_t st);
 
@@ -223,9 +221,7 @@ void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, const unsigned
 
 // k_composite.hip
 struct CompArgs {
-  const float4* r0;
-  const float4* r1;
-  const float4* r2;
+  const Rec* rec;         // projected records, by primitive
   const uint32_t* tile_start;
   const uint32_t* tile_cnt;
   const uint64_t* keys;
@@ -272,9 +268,7 @@ void launch_composite_items(const CompArgs& a, const ItemArgs& it, hipStream_t s
 // The clean state of one prepared view of a multi-view step: a camera view
 // of the batch's scene, or one of several scenes of uneven size.
 struct ViewArgs {
-  const float4* r0;
-  const float4* r1;
-  const float4* r2;
+  const Rec* rec;
   const uint32_t* tile_start;
   const uint32_t* tile_cnt;
   const uint64_t* keys;
