@@ -22,9 +22,9 @@
 // Only the entries a pixel takes (q within the cut and alpha at least
 // alpha_min) change its state or stop it, so removing or inserting an entry
 // the pixel does not take leaves its walk, its stop and its colour exactly as
-// they were.  A pixel is therefore unchanged, and not walked, when its clean
-// walk stopped before the first changed entry that it takes (none: never
-// reached).
+// they were.  A pixel is therefore unchanged, and not walked, when every
+// changed entry that it takes lies behind the entry at which its clean walk
+// stopped; the clean render keeps that entry's key per pixel.
 //
 // k_campaign_step holds, in one launch, the three stages of a campaign
 // stream's pipeline on separate buffers: the work items of its next batch,
@@ -49,10 +49,6 @@ struct MergeSpec {
   uint32_t ins_src[kMaxTouch];   // index into the override records
   uint32_t m0;                   // first index at which merged and clean lists differ
   uint32_t start;                // resume index (multiple of the checkpoint spacing, <= m0)
-  int n_chg;                     // changed entries of the tile: removals found in the list, then insertions
-  uint32_t chg_pos[2 * kMaxTouch];    // clean-list index of the entry removed, or of the first clean
-                                      // entry behind the insertion (the clean list's length if none)
-  uint32_t chg_slot[2 * kMaxTouch];   // staging slot of the change's record
 };
 
 // The loop's test of whether a pixel takes an entry (q within the cut and
@@ -75,13 +71,13 @@ enum { kFull = 0, kFullWrite = 1, kItem = 2 };
 
 
 // kItem: s_ids (nullable) holds the ids of the tile's whole clean list;
-// sp_in and cl*_in are the pixel's stop index and clean colour, read by the
-// caller.  Returns the tile's changed-pixel count in thread 0 (0 elsewhere,
+// walk_in says whether the pixel can change (item_work decides) and cl*_in
+// is its clean colour, read by the caller.  Returns the tile's changed-pixel count in thread 0 (0 elsewhere,
 // and when part is null).
 template <int TILE, int MODE>
 __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, const MergeSpec* ms, const Rec* ovr,
                                                    float* img, Partial* part, float4* s_r0, float4* s_r1,
-                                                   float4* s_r2, const uint32_t* s_ids = nullptr, uint32_t sp_in = 0,
+                                                   float4* s_r2, const uint32_t* s_ids = nullptr, bool walk_in = true,
                                                    float cl0_in = 0.f, float cl1_in = 0.f, float cl2_in = 0.f) {
   constexpr int BS = TILE * TILE;
   constexpr int NW = BS / 64;            // waves per tile; wave w covers an 8 x 8 pixel block
@@ -111,21 +107,7 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
   if (MODE == kItem && A.stop) {
     start = ms->start;
     if (inside) {
-      // sp: the clean walk's stop index (the list length if it never
-      // stopped, all ones if the clean pixel is not finite).  first: the
-      // clean index of the first changed entry this pixel may take; every
-      // change lies at or after m0.
-      const uint32_t sp = sp_in;
-      uint32_t first = ms->m0;
-      if (sp >= first) {
-        first = ~0u;
-        for (int k = 0; k < ms->n_chg; ++k) {
-          const uint32_t pos = ms->chg_pos[k];
-          const int slot = (int)ms->chg_slot[k];
-          if (pos < first && may_take(px, py, s_r0[slot], s_r1[slot], s_r2[slot], qc, amin, amax)) first = pos;
-        }
-      }
-      if (sp < first) {
+      if (!walk_in) {
         same = true;
         done = true;
       } else if (start) {
@@ -291,7 +273,7 @@ __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, 
     if (img) { img[off] = i0; img[off + 1] = i1; img[off + 2] = i2; }
     if (MODE == kFullWrite) {
       my_stop = nonfin ? ~0u : (done ? evals - 1u : mlen);
-      A.stop_out[(int64_t)y * A.W + x] = my_stop;
+      A.stop_out[(int64_t)y * A.W + x] = nonfin ? kStopNonfinite : (done ? A.keys[raw_start + evals - 1u] : kStopNever);
     }
     if (A.clean) {
       const float c0 = MODE == kItem ? cl0_in : A.clean[off], c1 = MODE == kItem ? cl1_in : A.clean[off + 1],
@@ -349,16 +331,27 @@ __global__ void __launch_bounds__(TILE * TILE) k_composite_full(CompArgs A) {
 // MV: the items are variant-views and each takes its view's clean state
 // from views[]: view v % K of variant-view v, or view_of[v] when given.
 // Their work items sit A0.ras.n_tiles apart per variant-view.
-// One (variant, tile) work item, run by the whole workgroup: the positions
-// of the corrupted primitives' old keys and new keys in the tile's sorted
-// clean list (each target's lower bound) are counted over the whole list,
-// which a list of at most KCAP entries brings into registers in one round of
-// loads (its ids then stay in LDS for the compositing); a longer list is
-// searched in two rounds: the last keys of TILE*TILE equal buckets locate each
-// target's bucket, and one pass over that bucket counts the keys below the
-// target.  ent is the item record {tile, first entry of its clean list, its
-// length, -}, v its variant (variant-view when MV) and `item` its partial's
-// slot.  The caller separates two calls by a barrier.
+// One (variant, tile) work item, run by the whole workgroup.
+//
+// First, which pixels can change.  Pixel p is walked when some changed entry
+// of the variant in the pixel's list (the clean record of a corrupted
+// primitive, removed, or its corrupted record, inserted) is one the pixel
+// takes and lies at or before the entry at which its clean walk stopped (its
+// stop key: every entry when it never stopped; always walked when its clean
+// colour was not finite).  Any other pixel's walk, stop and colour are exactly
+// the clean ones.  The test needs only the variant's touch records and the
+// pixel's stop key, loaded in one round; an item with no pixel to walk writes
+// a zero partial and ends there.
+//
+// Otherwise the positions of the corrupted primitives' old keys and new keys
+// in the tile's sorted clean list (each target's lower bound) are counted over
+// the whole list, which a list of at most KCAP entries brings into registers
+// in one round of loads (its ids then stay in LDS for the compositing); a
+// longer list is searched in two rounds: the last keys of TILE*TILE equal
+// buckets locate each target's bucket, and one pass over that bucket counts
+// the keys below the target.  ent is the item record {tile, first entry of
+// its clean list, its length, -}, v its variant (variant-view when MV) and
+// `item` its partial's slot.  The caller separates two calls by a barrier.
 // MV: the item takes its view's clean state from views[]: view v % K of
 // variant-view v, or view_of[v] when given.
 template <int TILE, bool MV>
@@ -366,19 +359,22 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
                                           int64_t image_stride, int K, const ViewArgs* views,
                                           const uint16_t* view_of, uint32_t v, uint4 ent, uint32_t item) {
   constexpr int BS = TILE * TILE;
+  constexpr int NW = BS / 64;
   constexpr int NT = 2 * kMaxTouch;
   constexpr int KPT = TILE == 8 ? 8 : (TILE == 16 ? 4 : 2);   // staged list keys per thread
   constexpr int KCAP = KPT * BS;
   constexpr int VSW = (int)(sizeof(VariantState) / sizeof(uint32_t));
   constexpr int BPR = TILE / 8;
+  constexpr int RQ = 3 * kRecSlots;        // float4 words of a variant's touch records
+  static_assert(sizeof(Rec) == 3 * sizeof(float4) && RQ <= BS, "touch records: one float4 per thread");
   __shared__ float4 s_r0[BS], s_r1[BS], s_r2[BS];
   __shared__ MergeSpec ms;
   __shared__ __align__(8) uint32_t s_vs[VSW];   // the item's VariantState
   __shared__ uint32_t s_ids[KCAP];      // ids of a staged clean list
   __shared__ uint64_t s_tgt[NT];        // removal keys, then insertion keys (sorted)
   __shared__ uint32_t s_cnt[NT], s_fnd[NT], s_bkt[NT];
-  __shared__ uint32_t s_tj[kMaxTouch];   // touch index of each removal target
   __shared__ int s_nr, s_ni;
+  __shared__ uint32_t s_walk[NW];       // per wave: a pixel of its block is walked
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int pxo = (wave % BPR) * 8 + (lane & 7), pyo = (wave / BPR) * 8 + (lane >> 3);   // as in composite_tile
   CompArgs Am;   // MV: A0 with the clean state of the item's view
@@ -392,11 +388,12 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
     Am.ras = w.ras; Am.W = w.W; Am.H = w.H; Am.ck_group = w.ck_group;
   }
   const CompArgs& A = MV ? Am : A0;
-  // The prologue's loads are all issued before any of them is waited for:
-  // branch-free, from clamped addresses, with a lane that has nothing to
-  // read reading the variant's state instead and dropping the value: the
-  // variant state, the pixel's stop index and clean colour and the clean
-  // list (all of them follow from the item record).
+  // Round 1, every load issued before any is waited for (branch-free, from
+  // clamped addresses; a lane with nothing to read reads a valid address of
+  // the same buffer or the variant's state, and drops the value): the variant
+  // state, the variant's touch records (float4 word tid of its kRecSlots
+  // records, staged where composite_tile's first list batch later goes: slot
+  // j in s_r0/s_r1/s_r2[j]) and the pixel's stop key.
   constexpr int VPT = (VSW + BS - 1) / BS;   // variant-state words per thread
   const uint32_t* vsrc = reinterpret_cast<const uint32_t*>(vs_all + v);
   uint32_t vw[VPT];
@@ -408,61 +405,52 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
   const int x = tx * TILE + pxo, y = ty * TILE + pyo;
   const bool inside = x < A.W && y < A.H;
   const int64_t p = (int64_t)min(y, A.H - 1) * A.W + min(x, A.W - 1);
-  const uint32_t sp_w = *(A.stop ? A.stop + p : vsrc);
-  const float* csrc = A.clean ? A.clean + 3 * p : reinterpret_cast<const float*>(vsrc);
-  const float cw0 = csrc[0], cw1 = csrc[1], cw2 = csrc[2];
-  const bool staged = L <= (uint32_t)KCAP;
-  const uint64_t* keys = A.keys + raw_start;
-  uint64_t kr[KPT];
-#pragma unroll
-  for (int k = 0; k < KPT; ++k) {
-    const uint32_t m = (uint32_t)(tid + k * BS);
-    const bool have = staged && m < L;
-    const uint64_t kv = *(have ? keys + m : reinterpret_cast<const uint64_t*>(vsrc));
-    kr[k] = have ? kv : ~0ull;   // padding compares above every key
-  }
+  const bool resume = A.stop != nullptr;
+  const uint64_t pk_w = *(resume ? A.stop + p : reinterpret_cast<const uint64_t*>(vsrc));
+  const bool rl = resume && tid < RQ;
+  const float4* rbase = reinterpret_cast<const float4*>(ovr);
+  const float4 rw = *(rl ? rbase + (int64_t)v * RQ + tid : rbase);
 #pragma unroll
   for (int k = 0; k < VPT; ++k)
     if (tid + k * BS < VSW) s_vs[tid + k * BS] = vw[k];
-  const bool use_px = inside && A.stop;
-  const uint32_t sp = use_px ? sp_w : 0u;
-  const bool use_cl = inside && A.clean;
-  const float cl0 = use_cl ? cw0 : 0.f, cl1 = use_cl ? cw1 : 0.f, cl2 = use_cl ? cw2 : 0.f;
+  if (rl) {
+    const int slot = tid / 3, comp = tid - 3 * (tid / 3);
+    (comp == 0 ? s_r0 : comp == 1 ? s_r1 : s_r2)[slot] = rw;
+  }
   if (tid < NT) { s_cnt[tid] = 0; s_fnd[tid] = 0; s_bkt[tid] = 0; }
   __syncthreads();
-  {
-    // The records of the variant's changed primitives for composite_tile's
-    // per-pixel test, staged where its first list batch goes (slot j: the
-    // clean record of touch j, slot kMaxTouch + j: its new record).  Loaded
-    // by the second wave while thread 0 lists the targets.
-    const int ls = BS > 64 ? tid - 64 : tid;
-    const VariantState& vs = *reinterpret_cast<const VariantState*>(s_vs);
-    if (A.stop && ls >= 0 && ls < 2 * kMaxTouch && ls % kMaxTouch < (int)vs.n_touch) {
-      const int j = ls % kMaxTouch;
+  const VariantState& vs = *reinterpret_cast<const VariantState*>(s_vs);
+  bool walk = inside;
+  if (resume && inside) {
+    const uint64_t pk = pk_w;
+    walk = pk == kStopNonfinite;
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float qc = A.ras.qcut2, amin = A.ras.amin, amax = A.ras.amax;
+    const uint32_t n_touch = min(vs.n_touch, (uint32_t)kMaxTouch);
+    for (uint32_t j = 0; j < n_touch; ++j) {
       const Touch& t = vs.touch[j];
-      if (ls < kMaxTouch && (t.flags & 5u) == 1u) {
-        const Rec& r = A.rec[t.prim];
-        s_r0[ls] = r.r0; s_r1[ls] = r.r1; s_r2[ls] = r.r2;
-      } else if (ls >= kMaxTouch && (t.flags & 6u) == 2u) {
-        const Rec& r = ovr[v * kMaxTouch + (uint32_t)j];
-        s_r0[ls] = r.r0; s_r1[ls] = r.r1; s_r2[ls] = r.r2;
-      }
+      if (t.flags & 4u) continue;   // unchanged primitive
+      const int so = kMaxTouch + (int)j, sn = (int)j;
+      if ((t.flags & 1u) && ((((uint64_t)t.old_depth << 32) | t.prim) <= pk) &&
+          may_take(px, py, s_r0[so], s_r1[so], s_r2[so], qc, amin, amax))
+        walk = true;
+      if ((t.flags & 2u) && ((((uint64_t)t.new_depth << 32) | t.prim) <= pk) &&
+          may_take(px, py, s_r0[sn], s_r1[sn], s_r2[sn], qc, amin, amax))
+        walk = true;
     }
   }
+  const bool wave_walk = __ballot(walk) != 0ull;
+  if (lane == 0) s_walk[wave] = wave_walk ? 1u : 0u;
   if (tid == 0) {
-    const VariantState& vs = *reinterpret_cast<const VariantState*>(s_vs);
     int nr = 0, ni = 0;
     // removal keys fill s_tgt from the front, insertion keys from the back
     for (uint32_t j = 0; j < vs.n_touch; ++j) {
       const Touch t = vs.touch[j];
       if (t.flags & 4u) continue;   // unchanged primitive
-      if ((t.flags & 1u) && rect_has(t.old_rect0, t.old_rect1, tx, ty)) {
-        s_tj[nr] = j;
-        s_tgt[nr++] = ((uint64_t)t.old_depth << 32) | t.prim;
-      }
+      if ((t.flags & 1u) && rect_has(t.old_rect0, t.old_rect1, tx, ty)) s_tgt[nr++] = ((uint64_t)t.old_depth << 32) | t.prim;
       if ((t.flags & 2u) && rect_has(t.new_rect0, t.new_rect1, tx, ty)) {
         s_tgt[NT - 1 - ni] = ((uint64_t)t.new_depth << 32) | t.prim;
-        ms.ins_src[ni] = v * kMaxTouch + j;
+        ms.ins_src[ni] = v * kRecSlots + j;
         ++ni;
       }
     }
@@ -478,7 +466,10 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
   }
   __syncthreads();
   const int nr = __builtin_amdgcn_readfirstlane(s_nr), nt = nr + __builtin_amdgcn_readfirstlane(s_ni);
-  if (nt == 0) {   // the variant changes nothing in this tile
+  bool any_walk = false;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) any_walk |= s_walk[w] != 0u;
+  if (nt == 0 || !any_walk) {   // the variant changes no pixel of this tile
     if (tid == 0) {
       Partial z;
       z.sse = 0.0; z.evals = 0; z.changed = 0; z.max_abs = 0.f; z.nonfinite = 0; z._pad = 0;
@@ -486,6 +477,22 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
     }
     return;
   }
+  // Round 2: the clean list (a staged one into registers) and the clean
+  // colour of the pixels that are walked.
+  const bool staged = L <= (uint32_t)KCAP;
+  const uint64_t* keys = A.keys + raw_start;
+  uint64_t kr[KPT];
+#pragma unroll
+  for (int k = 0; k < KPT; ++k) {
+    const uint32_t m = (uint32_t)(tid + k * BS);
+    const bool have = staged && m < L;
+    const uint64_t kv = *(have ? keys + m : reinterpret_cast<const uint64_t*>(vsrc));
+    kr[k] = have ? kv : ~0ull;   // padding compares above every key
+  }
+  const bool use_cl = walk && A.clean;
+  const float* csrc = use_cl ? A.clean + 3 * p : reinterpret_cast<const float*>(vsrc);
+  const float cw0 = csrc[0], cw1 = csrc[1], cw2 = csrc[2];
+  const float cl0 = use_cl ? cw0 : 0.f, cl1 = use_cl ? cw1 : 0.f, cl2 = use_cl ? cw2 : 0.f;
   const uint32_t G = (L + BS - 1) / BS;   // bucket width of a long list
   if (staged) {
 #pragma unroll
@@ -548,22 +555,13 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
       for (int b = a; b > 0 && ms.rm_pos[b - 1] > ms.rm_pos[b]; --b) {
         const uint32_t z = ms.rm_pos[b]; ms.rm_pos[b] = ms.rm_pos[b - 1]; ms.rm_pos[b - 1] = z;
       }
-    int nc = 0;
-    for (int j = 0; j < nr; ++j)
-      if (s_fnd[j]) {
-        ms.chg_pos[nc] = s_cnt[j] + min(s_bkt[j] * G, L);
-        ms.chg_slot[nc++] = s_tj[j];
-      }
     const int ni = nt - nr;
     for (int j = 0; j < ni; ++j) {
       const uint32_t praw = s_cnt[nr + j] + min(s_bkt[nr + j] * G, L);
       uint32_t rm_before = 0;
       for (int k = 0; k < n_rm; ++k) rm_before += ms.rm_pos[k] < praw ? 1u : 0u;
       ms.ins_mpos[j] = praw - rm_before + (uint32_t)j;
-      ms.chg_pos[nc] = praw;
-      ms.chg_slot[nc++] = (uint32_t)kMaxTouch + (ms.ins_src[j] - v * (uint32_t)kMaxTouch);
     }
-    ms.n_chg = nc;
     ms.raw_start = raw_start;
     ms.raw_len = L;
     ms.n_rm = n_rm;
@@ -578,7 +576,7 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
   __syncthreads();
   float* img = A.image ? A.image + (int64_t)v * image_stride : nullptr;
   const uint32_t changed = composite_tile<TILE, kItem>(A, tile, &ms, ovr, img, A.parts + item, s_r0, s_r1, s_r2,
-                                                       staged ? s_ids : nullptr, sp, cl0, cl1, cl2);
+                                                       staged ? s_ids : nullptr, walk, cl0, cl1, cl2);
   if (tid == 0 && changed)
     atomicOr((unsigned long long*)&vs_all[v].rend_regions,
              (unsigned long long)region_bit(tx, ty, A.ras.tiles_x, A.ras.tiles_y));
@@ -666,40 +664,50 @@ __device__ __forceinline__ void items_role(const CompArgs& A0, const ItemArgs& I
 // Campaign-wide persistent compositing: the work items of a whole campaign
 // chunk (every variant's dirty tiles, compact, each record tagged with its
 // variant) in one launch.  ctl[0] holds the item count, ctl[1] the work
-// counter.  Each workgroup keeps two items ahead: while item i runs, the
-// record of item i + 1 (popped during item i - 1) is loaded and item i + 2
-// is popped, so an item starts with its record, and therefore its variant,
-// tile and list range, already in hand.
+// counter.  A workgroup claims kPersistGroup consecutive items at a time:
+// increments of one counter are serialized by the device (about 13 ns each
+// here), which at one per item would bound the launch by the counter.  It
+// keeps its next group claimed ahead and the next item's record loaded
+// while an item runs, so an item starts with its record, and therefore its
+// variant, tile and list range, already in hand.  Groups are claimed in
+// increasing order, so a workgroup that meets an index at or past the count
+// holds no claim below it.
+constexpr uint32_t kPersistGroup = 4;
 template <int TILE, bool MV>
 __device__ __forceinline__ void persistent_role(const PersistArgs& P) {
-  __shared__ uint32_t s_cur, s_nxt;
+  __shared__ uint32_t s_cur, s_end, s_nbase;
   __shared__ uint4 s_rec;
   const int tid = threadIdx.x;
   const uint32_t total = P.ctl[0];
   if (tid == 0) {
-    const uint32_t a = atomicAdd(P.ctl + 1, 1u);
+    const uint32_t a = atomicAdd(P.ctl + 1, kPersistGroup);
     s_cur = a;
+    s_end = a + kPersistGroup;
     s_rec = a < total ? P.items[a] : make_uint4(0u, 0u, 0u, 0u);
-    s_nxt = atomicAdd(P.ctl + 1, 1u);
+    s_nbase = atomicAdd(P.ctl + 1, kPersistGroup);
   }
   __syncthreads();
   for (;;) {
     const uint32_t item = __builtin_amdgcn_readfirstlane(s_cur);
     if (item >= total) break;
-    const uint32_t nxt = __builtin_amdgcn_readfirstlane(s_nxt);
+    const uint32_t end = __builtin_amdgcn_readfirstlane(s_end), nbase = __builtin_amdgcn_readfirstlane(s_nbase);
     const uint4 ent = make_uint4(__builtin_amdgcn_readfirstlane(s_rec.x), __builtin_amdgcn_readfirstlane(s_rec.y),
                                  __builtin_amdgcn_readfirstlane(s_rec.z), __builtin_amdgcn_readfirstlane(s_rec.w));
+    // the next item: the next one of this group, else the first of the group claimed ahead
+    const bool in_group = item + 1u < end;
+    const uint32_t nxt = in_group ? item + 1u : nbase;
     uint4 rec_n = make_uint4(0u, 0u, 0u, 0u);
-    uint32_t nxt2 = 0;
+    uint32_t nbase_n = nbase;
     if (tid == 0) {
       if (nxt < total) rec_n = P.items[nxt];
-      nxt2 = atomicAdd(P.ctl + 1, 1u);
+      if (!in_group) nbase_n = atomicAdd(P.ctl + 1, kPersistGroup);
     }
     item_work<TILE, MV>(P.A, P.vs, P.ovr, 0, P.K, P.views, P.view_of, ent.w, ent, item);
     if (tid == 0) {
       s_cur = nxt;
+      s_end = in_group ? end : nbase + kPersistGroup;
       s_rec = rec_n;
-      s_nxt = nxt2;
+      s_nbase = nbase_n;
     }
     __syncthreads();
   }
@@ -726,6 +734,8 @@ __device__ __forceinline__ void tiles_role(const StepArgs& S, int v, VariantStat
   const uint32_t* tile_start = S.tile_start;
   const uint32_t* tile_cnt = S.tile_cnt;
   int tiles_x = S.tiles_x, tiles_y = S.tiles_y;
+  ReachArgs ra{S.t_ovr ? S.t_ovr + (int64_t)v * kRecSlots : nullptr, S.A.ras.tile, S.A.W, S.A.H, S.A.ras.qcut2,
+               S.A.ras.amin};
   if constexpr (MV) {
     const ViewArgs& w = S.views[S.t_view_of ? (int)S.t_view_of[v] : v % S.K];
     stop_key = w.stop_key;
@@ -733,8 +743,13 @@ __device__ __forceinline__ void tiles_role(const StepArgs& S, int v, VariantStat
     tile_cnt = w.tile_cnt;
     tiles_x = w.ras.tiles_x;
     tiles_y = w.ras.tiles_y;
+    ra.tile = w.ras.tile;
+    ra.W = w.W;
+    ra.H = w.H;
+    ra.qc = w.ras.qcut2;
+    ra.amin = w.ras.amin;
   }
-  enumerate_items(slot.touch, slot.n_touch, tiles_x, tiles_y, stop_key, tile_start, tile_cnt,
+  enumerate_items(slot.touch, slot.n_touch, tiles_x, tiles_y, stop_key, tile_start, tile_cnt, ra,
                   S.t_items + (int64_t)v * S.n_tiles, &nd, &ni, &pred);
   if (lane == 0) {
     S.t_vs[v].n_dirty = nd;
@@ -803,35 +818,57 @@ template <bool MV>
 __global__ void __launch_bounds__(256) k_persist_list(PersistArgs P) {
   constexpr int VSW = (int)(sizeof(VariantState) / sizeof(uint32_t));
   __shared__ VariantState s_v[4];
+  __shared__ uint32_t s_n[4], s_base[4];
   const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int v = (int)blockIdx.x * 4 + wave;
-  if (v >= P.nv) return;
+  const bool have = v < P.nv;
   VariantState& slot = s_v[wave];
-  const uint32_t* src = reinterpret_cast<const uint32_t*>(P.vs + v);
-  uint32_t* dst = reinterpret_cast<uint32_t*>(&slot);
-  for (int k = lane; k < VSW; k += 64) dst[k] = src[k];
-  wave_sync();
   const uint64_t* stop_key = P.A.stop_key;
   const uint32_t* tile_start = P.A.tile_start;
   const uint32_t* tile_cnt = P.A.tile_cnt;
   int tiles_x = P.A.ras.tiles_x, tiles_y = P.A.ras.tiles_y;
-  if constexpr (MV) {
-    const ViewArgs& w = P.views[P.view_of ? (int)P.view_of[v] : v % P.K];
-    stop_key = w.stop_key;
-    tile_start = w.tile_start;
-    tile_cnt = w.tile_cnt;
-    tiles_x = w.ras.tiles_x;
-    tiles_y = w.ras.tiles_y;
+  ReachArgs ra{P.ovr + (int64_t)v * kRecSlots, P.A.ras.tile, P.A.W, P.A.H, P.A.ras.qcut2, P.A.ras.amin};
+  uint32_t nd = 0, ni = 0;
+  uint64_t pred = 0;
+  if (have) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(P.vs + v);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&slot);
+    for (int k = lane; k < VSW; k += 64) dst[k] = src[k];
+    wave_sync();
+    if constexpr (MV) {
+      const ViewArgs& w = P.views[P.view_of ? (int)P.view_of[v] : v % P.K];
+      stop_key = w.stop_key;
+      tile_start = w.tile_start;
+      tile_cnt = w.tile_cnt;
+      tiles_x = w.ras.tiles_x;
+      tiles_y = w.ras.tiles_y;
+      ra.tile = w.ras.tile;
+      ra.W = w.W;
+      ra.H = w.H;
+      ra.qc = w.ras.qcut2;
+      ra.amin = w.ras.amin;
+    }
+    enumerate_items(slot.touch, slot.n_touch, tiles_x, tiles_y, stop_key, tile_start, tile_cnt, ra, nullptr, &nd,
+                    &ni, &pred);
   }
-  uint32_t nd, ni;
-  uint64_t pred;
-  enumerate_items(slot.touch, slot.n_touch, tiles_x, tiles_y, stop_key, tile_start, tile_cnt, nullptr, &nd, &ni, &pred);
-  uint32_t base = 0;
-  if (lane == 0 && ni) base = atomicAdd(P.ctl, ni);
-  base = (uint32_t)__shfl((int)base, 0);
+  // one reservation per workgroup: increments of a single counter are
+  // serialized by the device, so one per variant would bound the launch
+  if (lane == 0) s_n[wave] = ni;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t tot = s_n[0] + s_n[1] + s_n[2] + s_n[3];
+    uint32_t b = tot ? atomicAdd(P.ctl, tot) : 0u;
+    for (int w = 0; w < 4; ++w) {
+      s_base[w] = b;
+      b += s_n[w];
+    }
+  }
+  __syncthreads();
+  if (!have) return;
+  const uint32_t base = s_base[wave];
   if (ni)
-    enumerate_items(slot.touch, slot.n_touch, tiles_x, tiles_y, stop_key, tile_start, tile_cnt, P.items + base, &nd,
-                    &ni, &pred, (uint32_t)v);
+    enumerate_items(slot.touch, slot.n_touch, tiles_x, tiles_y, stop_key, tile_start, tile_cnt, ra, P.items + base,
+                    &nd, &ni, &pred, (uint32_t)v);
   if (lane == 0) {
     P.item_off[v] = base;
     P.n_items[v] = ni;

@@ -93,7 +93,8 @@ __global__ void __launch_bounds__(256) k_project(DevScene s, DevBox box, DevCam 
 // projects the primitive from the staged words and compares the result with
 // its clean record.  st (LDS) receives the touches, the clamp count and the
 // non-finite flag (n_dirty and the regions zero); ovr[j] receives touch j's
-// corrupted record.  One 64-thread workgroup; every lane calls it.
+// corrupted record and ovr[kMaxTouch + j] its clean one (when visible).  One
+// 64-thread workgroup; every lane calls it.
 template <int DEG>
 __device__ void stage_touches(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                               const Rec* __restrict__ rec, const uint32_t* __restrict__ depth,
@@ -174,6 +175,7 @@ __device__ void stage_touches(const DevScene& s, const DevBox& box, const DevCam
       }
       t.flags = (old_vis ? 1u : 0u) | (o.visible ? 2u : 0u) | (same ? 4u : 0u);
       ovr[j] = o.rec;
+      if (old_vis) ovr[kMaxTouch + j] = rec[p];
     }
     __syncthreads();
   }
@@ -190,10 +192,11 @@ __global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, Dev
   const int v = blockIdx.x;
   __shared__ VariantState st;
   const sg_variant var = bb.variants[v];
-  stage_touches<DEG>(s, box, cam, ras, rec, depth, rect, var, bb.sites, st, bb.ovr + (int64_t)v * kMaxTouch);
+  stage_touches<DEG>(s, box, cam, ras, rec, depth, rect, var, bb.sites, st, bb.ovr + (int64_t)v * kRecSlots);
   uint32_t nd, ni;
   uint64_t pred;
-  enumerate_items(st.touch, st.n_touch, bb.tiles_x, bb.tiles_y, bb.stop_key, bb.tile_start, bb.tile_cnt,
+  const ReachArgs ra{bb.ovr + (int64_t)v * kRecSlots, ras.tile, cam.W, cam.H, ras.qcut2, ras.amin};
+  enumerate_items(st.touch, st.n_touch, bb.tiles_x, bb.tiles_y, bb.stop_key, bb.tile_start, bb.tile_cnt, ra,
                   bb.items + (int64_t)v * bb.n_tiles, &nd, &ni, &pred);
   if (threadIdx.x == 0) {
     st.n_dirty = nd;
@@ -291,7 +294,8 @@ __global__ void __launch_bounds__(64) k_campaign_touch(DevScene s, DevBox box, D
     }
     t.flags = (old_vis ? 1u : 0u) | (o.visible ? 2u : 0u) | (same ? 4u : 0u);
     out->touch[j] = t;
-    ovr[slot * kMaxTouch + j] = o.rec;
+    ovr[slot * kRecSlots + j] = o.rec;
+    if (old_vis) ovr[slot * kRecSlots + kMaxTouch + j] = rec[p];
   }
   out->n_touch = n_touch;
   out->full = full;

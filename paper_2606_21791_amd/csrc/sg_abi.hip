@@ -488,13 +488,13 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
     }
     if (slots >= 0xffffffffull) return fail(SG_E_UNSUPPORTED, "too many checkpoints; raise the spacing");
     const size_t bs = (size_t)ras.tile * ras.tile;
-    SG_TRY(dev_alloc(ctx, resume->stop, (size_t)cam.W * cam.H * sizeof(uint32_t)));
+    SG_TRY(dev_alloc(ctx, resume->stop, (size_t)cam.W * cam.H * sizeof(uint64_t)));
     SG_TRY(dev_alloc(ctx, resume->ck_off, ras.n_tiles * sizeof(uint32_t)));
     SG_TRY(dev_alloc(ctx, resume->stop_key, ras.n_tiles * sizeof(uint64_t)));
     SG_TRY(dev_alloc(ctx, resume->ck, std::max<size_t>(slots, 1) * bs * sizeof(float4)));
     HIP_TRY(hipMemcpyAsync(resume->ck_off.p, off.data(), ras.n_tiles * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));        // `off` is released on return
-    ca.stop_out = P<uint32_t>(resume->stop);
+    ca.stop_out = P<uint64_t>(resume->stop);
     ca.ck_out = P<float4>(resume->ck);
     ca.ck_off = P<uint32_t>(resume->ck_off);
     ca.stop_key_out = P<uint64_t>(resume->stop_key);
@@ -829,7 +829,7 @@ sg_status sg_prep_copy_frame(const sg_prep* p, float* dst, void* stream) {
 static sg_status alloc_batch(sg_ctx* ctx, Workspace* W, const sg_prep* prep, int B, hipStream_t st) {
   const DevRaster& ras = prep->ras;
   SG_TRY(dev_alloc(ctx, W->vs, (size_t)B * sizeof(VariantState)));
-  SG_TRY(dev_alloc(ctx, W->ovr, (size_t)B * kMaxTouch * sizeof(Rec)));
+  SG_TRY(dev_alloc(ctx, W->ovr, (size_t)B * kRecSlots * sizeof(Rec)));
   SG_TRY(dev_alloc(ctx, W->item_off, (size_t)(B + 1) * sizeof(uint32_t)));
   SG_TRY(dev_alloc(ctx, W->n_items_v, (size_t)B * sizeof(uint32_t)));
   SG_TRY(dev_alloc(ctx, W->counter, 16));
@@ -858,7 +858,7 @@ static CompArgs item_comp_args(Workspace* W, const sg_prep* prep, float* images_
               P<uint32_t>(prep->tile_cnt), P<uint64_t>(prep->keys), P<float>(prep->frame), images_out,
               P<Partial>(W->bparts), prep->ras, prep->cam.W, prep->cam.H};
   if (prep->ck_group) {
-    ca.stop = P<uint32_t>(prep->stop);
+    ca.stop = P<uint64_t>(prep->stop);
     ca.ck = P<float4>(prep->ck);
     ca.ck_off = P<uint32_t>(prep->ck_off);
     ca.stop_key = P<uint64_t>(prep->stop_key);
@@ -1131,7 +1131,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
   SG_TRY(dev_alloc(ctx, ctx->camp_sites, std::max<size_t>(1, (size_t)n_sites) * sizeof(sg_site)));
   SG_TRY(dev_alloc(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant)));
   SG_TRY(dev_alloc(ctx, ctx->camp_vs, (size_t)chunk * per * sizeof(VariantState)));
-  SG_TRY(dev_alloc(ctx, ctx->camp_ovr, (size_t)chunk * per * kMaxTouch * sizeof(Rec)));
+  SG_TRY(dev_alloc(ctx, ctx->camp_ovr, (size_t)chunk * per * kRecSlots * sizeof(Rec)));
   if (K > 1) SG_TRY(dev_alloc(ctx, ctx->camp_views, (size_t)K * chunk * sizeof(sg_metrics_t)));
   const ViewArgs* d_views = nullptr;
   if (mv) {
@@ -1141,7 +1141,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
       const bool rs = p->ck_group != 0;
       ctx->camp_vargs_host[k] = ViewArgs{P<Rec>(p->rec),
                                          P<uint32_t>(p->tile_start), P<uint32_t>(p->tile_cnt), P<uint64_t>(p->keys),
-                                         P<float>(p->frame), rs ? P<uint32_t>(p->stop) : nullptr,
+                                         P<float>(p->frame), rs ? P<uint64_t>(p->stop) : nullptr,
                                          rs ? P<float4>(p->ck) : nullptr, rs ? P<uint32_t>(p->ck_off) : nullptr,
                                          rs ? P<uint64_t>(p->stop_key) : nullptr, p->ras, p->cam.W, p->cam.H,
                                          p->ck_group};
@@ -1238,6 +1238,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
               const int q = i % 3;
               a.tB = nvb(i) * per;
               a.t_vs = c_vs + (int64_t)lb(i) * per;
+              a.t_ovr = c_ovr + (int64_t)lb(i) * per * kRecSlots;
               if (sc) a.t_view_of = d_scene_of + c0 + lb(i);
               a.t_items = P<uint4>(W->st_items[q]);
               a.t_n_items = P<uint32_t>(W->st_n[q]);
@@ -1252,7 +1253,7 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
               const int q = (i - 1) % 3;
               a.A.parts = P<Partial>(W->st_parts[q]);
               a.I.vs = c_vs + (int64_t)lb(i - 1) * per;
-              a.I.ovr = c_ovr + (int64_t)lb(i - 1) * per * kMaxTouch;
+              a.I.ovr = c_ovr + (int64_t)lb(i - 1) * per * kRecSlots;
               a.I.items = P<uint4>(W->st_items[q]);
               a.I.item_off = P<uint32_t>(W->st_off[q]);
               a.I.counter = P<uint32_t>(W->st_ctl) + 4 * q;
@@ -1346,7 +1347,7 @@ static sg_status campaign_persistent(sg_ctx* ctx, sg_prep* const* preps, int K, 
   SG_TRY(dev_alloc(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant)));
   for (int k = 0; k < 2; ++k) {
     SG_TRY(dev_alloc(ctx, ctx->pst_vs[k], (size_t)nvv * sizeof(VariantState)));
-    SG_TRY(dev_alloc(ctx, ctx->pst_ovr[k], (size_t)nvv * kMaxTouch * sizeof(Rec)));
+    SG_TRY(dev_alloc(ctx, ctx->pst_ovr[k], (size_t)nvv * kRecSlots * sizeof(Rec)));
     SG_TRY(dev_alloc(ctx, ctx->pst_items[k], (size_t)nvv * max_tiles * sizeof(uint4)));
     SG_TRY(dev_alloc(ctx, ctx->pst_parts[k], (size_t)nvv * max_tiles * sizeof(Partial)));
     SG_TRY(dev_alloc(ctx, ctx->pst_off[k], (size_t)nvv * sizeof(uint32_t)));
@@ -1362,7 +1363,7 @@ static sg_status campaign_persistent(sg_ctx* ctx, sg_prep* const* preps, int K, 
       const bool rs = p->ck_group != 0;
       ctx->camp_vargs_host[k] = ViewArgs{P<Rec>(p->rec),
                                          P<uint32_t>(p->tile_start), P<uint32_t>(p->tile_cnt), P<uint64_t>(p->keys),
-                                         P<float>(p->frame), rs ? P<uint32_t>(p->stop) : nullptr,
+                                         P<float>(p->frame), rs ? P<uint64_t>(p->stop) : nullptr,
                                          rs ? P<float4>(p->ck) : nullptr, rs ? P<uint32_t>(p->ck_off) : nullptr,
                                          rs ? P<uint64_t>(p->stop_key) : nullptr, p->ras, p->cam.W, p->cam.H,
                                          p->ck_group};
@@ -1417,7 +1418,7 @@ static sg_status campaign_persistent(sg_ctx* ctx, sg_prep* const* preps, int K, 
                    P<uint32_t>(p0->tile_cnt), P<uint64_t>(p0->keys), P<float>(p0->frame), nullptr,
                    P<Partial>(ctx->pst_parts[set]), p0->ras, p0->cam.W, p0->cam.H};
     if (p0->ck_group) {
-      a.A.stop = P<uint32_t>(p0->stop);
+      a.A.stop = P<uint64_t>(p0->stop);
       a.A.ck = P<float4>(p0->ck);
       a.A.ck_off = P<uint32_t>(p0->ck_off);
       a.A.stop_key = P<uint64_t>(p0->stop_key);

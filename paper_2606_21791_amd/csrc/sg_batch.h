@@ -20,14 +20,16 @@ __device__ __forceinline__ void wave_sync() {
 // rectangles of its changed primitives (its predicted regions).  One wave
 // walks the rectangles' bounding box 64 tiles at a time in row order and
 // writes a work item {tile, first entry of its clean list, clean list
-// length, tag} for each dirty tile that can change: a tile is dropped when
-// its last pixel stopped, in the clean render, before every key the variant
-// removes from or inserts into its list (stop_key nullable: none dropped).
-// With items null it only counts.  The results are the same in every lane.
+// length, tag} for each dirty tile that can change.  A tile is dropped when
+// no changed record reaches a pixel centre of it (ra.rec null: no such
+// test), or when its last pixel stopped, in the clean render, before every
+// key of a change that reaches it (stop_key nullable: none dropped).  With
+// items null it only counts.  The results are the same in every lane.
 __device__ __forceinline__ void enumerate_items(const Touch* touch, uint32_t n_touch, int tiles_x, int tiles_y,
                                                 const uint64_t* stop_key, const uint32_t* tile_start,
-                                                const uint32_t* tile_cnt, uint4* items, uint32_t* n_dirty,
-                                                uint32_t* n_items, uint64_t* pred, uint32_t tag = 0u) {
+                                                const uint32_t* tile_cnt, const ReachArgs& ra, uint4* items,
+                                                uint32_t* n_dirty, uint32_t* n_items, uint64_t* pred,
+                                                uint32_t tag = 0u) {
   const int lane = threadIdx.x & 63;
   int x0 = tiles_x, y0 = tiles_y, x1 = -1, y1 = -1;
   for (uint32_t j = 0; j < n_touch; ++j) {
@@ -59,9 +61,10 @@ __device__ __forceinline__ void enumerate_items(const Touch* touch, uint32_t n_t
         if (dirty) {
           const int t = ty * tiles_x + tx;
           pr |= region_bit(tx, ty, tiles_x, tiles_y);
+          const unsigned long long mr = ra.rec ? tile_min_key_reach(touch, n_touch, ra, tx, ty) : mk;
           const unsigned long long sk = stop_key ? stop_key[t] : ~0ull;
           if (items) ent = make_uint4((uint32_t)t, tile_start[t], tile_cnt[t], tag);
-          keep = mk <= sk;
+          keep = mr != ~0ull && mr <= sk;
         }
       }
       nd += (uint32_t)__popcll(__ballot(dirty));

@@ -361,6 +361,73 @@ __device__ __forceinline__ unsigned long long tile_min_key(const Touch* touch, u
   return mk;
 }
 
+// Whether some pixel centre of tile (tx, ty) can take record r: whether the
+// smallest q of the record over the tile's pixel centres is within
+// min(cut, log2(o / alpha_min)) (scaled units, the loop's test), so that the
+// tile's pixels cannot change when no record of a variant reaches it.  In
+// coordinates relative to the ellipse's centre, q = i1 u^2 + i2 v^2 with
+// u = X c + Y s and v = Y c - X s.  q is convex, so its minimum over the box
+// of pixel centres is 0 when the box holds the centre, and otherwise lies on
+// one of the box's edges, where it is a one-dimensional quadratic minimized
+// in closed form (on X = const at Y = X gy, on Y = const at X = Y gx).
+// Computed in fp32 with margins (the box widened by 0.05 px, q allowed 1%
+// and 0.05 above the bound) well above the rounding of these steps and of
+// the loop's q while the centre lies within 4,096 px of the tile; farther
+// centres, and records with a non-finite field, are taken to reach the tile.
+__device__ __forceinline__ bool rec_reaches_tile(const Rec& r, int tx, int ty, int tile, int W, int H, float qc,
+                                                 float amin) {
+  const float Ux = r.r0.x, Uy = r.r0.y, c = r.r0.z, s = r.r0.w;
+  const float k1 = r.r1.x, k2 = r.r1.y, i1 = r.r1.z, i2 = r.r1.w, o = r.r2.x;
+  const float cx = Ux + (k1 * c - k2 * s), cy = Uy + (k1 * s + k2 * c);
+  const float x0 = (float)(tx * tile) + 0.45f - cx, x1 = (float)min((tx + 1) * tile, W) - 0.45f - cx;
+  const float y0 = (float)(ty * tile) + 0.45f - cy, y1 = (float)min((ty + 1) * tile, H) - 0.45f - cy;
+  const float far = fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fmaxf(fabsf(y0), fabsf(y1)));
+  if (!(far <= 4096.f) || !(i1 >= 0.f) || !(i2 >= 0.f) || !isfinite(c + s + i1 + i2 + o)) return true;
+  if (!(o >= amin)) return false;   // o 2^-q < alpha_min for every q >= 0
+  if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
+  const float qe = fminf(qc, __log2f(o / amin)) * 1.01f + 0.05f;
+  const float cs = c * s * (i2 - i1);
+  const float dy = i1 * s * s + i2 * c * c, dx = i1 * c * c + i2 * s * s;
+  const float gy = dy > 0.f ? cs / dy : 0.f, gx = dx > 0.f ? cs / dx : 0.f;
+  auto q_at = [&](float X, float Y) {
+    const float u = X * c + Y * s, v = Y * c - X * s;
+    return i1 * u * u + i2 * v * v;
+  };
+  const float qa = q_at(x0, fminf(fmaxf(x0 * gy, y0), y1));
+  const float qb = q_at(x1, fminf(fmaxf(x1 * gy, y0), y1));
+  const float qcc = q_at(fminf(fmaxf(y0 * gx, x0), x1), y0);
+  const float qd = q_at(fminf(fmaxf(y1 * gx, x0), x1), y1);
+  return fminf(fminf(qa, qb), fminf(qcc, qd)) <= qe;
+}
+
+// The records a variant's work-item listing tests tiles against: rec (the
+// variant's kRecSlots touch records; null: no test) on a raster of tile-pixel
+// tiles, W x H pixels, with the loop's cut and alpha_min.
+struct ReachArgs {
+  const Rec* rec;
+  int tile, W, H;
+  float qc, amin;
+};
+
+// tile_min_key over the changes whose record (clean for a removal, corrupted
+// for an insertion) reaches some pixel centre of the tile: all ones when no
+// pixel of the tile can change.
+__device__ __forceinline__ unsigned long long tile_min_key_reach(const Touch* touch, uint32_t n_touch,
+                                                                 const ReachArgs& ra, int tx, int ty) {
+  unsigned long long mk = ~0ull;
+  for (uint32_t j = 0; j < n_touch; ++j) {
+    const Touch& t = touch[j];
+    if (t.flags & 4u) continue;
+    if ((t.flags & 1u) && rect_has(t.old_rect0, t.old_rect1, tx, ty) &&
+        rec_reaches_tile(ra.rec[kMaxTouch + j], tx, ty, ra.tile, ra.W, ra.H, ra.qc, ra.amin))
+      mk = min(mk, ((unsigned long long)t.old_depth << 32) | t.prim);
+    if ((t.flags & 2u) && rect_has(t.new_rect0, t.new_rect1, tx, ty) &&
+        rec_reaches_tile(ra.rec[j], tx, ty, ra.tile, ra.W, ra.H, ra.qc, ra.amin))
+      mk = min(mk, ((unsigned long long)t.new_depth << 32) | t.prim);
+  }
+  return mk;
+}
+
 // Whether a site is corrected by the variant's emulated defense (the
 // protect field of sg_variant): the sign and exponent bits of the storage
 // format, or every bit.

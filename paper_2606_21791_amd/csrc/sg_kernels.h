@@ -165,7 +165,7 @@ struct BatchBuffers {
   const sg_variant* variants;
   int B;
   VariantState* vs;
-  Rec* ovr;                 // B * kMaxTouch override records
+  Rec* ovr;                 // B * kRecSlots records: each variant's corrupted and clean touch records
   uint32_t* item_off;       // B + 1: first item of each variant, then the total
   uint32_t* n_items_v;      // B: work items (dirty tiles that can change) per variant
   // B x n_tiles work items: variant v's at [v * n_tiles, ...), each
@@ -182,9 +182,10 @@ void launch_variant_prep(const DevScene& s, const DevBox& box, const DevCam& cam
                          const Rec* rec, const uint32_t* depth, const uint2* rect, const BatchBuffers& bb,
                          hipStream_t st);
 // Campaign pre-pass over n variants: states (touches, clamps, non-finite
-// flag) and override records (kMaxTouch per variant).  Variant g's state is
-// vs[g * stride + offset] and its records start at ovr[(g * stride + offset)
-// * kMaxTouch] (stride K, offset the view: the views of a variant side by side).
+// flag) and records (kRecSlots per variant: corrupted, then clean).  Variant
+// g's state is vs[g * stride + offset] and its records start at
+// ovr[(g * stride + offset) * kRecSlots] (stride K, offset the view: the views
+// of a variant side by side).
 // view_of (nullable): only the variants g with view_of[g] == view are staged
 // (a campaign over several scenes stages each scene's variants in its launch).
 void launch_campaign_touch(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
@@ -220,6 +221,11 @@ void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, const unsigned
                       hipStream_t st);
 
 // k_composite.hip
+// Per-pixel stop keys of a prepared clean render (CompArgs::stop): list keys
+// are (depth bits << 32 | id) with a finite positive depth, so both markers
+// compare above every key.
+constexpr uint64_t kStopNever = ~0ull;
+constexpr uint64_t kStopNonfinite = ~0ull - 1;
 struct CompArgs {
   const Rec* rec;         // projected records, by primitive
   const uint32_t* tile_start;
@@ -230,19 +236,19 @@ struct CompArgs {
   Partial* parts;         // per tile / per item; nullable when clean is null
   DevRaster ras;
   int32_t W, H;
-  // Resume state of a prepared clean render.  stop[p]: index, in its tile's
-  // list, of the entry at which pixel p stopped (the list length if it never
-  // stopped, ~0u if its colour was not finite).  ck: per tile, the (C, T)
+  // Resume state of a prepared clean render.  stop[p]: the key of the entry
+  // at which pixel p stopped (kStopNever if it never stopped, kStopNonfinite
+  // if its colour was not finite).  ck: per tile, the (C, T)
   // state of every pixel after each multiple of ck_group list entries, in
   // slots ck_off[tile] + k - 1 for k = 1 .. count / ck_group.  The clean
   // render of sg_prepare writes them (*_out); the incremental path reads them.
   // stop_key[t]: the key of the entry at which the last pixel of tile t
   // stopped (all ones if a pixel never stopped or was not finite).
-  const uint32_t* stop = nullptr;
+  const uint64_t* stop = nullptr;
   const float4* ck = nullptr;
   const uint32_t* ck_off = nullptr;
   const uint64_t* stop_key = nullptr;
-  uint32_t* stop_out = nullptr;
+  uint64_t* stop_out = nullptr;
   float4* ck_out = nullptr;
   uint64_t* stop_key_out = nullptr;
   uint32_t ck_group = 0;
@@ -273,7 +279,7 @@ struct ViewArgs {
   const uint32_t* tile_cnt;
   const uint64_t* keys;
   const float* clean;
-  const uint32_t* stop;
+  const uint64_t* stop;
   const float4* ck;
   const uint32_t* ck_off;
   const uint64_t* stop_key;
@@ -286,6 +292,7 @@ struct StepArgs {
   // work items of the next batch: one workgroup (its first wave) per variant
   int tB;
   VariantState* t_vs;       // the batch's variant states (touches in, n_dirty and regions out)
+  const Rec* t_ovr;         // their touch records (kRecSlots per variant)
   uint4* t_items;           // tB x n_tiles
   uint32_t* t_n_items;
   uint32_t* t_item_off;
@@ -329,7 +336,7 @@ void launch_campaign_step(const StepArgs& a, hipStream_t st, hipEvent_t e0 = nul
 struct PersistArgs {
   CompArgs A;               // clean state of the single view and the per-item partials A.parts (no images)
   VariantState* vs;         // the chunk's variant states (from the campaign pre-pass)
-  const Rec* ovr;           // their override records, kMaxTouch per variant
+  const Rec* ovr;           // their touch records, kRecSlots per variant
   uint4* items;             // work items {tile, first entry of its clean list, its length, variant}
   uint32_t* item_off;       // per variant: index of its first item
   uint32_t* n_items;        // per variant: its item count

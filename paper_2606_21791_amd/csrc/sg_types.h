@@ -68,6 +68,9 @@ struct Touch {
 };
 
 constexpr int kMaxTouch = 8;
+// Records staged per variant: slot j holds touch j's corrupted record, slot
+// kMaxTouch + j its clean record (when the clean primitive is visible).
+constexpr int kRecSlots = 2 * kMaxTouch;
 constexpr int kMaxBatch = 2048;   // variants per sg_render_batch launch
 
 struct VariantState {
