@@ -180,6 +180,34 @@ def test_incremental_equals_full_render(ctx, fmt):
 
 
 @pytest.mark.parametrize("tile", [8, 16, 32])
+def test_elongated_footprints_equal_full_render(ctx, tile):
+    """Exponent flips of one log-scale component stretch a Gaussian along one
+    axis, into a footprint whose tile rectangle holds many tiles the ellipse
+    never reaches.  The work-item listing drops those tiles (no changed record
+    reaches a pixel centre of them) and the items drop the pixels that cannot
+    change: the images and records still equal the full renders of the
+    corrupted scenes bit for bit."""
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(6741, seed=5, sh_degree=1)
+    cam = synth.make_camera(400, 400)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam, b.raster_struct(tile=tile))
+    rng = np.random.default_rng(23)
+    n = 96
+    sites = synth.Sites(np.full(n, synth.LOG_SCALES, np.uint8), rng.integers(0, 3, n).astype(np.uint16),
+                        rng.integers(0, sc.n, n).astype(np.uint32), rng.integers(23, 31, n).astype(np.uint8))
+    groups = [np.array([k]) for k in range(n)] + [np.array([0, 1]), np.array([2, 3, 4])]
+    inc, mi = _batch(ctx, prep, sites, groups, mode=0)
+    full, mf = _batch(ctx, prep, sites, groups, mode=1)
+    assert np.array_equal(inc, full)
+    for key in ("changed_px", "max_abs", "nonfinite"):
+        assert np.array_equal(mi[key], mf[key]), key
+    assert np.allclose(mi["sse"], mf["sse"], rtol=1e-12, atol=0.0)
+    assert (mi["changed_px"] > 0).sum() > n // 4          # the flips do change the frame
+    assert mi["dirty_tiles"].max() > (400 // tile) ** 2 // 8   # and some rectangles hold many tiles
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
 def test_resume_spacing_invariance(ctx, tile):
     """Skipping pixels that stopped before the first changed list entry and
     resuming the others from clean checkpoints gives the same images and the
