@@ -156,13 +156,15 @@ typedef struct {
   uint32_t nonfinite;
   uint32_t catastrophic;
   uint32_t changed_px;
-  uint32_t dirty_tiles;   /* tiles re-composited for this variant */
+  uint32_t dirty_tiles;   /* tiles of the corrupted primitives' old and new footprint
+                             rectangles (the incremental path re-composites those of
+                             them that a changed record reaches) */
   uint64_t clamps;        /* guard clamps applied to this variant */
   uint32_t n_pixels;      /* K * H * W compared */
   uint32_t path;          /* 0 incremental, 1 full render */
   uint64_t evals;         /* pixel-primitive evaluations of the front-to-back loop
                              (per pixel: list entries up to and including the one
-                             that stops it) over the re-composited tiles */
+                             that stops it) over the pixels walked */
   uint64_t predicted_regions;
   uint64_t rendered_regions;
 } sg_metrics_t;
