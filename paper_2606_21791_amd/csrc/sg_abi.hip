@@ -172,6 +172,25 @@ sg_status dev_alloc(sg_ctx* ctx, DevBuf& b, size_t bytes) {
   return SG_OK;
 }
 
+// Variants staged per campaign pre-pass (one view: 562 MB of states and touch records).
+constexpr int kCampaignChunk = 1 << 19;
+
+// dev_alloc of `reserve` bytes where the context's budget allows them (and
+// they exceed `want`), else of `want`: buffers that later calls are likely
+// to need larger are sized for those calls once, since growing a buffer
+// frees and reallocates it, which waits for the device.
+sg_status dev_reserve(sg_ctx* ctx, DevBuf& b, size_t want, size_t reserve) {
+  if (reserve > want && reserve > b.bytes) {
+    bool fits;
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      fits = !ctx->budget || ctx->in_use - b.bytes + reserve <= ctx->budget;
+    }
+    if (fits) return dev_alloc(ctx, b, reserve);
+  }
+  return dev_alloc(ctx, b, want);
+}
+
 void dev_free(sg_ctx* ctx, DevBuf& b) {
   if (b.p) {
     (void)hipFree(b.p);
@@ -1098,7 +1117,6 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
                                     const sg_variant* variants, int32_t n_variants, const DevBox& box, int B, int NS,
                                     int NT, sg_metrics_t* metrics_out, hipStream_t caller,
                                     const uint16_t* scene_of = nullptr, const DevBox* scene_boxes = nullptr) {
-  constexpr int kChunk = 1 << 19;   // variants staged per pre-pass (one view; 360 MB of states and records)
   SG_TRY(check_hw_queues());
   std::lock_guard<std::mutex> cg(ctx->camp_mu);
   if (ctx->camp_done) HIP_TRY(hipEventSynchronize(ctx->camp_done));   // the previous campaign's buffers are free
@@ -1126,12 +1144,16 @@ static sg_status campaign_pipelined(sg_ctx* ctx, sg_prep* const* preps, int K, c
          std::memcmp(&a->ras, &c->ras, sizeof(DevRaster)) == 0;
   }
   const int per = mv && !sc ? K : 1;                           // variant-views per variant in a launch
-  const int64_t cap = mv ? (int64_t)1 << 21 : (int64_t)kChunk;  // variant-views staged per pre-pass
+  const int64_t cap = mv ? (int64_t)1 << 21 : (int64_t)kCampaignChunk;  // variant-views staged per pre-pass
   const int chunk = (int)std::min<int64_t>(n_variants, std::max<int64_t>(B, (cap / per / B) * B));
+  // Single-view campaigns stage a whole pre-pass chunk from the first call on
+  // (when the context's budget allows), so that a later, larger campaign
+  // reuses the buffers instead of growing them inside its run.
+  const size_t rv = mv ? 0 : (size_t)kCampaignChunk;
   SG_TRY(dev_alloc(ctx, ctx->camp_sites, std::max<size_t>(1, (size_t)n_sites) * sizeof(sg_site)));
-  SG_TRY(dev_alloc(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant)));
-  SG_TRY(dev_alloc(ctx, ctx->camp_vs, (size_t)chunk * per * sizeof(VariantState)));
-  SG_TRY(dev_alloc(ctx, ctx->camp_ovr, (size_t)chunk * per * kRecSlots * sizeof(Rec)));
+  SG_TRY(dev_reserve(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant), rv * sizeof(sg_variant)));
+  SG_TRY(dev_reserve(ctx, ctx->camp_vs, (size_t)chunk * per * sizeof(VariantState), rv * sizeof(VariantState)));
+  SG_TRY(dev_reserve(ctx, ctx->camp_ovr, (size_t)chunk * per * kRecSlots * sizeof(Rec), rv * kRecSlots * sizeof(Rec)));
   if (K > 1) SG_TRY(dev_alloc(ctx, ctx->camp_views, (size_t)K * chunk * sizeof(sg_metrics_t)));
   const ViewArgs* d_views = nullptr;
   if (mv) {
@@ -1344,7 +1366,8 @@ static sg_status campaign_persistent(sg_ctx* ctx, sg_prep* const* preps, int K, 
   chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, n_variants));
   const int64_t nvv = chunk * per;   // variant-views per chunk
   SG_TRY(dev_alloc(ctx, ctx->camp_sites, std::max<size_t>(1, (size_t)n_sites) * sizeof(sg_site)));
-  SG_TRY(dev_alloc(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant)));
+  SG_TRY(dev_reserve(ctx, ctx->camp_vars, (size_t)n_variants * sizeof(sg_variant),
+                     mv ? 0 : (size_t)kCampaignChunk * sizeof(sg_variant)));
   for (int k = 0; k < 2; ++k) {
     SG_TRY(dev_alloc(ctx, ctx->pst_vs[k], (size_t)nvv * sizeof(VariantState)));
     SG_TRY(dev_alloc(ctx, ctx->pst_ovr[k], (size_t)nvv * kRecSlots * sizeof(Rec)));

@@ -93,13 +93,16 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
     s.graphs = c.graphs;
     sg_settings_set(ctx, s);
     sg_campaign_cfg cc{c.batch, c.streams, c.threads, 0};
-    const int want = std::min(kMaxVars, std::max(n_sites, 8 * c.streams * c.batch));
+    // campaigns of one size for every stream count (so that a fixed per-call
+    // cost weighs the same on each), long enough for each stream's pipeline
+    // to run 16 batches
+    const int want = std::min(kMaxVars, std::max(n_sites, std::max(16 * c.streams * c.batch, 32768)));
     const int use = std::max(c.batch, (want / c.batch) * c.batch);
     // one untimed campaign warms the workspaces; then campaigns are
-    // timed until at least 40 ms (and two campaigns) have elapsed
+    // timed until at least 100 ms (and two campaigns) have elapsed
     double total = 0.0;
     int64_t done = 0;
-    for (int rep = 0; rep < 200 && (rep < 3 || total < 0.04); ++rep) {
+    for (int rep = 0; rep < 200 && (rep < 3 || total < 0.1); ++rep) {
       if (hipStreamSynchronize(st) != hipSuccess) { rc = sg_fail(SG_E_DEVICE, "stream synchronize failed"); return -1.0; }
       const auto t0 = std::chrono::steady_clock::now();
       rc = sg_campaign(ctx, p, sites, n_sites, vars.data(), use, nullptr, 0, &cc, met, stream);
@@ -116,7 +119,7 @@ extern "C" sg_status sg_autotune(sg_ctx* ctx, const sg_scene* scene, const sg_ca
   cur.batch = fixed_batch > 0 ? fixed_batch : std::min(32, max_batch);
   double cur_rate = measure(cur);
   const std::vector<int> tiles = {8, 16, 32}, resumes = {16, 32, 64, 128, 256}, wgss = {1, 2, 4, 8}, grids = {0, 64, 128},
-                         streams = {4, 8, 16, 32, 64}, threads = {1, 2, 4};
+                         streams = {4, 8, 16, 24, 32, 48, 64}, threads = {1, 2, 4};
   std::vector<int> batches;
   if (fixed_batch > 0) batches = {fixed_batch};
   else
