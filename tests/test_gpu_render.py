@@ -842,8 +842,9 @@ def test_persistent_campaign_matches_batches(ctx):
     composited in one persistent launch and reduced) gives exactly the
     records of sg_render_batch on the same variants: guarded and multi-site
     variants, an empty variant, chunks of one size and of several (the two
-    buffer sets alternating, a ragged last chunk), and, with a variant of
-    more than eight primitives, the batch-by-batch fallback."""
+    buffer sets alternating, a ragged last chunk), campaigns of one variant
+    and of one variant with no sites, and, with a variant of more than eight
+    primitives, the batch-by-batch fallback."""
     import torch
     from paper_2606_21791_amd import binding as b
     sc = synth.make_scene(4000, seed=14, sh_degree=1)
@@ -868,7 +869,10 @@ def test_persistent_campaign_matches_batches(ctx):
         ctx.render_batch(prep, sa, va[v0:v0 + 7], box=box, metrics=mt)
         ref.append(b.read_metrics(mt))
     ref = np.concatenate(ref)
-    for vs, r in ((va[:-1], ref[:-1]), (va, ref)):
+    # also single variants and a variant that changes nothing alone (no work
+    # items at all: every workgroup's first claim is past the count)
+    for vs, r in ((va[:1], ref[:1]), (va[ns + 1:ns + 2], ref[ns + 1:ns + 2]), (va[:3], ref[:3]), (va[:-1], ref[:-1]),
+                  (va, ref)):
         for batch in (0, 5, 64):
             mt = b.metrics_tensor(len(vs))
             ctx.campaign(prep, sa, vs, mt, box=box, batch=batch, engine=b.SG_ENGINE_PERSISTENT)
