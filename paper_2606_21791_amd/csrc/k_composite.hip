@@ -13,18 +13,18 @@
 // run this same code per pixel, so an incrementally re-composited tile is
 // bit-identical to a full render of the variant.
 //
-// Resume: the merged list equals the clean list up to its first differing
-// index m0.  A pixel whose clean walk stopped before m0 is unchanged and is
-// not walked at all; the others restart from the clean render's checkpoint at
-// the largest multiple of the checkpoint spacing not above m0, which holds the
-// exact (C, T) state after that many entries.
-//
 // Only the entries a pixel takes (q within the cut and alpha at least
 // alpha_min) change its state or stop it, so removing or inserting an entry
 // the pixel does not take leaves its walk, its stop and its colour exactly as
 // they were.  A pixel is therefore unchanged, and not walked, when every
 // changed entry that it takes lies behind the entry at which its clean walk
-// stopped; the clean render keeps that entry's key per pixel.
+// stopped (in particular when its walk stopped before the first changed
+// entry); the clean render keeps that entry's key per pixel.
+//
+// Resume: the merged list equals the clean list up to its first differing
+// index m0.  The pixels that are walked restart from the clean render's
+// checkpoint at the largest multiple of the checkpoint spacing not above m0,
+// which holds the exact (C, T) state after that many entries.
 //
 // k_campaign_step holds, in one launch, the three stages of a campaign
 // stream's pipeline on separate buffers: the work items of its next batch,
@@ -46,7 +46,7 @@ struct MergeSpec {
   int n_rm, n_ins;
   uint32_t rm_pos[kMaxTouch];
   uint32_t ins_mpos[kMaxTouch];
-  uint32_t ins_src[kMaxTouch];   // index into the override records
+  uint32_t ins_src[kMaxTouch];   // index of the inserted entry's record in the touch records
   uint32_t m0;                   // first index at which merged and clean lists differ
   uint32_t start;                // resume index (multiple of the checkpoint spacing, <= m0)
 };
@@ -72,8 +72,8 @@ enum { kFull = 0, kFullWrite = 1, kItem = 2 };
 
 // kItem: s_ids (nullable) holds the ids of the tile's whole clean list;
 // walk_in says whether the pixel can change (item_work decides) and cl*_in
-// is its clean colour, read by the caller.  Returns the tile's changed-pixel count in thread 0 (0 elsewhere,
-// and when part is null).
+// is its clean colour, read by the caller.  Returns the tile's changed-pixel
+// count in thread 0 (0 elsewhere, and when part is null).
 template <int TILE, int MODE>
 __device__ __forceinline__ uint32_t composite_tile(const CompArgs& A, int tile, const MergeSpec* ms, const Rec* ovr,
                                                    float* img, Partial* part, float4* s_r0, float4* s_r1,
@@ -586,13 +586,15 @@ __device__ __forceinline__ void item_work(const CompArgs& A0, VariantState* __re
 // workgroups pops (variant, tile) work items from a device counter until the
 // batch's item count (known only on the device) is exhausted.  Variant v's
 // items sit at [v * n_tiles, ...) and its first item index is item_off[v].
-// Each workgroup keeps two items ahead, as the campaign-wide role below:
-// while item i runs, wave 0 locates item i + 1 (popped during item i - 1) in
-// the offsets and loads its record, and item i + 2 is popped, so an item
-// starts with its variant, tile and list range in hand.
+// Each workgroup keeps two items ahead: while item i runs, wave 0 locates
+// item i + 1 (popped during item i - 1) in the offsets and loads its record,
+// and item i + 2 is popped, so an item starts with its variant, tile and list
+// range in hand.  (A batch holds a few hundred items over as many
+// workgroups, so one pop per item keeps the counter far from its limit.)
 //
-// The variant prep has already dropped every dirty tile whose last pixel
-// stopped, in the clean render, before all of the tile's target keys.
+// The work-item listing has already dropped every dirty tile that no changed
+// record reaches and every one whose last pixel stopped, in the clean
+// render, before all of the keys of the changes that reach it.
 // 16 x 16 tiles: registers are held to five resident workgroups per CU, the
 // number their LDS allows.
 // MV: the items are variant-views (see item_work); their work items sit
@@ -878,8 +880,9 @@ __global__ void __launch_bounds__(256) k_persist_list(PersistArgs P) {
 }
 
 // 16 x 16 tiles: registers bounded for eight resident workgroups per CU (the
-// LDS allows eight; a few values spill), which outruns the five that the
-// unbounded build holds: 5.0 against 4.6 M injections/s on the large scene.
+// LDS allows eight; a few values spill), which outran the five that the
+// unbounded build holds when the kernel was first measured (5.0 against
+// 4.6 M injections/s on the headline scene).
 template <int TILE, bool MV>
 __global__ void __launch_bounds__(TILE * TILE, TILE == 16 ? 8 : 1) k_persist_composite(PersistArgs P) {
   persistent_role<TILE, MV>(P);

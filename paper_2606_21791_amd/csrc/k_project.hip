@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(64) k_variant_prep(DevScene s, DevBox box, Dev
 
 // Campaign pre-pass: the staged corrupted primitives of every variant of a
 // campaign chunk at once, one thread per variant, written to the campaign's
-// per-variant states and override records.  The steps are those of
+// per-variant states and touch records.  The steps are those of
 // stage_touches, in its order: the first kMaxTouch distinct primitives of
 // the variant's sites (more: st.full and none staged), each primitive's
 // stored words with the variant's sites XORed in and the guard clamp

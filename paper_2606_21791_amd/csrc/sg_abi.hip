@@ -103,7 +103,7 @@ struct sg_ctx {
   std::vector<Workspace*> ws;
   std::vector<hipStream_t> campaign_streams;   // created by sg_campaign, default priority
   // device copies of a pipelined campaign's sites and variants, and the
-  // states and override records of a chunk of its variants; camp_done marks
+  // states and touch records of a chunk of its variants; camp_done marks
   // the end of the campaign that last used them; camp_mu serialises
   // campaigns on one context; camp_vargs holds the per-view clean state of a
   // multi-view campaign (its host copy stays alive for the upload)
@@ -111,7 +111,7 @@ struct sg_ctx {
   std::vector<ViewArgs> camp_vargs_host;
   std::vector<uint16_t> camp_scene_of_host;
   // the persistent campaign path's two buffer sets (its chunks alternate
-  // between them and between two streams): states, override records, work
+  // between them and between two streams): states, touch records, work
   // items, partials, per-variant item ranges, control words, per-view records
   DevBuf pst_vs[2], pst_ovr[2], pst_items[2], pst_parts[2], pst_off[2], pst_n[2], pst_ctl[2], pst_views[2];
   hipEvent_t camp_done = nullptr;
