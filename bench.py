@@ -874,10 +874,23 @@ def run_views(args):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
         r = sgb.read_metrics(mt)
+        # the same injections through the persistent engine (every variant of
+        # a chunk in all K views in one compositing launch)
+        mp = sgb.metrics_tensor(n)
+        ctx.campaign(preps, sa, va[:n], mp, engine=sgb.SG_ENGINE_PERSISTENT)
+        torch.cuda.synchronize()
+        with _no_gc():
+            t0 = time.perf_counter()
+            ctx.campaign(preps, sa, va[:n], mp, engine=sgb.SG_ENGINE_PERSISTENT)
+            torch.cuda.synchronize()
+            dt_p = time.perf_counter() - t0
+        rp = sgb.read_metrics(mp)
         # dense equivalent: K full 800 x 800 frames per injection; the
         # incremental path re-composites only the dirty tiles (an upper bound
         # of the pixels it composites)
         curve.append({"K": K, "inj_per_s": round(n / dt, 1),
+                      "persistent_inj_per_s": round(n / dt_p, 1),
+                      "persistent_records_identical": bool(all(np.array_equal(rp[k], r[k]) for k in r.dtype.names)),
                       "dense_equiv_view_mpix_per_s": round(n * K * 0.64 / dt, 1),
                       "dirty_tile_mpix_per_s": round(float(r["dirty_tiles"].sum()) * args.tile ** 2 / dt / 1e6, 1),
                       "mean_footprint": round(float(r["footprint"].mean()), 6),
@@ -956,6 +969,16 @@ def run_scenes(args):
         dt_split = time.perf_counter() - t0
     same = all(np.array_equal(sgb.read_metrics(mk)[key], mixed[key][idx])
                for idx, _, _, mk in per_scene for key in ("sse", "changed_px", "dirty_tiles", "evals"))
+    # the mixed campaign through the persistent engine
+    mp = sgb.metrics_tensor(n_inj)
+    ctx.campaign_scenes(preps, sa, va, scene_of, mp, engine=sgb.SG_ENGINE_PERSISTENT)
+    torch.cuda.synchronize()
+    with _no_gc():
+        t0 = time.perf_counter()
+        ctx.campaign_scenes(preps, sa, va, scene_of, mp, engine=sgb.SG_ENGINE_PERSISTENT)
+        torch.cuda.synchronize()
+        dt_pers = time.perf_counter() - t0
+    pers = sgb.read_metrics(mp)
     out = {"metric": "scenes of uneven size: injections/s of one mixed campaign vs one campaign per scene",
            "config": {"workload": "3 scenes (6,741 fp32 512x512; 134,826 fp32 800x800; 500,000 clustered bf16 "
                                   f"1600x900; SH degree 3), single-bit variants in random scene order, B={B}",
@@ -963,6 +986,8 @@ def run_scenes(args):
                       "wgs_per_cu": args.wgs_per_cu, "resume_spacing": args.resume},
            "mixed_inj_per_s": round(n_inj / dt_mixed, 1), "per_scene_inj_per_s": round(n_inj / dt_split, 1),
            "records_identical": bool(same),
+           "persistent_mixed_inj_per_s": round(n_inj / dt_pers, 1),
+           "persistent_records_identical": bool(all(np.array_equal(pers[k], mixed[k]) for k in mixed.dtype.names)),
            "per_scene_injections": [int(len(idx)) for idx, _, _, _ in per_scene]}
     print(json.dumps(out), flush=True)
 
