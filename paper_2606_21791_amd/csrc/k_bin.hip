@@ -13,7 +13,8 @@
 
 namespace sg {
 
-constexpr int kSortCap = 4096;       // keys sorted in LDS by one block
+constexpr int kSortCap = 4096;       // lists up to this long are sorted in LDS by one block
+constexpr int kChunkKeys = 4096;     // longer lists are cut into chunks of this many keys, each sorted by one block
 constexpr int kMergeTile = 2048;     // outputs of one block in a merge pass
 constexpr int kEmitSmall = 32;       // rectangles up to this many tiles are emitted by one thread
 
@@ -95,7 +96,7 @@ __global__ void __launch_bounds__(1024) k_tile_prefix(DevRaster ras, BinBuffers 
     const int t = base + threadIdx.x;
     const uint32_t c = t < ras.n_tiles ? bb.tile_cnt[t] : 0u;
     const bool big = c > (uint32_t)kSortCap;
-    const uint32_t nch = big ? (c + kSortCap - 1) / kSortCap : 0u, ngr = big ? (c + kMergeTile - 1) / kMergeTile : 0u;
+    const uint32_t nch = big ? (c + kChunkKeys - 1) / kChunkKeys : 0u, ngr = big ? (c + kMergeTile - 1) / kMergeTile : 0u;
     uint32_t v[3] = {big ? 1u : 0u, nch, ngr}, tot[3];
     block_scan<3>(v, tot, s_w);
     if (big) {
@@ -234,12 +235,29 @@ __global__ void __launch_bounds__(256) k_tile_sort(DevRaster ras, BinBuffers bb)
 }
 
 // Tiles with more than kSortCap instances are sorted by the whole grid:
-// every LDS-sized chunk of every such tile is sorted by one block, then runs
+// every chunk of kChunkKeys keys of every such tile is sorted by one block
+// (a tile's last chunk may be shorter), then runs
 // are merged pairwise in passes of doubling width.  A pass first finds, for
 // every kMergeTile-output block, where its outputs start in the two runs
 // (merge path, one thread per block), then each block stages its inputs in
 // LDS and merges them.  Passes alternate between keys and keys_tmp at the
-// tile's own offset.
+// tile's own offset; a tile that takes an odd number of passes has its
+// sorted chunks written to keys_tmp, so that every tile's last pass ends in
+// keys.
+
+// Merge passes a big tile takes: one per width kChunkKeys, 2 kChunkKeys, ...
+// below its length.
+__device__ __forceinline__ uint32_t merge_passes(uint32_t n) {
+  uint32_t p = 0;
+  for (uint64_t w = kChunkKeys; w < n; w <<= 1) ++p;
+  return p;
+}
+
+// The buffer that holds a big tile's keys before merge pass p (after its
+// last pass, p = merge_passes(n): keys).
+__device__ __forceinline__ uint64_t* pass_buffer(const BinBuffers& bb, uint32_t n, uint32_t p) {
+  return ((merge_passes(n) - p) & 1u) ? bb.keys_tmp : bb.keys;
+}
 
 // The big tile holding global item g (off has nb + 1 prefix entries).
 __device__ __forceinline__ int big_of(const uint32_t* off, int nb, uint32_t g) {
@@ -251,73 +269,151 @@ __device__ __forceinline__ int big_of(const uint32_t* off, int nb, uint32_t g) {
   return lo;
 }
 
-// Element i of a bitonic stage (k, j) keeps min(own, partner) when it is the
-// lower element of an ascending pair or the upper one of a descending pair.
-__device__ __forceinline__ uint64_t bitonic_keep(uint64_t v, uint64_t p, int i, int k, int j) {
-  const bool take_min = ((i & k) == 0) == ((i & j) == 0);
-  return take_min ? (v < p ? v : p) : (v < p ? p : v);
-}
+// Bitonic sort of one chunk of kChunkKeys keys by kChunkThreads threads holding
+// kPerThread keys each in registers (thread t holds elements
+// kPerThread * t + r).  Element i pairs with i ^ J in stage (K, J) and the
+// pair sorts ascending when (i & K) == 0.  Partners in the same thread are
+// exchanged in registers, partners in the same wave by lane permutes on the
+// VALU (no LDS traffic: the LDS pipe bounds a shuffle-based network), and
+// the rest through LDS (element i at
+// sk[(i % kPerThread) * kChunkThreads + i / kPerThread]).  Every stage is
+// unrolled, so distances and offsets are constants.
+constexpr int kPerThread = 8;
+constexpr int kChunkThreads = kChunkKeys / kPerThread;
 
 __device__ __forceinline__ void bitonic_pair(uint64_t& lo, uint64_t& hi, bool asc) {
-  if ((lo > hi) == asc) { const uint64_t t = lo; lo = hi; hi = t; }
+  const bool sw = (lo > hi) == asc;
+  const uint64_t a = lo;
+  lo = sw ? hi : lo;
+  hi = sw ? a : hi;
 }
 
-// Ascending sort of 4096 keys by 1024 threads, four keys per thread in
-// registers (thread t holds elements 4t..4t+3): partners in the same thread
-// are exchanged in registers, partners in the same wave by lane shuffles,
-// and the rest through LDS (element i at sk[(i & 3) * 1024 + (i >> 2)]).
-__device__ void sort4096(uint64_t* sk, uint64_t& v0, uint64_t& v1, uint64_t& v2, uint64_t& v3) {
+// DPP lane permutes of one dword (full row and bank masks: every lane is written).
+template <int Ctrl>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, Ctrl, 0xF, 0xF, true);
+}
+
+constexpr int kDppXor1 = 0xB1;          // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;          // quad_perm [2,3,0,1]
+constexpr int kDppXor3 = 0x1B;          // quad_perm [3,2,1,0]
+constexpr int kDppHalfMirror = 0x141;   // lane i of each group of 8 takes lane 7 - i (i ^ 7)
+constexpr int kDppRowRor8 = 0x128;      // rotation by 8 within each row of 16 (i ^ 8)
+
+// The dword of lane (lane ^ M), for M < 64, without LDS: DPP for M <= 8,
+// the gfx950 row swaps for 16 and 32 (swapping a register with itself gives
+// each lane its partner row's value in one of the two results).
+template <int M>
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t x) {
+  if constexpr (M == 1) {
+    return dpp32<kDppXor1>(x);
+  } else if constexpr (M == 2) {
+    return dpp32<kDppXor2>(x);
+  } else if constexpr (M == 4) {
+    return dpp32<kDppXor3>(dpp32<kDppHalfMirror>(x));   // (i ^ 3) ^ 7 = i ^ 4
+  } else if constexpr (M == 8) {
+    return dpp32<kDppRowRor8>(x);
+  } else if constexpr (M == 16) {
+    // odd rows of the first operand swap with even rows of the second
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (threadIdx.x & 16) ? r[0] : r[1];
+  } else {
+    static_assert(M == 32, "lane distance");
+    // rows 2-3 of the first operand swap with rows 0-1 of the second
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (threadIdx.x & 32) ? r[0] : r[1];
+  }
+}
+
+template <int M>
+__device__ __forceinline__ uint64_t lane_xor(uint64_t v) {
+  const uint32_t lo = lane_xor32<M>((uint32_t)v), hi = lane_xor32<M>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int K, int J>
+__device__ __forceinline__ void bitonic_stage(uint64_t* sk, uint64_t (&v)[kPerThread]) {
   const int t = threadIdx.x;
-  const int i0 = 4 * t;
-  for (int k = 2; k <= kSortCap; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j >= 256) {
-        __syncthreads();
-        sk[t] = v0; sk[1024 + t] = v1; sk[2048 + t] = v2; sk[3072 + t] = v3;
-        __syncthreads();
-        const int pt = t ^ (j >> 2);
-        v0 = bitonic_keep(v0, sk[pt], i0, k, j);
-        v1 = bitonic_keep(v1, sk[1024 + pt], i0 + 1, k, j);
-        v2 = bitonic_keep(v2, sk[2048 + pt], i0 + 2, k, j);
-        v3 = bitonic_keep(v3, sk[3072 + pt], i0 + 3, k, j);
-      } else if (j >= 4) {
-        const int m = j >> 2;
-        const uint64_t p0 = __shfl_xor(v0, m), p1 = __shfl_xor(v1, m), p2 = __shfl_xor(v2, m), p3 = __shfl_xor(v3, m);
-        v0 = bitonic_keep(v0, p0, i0, k, j);
-        v1 = bitonic_keep(v1, p1, i0 + 1, k, j);
-        v2 = bitonic_keep(v2, p2, i0 + 2, k, j);
-        v3 = bitonic_keep(v3, p3, i0 + 3, k, j);
-      } else if (j == 2) {
-        bitonic_pair(v0, v2, (i0 & k) == 0);
-        bitonic_pair(v1, v3, ((i0 + 1) & k) == 0);
-      } else {
-        bitonic_pair(v0, v1, (i0 & k) == 0);
-        bitonic_pair(v2, v3, ((i0 + 2) & k) == 0);
+  const int i0 = kPerThread * t;
+  if constexpr (J < kPerThread) {
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+      if ((r & J) == 0) {
+        // K < kPerThread: the direction depends on r only; otherwise on the thread only
+        const bool asc = K < kPerThread ? (r & K) == 0 : (i0 & K) == 0;
+        bitonic_pair(v[r], v[r | J], asc);
       }
     }
+  } else {
+    // the thread's elements share the pair direction and their side of the pair:
+    // keep own when (own < partner) agrees with take_min
+    const bool take_min = ((i0 & K) == 0) == ((i0 & J) == 0);
+    constexpr int M = J / kPerThread;   // partner thread t ^ M
+    uint64_t p[kPerThread];
+    if constexpr (M >= 64) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kPerThread; ++r) sk[kChunkThreads * r + t] = v[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kPerThread; ++r) p[r] = sk[kChunkThreads * r + (t ^ M)];
+    } else {
+#pragma unroll
+      for (int r = 0; r < kPerThread; ++r) p[r] = lane_xor<M>(v[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) v[r] = (v[r] < p[r]) == take_min ? v[r] : p[r];
   }
-  __syncthreads();   // the caller may reuse sk
 }
 
-__global__ void __launch_bounds__(1024) k_big_chunks(BinBuffers bb) {
-  __shared__ uint64_t sk[kSortCap];
-  const int nb = (int)bb.total[2];
-  const uint32_t nch = (uint32_t)bb.total[4];
+template <int K, int J>
+__device__ __forceinline__ void bitonic_merge_stages(uint64_t* sk, uint64_t (&v)[kPerThread]) {
+  bitonic_stage<K, J>(sk, v);
+  if constexpr (J > 1) bitonic_merge_stages<K, J / 2>(sk, v);
+}
+
+template <int K>
+__device__ __forceinline__ void bitonic_from(uint64_t* sk, uint64_t (&v)[kPerThread]) {
+  bitonic_merge_stages<K, K / 2>(sk, v);
+  if constexpr (K < kChunkKeys) bitonic_from<2 * K>(sk, v);
+}
+
+// Each merge block's and each LDS chunk's big tile and index within that
+// tile (big_map: merge blocks first, then chunks), found once per sort by
+// binary searches over the prefix counts, so that the chunk sort and every
+// merge pass begin with two dependent loads instead of a search.
+__global__ void __launch_bounds__(256) k_big_map(BinBuffers bb) {
+  const int nbig = (int)bb.total[2];
+  const uint32_t nblk = (uint32_t)bb.total[5], nch = (uint32_t)bb.total[4];
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nblk + nch; g += gridDim.x * blockDim.x) {
+    const bool blk = g < nblk;
+    const uint32_t x = blk ? g : g - nblk;
+    const uint32_t* off = blk ? bb.big_goff : bb.big_choff;
+    const int k = big_of(off, nbig, x);
+    bb.big_map[g] = make_uint2(bb.big_tiles[k], x - off[k]);
+  }
+}
+
+__global__ void __launch_bounds__(kChunkThreads) k_big_chunks(BinBuffers bb) {
+  __shared__ uint64_t sk[kChunkKeys];
+  const uint32_t nblk = (uint32_t)bb.total[5], nch = (uint32_t)bb.total[4];
   for (uint32_t g = blockIdx.x; g < nch; g += gridDim.x) {
-    const int k = big_of(bb.big_choff, nb, g);
-    const uint32_t t = bb.big_tiles[k];
+    const uint2 mp = bb.big_map[nblk + g];
+    const uint32_t t = mp.x;
     const int n = (int)bb.tile_cnt[t];
-    const int c0 = (int)(g - bb.big_choff[k]) * kSortCap;
-    const int m = min(kSortCap, n - c0);
-    uint64_t* a = bb.keys + bb.tile_start[t] + c0;
-    const int e = 4 * threadIdx.x;
-    uint64_t v0 = e < m ? a[e] : ~0ull, v1 = e + 1 < m ? a[e + 1] : ~0ull, v2 = e + 2 < m ? a[e + 2] : ~0ull,
-             v3 = e + 3 < m ? a[e + 3] : ~0ull;
-    sort4096(sk, v0, v1, v2, v3);
-    if (e < m) a[e] = v0;
-    if (e + 1 < m) a[e + 1] = v1;
-    if (e + 2 < m) a[e + 2] = v2;
-    if (e + 3 < m) a[e + 3] = v3;
+    const int c0 = (int)mp.y * kChunkKeys;
+    const int m = min(kChunkKeys, n - c0);
+    const uint64_t* a = bb.keys + bb.tile_start[t] + c0;
+    uint64_t* out = pass_buffer(bb, (uint32_t)n, 0u) + bb.tile_start[t] + c0;
+    const int e = kPerThread * threadIdx.x;
+    uint64_t v[kPerThread];
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) v[r] = e + r < m ? a[e + r] : ~0ull;
+    bitonic_from<2>(sk, v);
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r)
+      if (e + r < m) out[e + r] = v[r];
+    __syncthreads();   // the next chunk's LDS stages reuse sk
   }
 }
 
@@ -326,12 +422,12 @@ struct MergeBlock {
   uint32_t t, n, o0, o1, a0, na, b0, nb;
 };
 
-__device__ __forceinline__ MergeBlock merge_block(const BinBuffers& bb, int nbig, uint32_t g, uint32_t w) {
+__device__ __forceinline__ MergeBlock merge_block(const BinBuffers& bb, uint32_t g, uint32_t w) {
   MergeBlock m;
-  const int k = big_of(bb.big_goff, nbig, g);
-  m.t = bb.big_tiles[k];
+  const uint2 mp = bb.big_map[g];
+  m.t = mp.x;
   m.n = bb.tile_cnt[m.t];
-  m.o0 = (g - bb.big_goff[k]) * (uint32_t)kMergeTile;
+  m.o0 = mp.y * (uint32_t)kMergeTile;
   m.o1 = min(m.o0 + (uint32_t)kMergeTile, m.n);
   if (m.n <= w) {   // a single run: copied
     m.a0 = 0; m.na = m.n; m.b0 = m.n; m.nb = 0;
@@ -355,37 +451,25 @@ __device__ __forceinline__ uint32_t merge_split(const uint64_t* A, uint32_t na, 
   return lo;
 }
 
-__global__ void __launch_bounds__(256) k_big_partition(BinBuffers bb, uint32_t w, const uint64_t* __restrict__ src_all) {
-  const int nbig = (int)bb.total[2];
+// Pass p merges runs of width w = kChunkKeys << p.
+__global__ void __launch_bounds__(256) k_big_partition(BinBuffers bb, uint32_t w, uint32_t p) {
   const uint32_t nblk = (uint32_t)bb.total[5];
   for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nblk; g += gridDim.x * blockDim.x) {
-    const MergeBlock m = merge_block(bb, nbig, g, w);
+    const MergeBlock m = merge_block(bb, g, w);
     if (m.n <= w) continue;   // the tile is already one sorted run (k_big_merge skips it)
-    const uint64_t* src = src_all + bb.tile_start[m.t];
+    const uint64_t* src = pass_buffer(bb, m.n, p) + bb.tile_start[m.t];
     bb.big_split[g] = m.nb ? merge_split(src + m.a0, m.na, src + m.b0, m.nb, m.o0 - m.a0) : m.o0 - m.a0;
   }
 }
 
-// Merge passes a big tile takes: one per width kSortCap, 2 kSortCap, ...
-// below its length.  Its sorted keys end in keys after an even number and in
-// keys_tmp after an odd one.
-__device__ __forceinline__ uint32_t merge_passes(uint32_t n) {
-  uint32_t p = 0;
-  for (uint64_t w = kSortCap; w < n; w <<= 1) ++p;
-  return p;
-}
-
-__global__ void __launch_bounds__(256) k_big_merge(BinBuffers bb, uint32_t w, const uint64_t* __restrict__ src_all,
-                                                   uint64_t* __restrict__ dst_all) {
+__global__ void __launch_bounds__(256) k_big_merge(BinBuffers bb, uint32_t w, uint32_t p) {
   __shared__ uint64_t s[kMergeTile];
-  const int nbig = (int)bb.total[2];
   const uint32_t nblk = (uint32_t)bb.total[5];
   for (uint32_t g = blockIdx.x; g < nblk; g += gridDim.x) {
-    // w = 0: the final copy of the tiles whose keys ended in keys_tmp
-    const MergeBlock m = merge_block(bb, nbig, g, w ? w : 0xffffffffu);
-    if (w ? m.n <= w : (merge_passes(m.n) & 1u) == 0u) continue;   // nothing to move for this tile
-    const uint64_t* src = src_all + bb.tile_start[m.t];
-    uint64_t* dst = dst_all + bb.tile_start[m.t];
+    const MergeBlock m = merge_block(bb, g, w);
+    if (m.n <= w) continue;   // the tile is already one sorted run, in keys
+    const uint64_t* src = pass_buffer(bb, m.n, p) + bb.tile_start[m.t];
+    uint64_t* dst = pass_buffer(bb, m.n, p + 1u) + bb.tile_start[m.t];
     const uint32_t cnt = m.o1 - m.o0;
     if (m.nb == 0) {
       for (uint32_t o = threadIdx.x; o < cnt; o += blockDim.x) dst[m.o0 + o] = src[m.o0 + o];
@@ -433,22 +517,20 @@ void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, const unsigned
   k_tile_sort<<<ras.n_tiles, 256, 0, st>>>(ras, bb);
   if (totals[2] == 0) return;
   const unsigned long long nch = totals[4], nblk = totals[5], maxn = totals[3];
-  k_big_chunks<<<(unsigned)std::min<unsigned long long>(nch, (unsigned long long)n_cu * 2), 1024, 0, st>>>(bb);
+  k_big_map<<<(unsigned)std::min<unsigned long long>((nblk + nch + 255) / 256, (unsigned long long)n_cu * 8), 256, 0,
+              st>>>(bb);
+  k_big_chunks<<<(unsigned)std::min<unsigned long long>(nch, (unsigned long long)n_cu * 4), kChunkThreads, 0, st>>>(bb);
   const unsigned pgrid = (unsigned)std::max<unsigned long long>(1, (nblk + 255) / 256);
-  const unsigned mgrid = (unsigned)std::min<unsigned long long>(nblk, (unsigned long long)n_cu * 8);
-  // Pass k merges runs of width kSortCap << k into runs of twice that width,
+  // one workgroup per merge block (below 2^31 blocks: lists are shorter than 2^31)
+  const unsigned mgrid = (unsigned)nblk;
+  // Pass p merges runs of width kChunkKeys << p into runs of twice that width,
   // from one buffer into the other, for the tiles still longer than one run;
-  // a tile that is already one sorted run is left where its last pass put it.
-  uint64_t* src = bb.keys;
-  uint64_t* dst = bb.keys_tmp;
-  int passes = 0;
-  for (unsigned long long w = kSortCap; w < maxn; w <<= 1, ++passes) {
-    k_big_partition<<<pgrid, 256, 0, st>>>(bb, (uint32_t)w, src);
-    k_big_merge<<<mgrid, 256, 0, st>>>(bb, (uint32_t)w, src, dst);
-    std::swap(src, dst);
+  // a tile that is already one sorted run has reached keys.
+  uint32_t p = 0;
+  for (unsigned long long w = kChunkKeys; w < maxn; w <<= 1, ++p) {
+    k_big_partition<<<pgrid, 256, 0, st>>>(bb, (uint32_t)w, p);
+    k_big_merge<<<mgrid, 256, 0, st>>>(bb, (uint32_t)w, p);
   }
-  // the tiles that took an odd number of passes, back into keys
-  if (passes) k_big_merge<<<mgrid, 256, 0, st>>>(bb, 0u, bb.keys_tmp, bb.keys);
 }
 
 }  // namespace sg

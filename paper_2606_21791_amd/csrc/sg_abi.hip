@@ -64,7 +64,7 @@ struct Workspace {
   hipStream_t stream = nullptr;
   // full renders
   DevBuf rec, depth, rect, diff, flags, clamps, tile_cnt, tile_start, cursor, total, keys, keys_tmp,
-      big_prims, big_tiles, big_choff, big_goff, big_split, parts, work_scene, sites_dev, box_keys, metrics_tmp;
+      big_prims, big_tiles, big_choff, big_goff, big_split, big_map, parts, work_scene, sites_dev, box_keys, metrics_tmp;
   // batches of variants
   DevBuf vs, ovr, item_off, n_items_v, tiles, bparts, counter, arrive, gmetrics, views_tmp, ssim_tmp;
   unsigned long long* h_total = nullptr;   // pinned
@@ -218,7 +218,7 @@ Workspace* workspace(sg_ctx* ctx, hipStream_t st) {
 void free_workspace(sg_ctx* ctx, Workspace* w) {
   DevBuf* bufs[] = {&w->rec, &w->depth, &w->rect, &w->diff, &w->flags, &w->clamps, &w->tile_cnt,
                     &w->tile_start, &w->cursor, &w->total, &w->keys, &w->keys_tmp, &w->big_prims, &w->big_tiles,
-                    &w->big_choff, &w->big_goff, &w->big_split,
+                    &w->big_choff, &w->big_goff, &w->big_split, &w->big_map,
                     &w->parts, &w->work_scene, &w->sites_dev, &w->box_keys, &w->metrics_tmp, &w->vs, &w->ovr,
                     &w->item_off, &w->n_items_v, &w->tiles, &w->bparts,
                     &w->counter, &w->arrive, &w->gmetrics, &w->views_tmp, &w->ssim_tmp, &w->st_ctl};
@@ -466,7 +466,8 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
   }
   BinBuffers bb{P<int32_t>(W->diff), P<uint32_t>(tile_cnt), P<uint32_t>(tile_start), P<uint32_t>(W->cursor),
                 P<unsigned long long>(W->total), nullptr, nullptr, P<uint32_t>(W->big_prims),
-                P<uint32_t>(W->big_tiles), P<uint32_t>(W->big_choff), P<uint32_t>(W->big_goff), nullptr, 0};
+                P<uint32_t>(W->big_tiles), P<uint32_t>(W->big_choff), P<uint32_t>(W->big_goff), nullptr, nullptr,
+                0};
   {
     PassScope ps(ctx, SG_PASS_BIN, st);
     launch_tile_prefix(ras, bb, st);
@@ -489,7 +490,9 @@ sg_status full_render(sg_ctx* ctx, Workspace* W, const DevScene& s, const DevBox
     PassScope ps(ctx, SG_PASS_SORT, st);
     if (W->h_total[3] > (1ull << 31)) return fail(SG_E_UNSUPPORTED, "a tile list longer than 2^31 entries");
     SG_TRY(dev_alloc(ctx, W->big_split, (W->h_total[5] + 1) * sizeof(uint32_t)));
+    SG_TRY(dev_alloc(ctx, W->big_map, (W->h_total[5] + W->h_total[4] + 1) * sizeof(uint2)));
     bb.big_split = P<uint32_t>(W->big_split);
+    bb.big_map = P<uint2>(W->big_map);
     launch_tile_sort(ras, bb, W->h_total, ctx->n_cu, st);
   }
   CompArgs ca{P<Rec>(rec), P<uint32_t>(tile_start), P<uint32_t>(tile_cnt),

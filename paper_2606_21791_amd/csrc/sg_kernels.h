@@ -211,6 +211,7 @@ struct BinBuffers {
   uint32_t* big_choff;        // per big tile (+1): first LDS chunk
   uint32_t* big_goff;         // per big tile (+1): first merge block
   uint32_t* big_split;        // per merge block: its first output's position in run A
+  uint2* big_map;             // per merge block, then per LDS chunk: (tile, index within the tile)
   int64_t capacity;
 };
 void launch_tile_prefix(const DevRaster& ras, const BinBuffers& bb, hipStream_t st);

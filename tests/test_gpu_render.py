@@ -244,10 +244,12 @@ def test_resume_spacing_invariance(ctx, tile):
 
 @pytest.mark.parametrize("n", [14000, 40000])
 def test_long_tile_lists(ctx, n):
-    """Lists longer than one LDS sort (thousands of entries per 32x32 tile, so
-    the grid-wide chunk sort and two or three merge passes run) give the same
-    frame as 8x8 tiles (lists within one LDS sort at n=14,000; two merge
-    passes at n=40,000) and agree with the oracle on every decided pixel."""
+    """Lists longer than one LDS sort (thousands of entries per 32x32 tile,
+    cut into 4,096-key chunks: up to about 12,000 entries and two merge passes
+    at n=14,000, about 34,000 and four passes at n=40,000) give the same
+    frame as 8x8 tiles (lists within one LDS sort at n=14,000; up to about
+    12,000 entries at n=40,000) and agree with the oracle on every decided
+    pixel."""
     from paper_2606_21791_amd import binding as b
     sc = synth.make_scene(n, seed=29)
     sc.fields[1][:] += 1.5                    # larger primitives: each covers several tiles
