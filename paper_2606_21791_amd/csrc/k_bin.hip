@@ -16,6 +16,7 @@ namespace sg {
 constexpr int kSortCap = 4096;       // lists up to this long are sorted in LDS by one block
 constexpr int kChunkKeys = 4096;     // longer lists are cut into chunks of this many keys, each sorted by one block
 constexpr int kMergeTile = 2048;     // outputs of one block in a merge pass
+constexpr int kMergeThreads = kMergeTile / 8;   // 8 outputs per thread
 constexpr int kEmitSmall = 32;       // rectangles up to this many tiles are emitted by one thread
 
 constexpr int kPrefixLds = 12288;   // difference-grid entries prefix-summed in LDS (48 KB)
@@ -462,8 +463,12 @@ __global__ void __launch_bounds__(256) k_big_partition(BinBuffers bb, uint32_t w
   }
 }
 
-__global__ void __launch_bounds__(256) k_big_merge(BinBuffers bb, uint32_t w, uint32_t p) {
-  __shared__ uint64_t s[kMergeTile];
+// Each thread merges 8 consecutive outputs into registers, keeping the next
+// key of each run in a register (one LDS read per output); the block then
+// writes its outputs back into the staging buffer and stores them with
+// consecutive threads on consecutive keys.
+__global__ void __launch_bounds__(kMergeThreads) k_big_merge(BinBuffers bb, uint32_t w, uint32_t p) {
+  __shared__ uint64_t s[kMergeTile];   // the block's inputs (its part of run A, then of run B), then its outputs
   const uint32_t nblk = (uint32_t)bb.total[5];
   for (uint32_t g = blockIdx.x; g < nblk; g += gridDim.x) {
     const MergeBlock m = merge_block(bb, g, w);
@@ -480,19 +485,35 @@ __global__ void __launch_bounds__(256) k_big_merge(BinBuffers bb, uint32_t w, ui
     const uint32_t ia1 = m.o1 == m.a0 + m.na + m.nb ? m.na : bb.big_split[g + 1];
     const uint32_t ib0 = (m.o0 - m.a0) - ia0, ib1 = (m.o1 - m.a0) - ia1;
     const uint32_t nA = ia1 - ia0, nB = ib1 - ib0;
-    __syncthreads();
+    __syncthreads();   // the previous block's outputs have been stored
     for (uint32_t x = threadIdx.x; x < nA; x += blockDim.x) s[x] = src[m.a0 + ia0 + x];
     for (uint32_t x = threadIdx.x; x < nB; x += blockDim.x) s[nA + x] = src[m.b0 + ib0 + x];
     __syncthreads();
-    const uint32_t d = 8u * threadIdx.x;
+    const uint32_t d = 8u * threadIdx.x;   // d + 7 < kMergeTile
+    uint64_t out[8];
     if (d < cnt) {
       uint32_t i = merge_split(s, nA, s + nA, nB, d), j = d - i;
-      const uint32_t end = min(d + 8u, cnt);
-      for (uint32_t o = d; o < end; ++o) {
-        if (j >= nB || (i < nA && s[i] < s[nA + j])) dst[m.o0 + o] = s[i++];
-        else dst[m.o0 + o] = s[nA + j++];
+      uint64_t ka = i < nA ? s[i] : 0ull, kb = j < nB ? s[nA + j] : 0ull;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {   // outputs past cnt are computed but not stored
+        const bool take_a = j >= nB || (i < nA && ka < kb);
+        out[q] = take_a ? ka : kb;
+        if (take_a) {
+          ++i;
+          ka = i < nA ? s[i] : 0ull;
+        } else {
+          ++j;
+          kb = j < nB ? s[nA + j] : 0ull;
+        }
       }
     }
+    __syncthreads();   // every thread has read its inputs
+    if (d < cnt) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s[d + q] = out[q];
+    }
+    __syncthreads();
+    for (uint32_t o = threadIdx.x; o < cnt; o += blockDim.x) dst[m.o0 + o] = s[o];
   }
 }
 
@@ -529,7 +550,7 @@ void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, const unsigned
   uint32_t p = 0;
   for (unsigned long long w = kChunkKeys; w < maxn; w <<= 1, ++p) {
     k_big_partition<<<pgrid, 256, 0, st>>>(bb, (uint32_t)w, p);
-    k_big_merge<<<mgrid, 256, 0, st>>>(bb, (uint32_t)w, p);
+    k_big_merge<<<mgrid, kMergeThreads, 0, st>>>(bb, (uint32_t)w, p);
   }
 }
 
