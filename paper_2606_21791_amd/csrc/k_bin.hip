@@ -203,38 +203,6 @@ __global__ void __launch_bounds__(1024) k_emit_chunk(int n, int chunk, const uin
   }
 }
 
-// Bitonic sort of n <= P keys in LDS (P a power of two <= kSortCap).
-__device__ __forceinline__ void lds_bitonic(uint64_t* sk, int P) {
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        const int l = i ^ j;
-        if (l > i) {
-          const uint64_t a = sk[i], b = sk[l];
-          const bool asc = (i & k) == 0;
-          if ((a > b) == asc) { sk[i] = b; sk[l] = a; }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-__global__ void __launch_bounds__(256) k_tile_sort(DevRaster ras, BinBuffers bb) {
-  const int t = blockIdx.x;
-  const uint32_t n = bb.tile_cnt[t];
-  if (n <= 1) return;
-  if (n > (uint32_t)kSortCap) return;   // sorted by k_big_chunks and k_big_merge
-  __shared__ uint64_t sk[kSortCap];
-  int P = 2;
-  while (P < (int)n) P <<= 1;
-  uint64_t* g = bb.keys + bb.tile_start[t];
-  for (int i = threadIdx.x; i < P; i += blockDim.x) sk[i] = i < (int)n ? g[i] : ~0ull;
-  __syncthreads();
-  lds_bitonic(sk, P);
-  for (int i = threadIdx.x; i < (int)n; i += blockDim.x) g[i] = sk[i];
-}
-
 // Tiles with more than kSortCap instances are sorted by the whole grid:
 // every chunk of kChunkKeys keys of every such tile is sorted by one block
 // (a tile's last chunk may be shorter), then runs
@@ -377,6 +345,97 @@ template <int K>
 __device__ __forceinline__ void bitonic_from(uint64_t* sk, uint64_t (&v)[kPerThread]) {
   bitonic_merge_stages<K, K / 2>(sk, v);
   if constexpr (K < kChunkKeys) bitonic_from<2 * K>(sk, v);
+}
+
+// Tiles of up to kSortCap instances: one workgroup sorts a tile's list with
+// the same exchanges as the chunk sort, for a length P (the list's length
+// rounded up to a power of two) known only at run time, by NT threads of
+// eight keys (LDS layout sk[NT * r + t]).  A wave whose elements all lie at or
+// beyond P holds padding only and pairs only with padding, so it skips the
+// exchanges and only takes part in the barriers.
+template <int NT, int J>
+__device__ __forceinline__ void bitonic_stage_rt(uint64_t* sk, uint64_t (&v)[kPerThread], int K, bool live) {
+  const int t = threadIdx.x;
+  const int i0 = kPerThread * t;
+  if constexpr (J < kPerThread) {
+    if (!live) return;
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+      if ((r & J) == 0) {
+        const bool asc = K < kPerThread ? (r & K) == 0 : (i0 & K) == 0;
+        bitonic_pair(v[r], v[r | J], asc);
+      }
+    }
+  } else {
+    const bool take_min = ((i0 & K) == 0) == ((i0 & J) == 0);
+    constexpr int M = J / kPerThread;   // partner thread t ^ M, below NT since J < P <= NT * kPerThread
+    uint64_t p[kPerThread];
+    if constexpr (M >= 64) {
+      __syncthreads();
+      if (live) {
+#pragma unroll
+        for (int r = 0; r < kPerThread; ++r) sk[NT * r + t] = v[r];
+      }
+      __syncthreads();
+      if (!live) return;
+#pragma unroll
+      for (int r = 0; r < kPerThread; ++r) p[r] = sk[NT * r + (t ^ M)];
+    } else {
+      if (!live) return;
+#pragma unroll
+      for (int r = 0; r < kPerThread; ++r) p[r] = lane_xor<M>(v[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) v[r] = (v[r] < p[r]) == take_min ? v[r] : p[r];
+  }
+}
+
+template <int NT, int J>
+__device__ __forceinline__ void bitonic_stage_if(uint64_t* sk, uint64_t (&v)[kPerThread], int K, bool live) {
+  if constexpr (J < NT * kPerThread) bitonic_stage_rt<NT, J>(sk, v, K, live);
+}
+
+template <int NT>
+__device__ void bitonic_runtime(uint64_t* sk, uint64_t (&v)[kPerThread], int P) {
+  const bool live = (int)(threadIdx.x & ~63u) * kPerThread < P;   // wave-uniform
+  for (int K = 2; K <= P; K <<= 1) {
+    for (int J = K >> 1; J > 0; J >>= 1) {
+      switch (J) {
+        case 1: bitonic_stage_if<NT, 1>(sk, v, K, live); break;
+        case 2: bitonic_stage_if<NT, 2>(sk, v, K, live); break;
+        case 4: bitonic_stage_if<NT, 4>(sk, v, K, live); break;
+        case 8: bitonic_stage_if<NT, 8>(sk, v, K, live); break;
+        case 16: bitonic_stage_if<NT, 16>(sk, v, K, live); break;
+        case 32: bitonic_stage_if<NT, 32>(sk, v, K, live); break;
+        case 64: bitonic_stage_if<NT, 64>(sk, v, K, live); break;
+        case 128: bitonic_stage_if<NT, 128>(sk, v, K, live); break;
+        case 256: bitonic_stage_if<NT, 256>(sk, v, K, live); break;
+        case 512: bitonic_stage_if<NT, 512>(sk, v, K, live); break;
+        case 1024: bitonic_stage_if<NT, 1024>(sk, v, K, live); break;
+        default: bitonic_stage_if<NT, 2048>(sk, v, K, live); break;
+      }
+    }
+  }
+}
+
+// Lists of lo..hi instances (hi <= NT * kPerThread); one workgroup per tile.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_tile_sort(BinBuffers bb, uint32_t lo, uint32_t hi) {
+  const int t = blockIdx.x;
+  const uint32_t n = bb.tile_cnt[t];
+  if (n < lo || n > hi) return;   // another launch's lists (longer than kSortCap: the chunk sort and merges)
+  __shared__ uint64_t sk[NT * kPerThread];
+  int P = 2;
+  while (P < (int)n) P <<= 1;
+  uint64_t* g = bb.keys + bb.tile_start[t];
+  const int e = kPerThread * threadIdx.x;
+  uint64_t v[kPerThread];
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) v[r] = e + r < (int)n ? g[e + r] : ~0ull;
+  bitonic_runtime<NT>(sk, v, P);
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r)
+    if (e + r < (int)n) g[e + r] = v[r];
 }
 
 // Each merge block's and each LDS chunk's big tile and index within that
@@ -533,14 +592,30 @@ void launch_emit(int n, const uint32_t* depth, const uint2* rect, const DevRaste
   k_emit_big<<<1024, 256, 0, st>>>(depth, rect, ras, bb);
 }
 
+// Workgroups of k_big_chunks resident per CU: its grid-stride launch uses
+// exactly that many per CU, so that all of them run in one round.
+static int big_chunks_occupancy() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_big_chunks, kChunkThreads, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  return nb > 0 ? nb : 1;
+}
+
 void launch_tile_sort(const DevRaster& ras, const BinBuffers& bb, const unsigned long long* totals, int n_cu,
                       hipStream_t st) {
-  k_tile_sort<<<ras.n_tiles, 256, 0, st>>>(ras, bb);
+  // lists of 2..512 keys in one wave (no LDS), 513..2,048 in four, 2,049..kSortCap in eight
+  k_tile_sort<64><<<ras.n_tiles, 64, 0, st>>>(bb, 2u, 512u);
+  k_tile_sort<256><<<ras.n_tiles, 256, 0, st>>>(bb, 513u, 2048u);
+  k_tile_sort<512><<<ras.n_tiles, 512, 0, st>>>(bb, 2049u, (uint32_t)kSortCap);
   if (totals[2] == 0) return;
   const unsigned long long nch = totals[4], nblk = totals[5], maxn = totals[3];
   k_big_map<<<(unsigned)std::min<unsigned long long>((nblk + nch + 255) / 256, (unsigned long long)n_cu * 8), 256, 0,
               st>>>(bb);
-  k_big_chunks<<<(unsigned)std::min<unsigned long long>(nch, (unsigned long long)n_cu * 4), kChunkThreads, 0, st>>>(bb);
+  static const int chunk_occ = big_chunks_occupancy();
+  k_big_chunks<<<(unsigned)std::min<unsigned long long>(nch, (unsigned long long)n_cu * chunk_occ), kChunkThreads, 0,
+                 st>>>(bb);
   const unsigned pgrid = (unsigned)std::max<unsigned long long>(1, (nblk + 255) / 256);
   // one workgroup per merge block (below 2^31 blocks: lists are shorter than 2^31)
   const unsigned mgrid = (unsigned)nblk;

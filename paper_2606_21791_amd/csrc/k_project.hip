@@ -28,7 +28,14 @@ __global__ void __launch_bounds__(256) k_project(DevScene s, DevBox box, DevCam 
   }
   uint32_t clamps = 0;
   bool nonfin = false;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s.n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < s.n; i0 += (int64_t)gridDim.x * blockDim.x) {
+    // The index passes through an empty asm statement, so the compiler forms
+    // each word's address from it inside the loop instead of keeping one
+    // 64-bit pointer per loaded word, box word and output live across
+    // iterations (that strength reduction took SH degree 0 from 153 to 238
+    // VGPRs, two waves per SIMD instead of three, and made degree 3 spill).
+    int64_t i = i0;
+    asm volatile("" : "+v"(i));
     uint32_t w[L::kWords];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
@@ -308,16 +315,40 @@ __global__ void __launch_bounds__(64) k_campaign_touch(DevScene s, DevBox box, D
   out->rend_regions = 0;
 }
 
+// Workgroups of k_project<D, LDS> resident per CU with shm bytes of LDS
+// each.  The grid-stride launch uses exactly that many per CU, so that all of
+// them run in one round: a partial second round would run with one wave per
+// SIMD.  Cached per host thread for the last LDS size asked.
+template <int D, bool LDS>
+static int project_occupancy(size_t shm) {
+  thread_local size_t last_shm = ~(size_t)0;
+  thread_local int last = 1;
+  if (shm != last_shm) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_project<D, LDS>, 256, shm) != hipSuccess) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    last_shm = shm;
+    last = nb > 0 ? nb : 1;
+  }
+  return last;
+}
+
 void launch_project(const DevScene& s, const DevBox& box, const DevCam& cam, const DevRaster& ras,
                     const ProjBuffers& pb, int n_cu, hipStream_t st) {
   const int64_t need = ((int64_t)s.n + 255) / 256;
   const int nd = (ras.tiles_x + 1) * (ras.tiles_y + 1);
   const bool lds = nd <= 16384;
-  const unsigned blocks = (unsigned)(lds ? std::min<int64_t>(need, (int64_t)n_cu * 4) : need);
   const size_t shm = lds ? (size_t)nd * sizeof(int) : 0;
-#define SG_PROJ(D)                                                                          \
-  if (lds) k_project<D, true><<<blocks, 256, shm, st>>>(s, box, cam, ras, pb);            \
-  else k_project<D, false><<<blocks, 256, 0, st>>>(s, box, cam, ras, pb);
+  // with the grid in LDS: one round of resident workgroups, each flushing its grid once
+#define SG_PROJ(D)                                                                                              \
+  if (lds) {                                                                                                    \
+    const unsigned blocks = (unsigned)std::min<int64_t>(need, (int64_t)n_cu * project_occupancy<D, true>(shm)); \
+    k_project<D, true><<<blocks, 256, shm, st>>>(s, box, cam, ras, pb);                                         \
+  } else {                                                                                                      \
+    k_project<D, false><<<(unsigned)need, 256, 0, st>>>(s, box, cam, ras, pb);                                  \
+  }
   switch (s.sh_degree) {
     case 0: SG_PROJ(0) break;
     case 1: SG_PROJ(1) break;
