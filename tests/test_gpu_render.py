@@ -279,6 +279,33 @@ def test_tile_size_invariance(ctx):
     assert np.array_equal(frames[0], frames[1]) and np.array_equal(frames[1], frames[2])
 
 
+def test_tile_grids_beyond_lds(ctx):
+    """At 1100 x 1100 with 8x8 tiles the tile-count difference grid has
+    139 x 139 = 19,321 entries and there are 18,769 tiles: the projection adds
+    rectangles to the grid in global memory (one primitive per thread instead
+    of a grid-stride loop over an LDS grid), the tile prefix sums the grid in
+    global memory, and instances are emitted one thread per primitive.  The
+    frame equals the one from 16x16 tiles (LDS grid, chunked emission) bit for
+    bit and agrees with the oracle on three windows: the centre, one near the
+    corner where the scene ends, and one reaching the frame's last row and
+    column of tiles."""
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(20000, seed=41, sh_degree=1)
+    sc.fields[1][:] -= 1.0                    # smaller primitives: many small tiles in use
+    cam = synth.make_camera(1100, 1100)
+    assert (1100 // 8 + 2) ** 2 > 16384 and (1100 // 8 + 1) ** 2 > 16384
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    frames = {t: ctx.prepare(ds, cam, b.raster_struct(tile=t)).frame().cpu().numpy() for t in (8, 16)}
+    assert np.array_equal(frames[8], frames[16])
+    proj = orender.project(orender.decode_scene(stored(sc, "f32"), "f32"), 1, cam)
+    for win in ((500, 500, 564, 564), (960, 960, 1024, 1024), (980, 980, 1100, 1100)):
+        ref = orender.render(proj, cam, window=win)
+        x0, y0, x1, y1 = ref["window"]
+        worst, amb = compare_image(frames[8][y0:y1, x0:x1], ref)
+        print(f"window {win}: max err {worst:.3g}, ambiguous {amb:.2e}", flush=True)
+        assert worst <= PIXEL_TOL and amb <= 2e-3, (win, worst, amb)
+
+
 def test_guarded_and_multi_upset_variants(ctx):
     from paper_2606_21791_amd import binding as b
     sc = synth.make_scene(4000, seed=14)
