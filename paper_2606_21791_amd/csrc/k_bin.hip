@@ -204,9 +204,9 @@ __global__ void __launch_bounds__(1024) k_emit_chunk(int n, int chunk, const uin
 }
 
 // Tiles with more than kSortCap instances are sorted by the whole grid:
-// every chunk of kChunkKeys keys of every such tile is sorted by one block
-// (a tile's last chunk may be shorter), then runs
-// are merged pairwise in passes of doubling width.  A pass first finds, for
+// every chunk of kChunkKeys keys of every such tile is sorted by one block (a
+// tile's last chunk may be shorter), then runs are merged pairwise in passes
+// of doubling width.  A pass first finds, for
 // every kMergeTile-output block, where its outputs start in the two runs
 // (merge path, one thread per block), then each block stages its inputs in
 // LDS and merges them.  Passes alternate between keys and keys_tmp at the
@@ -238,15 +238,13 @@ __device__ __forceinline__ int big_of(const uint32_t* off, int nb, uint32_t g) {
   return lo;
 }
 
-// Bitonic sort of one chunk of kChunkKeys keys by kChunkThreads threads holding
-// kPerThread keys each in registers (thread t holds elements
-// kPerThread * t + r).  Element i pairs with i ^ J in stage (K, J) and the
-// pair sorts ascending when (i & K) == 0.  Partners in the same thread are
-// exchanged in registers, partners in the same wave by lane permutes on the
-// VALU (no LDS traffic: the LDS pipe bounds a shuffle-based network), and
-// the rest through LDS (element i at
-// sk[(i % kPerThread) * kChunkThreads + i / kPerThread]).  Every stage is
-// unrolled, so distances and offsets are constants.
+// Bitonic networks over keys held kPerThread per thread in registers (thread
+// t holds elements kPerThread * t + r).  Element i pairs with i ^ J in stage
+// (K, J) and the pair sorts ascending when (i & K) == 0.  Partners in the same
+// thread are exchanged in registers, partners in the same wave by lane
+// permutes on the VALU (no LDS traffic: the LDS pipe bounds a shuffle-based
+// network), and the rest through LDS (element i of a block of NT threads at
+// sk[(i % kPerThread) * NT + i / kPerThread]).
 constexpr int kPerThread = 8;
 constexpr int kChunkThreads = kChunkKeys / kPerThread;
 
@@ -300,11 +298,16 @@ __device__ __forceinline__ uint64_t lane_xor(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <int K, int J>
-__device__ __forceinline__ void bitonic_stage(uint64_t* sk, uint64_t (&v)[kPerThread]) {
+// One stage (K, J) by a block of NT threads.  A wave whose flag live is false
+// holds only padding that pairs only with padding (elements at or beyond the
+// network's length), so it skips the exchanges and only takes part in the
+// barriers.
+template <int NT, int J>
+__device__ __forceinline__ void bitonic_stage(uint64_t* sk, uint64_t (&v)[kPerThread], int K, bool live) {
   const int t = threadIdx.x;
   const int i0 = kPerThread * t;
   if constexpr (J < kPerThread) {
+    if (!live) return;
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
       if ((r & J) == 0) {
@@ -317,58 +320,7 @@ __device__ __forceinline__ void bitonic_stage(uint64_t* sk, uint64_t (&v)[kPerTh
     // the thread's elements share the pair direction and their side of the pair:
     // keep own when (own < partner) agrees with take_min
     const bool take_min = ((i0 & K) == 0) == ((i0 & J) == 0);
-    constexpr int M = J / kPerThread;   // partner thread t ^ M
-    uint64_t p[kPerThread];
-    if constexpr (M >= 64) {
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < kPerThread; ++r) sk[kChunkThreads * r + t] = v[r];
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < kPerThread; ++r) p[r] = sk[kChunkThreads * r + (t ^ M)];
-    } else {
-#pragma unroll
-      for (int r = 0; r < kPerThread; ++r) p[r] = lane_xor<M>(v[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < kPerThread; ++r) v[r] = (v[r] < p[r]) == take_min ? v[r] : p[r];
-  }
-}
-
-template <int K, int J>
-__device__ __forceinline__ void bitonic_merge_stages(uint64_t* sk, uint64_t (&v)[kPerThread]) {
-  bitonic_stage<K, J>(sk, v);
-  if constexpr (J > 1) bitonic_merge_stages<K, J / 2>(sk, v);
-}
-
-template <int K>
-__device__ __forceinline__ void bitonic_from(uint64_t* sk, uint64_t (&v)[kPerThread]) {
-  bitonic_merge_stages<K, K / 2>(sk, v);
-  if constexpr (K < kChunkKeys) bitonic_from<2 * K>(sk, v);
-}
-
-// Tiles of up to kSortCap instances: one workgroup sorts a tile's list with
-// the same exchanges as the chunk sort, for a length P (the list's length
-// rounded up to a power of two) known only at run time, by NT threads of
-// eight keys (LDS layout sk[NT * r + t]).  A wave whose elements all lie at or
-// beyond P holds padding only and pairs only with padding, so it skips the
-// exchanges and only takes part in the barriers.
-template <int NT, int J>
-__device__ __forceinline__ void bitonic_stage_rt(uint64_t* sk, uint64_t (&v)[kPerThread], int K, bool live) {
-  const int t = threadIdx.x;
-  const int i0 = kPerThread * t;
-  if constexpr (J < kPerThread) {
-    if (!live) return;
-#pragma unroll
-    for (int r = 0; r < kPerThread; ++r) {
-      if ((r & J) == 0) {
-        const bool asc = K < kPerThread ? (r & K) == 0 : (i0 & K) == 0;
-        bitonic_pair(v[r], v[r | J], asc);
-      }
-    }
-  } else {
-    const bool take_min = ((i0 & K) == 0) == ((i0 & J) == 0);
-    constexpr int M = J / kPerThread;   // partner thread t ^ M, below NT since J < P <= NT * kPerThread
+    constexpr int M = J / kPerThread;   // partner thread t ^ M, below NT since J < length <= NT * kPerThread
     uint64_t p[kPerThread];
     if constexpr (M >= 64) {
       __syncthreads();
@@ -390,9 +342,26 @@ __device__ __forceinline__ void bitonic_stage_rt(uint64_t* sk, uint64_t (&v)[kPe
   }
 }
 
+// The chunk sort: kChunkKeys keys, every stage unrolled, so distances and
+// offsets are constants.
+template <int K, int J>
+__device__ __forceinline__ void bitonic_merge_stages(uint64_t* sk, uint64_t (&v)[kPerThread]) {
+  bitonic_stage<kChunkThreads, J>(sk, v, K, true);
+  if constexpr (J > 1) bitonic_merge_stages<K, J / 2>(sk, v);
+}
+
+template <int K>
+__device__ __forceinline__ void bitonic_from(uint64_t* sk, uint64_t (&v)[kPerThread]) {
+  bitonic_merge_stages<K, K / 2>(sk, v);
+  if constexpr (K < kChunkKeys) bitonic_from<2 * K>(sk, v);
+}
+
+// Tiles of up to kSortCap instances: one workgroup of NT threads sorts a
+// tile's list with a network of length P (the list's length rounded up to a
+// power of two) known only at run time; the waves beyond P idle.
 template <int NT, int J>
 __device__ __forceinline__ void bitonic_stage_if(uint64_t* sk, uint64_t (&v)[kPerThread], int K, bool live) {
-  if constexpr (J < NT * kPerThread) bitonic_stage_rt<NT, J>(sk, v, K, live);
+  if constexpr (J < NT * kPerThread) bitonic_stage<NT, J>(sk, v, K, live);
 }
 
 template <int NT>
