@@ -306,6 +306,38 @@ def test_tile_grids_beyond_lds(ctx):
         assert worst <= PIXEL_TOL and amb <= 2e-3, (win, worst, amb)
 
 
+def test_incremental_on_tile_grids_beyond_lds(ctx):
+    """The incremental path over 18,769 tiles of 8x8 (1100 x 1100): its frames
+    equal full renders of the same variants bit for bit, and a pipelined
+    campaign gives the records of sg_render_batch."""
+    import torch
+    from paper_2606_21791_amd import binding as b
+    sc = synth.make_scene(20000, seed=41, sh_degree=1)
+    sc.fields[1][:] -= 1.0
+    cam = synth.make_camera(1100, 1100)
+    ds = b.DeviceScene.upload(ctx, sc, "f32")
+    prep = ctx.prepare(ds, cam, b.raster_struct(tile=8))
+    sites = synth.make_sites_stratified(sc.n, 1, 32, seed=47, width_bits=32)
+    groups = [np.array([k]) for k in range(0, len(sites), max(1, len(sites) // 10))][:10]
+    groups.append(np.array([1, 2, 3]))                         # a multi-site variant
+    inc, mi = _batch(ctx, prep, sites, groups, mode=0)
+    full, mf = _batch(ctx, prep, sites, groups, mode=1)
+    assert np.array_equal(inc, full)
+    for key in ("changed_px", "max_abs", "nonfinite"):
+        assert np.array_equal(mi[key], mf[key]), key
+    assert np.all(mi["path"] == 0) and mi["dirty_tiles"].max() > 1
+    flat = np.concatenate(groups)
+    sa = b.sites_array(sites.field[flat], sites.comp[flat], sites.prim[flat], sites.bit[flat])
+    counts = np.array([len(g) for g in groups])
+    va = b.variants_array(np.concatenate([[0], np.cumsum(counts)[:-1]]), counts)
+    got = b.metrics_tensor(len(va))
+    ctx.campaign(prep, sa, va, got, batch=4, streams=2, threads=1)
+    torch.cuda.synchronize()
+    G = b.read_metrics(got)
+    for key in mi.dtype.names:
+        assert np.array_equal(G[key], mi[key]), key
+
+
 def test_guarded_and_multi_upset_variants(ctx):
     from paper_2606_21791_amd import binding as b
     sc = synth.make_scene(4000, seed=14)
