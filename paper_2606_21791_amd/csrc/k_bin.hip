@@ -304,7 +304,12 @@ __device__ __forceinline__ uint64_t lane_xor(uint64_t v) {
 // barriers.
 template <int NT, int J>
 __device__ __forceinline__ void bitonic_stage(uint64_t* sk, uint64_t (&v)[kPerThread], int K, bool live) {
-  const int t = threadIdx.x;
+  // The thread index passes through an empty asm statement so that each
+  // stage forms its lane masks where it uses them: hoisted, the masks of all
+  // 78 stages of the chunk sort held 106 SGPRs (with spills), three
+  // workgroups per CU instead of four.
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
   const int i0 = kPerThread * t;
   if constexpr (J < kPerThread) {
     if (!live) return;
