@@ -159,7 +159,8 @@ def cpu_baseline(sc, cam, sites, fmt, procs):
     return res
 
 
-def main():
+def make_parser():
+    """The command line of bench.py."""
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60,
@@ -202,6 +203,11 @@ def main():
                     help="w2: the headline; guard: support guard and accumulated dose on the N=134,826 scene; "
                          "large: the 2,056,645-primitive bf16 scene at 1600x900; stress: one guarded render at "
                          "65,812,640 primitives")
+    return ap
+
+
+def main():
+    ap = make_parser()
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every run here uses a single MI355X (--gpus 1).", file=sys.stderr)

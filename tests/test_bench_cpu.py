@@ -1,5 +1,6 @@
-"""Host-side checks of bench.py: the one-GPU contract and the staleness rule
-of the committed HBM-traffic figure (no device needed)."""
+"""Host-side checks of bench.py: the one-GPU contract, the staleness rule
+of the committed HBM-traffic figure, and that the commands the committed
+profiles record still parse (no device needed)."""
 import os
 import subprocess
 import sys
@@ -27,3 +28,27 @@ def test_traffic_figure_follows_the_measured_sources(tmp_path, monkeypatch):
     # and a missing one none either
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "absent.txt"))
     assert bench._measured_traffic() is None
+
+
+def test_profile_commands_parse():
+    """Every bench.py command recorded in profiles/ parses with the current
+    command line, so each committed summary can be taken again from committed
+    files."""
+    import glob
+    import shlex
+    sys.path.insert(0, ROOT)
+    import bench
+    ap = bench.make_parser()
+    seen = 0
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        for line in open(path):
+            if "<repo>/bench.py" not in line:
+                continue
+            args = shlex.split(line.split("<repo>/bench.py", 1)[1])
+            try:
+                _, extra = ap.parse_known_args(args)
+            except SystemExit:
+                raise AssertionError(f"{os.path.basename(path)}: bench.py rejects {args}")
+            assert not extra, (os.path.basename(path), extra)
+            seen += 1
+    assert seen >= 10, seen
